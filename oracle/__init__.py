@@ -1,0 +1,181 @@
+"""CPU oracle of the Digital Brain per-timestep step.
+
+TEST INFRASTRUCTURE ONLY: only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package. It shares no code
+with the GPU library (``paper_2211_15963_amd``); both take their network from the
+seeded generator in ``netgen``.
+
+``Oracle`` wraps ``liboracle.so`` (plain C, FP32 or FP64; see ``oracle.c`` for the
+equations and the readings of the paper). ``brute`` holds a dense numpy simulator
+for networks of at most ~50 neurons, used to pin the oracle's sparse fan-in.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int, c_int32, c_int64, c_size_t, c_uint8, c_uint32, c_uint64, c_void_p
+
+import numpy as np
+
+from netgen.desc import Desc, NetSpec
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = os.path.join(_HERE, "liboracle.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"oracle library missing: {path} (run oracle/build.py)")
+    L = ctypes.CDLL(path)
+    L.orc_create.argtypes = [POINTER(Desc), c_int, c_char_p, c_size_t]
+    L.orc_create.restype = c_void_p
+    L.orc_destroy.argtypes = [c_void_p]
+    L.orc_step.argtypes = [c_void_p, c_uint64]
+    L.orc_step.restype = c_int
+    for nm, rt in [("orc_num_neurons", c_uint32), ("orc_num_receptors", c_uint32), ("orc_steps_per_bin", c_uint32),
+                   ("orc_steps_done", c_uint64), ("orc_num_edges", c_uint64), ("orc_edge_events", c_uint64),
+                   ("orc_num_spikes", c_uint64), ("orc_bins_recorded", c_uint64)]:
+        f = getattr(L, nm)
+        f.argtypes = [c_void_p]
+        f.restype = rt
+    L.orc_get_spikes.argtypes = [c_void_p, POINTER(c_uint64), POINTER(c_uint32)]
+    L.orc_get_region_signal.argtypes = [c_void_p, POINTER(c_double), POINTER(c_uint32)]
+    L.orc_get_state.argtypes = [c_void_p, POINTER(c_double), POINTER(c_double), POINTER(c_int32)]
+    L.orc_set_state.argtypes = [c_void_p, POINTER(c_double), POINTER(c_double), POINTER(c_int32)]
+    L.orc_set_state.restype = c_int
+    L.orc_get_in_edges.argtypes = [c_void_p, POINTER(c_uint64), POINTER(c_uint32), POINTER(c_float), POINTER(c_float), POINTER(c_uint8)]
+    L.orc_philox4x32_10.argtypes = [POINTER(c_uint32), POINTER(c_uint32), POINTER(c_uint32)]
+    L.orc_bg_word.argtypes = [c_uint64, c_uint32, c_uint64, c_uint32]
+    L.orc_bg_word.restype = c_uint32
+    L.orc_poisson_table.argtypes = [c_double, POINTER(c_uint32), c_int]
+    L.orc_poisson_table.restype = c_int
+    L.orc_poisson_count.argtypes = [c_uint32, POINTER(c_uint32), c_int]
+    L.orc_poisson_count.restype = c_uint32
+    L.orc_quantize.argtypes = [c_float, c_uint32]
+    L.orc_quantize.restype = c_int64
+    L.orc_i64_to_f32.argtypes = [c_int64]
+    L.orc_i64_to_f32.restype = c_float
+    _LIB = L
+    return L
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(POINTER(ct))
+
+
+class Oracle:
+    """One oracle simulation of a ``NetSpec`` in FP32 (``precision=32``) or FP64."""
+
+    def __init__(self, spec: NetSpec, precision: int = 32):
+        L = lib()
+        self.spec = spec
+        self._holder = spec.to_c()
+        err = ctypes.create_string_buffer(512)
+        h = L.orc_create(self._holder.ptr, precision, err, 512)
+        if not h:
+            raise ValueError(f"oracle rejected the description: {err.value.decode()}")
+        self._h = h
+        self.precision = precision
+        self.N = int(L.orc_num_neurons(h))
+        self.U = int(L.orc_num_receptors(h))
+        self.S = int(L.orc_steps_per_bin(h))
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_destroy(self._h)
+            self._h = None
+
+    def step(self, n: int) -> None:
+        if lib().orc_step(self._h, int(n)) != 0:
+            raise MemoryError("oracle ran out of host memory")
+
+    @property
+    def steps_done(self) -> int:
+        return int(lib().orc_steps_done(self._h))
+
+    @property
+    def edge_events(self) -> int:
+        return int(lib().orc_edge_events(self._h))
+
+    @property
+    def num_edges(self) -> int:
+        return int(lib().orc_num_edges(self._h))
+
+    def spikes(self):
+        """(steps uint64, ids uint32) sorted by (step, id)."""
+        n = int(lib().orc_num_spikes(self._h))
+        st = np.zeros(max(n, 1), np.uint64)
+        ids = np.zeros(max(n, 1), np.uint32)
+        lib().orc_get_spikes(self._h, _p(st, c_uint64), _p(ids, c_uint32))
+        return st[:n], ids[:n]
+
+    def region_signal(self):
+        """(sig float64 [bins, regions], counts uint32 [bins, regions])."""
+        nb = int(lib().orc_bins_recorded(self._h))
+        R = self.spec.n_regions
+        sig = np.zeros(max(nb * R, 1), np.float64)
+        cnt = np.zeros(max(nb * R, 1), np.uint32)
+        lib().orc_get_region_signal(self._h, _p(sig, c_double), _p(cnt, c_uint32))
+        return sig[: nb * R].reshape(nb, R), cnt[: nb * R].reshape(nb, R)
+
+    def state(self):
+        """(V [N], J [U, N], ref [N]) as float64/int32 (exact for the FP32 variant)."""
+        V = np.zeros(self.N, np.float64)
+        J = np.zeros(self.U * self.N, np.float64)
+        ref = np.zeros(self.N, np.int32)
+        lib().orc_get_state(self._h, _p(V, c_double), _p(J, c_double), _p(ref, c_int32))
+        return V, J.reshape(self.U, self.N), ref
+
+    def set_state(self, V, J, ref=None) -> None:
+        V = np.ascontiguousarray(V, np.float64)
+        J = np.ascontiguousarray(J, np.float64).reshape(-1)
+        ref = np.zeros(self.N, np.int32) if ref is None else np.ascontiguousarray(ref, np.int32)
+        assert V.size == self.N and J.size == self.U * self.N and ref.size == self.N
+        lib().orc_set_state(self._h, _p(V, c_double), _p(J, c_double), _p(ref, c_int32))
+
+    def in_edges(self):
+        E = self.num_edges
+        ptr = np.zeros(self.N + 1, np.uint64)
+        src = np.zeros(max(E, 1), np.uint32)
+        w0 = np.zeros(max(E, 1), np.float32)
+        w1 = np.zeros(max(E, 1), np.float32)
+        dl = np.zeros(max(E, 1), np.uint8)
+        lib().orc_get_in_edges(self._h, _p(ptr, c_uint64), _p(src, c_uint32), _p(w0, c_float), _p(w1, c_float), _p(dl, c_uint8))
+        return ptr.astype(np.int64), src[:E], w0[:E], w1[:E], dl[:E]
+
+
+def philox(ctr, key):
+    c = (c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return [int(x) for x in o]
+
+
+def bg_word(seed: int, net_id: int, n: int, i: int) -> int:
+    return int(lib().orc_bg_word(seed, net_id, n, i))
+
+
+def poisson_table(lam: float):
+    T = (c_uint32 * 256)()
+    c = lib().orc_poisson_table(float(lam), T, 256)
+    if c < 0:
+        raise ValueError("rate out of range")
+    return np.array(T[:c], dtype=np.uint64)
+
+
+def poisson_count(x: int, table) -> int:
+    t = np.ascontiguousarray(table, np.uint32)
+    return int(lib().orc_poisson_count(int(x), _p(t, c_uint32), len(t)))
+
+
+def quantize(w: float, F: int) -> int:
+    return int(lib().orc_quantize(float(w), int(F)))
+
+
+def i64_to_f32(v: int) -> float:
+    return float(lib().orc_i64_to_f32(int(v)))

@@ -1,0 +1,64 @@
+/*
+ * oracle.h - CPU oracle of the Digital Brain per-timestep step.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the test-suite, the smoke check and
+ * the CPU-baseline leg of the benchmark. Never part of the product path.
+ * See oracle.c for the equations, the readings of the paper and the
+ * operation order.
+ */
+#ifndef DB_ORACLE_H
+#define DB_ORACLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "dbnet.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc orc;
+
+/* Builds the network from the seeded description (via the dbnet
+   generator) and the initial state. precision is 32 or 64. Returns NULL
+   with a message in err on failure. */
+orc* orc_create(const dbnet_desc* d, int precision, char* err, size_t errlen);
+void orc_destroy(orc* o);
+
+/* Advances n Euler steps. Returns 0, or -1 if host memory ran out. */
+int orc_step(orc* o, uint64_t n);
+
+uint32_t orc_num_neurons(const orc* o);
+uint32_t orc_num_receptors(const orc* o);
+uint32_t orc_steps_per_bin(const orc* o);
+uint64_t orc_steps_done(const orc* o);
+uint64_t orc_num_edges(const orc* o);
+/* Synaptic events delivered so far (one per edge whose source spike arrived). */
+uint64_t orc_edge_events(const orc* o);
+uint64_t orc_num_spikes(const orc* o);
+uint64_t orc_bins_recorded(const orc* o);
+
+/* All spikes so far, ordered by (step, id). Arrays sized orc_num_spikes. */
+void orc_get_spikes(const orc* o, uint64_t* steps, uint32_t* ids);
+/* Region signal and spike counts per completed bin, row-major [bin][region]. */
+void orc_get_region_signal(const orc* o, double* sig, uint32_t* cnt);
+/* State as double: V[N], J[U*N] (receptor-major), ref[N]. */
+void orc_get_state(const orc* o, double* V, double* J, int32_t* ref);
+/* Overwrites the state (FP32 variant rounds to float). */
+int orc_set_state(orc* o, const double* V, const double* J, const int32_t* ref);
+/* The incoming-edge table the oracle works from (ptr[N+1], then E entries). */
+void orc_get_in_edges(const orc* o, uint64_t* ptr, uint32_t* src, float* w0, float* w1, uint8_t* dl);
+
+/* Building blocks, exported so that the tests can pin them. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+uint32_t orc_bg_word(uint64_t seed, uint32_t net_id, uint64_t n, uint32_t i);
+int orc_poisson_table(double lambda, uint32_t* T, int cap);
+uint32_t orc_poisson_count(uint32_t x, const uint32_t* T, int cmax);
+int64_t orc_quantize(float w, uint32_t F);
+float orc_i64_to_f32(int64_t v);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

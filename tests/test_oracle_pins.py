@@ -1,0 +1,505 @@
+"""Pins of the CPU oracle against closed forms, library routines and brute force.
+
+None of these compares the oracle with itself or retypes its formulas: each
+check is a fact fixed by the mathematics of the method (closed-form solutions
+of the discrete equations, Campbell's theorem, exact rational rounding), by an
+independent library (rocRAND's Philox4x32-10, scipy's Poisson CDF), or by an
+independent dense reformulation (``oracle.brute``).
+"""
+import math
+import os
+import shutil
+import subprocess
+import tempfile
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Oracle, brute
+from netgen import configs
+from netgen.desc import (NetSpec, PopSpec, ProjSpec, RECEPTORS_2, RECEPTORS_4, SRC_POP, W_CONST, D_FIXED,
+                         D_UNIFORM)
+
+INF = float("inf")
+
+
+# --------------------------------------------------------------------------------------
+# Philox4x32-10 (counter-based generator of Salmon et al., SC'11) vs rocRAND's engine
+# --------------------------------------------------------------------------------------
+
+ROCRAND_PROBE = r"""
+#include <rocrand/rocrand_kernel.h>
+#include <cstdio>
+#include <cstdlib>
+int main(int argc, char** argv) {
+  for (int a = 1; a + 5 < argc; a += 6) {
+    unsigned long long key = strtoull(argv[a], 0, 16) | (strtoull(argv[a+1], 0, 16) << 32);
+    unsigned long long c01 = strtoull(argv[a+2], 0, 16) | (strtoull(argv[a+3], 0, 16) << 32);
+    unsigned long long c23 = strtoull(argv[a+4], 0, 16) | (strtoull(argv[a+5], 0, 16) << 32);
+    rocrand_state_philox4x32_10 st;
+    rocrand_init(key, c23, c01 * 4ull, &st);   /* counter = (c01, c23), key = seed */
+    uint4 r = rocrand4(&st);
+    printf("%u %u %u %u\n", r.x, r.y, r.z, r.w);
+  }
+  return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def rocrand_probe():
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available to build the rocRAND probe")
+    d = tempfile.mkdtemp()
+    src = os.path.join(d, "probe.cpp")
+    exe = os.path.join(d, "probe")
+    with open(src, "w") as f:
+        f.write(ROCRAND_PROBE)
+    subprocess.run([hipcc, "-x", "hip", "--offload-arch=gfx950", "-O1", src, "-o", exe], check=True,
+                   capture_output=True)
+    yield exe
+    shutil.rmtree(d, ignore_errors=True)
+
+
+def test_philox_matches_rocrand(rocrand_probe):
+    rng = np.random.default_rng(7)
+    cases = [(0, 0, 0, 0, 0, 0), (1, 0, 0, 0, 0, 0), (0, 0, 1, 0, 0, 0), (0, 0, 0, 0, 1, 0), (0, 0, 0, 0, 0, 1)]
+    for _ in range(40):
+        k0, k1, c0, c2, c3 = (int(x) for x in rng.integers(0, 2 ** 32, 5))
+        c1 = int(rng.integers(0, 2 ** 30))  # the probe encodes the counter as a discard offset * 4
+        cases.append((k0, k1, c0, c1, c2, c3))
+    args = []
+    for k0, k1, c0, c1, c2, c3 in cases:
+        args += [f"{k0:x}", f"{k1:x}", f"{c0:x}", f"{c1:x}", f"{c2:x}", f"{c3:x}"]
+    out = subprocess.run([rocrand_probe, *args], check=True, capture_output=True, text=True).stdout.split("\n")
+    for (k0, k1, c0, c1, c2, c3), line in zip(cases, out):
+        want = [int(x) for x in line.split()]
+        assert oracle.philox([c0, c1, c2, c3], [k0, k1]) == want
+        # the dense brute-force simulator carries its own numpy Philox
+        got = brute.philox_np([c0], [c1], [c2], [c3], k0, k1)
+        assert [int(x[0]) for x in got] == want
+
+
+def test_bg_word_layout():
+    # word n mod 4 of the block with counter (n/4, i, stream tag | net_id), key = seed
+    seed, net, i = 0x123456789ABCDEF0, 5, 77
+    for n in [0, 1, 2, 3, 4, 9, 4 * 2 ** 31 + 3]:
+        blk = n // 4
+        words = oracle.philox([blk & 0xFFFFFFFF, blk >> 32, i, (1 << 24) | net], [seed & 0xFFFFFFFF, seed >> 32])
+        assert oracle.bg_word(seed, net, n, i) == words[n % 4]
+
+
+def test_philox_bit_balance():
+    # every output bit of the background stream is set about half of the time
+    words = np.array([oracle.bg_word(0, 0, n, i) for n in range(64) for i in range(256)], dtype=np.uint64)
+    bits = np.array([((words >> np.uint64(b)) & np.uint64(1)).mean() for b in range(32)])
+    assert np.all(np.abs(bits - 0.5) < 0.02)
+
+
+# --------------------------------------------------------------------------------------
+# Poisson background (Extended Data Table 2: independent Poisson spike trains)
+# --------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("lam", [0.0, 0.05, 0.2, 0.556, 2.0, 10.0])
+def test_poisson_table_matches_scipy_cdf(lam):
+    from scipy.stats import poisson
+    T = oracle.poisson_table(lam)
+    if lam == 0.0:
+        assert len(T) == 0
+        return
+    cdf = poisson.cdf(np.arange(len(T) + 1), lam)
+    # thresholds are floor(2^32 * CDF(c)); CDF rounding differs only in the last bits
+    assert np.all(np.abs(T.astype(np.float64) - np.floor(cdf[:-1] * 2.0 ** 32)) <= 2)
+    assert np.all(np.diff(T.astype(np.int64)) >= 0)
+    # the table stops where the remaining tail drops below 2^-32
+    assert poisson.sf(len(T), lam) < 2.0 ** -32 * 1.01
+    assert len(T) == 0 or poisson.sf(len(T) - 1, lam) >= 2.0 ** -32 * 0.99
+
+
+def test_poisson_count_is_cdf_inversion():
+    T = oracle.poisson_table(0.7)
+    for x in [0, 1, int(T[0]) - 1, int(T[0]), int(T[1]) - 1, int(T[1]), 2 ** 32 - 1]:
+        want = int(np.searchsorted(T, x, side="right"))   # smallest c with x < T_c
+        assert oracle.poisson_count(x, T) == want
+
+
+@pytest.mark.parametrize("lam", [0.2, 0.556, 3.0])
+def test_poisson_counts_chi_square(lam):
+    from scipy.stats import chi2, poisson
+    T = oracle.poisson_table(lam)
+    n = 60000
+    counts = np.array([oracle.poisson_count(oracle.bg_word(11, 0, s, i), T) for s in range(60) for i in range(1000)])
+    kmax = int(poisson.ppf(1 - 1e-4, lam))
+    obs = np.array([np.sum(counts == c) for c in range(kmax)] + [np.sum(counts >= kmax)], dtype=np.float64)
+    exp_ = np.array([poisson.pmf(c, lam) for c in range(kmax)] + [poisson.sf(kmax - 1, lam)]) * n
+    stat = np.sum((obs - exp_) ** 2 / exp_)
+    assert chi2.sf(stat, len(obs) - 1) > 1e-4
+    assert abs(counts.mean() - lam) < 5 * math.sqrt(lam / n)
+
+
+# --------------------------------------------------------------------------------------
+# fixed point and conversions (exact rational references)
+# --------------------------------------------------------------------------------------
+
+def _rne(fr: Fraction) -> int:
+    fl = math.floor(fr)
+    rem = fr - fl
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and fl % 2 == 1):
+        return fl + 1
+    return fl
+
+
+def test_quantize_round_half_even():
+    rng = np.random.default_rng(3)
+    ws = list(rng.random(300).astype(np.float32)) + list((rng.random(100) * 4).astype(np.float32))
+    # exact ties at F = 32: (2m+1) * 2^-33
+    ws += [np.float32((2 * m + 1) * 2.0 ** -33) for m in range(8)]
+    ws += [np.float32(0.0), np.float32(1.0), np.float32(2.0 ** -40), np.float32(-0.3)]
+    for F in (32, 20, 40):
+        for w in ws:
+            want = _rne(Fraction(float(w)) * 2 ** F)
+            assert oracle.quantize(float(w), F) == want, (w, F)
+
+
+def _i64_to_f32_exact(v: int) -> float:
+    if v == 0:
+        return 0.0
+    s = -1 if v < 0 else 1
+    a = abs(v)
+    e = a.bit_length() - 24
+    if e <= 0:
+        return float(s * a)
+    q = _rne(Fraction(a, 2 ** e))
+    return float(s * q * 2 ** e)
+
+
+def test_int64_to_float_correctly_rounded():
+    rng = np.random.default_rng(4)
+    vals = [int(x) for x in rng.integers(-2 ** 62, 2 ** 62, 500)]
+    vals += [2 ** 24 + 1, 2 ** 25 + 1, 2 ** 25 + 3, 2 ** 25 + 2, -(2 ** 25 + 1), 2 ** 40 + 2 ** 16, 2 ** 40 + 2 ** 16 + 1,
+             (1 << 62) - 1, 1, -1, 0, 16777217 * 2 ** 20]
+    for v in vals:
+        assert oracle.i64_to_f32(v) == _i64_to_f32_exact(v), v
+
+
+# --------------------------------------------------------------------------------------
+# membrane integration: closed form of the discrete CV equation
+# --------------------------------------------------------------------------------------
+
+def _single_pop(size, **kw):
+    base = dict(g=(0.0, 0.0, 0.0, 0.0), tau=(INF, INF, INF, INF), V_th=INF, bg_rate_hz=0.0, w_bg=0.0,
+                v0_lo=-60.0, v0_hi=-60.0)
+    base.update(kw)
+    return PopSpec(size, True, **base)
+
+
+def test_membrane_relaxation_closed_form():
+    """tau_u = inf keeps J fixed; then V_n = V_inf + (V_0 - V_inf)(1 - kG)^n exactly."""
+    g = (2.0, 0.1, 1.5, 0.05)
+    spec = NetSpec([_single_pop(6, g=g, I_ext=100.0)], [], receptor_mask=RECEPTORS_4)
+    o = Oracle(spec, 64)
+    P = spec.pops[0]
+    V0 = np.array([-80.0, -70.0, -60.0, -55.0, -45.0, -20.0])
+    J0 = np.array([[0.0, 1.0, 2.0, 3.0, 0.5, 7.0], [0.0, 10.0, 20.0, 5.0, 1.0, 0.0],
+                   [0.0, 2.0, 0.0, 4.0, 9.0, 1.0], [0.0, 30.0, 1.0, 0.0, 3.0, 8.0]])
+    o.set_state(V0, J0)
+    n = 1500
+    o.step(n)
+    V, J, _ = o.state()
+    np.testing.assert_array_equal(J, J0)       # no decay, no input
+    f32 = lambda x: float(np.float32(x))
+    dt = f32(0.1)
+    k = dt / f32(P.C)
+    G = f32(P.g_L) + sum(f32(g[u]) * J0[u] for u in range(4))
+    Vr = (f32(P.g_L) * f32(P.V_L) + sum(f32(g[u]) * J0[u] * f32(P.V_rev[u]) for u in range(4)) + f32(P.I_ext)) / G
+    Vn = Vr + (V0 - Vr) * (1.0 - k * G) ** n
+    np.testing.assert_allclose(V, Vn, rtol=1e-11, atol=0)
+    # first-order convergence to the continuous solution exp(-t G / C)
+    t = n * dt
+    Vc = Vr + (V0 - Vr) * np.exp(-t * G / f32(P.C))
+    err = np.abs(V - Vc)
+    bound = t * (k * G) ** 2 / (2 * dt) * np.abs(V0 - Vr) / (1 - k * G) * np.exp(-(n - 1) * k * G)
+    assert np.all(err <= bound * 1.0001 + 1e-12)
+
+
+def test_membrane_relaxation_fp32_close():
+    g = (2.0, 0.1, 1.5, 0.05)
+    spec = NetSpec([_single_pop(3, g=g, I_ext=50.0)], [], receptor_mask=RECEPTORS_4)
+    o32, o64 = Oracle(spec, 32), Oracle(spec, 64)
+    V0 = np.array([-75.0, -62.0, -51.0])
+    J0 = np.array([[1.0, 2.0, 3.0], [4.0, 5.0, 6.0], [0.5, 1.5, 2.5], [3.0, 2.0, 1.0]])
+    for o in (o32, o64):
+        o.set_state(V0, J0)
+        o.step(2000)
+    assert np.max(np.abs(o32.state()[0] - o64.state()[0]) / np.abs(o64.state()[0])) < 1e-5
+
+
+# --------------------------------------------------------------------------------------
+# threshold, reset and refractory clamp: exact discrete f-I relation
+# --------------------------------------------------------------------------------------
+
+def _fi_case(dt_ms, I_ext, T_ref=2.0):
+    spec = NetSpec([_single_pop(1, V_th=-50.0, V_reset=-55.0, T_ref=T_ref, I_ext=I_ext, v0_lo=-55.0, v0_hi=-55.0)],
+                   [], dt_ms=dt_ms, bin_ms=dt_ms * 5, receptor_mask=RECEPTORS_2)
+    P = spec.pops[0]
+    f32 = lambda x: float(np.float32(x))
+    dt = f32(dt_ms)
+    a = 1.0 - dt / f32(P.C) * f32(P.g_L)
+    Vinf = f32(P.V_L) + f32(I_ext) / f32(P.g_L)
+    n = 1
+    while Vinf + (f32(P.V_reset) - Vinf) * a ** n < f32(P.V_th):
+        n += 1
+    margin = min(abs(Vinf + (f32(P.V_reset) - Vinf) * a ** m - f32(P.V_th)) for m in (n - 1, n))
+    r = int(round(f32(T_ref) / dt))
+    return spec, n, r, margin, Vinf
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_lif_fI_exact_interspike_interval(prec):
+    spec, nstar, r, margin, _ = _fi_case(0.1, 600.0)
+    assert margin > 1e-3  # the crossing is not borderline for either precision
+    o = Oracle(spec, prec)
+    o.step(3000)
+    st, ids = o.spikes()
+    assert st[0] == nstar - 1                     # V_0 = V_reset, first crossing after n* updates
+    assert np.all(np.diff(st) == r + nstar)       # ISI = r + n* steps (refractory then n* updates)
+
+
+def test_lif_fI_converges_to_continuous_curve():
+    """Discrete ISI -> T_ref + tau_m ln((V_inf - V_reset)/(V_inf - V_th)) with error O(dt).
+
+    The discrete approach a^n, a = 1 - dt g_L / C, undershoots exp(-n dt g_L / C) by a
+    relative O(dt g_L / C) per unit time and the crossing is rounded up to a whole step,
+    so |ISI_disc - ISI_cont| <= dt + t* dt g_L / C."""
+    for dt in (0.2, 0.1, 0.05):
+        spec, nstar, r, margin, Vinf = _fi_case(dt, 600.0)
+        P = spec.pops[0]
+        dtf = float(np.float32(dt))
+        isi_disc = (r + nstar) * dtf
+        tau_m = P.C / P.g_L
+        tstar = tau_m * math.log((Vinf - P.V_reset) / (Vinf - P.V_th))
+        isi_cont = P.T_ref + tstar
+        assert abs(isi_disc - isi_cont) <= dtf + tstar * dtf * P.g_L / P.C
+        o = Oracle(spec, 64)
+        o.step(int(round(60.0 / dt)))
+        st, _ = o.spikes()
+        assert np.all(np.diff(st) == r + nstar)
+
+
+# --------------------------------------------------------------------------------------
+# synaptic kinetics and delayed delivery (eq. 3; delay reading: bin k -> step (k+d)S)
+# --------------------------------------------------------------------------------------
+
+def _pair(delay, w=0.7, prec_mask=RECEPTORS_4, I_ext=0.0, v0=-40.0):
+    src = _single_pop(1, V_th=-50.0, V_reset=-55.0, T_ref=2.0, I_ext=I_ext, v0_lo=v0, v0_hi=v0,
+                      tau=(2.0, 100.0, 10.0, 150.0))
+    dst = _single_pop(1, tau=(2.0, 100.0, 10.0, 150.0))
+    pr = ProjSpec(1, dst_pop=1, src_mode=SRC_POP, src_pop=0, w_dist=W_CONST, w_a=w, d_mode=D_FIXED, d_min=delay,
+                  d_max=delay)
+    return NetSpec([src, dst], [pr], receptor_mask=prec_mask)
+
+
+@pytest.mark.parametrize("delay", [1, 2, 3, 7])
+def test_delayed_delivery_and_exponential_decay(delay):
+    spec = _pair(delay)
+    o = Oracle(spec, 64)
+    S = spec.steps_per_bin
+    Js = []
+    for _ in range((delay + 3) * S):
+        o.step(1)
+        Js.append(o.state()[1][:, 1].copy())
+    Js = np.array(Js)                      # Js[n] = J after step n
+    st, ids = o.spikes()
+    assert list(zip(st.tolist(), ids.tolist())) == [(0, 0)]   # the source fires at step 0 (bin 0)
+    m = delay * S                          # arrival at the start of bin 0 + delay
+    assert np.all(Js[:m] == 0.0)
+    w = float(np.float32(0.7))
+    f32 = lambda x: float(np.float32(x))
+    for u, tau in [(0, 2.0), (1, 100.0)]:
+        dec = math.exp(-f32(0.1) / tau)
+        want = w * dec ** np.arange(len(Js) - m)
+        np.testing.assert_allclose(Js[m:, u], want, rtol=1e-12)
+    assert np.all(Js[:, 2:] == 0.0)        # excitatory source never touches GABA receptors
+    assert o.edge_events == 1
+
+
+def test_delivery_at_bin_boundary_from_late_substep():
+    """A spike at substep 1 of bin 16 (step 161) arrives at step (16 + d) * S."""
+    spec = _pair(2, I_ext=600.0, v0=-55.0)
+    o = Oracle(spec, 64)
+    o.step(200)
+    st, _ = o.spikes()
+    assert st[0] == 161
+    V, J, _ = o.state()
+    o2 = Oracle(spec, 64)
+    o2.step(180)                           # steps 0..179 done: nothing has arrived yet
+    assert np.all(o2.state()[1][:, 1] == 0.0)
+    o2.step(1)
+    assert o2.state()[1][0, 1] == float(np.float32(0.7))
+
+
+def test_fixed_point_arrival_in_fp32():
+    spec = _pair(1, w=0.3)
+    o = Oracle(spec, 32)
+    o.step(11)
+    J = o.state()[1][:, 1]
+    q = _rne(Fraction(float(np.float32(0.3))) * 2 ** 32)
+    assert J[0] == float(np.float32(q) * np.float32(2.0 ** -32))
+
+
+# --------------------------------------------------------------------------------------
+# background drive: discrete Campbell theorem for the AMPA shot noise
+# --------------------------------------------------------------------------------------
+
+def test_background_shot_noise_campbell():
+    lam, w, tau = 0.2, 1.5, 2.0
+    pop = _single_pop(3000, tau=(tau, INF, INF, INF), bg_rate_hz=2000.0, w_bg=w)
+    spec = NetSpec([pop], [], receptor_mask=RECEPTORS_2)
+    o = Oracle(spec, 64)
+    o.step(400)
+    xs = []
+    for _ in range(150):
+        o.step(10)
+        xs.append(o.state()[1][0].copy())
+    x = np.concatenate(xs)
+    lam = 2000.0 * float(np.float32(0.1)) * 1e-3
+    d = math.exp(-float(np.float32(0.1)) / tau)
+    mean = lam * w / (1 - d)
+    var = lam * w * w / (1 - d * d)
+    assert abs(x.mean() - mean) / mean < 0.01
+    assert abs(x.var() - var) / var < 0.03
+
+
+# --------------------------------------------------------------------------------------
+# the network: brute-force dense reformulation and counting invariants
+# --------------------------------------------------------------------------------------
+
+def _small_specs():
+    a = configs.tiny(n_exc=24, n_inh=6, indegree=8, bg_rate_hz=3000)
+    a.projs[0].d_mode, a.projs[0].d_min, a.projs[0].d_max = D_UNIFORM, 1, 3
+    b = configs.share(n=40, indegree=12, regime_hz=15, d_max=4, seed=3, bg_rate_hz=9000.0)
+    c = configs.multi_region(n_regions=4, per_region=10, intra_indegree=5, long_indegree=3, seed=2,
+                             bg_rate_hz=9000.0, d_max=6)
+    d = configs.tiny(n_exc=20, n_inh=10, indegree=29, bg_rate_hz=2500, seed=5)   # all-to-all minus self
+    return [a, b, c, d]
+
+
+@pytest.mark.parametrize("idx", range(4))
+def test_oracle_matches_dense_brute_force(idx):
+    spec = _small_specs()[idx]
+    n = 700
+    raster, V, J, ref, events = brute.simulate(spec, n)
+    o = Oracle(spec, 32)
+    o.step(n)
+    st, ids = o.spikes()
+    assert len(raster) > 5
+    assert list(zip(st.tolist(), ids.tolist())) == raster
+    V2, J2, ref2 = o.state()
+    np.testing.assert_array_equal(V2, V.astype(np.float64))
+    np.testing.assert_array_equal(J2, J.astype(np.float64))
+    np.testing.assert_array_equal(ref2, ref)
+    assert o.edge_events == events
+
+
+def test_edge_events_equal_delivered_out_edges():
+    spec = configs.share(n=300, indegree=40, d_max=5, bg_rate_hz=8000.0, seed=9)
+    o = Oracle(spec, 32)
+    S = spec.steps_per_bin
+    K = 60
+    o.step(K * S)
+    st, ids = o.spikes()
+    ptr, src, w0, w1, dl = o.in_edges()
+    # expected: every (spike j at bin b, out-edge with delay d) with b + d <= K - 1
+    outd = {}
+    for e in range(len(src)):
+        outd.setdefault(int(src[e]), []).append(int(dl[e]))
+    want = 0
+    for n, j in zip(st.tolist(), ids.tolist()):
+        b = n // S
+        want += sum(1 for d in outd.get(j, []) if b + d <= K - 1)
+    assert o.edge_events == want
+
+
+def test_at_most_one_spike_per_bin():
+    o = Oracle(configs.tiny(), 32)
+    o.step(3000)
+    st, ids = o.spikes()
+    bins = st // 10
+    pairs = set()
+    for b, i in zip(bins.tolist(), ids.tolist()):
+        assert (b, i) not in pairs
+        pairs.add((b, i))
+
+
+def test_step_splitting_is_invisible():
+    spec = configs.tiny(n_exc=80, n_inh=20, indegree=20)
+    a, b = Oracle(spec, 32), Oracle(spec, 32)
+    a.step(1000)
+    for n in (3, 7, 10, 1, 179, 800):
+        b.step(n)
+    for x, y in zip(a.spikes(), b.spikes()):
+        np.testing.assert_array_equal(x, y)
+    for x, y in zip(a.state(), b.state()):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_region_signal_closed_form():
+    """With fixed J (tau = inf) the bin-end region signal is the mean of sum_u g_u J_u (V_u - V_n)."""
+    g = (2.0, 0.1, 1.5, 0.05)
+    p0 = _single_pop(3, g=g, I_ext=10.0, region=0)
+    p1 = _single_pop(2, g=g, I_ext=30.0, region=1)
+    spec = NetSpec([p0, p1], [], n_regions=2, receptor_mask=RECEPTORS_4)
+    o = Oracle(spec, 64)
+    V0 = np.array([-70.0, -65.0, -60.0, -58.0, -52.0])
+    J0 = np.abs(np.random.default_rng(1).normal(size=(4, 5))) * 3
+    o.set_state(V0, J0)
+    o.step(50)
+    sig, cnt = o.region_signal()
+    assert sig.shape == (5, 2) and np.all(cnt == 0)
+    f32 = lambda x: float(np.float32(x))
+    P = spec.pops[0]
+    k = f32(0.1) / f32(P.C)
+    Iext = np.array([10.0] * 3 + [30.0] * 2)
+    G = f32(P.g_L) + sum(f32(g[u]) * J0[u] for u in range(4))
+    Vr = (f32(P.g_L) * f32(P.V_L) + sum(f32(g[u]) * J0[u] * f32(P.V_rev[u]) for u in range(4)) + Iext) / G
+    for b in range(5):
+        n = (b + 1) * 10
+        Vn = Vr + (V0 - Vr) * (1 - k * G) ** n
+        cur = sum(f32(g[u]) * J0[u] * (f32(P.V_rev[u]) - Vn) for u in range(4))
+        np.testing.assert_allclose(sig[b], [cur[:3].mean(), cur[3:].mean()], rtol=1e-10)
+
+
+def test_fp32_state_error_against_fp64():
+    """FP32 vs FP64 oracle: state error before the first raster divergence (paper's
+    precedent: relative V error below 1e-4 over 1 s between GPU and CPU)."""
+    spec = configs.tiny()
+    a, b = Oracle(spec, 32), Oracle(spec, 64)
+    worst = 0.0
+    diverged_at = None
+    for t in range(100):
+        a.step(100)
+        b.step(100)
+        sa, sb = a.spikes(), b.spikes()
+        if len(sa[0]) != len(sb[0]) or not (np.array_equal(sa[0], sb[0]) and np.array_equal(sa[1], sb[1])):
+            diverged_at = (t + 1) * 100
+            break
+        Va, Vb = a.state()[0], b.state()[0]
+        worst = max(worst, float(np.max(np.abs(Va - Vb) / np.abs(Vb))))
+    print(f"FP32 vs FP64: max relative V error {worst:.3e} before first raster divergence at step {diverged_at}")
+    assert worst < 1e-4
+
+
+def test_oracle_regression_fixture():
+    """Stored digests written by tests/golden/make_golden.py (oracle only)."""
+    import json
+    import importlib.util
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec_ = importlib.util.spec_from_file_location("make_golden", os.path.join(here, "make_golden.py"))
+    mg = importlib.util.module_from_spec(spec_)
+    spec_.loader.exec_module(mg)
+    stored = json.load(open(os.path.join(here, "oracle_regression.json")))
+    for name, (f, steps, prec) in mg.CASES.items():
+        assert mg.digest(f(), steps, prec) == stored[name], name
