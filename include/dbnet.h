@@ -167,6 +167,8 @@ size_t dbnet_scratch_bytes(const dbnet_desc* d);
  * description order, ascending source id within a projection. scratch must
  * hold dbnet_scratch_bytes(d) bytes. Returns the number of edges, or -1 if
  * the description is invalid for this target (run dbnet_validate first).
+ * w0, w1 and delay may be NULL to skip those draws (the sources and the other
+ * outputs are unchanged).
  */
 int64_t dbnet_in_edges(const dbnet_desc* d, uint32_t i, uint32_t* src, float* w0, float* w1,
                        uint8_t* delay, void* scratch);

@@ -1,0 +1,196 @@
+/*
+ * dbsim.h - C ABI of the MI355X spiking-network step library (libdbsim.so).
+ *
+ * The library advances one GPU's share of a Digital Brain network
+ * (Lu et al., "Simulation and assimilation of the digital human brain"):
+ * leaky integrate-and-fire neurons with four receptor conductances
+ * (Methods, CV equation and eq. 2), explicit Euler-Maruyama steps of dt with
+ * spikes exchanged once per bin b_t (SI Section 3, eqs. 3 and 5 and the
+ * definition of A_j), and the fan-out of each bin's spikes through a sparse
+ * synapse table (the push-based integration of Suppl. Algorithm 2), extended
+ * with integer synaptic delays (the paper has none; one bin reproduces it).
+ *
+ * The workflow follows the paper's statement of the simulation steps
+ * (Methods, end of "Simulating Digital Brain on GPUs"): build the neuron
+ * attribute and connection tables from a description, load and deploy them,
+ * initialise, run while recording spikes and population signals.
+ *
+ * Conventions
+ *  - All functions return a dbsim_status (0 = success, negative = error);
+ *    dbsim_last_error() gives a message for the calling thread.
+ *  - Host buffers passed in are owned by the caller and are not retained.
+ *    Device memory is owned by the library (allocated through the caller's
+ *    callbacks when given, else hipMalloc) and released by dbsim_destroy.
+ *  - A handle is not thread-safe; distinct handles may be used concurrently.
+ *  - After DBSIM_EDEVICE or DBSIM_EOVERFLOW the handle is dead: only
+ *    dbsim_destroy (and the read-only query calls) remain valid.
+ *  - Step n covers simulated time [n dt, (n+1) dt); bin k covers steps
+ *    kS .. kS+S-1 with S = bin_ms / dt_ms.
+ */
+#ifndef DBSIM_H
+#define DBSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "dbnet.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DBSIM_ABI_VERSION 1u
+
+typedef enum dbsim_status {
+    DBSIM_OK = 0,
+    DBSIM_EINVAL = -1,    /* invalid argument or description */
+    DBSIM_ENOMEM = -2,    /* host allocation failed */
+    DBSIM_EHBM = -3,      /* device allocation failed (handle not created) */
+    DBSIM_EDEVICE = -4,   /* HIP runtime error (sticky) */
+    DBSIM_ETRUNC = -5,    /* output buffer too small; the needed count is returned */
+    DBSIM_EOVERFLOW = -6, /* a device-side capacity was exceeded (sticky) */
+    DBSIM_ESTATE = -7,    /* call not valid in the handle's current state */
+    DBSIM_ERANGE = -8     /* requested steps/bins are not (or no longer) recorded */
+} dbsim_status;
+
+/* Device-memory callbacks (e.g. a framework's caching allocator). alloc
+   returns a device pointer aligned to at least 256 bytes, or NULL. */
+typedef void* (*dbsim_alloc_fn)(void* ctx, size_t bytes);
+typedef void (*dbsim_free_fn)(void* ctx, void* ptr, size_t bytes);
+
+/* record_flags */
+#define DBSIM_REC_REGIONS 1u /* per-bin region signal and spike counts */
+
+typedef struct dbsim_desc {
+    uint32_t abi_version;           /* DBSIM_ABI_VERSION */
+    uint32_t record_flags;          /* DBSIM_REC_* */
+    dbnet_desc net;                 /* the seeded network description (dbnet.h) */
+    uint64_t spike_record_capacity; /* spike entries kept on the device (rounded up to
+                                       a power of two >= (max delay + 1) * N); 0 = 2^22 */
+    uint32_t record_bins;           /* bins of spike/region history kept (power of two,
+                                       >= max delay + 1); 0 = 4096 */
+    int32_t device;                 /* HIP device ordinal, -1 = the current device */
+    void* hip_stream;               /* hipStream_t to run on; NULL = a stream of the library */
+    dbsim_alloc_fn dev_alloc;       /* optional device allocator (NULL = hipMalloc) */
+    dbsim_free_fn dev_free;         /* required when dev_alloc is given */
+    void* alloc_ctx;
+    uint32_t host_threads;          /* threads for network construction, 0 = all cores */
+    uint32_t flags;                 /* DBSIM_F_* */
+} dbsim_desc;
+
+/* flags */
+#define DBSIM_F_NO_GRAPH 1u /* launch kernels directly instead of replaying HIP graphs */
+
+typedef struct dbsim_stats {
+    uint64_t steps;        /* Euler steps completed (queued) */
+    uint64_t bins;         /* bins completed */
+    uint64_t spikes;       /* spikes emitted in completed bins */
+    uint64_t edge_events;  /* synaptic events delivered (edge whose source spike arrived) */
+    uint64_t num_neurons;
+    uint64_t num_edges;
+    uint64_t hbm_bytes;    /* device bytes held by the handle */
+    uint64_t timed_bins;   /* bins covered by the phase timers below */
+    double ms_scatter;     /* summed kernel time per phase while timing is on */
+    double ms_gather;
+    double ms_neuron;
+    double ms_readout;
+    double build_seconds;  /* host time spent constructing the network in dbsim_create */
+} dbsim_stats;
+
+typedef struct dbsim_info {
+    uint64_t num_neurons, num_edges;
+    uint32_t receptors;        /* |U|: 2 or 4 */
+    uint32_t weights_per_edge; /* 1 or 2 */
+    uint32_t steps_per_bin;    /* S */
+    uint32_t max_delay;        /* D (bins) */
+    uint32_t n_regions;
+    uint32_t tile_neurons;     /* targets per accumulation tile */
+    uint32_t n_tiles;
+    uint32_t frac_bits;        /* F of the fixed-point arrival sums */
+} dbsim_info;
+
+/* Library ABI version (DBSIM_ABI_VERSION of the build). */
+uint32_t dbsim_abi_version(void);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* dbsim_last_error(void);
+
+/*
+ * Builds the network from the seeded description (neuron attribute table,
+ * connection table re-laid out by presynaptic neuron, derived constants),
+ * allocates device memory, uploads, and sets the initial state (V from the
+ * generator, J = 0, not refractory). Host work runs on host_threads threads.
+ * Errors: EINVAL (description; message says why), ENOMEM, EHBM (allocation
+ * failed; nothing is leaked), EDEVICE.
+ */
+int dbsim_create(const dbsim_desc* desc, struct dbsim** out);
+
+/* Exact device bytes dbsim_create would allocate for desc, without building. */
+int dbsim_footprint(const dbsim_desc* desc, uint64_t* hbm_bytes);
+
+/* Queries sizes of a built network. */
+int dbsim_get_info(struct dbsim* h, dbsim_info* info);
+
+/*
+ * Advances n_steps Euler steps (any count; partial bins are legal).
+ * Asynchronous on the handle's stream; errors from device work surface at
+ * the next dbsim_sync or read call.
+ */
+int dbsim_step(struct dbsim* h, uint64_t n_steps);
+
+/* Waits for queued work; surfaces deferred device errors (EDEVICE, EOVERFLOW). */
+int dbsim_sync(struct dbsim* h);
+
+/*
+ * Spikes with step_lo <= step < step_hi, sorted by (step, id), copied to
+ * steps[] / ids[] (cap entries each). Only completed bins are visible. If
+ * cap is too small returns ETRUNC with *n_out = the count needed. ERANGE if
+ * part of the range has left the device history. Synchronises.
+ */
+int dbsim_read_spikes(struct dbsim* h, uint64_t step_lo, uint64_t step_hi, uint64_t* steps,
+                      uint32_t* ids, uint64_t cap, uint64_t* n_out);
+
+/*
+ * Region signal for bins bin_lo <= k < bin_hi: sig[(k - bin_lo) * n_regions + r]
+ * is the mean over region r's neurons of the total synaptic current
+ * sum_u g_u J_u (V_u - V) at the end of bin k (pA); counts (may be NULL)
+ * holds the region's spike count in that bin. cap counts entries
+ * (bins * regions). Requires DBSIM_REC_REGIONS. Synchronises.
+ */
+int dbsim_read_region_signal(struct dbsim* h, uint64_t bin_lo, uint64_t bin_hi, double* sig,
+                             uint32_t* counts, uint64_t cap, uint64_t* n_out);
+
+/* Host copies of the state: V[N], J[|U| * N] (receptor-major: AMPA, [NMDA],
+   GABA_A, [GABA_B]), refractory steps left ref[N]. Any pointer may be NULL. */
+int dbsim_read_state(struct dbsim* h, float* V, float* J, int32_t* ref);
+
+/* Overwrites the state (checkpoint restore). Only at a bin boundary (ESTATE
+   otherwise). ref values must lie in [0, 255]. */
+int dbsim_write_state(struct dbsim* h, const float* V, const float* J, const int32_t* ref);
+
+/*
+ * Host copy of the device connection table: row_ptr[N+1] (edge offsets of
+ * each presynaptic row), seg[N * (D+1)] (offset of each delay's first edge
+ * within the row; seg[j*(D+1)+d-1] .. seg[j*(D+1)+d] are the delay-d edges),
+ * tgt[E], w0[E], w1[E] (w1 ignored and may be NULL with one weight per
+ * edge). Rows hold edges sorted by (delay, target).
+ */
+int dbsim_export_csr(struct dbsim* h, uint64_t* row_ptr, uint32_t* seg, uint32_t* tgt, float* w0,
+                     float* w1);
+
+/* Turns per-phase kernel timing (HIP events around each phase of every
+   bin) on or off; while on, bins are launched directly, not via graphs. */
+int dbsim_set_timing(struct dbsim* h, int on);
+
+/* Counters and timers (synchronises to resolve timers). */
+int dbsim_get_stats(struct dbsim* h, dbsim_stats* s);
+
+/* Frees everything; NULL is a no-op. */
+int dbsim_destroy(struct dbsim* h);
+
+typedef struct dbsim dbsim;
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DBSIM_H */

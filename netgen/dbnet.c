@@ -325,8 +325,8 @@ int64_t dbnet_in_edges(const dbnet_desc* d, uint32_t i, uint32_t* src, float* w0
             const dbnet_pop* Sp = &d->pops[q];
             double scale = Sp->exc ? (double)pr->w_scale_exc : (double)pr->w_scale_inh;
             src[out] = s;
-            w0[out] = (float)(scale * weight_draw(d, pr, ST_W0, ST_W0B, i, j, a));
-            w1[out] = kw == 2 ? (float)(scale * weight_draw(d, pr, ST_W1, ST_W1B, i, j, a)) : 0.0f;
+            if (w0) w0[out] = (float)(scale * weight_draw(d, pr, ST_W0, ST_W0B, i, j, a));
+            if (w1) w1[out] = kw == 2 ? (float)(scale * weight_draw(d, pr, ST_W1, ST_W1B, i, j, a)) : 0.0f;
             uint32_t dl;
             if (pr->d_mode == DBNET_D_FIXED) {
                 dl = pr->d_min;
@@ -340,7 +340,7 @@ int64_t dbnet_in_edges(const dbnet_desc* d, uint32_t i, uint32_t* src, float* w0
                 double bins = ceil(dist / ((double)d->velocity_mm_per_ms * (double)d->bin_ms));
                 dl = bins < (double)pr->d_min ? pr->d_min : bins > (double)pr->d_max ? pr->d_max : (uint32_t)bins;
             }
-            delay[out] = (uint8_t)dl;
+            if (delay) delay[out] = (uint8_t)dl;
             out++;
         }
     }

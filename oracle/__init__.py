@@ -33,6 +33,14 @@ def lib():
     L = ctypes.CDLL(path)
     L.orc_create.argtypes = [POINTER(Desc), c_int, c_char_p, c_size_t]
     L.orc_create.restype = c_void_p
+    L.orc_create_ex.argtypes = [POINTER(Desc), c_int, c_uint32, c_char_p, c_size_t]
+    L.orc_create_ex.restype = c_void_p
+    L.orc_point_arrivals.argtypes = [c_void_p, c_uint64, c_uint64, POINTER(c_uint64), POINTER(c_uint32), c_uint32,
+                                     POINTER(c_uint32), POINTER(c_float), POINTER(c_uint64)]
+    L.orc_point_arrivals.restype = c_int
+    L.orc_point_step.argtypes = [c_void_p, c_uint32, c_uint64, POINTER(c_float), POINTER(c_float), POINTER(c_float),
+                                 POINTER(c_int32), POINTER(c_int)]
+    L.orc_point_step.restype = c_int
     L.orc_destroy.argtypes = [c_void_p]
     L.orc_step.argtypes = [c_void_p, c_uint64]
     L.orc_step.restype = c_int
@@ -70,12 +78,12 @@ def _p(a, ct):
 class Oracle:
     """One oracle simulation of a ``NetSpec`` in FP32 (``precision=32``) or FP64."""
 
-    def __init__(self, spec: NetSpec, precision: int = 32):
+    def __init__(self, spec: NetSpec, precision: int = 32, params_only: bool = False):
         L = lib()
         self.spec = spec
         self._holder = spec.to_c()
         err = ctypes.create_string_buffer(512)
-        h = L.orc_create(self._holder.ptr, precision, err, 512)
+        h = L.orc_create_ex(self._holder.ptr, precision, 1 if params_only else 0, err, 512)
         if not h:
             raise ValueError(f"oracle rejected the description: {err.value.decode()}")
         self._h = h
@@ -136,6 +144,31 @@ class Oracle:
         ref = np.zeros(self.N, np.int32) if ref is None else np.ascontiguousarray(ref, np.int32)
         assert V.size == self.N and J.size == self.U * self.N and ref.size == self.N
         lib().orc_set_state(self._h, _p(V, c_double), _p(J, c_double), _p(ref, c_int32))
+
+    def point_arrivals(self, bin_k: int, spk_steps, spk_ids, targets):
+        """Arrivals A [len(targets), U] due at the start of bin_k, from the given spikes."""
+        st = np.ascontiguousarray(spk_steps, np.uint64)
+        ids = np.ascontiguousarray(spk_ids, np.uint32)
+        tg = np.ascontiguousarray(targets, np.uint32)
+        A = np.zeros(len(tg) * self.U, np.float32)
+        ev = c_uint64(0)
+        rc = lib().orc_point_arrivals(self._h, int(bin_k), len(st), _p(st, c_uint64), _p(ids, c_uint32), len(tg),
+                                      _p(tg, c_uint32), _p(A, c_float), ctypes.byref(ev))
+        if rc != 0:
+            raise RuntimeError("point arrivals failed")
+        return A.reshape(len(tg), self.U), int(ev.value)
+
+    def point_step(self, i: int, n: int, A, V: float, J, ref: int):
+        """One FP32 Euler step of neuron i at step n from the given state; returns (V, J, ref, spiked)."""
+        a = np.ascontiguousarray(A, np.float32)
+        v = np.array([V], np.float32)
+        j = np.ascontiguousarray(J, np.float32).copy()
+        r = np.array([ref], np.int32)
+        sp = ctypes.c_int(0)
+        if lib().orc_point_step(self._h, int(i), int(n), _p(a, c_float), _p(v, c_float), _p(j, c_float),
+                                _p(r, c_int32), ctypes.byref(sp)) != 0:
+            raise RuntimeError("point step failed")
+        return float(v[0]), j, int(r[0]), bool(sp.value)
 
     def in_edges(self):
         E = self.num_edges

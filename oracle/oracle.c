@@ -162,6 +162,7 @@ struct orc {
     uint64_t* spk_step; uint32_t* spk_id;
     uint64_t nbins_rec, capbins;
     double* sig; uint32_t* cnt;
+    int params_only;
 };
 
 static void* xcalloc(size_t n, size_t s) {
@@ -185,6 +186,10 @@ static void seterr(char* err, size_t len, const char* m) {
 }
 
 orc* orc_create(const dbnet_desc* d, int precision, char* err, size_t errlen) {
+    return orc_create_ex(d, precision, 0, err, errlen);
+}
+
+orc* orc_create_ex(const dbnet_desc* d, int precision, uint32_t flags, char* err, size_t errlen) {
     if (dbnet_validate(d, err, errlen) != 0) return NULL;
     if (precision != 32 && precision != 64) { seterr(err, errlen, "precision must be 32 or 64"); return NULL; }
     orc* o = (orc*)xcalloc(1, sizeof(orc));
@@ -262,7 +267,8 @@ orc* orc_create(const dbnet_desc* d, int precision, char* err, size_t errlen) {
     o->in_ptr = (uint64_t*)malloc(sizeof(uint64_t) * (N + 1));
     o->in_ptr[0] = 0;
     for (uint32_t i = 0; i < N; i++) o->in_ptr[i + 1] = o->in_ptr[i] + dbnet_indegree(d, i);
-    uint64_t E = o->in_ptr[N];
+    o->params_only = (flags & ORC_PARAMS_ONLY) != 0;
+    uint64_t E = o->params_only ? 0 : o->in_ptr[N];
     o->in_src = (uint32_t*)malloc(sizeof(uint32_t) * (E ? E : 1));
     o->in_w0 = (float*)malloc(sizeof(float) * (E ? E : 1));
     o->in_w1 = (float*)malloc(sizeof(float) * (E ? E : 1));
@@ -271,7 +277,7 @@ orc* orc_create(const dbnet_desc* d, int precision, char* err, size_t errlen) {
     if (!o->in_src || !o->in_w0 || !o->in_w1 || !o->in_d || !scratch) {
         free(scratch); seterr(err, errlen, "out of host memory"); orc_destroy(o); return NULL;
     }
-    for (uint32_t i = 0; i < N; i++) {
+    for (uint32_t i = 0; i < N && !o->params_only; i++) {
         uint64_t a = o->in_ptr[i];
         int64_t k = dbnet_in_edges(d, i, o->in_src + a, o->in_w0 + a, o->in_w1 + a, o->in_d + a, scratch);
         if (k != (int64_t)(o->in_ptr[i + 1] - a)) {
@@ -388,8 +394,64 @@ static void arrivals(orc* o, uint64_t k) {
     }
 }
 
+/* One Euler step of one neuron (FP32): all right-hand sides use the old V and
+   J; A is this step's arrival (zero except at a bin start), c the background
+   count. Returns 1 if the neuron spiked. */
+static int neuron_step32(const orc_pop* P, uint32_t U, uint32_t c, const float* A, float* Vp, float* J, int32_t* ref) {
+    const float V = *Vp;
+    float Vn;
+    int spiked = 0;
+    if (*ref > 0) {
+        Vn = P->Vr32;
+        *ref -= 1;
+    } else {
+        float I = P->gL32 * (P->VL32 - V);
+        for (uint32_t u = 0; u < U; u++) {
+            float gJ = P->g32[u] * J[u];
+            I = I + gJ * (P->Vu32[u] - V);
+        }
+        I = I + P->Iext32;
+        Vn = V + P->k32 * I;
+        if (Vn >= P->Vth32) { spiked = 1; Vn = P->Vr32; *ref = P->r; }
+    }
+    *Vp = Vn;
+    float B = P->wbg32 * (float)c;
+    for (uint32_t u = 0; u < U; u++) {
+        float Jn = P->d32[u] * J[u] + A[u];
+        if (u == 0) Jn = Jn + B;
+        J[u] = Jn;
+    }
+    return spiked;
+}
+
+/* The same step in FP64. */
+static int neuron_step64(const orc_pop* P, uint32_t U, uint32_t c, const double* A, double* Vp, double* J, int32_t* ref) {
+    const double V = *Vp;
+    double Vn;
+    int spiked = 0;
+    if (*ref > 0) {
+        Vn = P->Vr64;
+        *ref -= 1;
+    } else {
+        double I = P->gL64 * (P->VL64 - V);
+        for (uint32_t u = 0; u < U; u++) I = I + (P->g64[u] * J[u]) * (P->Vu64[u] - V);
+        I = I + P->Iext64;
+        Vn = V + P->k64 * I;
+        if (Vn >= P->Vth64) { spiked = 1; Vn = P->Vr64; *ref = P->r; }
+    }
+    *Vp = Vn;
+    double B = P->wbg64 * (double)c;
+    for (uint32_t u = 0; u < U; u++) {
+        double Jn = P->d64[u] * J[u] + A[u];
+        if (u == 0) Jn = Jn + B;
+        J[u] = Jn;
+    }
+    return spiked;
+}
+
 int orc_step(orc* o, uint64_t nsteps) {
     const uint32_t N = o->N, U = o->U, S = o->S;
+    if (o->params_only) return -2;
     for (uint64_t t = 0; t < nsteps; t++) {
         const uint64_t n = o->step;
         const uint64_t k = n / S;
@@ -403,50 +465,23 @@ int orc_step(orc* o, uint64_t nsteps) {
             /* background Poisson count */
             uint32_t x = orc_bg_word(o->d.seed, o->d.net_id, n, i);
             uint32_t c = orc_poisson_count(x, P->T, P->cmax);
-            int spiked = 0;
+            int spiked;
             if (o->prec == 32) {
-                float V = o->V32[i], Vn;
-                if (o->ref[i] > 0) {
-                    Vn = P->Vr32;
-                    o->ref[i] -= 1;
-                } else {
-                    float I = P->gL32 * (P->VL32 - V);
-                    for (uint32_t u = 0; u < U; u++) {
-                        float gJ = P->g32[u] * o->J32[(size_t)u * N + i];
-                        I = I + gJ * (P->Vu32[u] - V);
-                    }
-                    I = I + P->Iext32;
-                    Vn = V + P->k32 * I;
-                    if (Vn >= P->Vth32) { spiked = 1; Vn = P->Vr32; o->ref[i] = P->r; }
-                }
-                o->V32[i] = Vn;
-                float B = P->wbg32 * (float)c;
+                float J[4], A[4];
                 for (uint32_t u = 0; u < U; u++) {
-                    float A = (s == 0) ? o->A32[(size_t)u * N + i] : 0.0f;
-                    float Jn = P->d32[u] * o->J32[(size_t)u * N + i] + A;
-                    if (u == 0) Jn = Jn + B;
-                    o->J32[(size_t)u * N + i] = Jn;
+                    J[u] = o->J32[(size_t)u * N + i];
+                    A[u] = (s == 0) ? o->A32[(size_t)u * N + i] : 0.0f;
                 }
+                spiked = neuron_step32(P, U, c, A, &o->V32[i], J, &o->ref[i]);
+                for (uint32_t u = 0; u < U; u++) o->J32[(size_t)u * N + i] = J[u];
             } else {
-                double V = o->V64[i], Vn;
-                if (o->ref[i] > 0) {
-                    Vn = P->Vr64;
-                    o->ref[i] -= 1;
-                } else {
-                    double I = P->gL64 * (P->VL64 - V);
-                    for (uint32_t u = 0; u < U; u++) I = I + (P->g64[u] * o->J64[(size_t)u * N + i]) * (P->Vu64[u] - V);
-                    I = I + P->Iext64;
-                    Vn = V + P->k64 * I;
-                    if (Vn >= P->Vth64) { spiked = 1; Vn = P->Vr64; o->ref[i] = P->r; }
-                }
-                o->V64[i] = Vn;
-                double B = P->wbg64 * (double)c;
+                double J[4], A[4];
                 for (uint32_t u = 0; u < U; u++) {
-                    double A = (s == 0) ? o->A64[(size_t)u * N + i] : 0.0;
-                    double Jn = P->d64[u] * o->J64[(size_t)u * N + i] + A;
-                    if (u == 0) Jn = Jn + B;
-                    o->J64[(size_t)u * N + i] = Jn;
+                    J[u] = o->J64[(size_t)u * N + i];
+                    A[u] = (s == 0) ? o->A64[(size_t)u * N + i] : 0.0;
                 }
+                spiked = neuron_step64(P, U, c, A, &o->V64[i], J, &o->ref[i]);
+                for (uint32_t u = 0; u < U; u++) o->J64[(size_t)u * N + i] = J[u];
             }
             if (spiked) {
                 o->binspk[i] = 1;
@@ -468,7 +503,7 @@ uint32_t orc_num_neurons(const orc* o) { return o->N; }
 uint32_t orc_num_receptors(const orc* o) { return o->U; }
 uint32_t orc_steps_per_bin(const orc* o) { return o->S; }
 uint64_t orc_steps_done(const orc* o) { return o->step; }
-uint64_t orc_num_edges(const orc* o) { return o->in_ptr[o->N]; }
+uint64_t orc_num_edges(const orc* o) { return o->params_only ? 0 : o->in_ptr[o->N]; }
 uint64_t orc_edge_events(const orc* o) { return o->edge_events; }
 uint64_t orc_num_spikes(const orc* o) { return o->nspk; }
 uint64_t orc_bins_recorded(const orc* o) { return o->nbins_rec; }
@@ -511,4 +546,61 @@ void orc_get_in_edges(const orc* o, uint64_t* ptr, uint32_t* src, float* w0, flo
     memcpy(w0, o->in_w0, sizeof(float) * E);
     memcpy(w1, o->in_w1, sizeof(float) * E);
     memcpy(dl, o->in_d, E);
+}
+
+/* ---------------- point evaluations (sampled checks of large runs) ---------------- */
+
+static int cmp_u64(const void* a, const void* b) {
+    uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+    return x < y ? -1 : x > y;
+}
+
+int orc_point_arrivals(orc* o, uint64_t bin, uint64_t nspk, const uint64_t* spk_steps, const uint32_t* spk_ids,
+                       uint32_t ntargets, const uint32_t* targets, float* A, uint64_t* events) {
+    const uint32_t U = o->U, KW = o->KW, S = o->S;
+    /* spikes of bins bin-D .. bin-1 as sorted (bin << 32 | id) keys */
+    uint64_t* keys = (uint64_t*)malloc(sizeof(uint64_t) * (nspk ? nspk : 1));
+    if (!keys) return -1;
+    uint64_t nk = 0;
+    for (uint64_t x = 0; x < nspk; x++) {
+        uint64_t b = spk_steps[x] / S;
+        if (b < bin && bin - b < o->R) keys[nk++] = (b << 32) | spk_ids[x];
+    }
+    qsort(keys, nk, sizeof(uint64_t), cmp_u64);
+    uint32_t kmax = dbnet_max_indegree(&o->d);
+    uint32_t* src = (uint32_t*)malloc(sizeof(uint32_t) * (kmax ? kmax : 1));
+    float* w0 = (float*)malloc(sizeof(float) * (kmax ? kmax : 1));
+    float* w1 = (float*)malloc(sizeof(float) * (kmax ? kmax : 1));
+    uint8_t* dl = (uint8_t*)malloc(kmax ? kmax : 1);
+    void* scratch = malloc(dbnet_scratch_bytes(&o->d));
+    int rc = (src && w0 && w1 && dl && scratch) ? 0 : -1;
+    uint64_t ev = 0;
+    for (uint32_t t = 0; t < ntargets && rc == 0; t++) {
+        int64_t k = dbnet_in_edges(&o->d, targets[t], src, w0, w1, dl, scratch);
+        if (k < 0) { rc = -1; break; }
+        int64_t q[4] = {0, 0, 0, 0};
+        for (int64_t e = 0; e < k; e++) {
+            if ((uint64_t)dl[e] > bin) continue;
+            uint64_t key = ((bin - dl[e]) << 32) | src[e];
+            if (!bsearch(&key, keys, nk, sizeof(uint64_t), cmp_u64)) continue;
+            uint32_t base = o->is_exc[src[e]] ? 0u : KW;
+            q[base] += orc_quantize(w0[e], o->F);
+            if (KW == 2) q[base + 1] += orc_quantize(w1[e], o->F);
+            ev++;
+        }
+        for (uint32_t u = 0; u < U; u++) A[(size_t)t * U + u] = orc_i64_to_f32(q[u]) * ldexpf(1.0f, -(int)o->F);
+    }
+    if (events) *events = ev;
+    free(keys); free(src); free(w0); free(w1); free(dl); free(scratch);
+    return rc;
+}
+
+int orc_point_step(orc* o, uint32_t i, uint64_t n, const float* A, float* V, float* J, int32_t* ref, int* spiked) {
+    if (o->prec != 32 || i >= o->N) return -1;
+    const orc_pop* P = &o->P[o->pop_of[i]];
+    uint32_t c = orc_poisson_count(orc_bg_word(o->d.seed, o->d.net_id, n, i), P->T, P->cmax);
+    float Az[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    int s = neuron_step32(P, o->U, c, (n % o->S == 0 && A) ? A : Az, V, J, ref);
+    if (spiked) *spiked = s;
+    return 0;
 }

@@ -24,6 +24,10 @@ typedef struct orc orc;
    generator) and the initial state. precision is 32 or 64. Returns NULL
    with a message in err on failure. */
 orc* orc_create(const dbnet_desc* d, int precision, char* err, size_t errlen);
+/* flags: ORC_PARAMS_ONLY builds the constants and the state but not the edge
+   table (for point evaluations of networks too large to simulate here). */
+#define ORC_PARAMS_ONLY 1u
+orc* orc_create_ex(const dbnet_desc* d, int precision, uint32_t flags, char* err, size_t errlen);
 void orc_destroy(orc* o);
 
 /* Advances n Euler steps. Returns 0, or -1 if host memory ran out. */
@@ -49,6 +53,14 @@ void orc_get_state(const orc* o, double* V, double* J, int32_t* ref);
 int orc_set_state(orc* o, const double* V, const double* J, const int32_t* ref);
 /* The incoming-edge table the oracle works from (ptr[N+1], then E entries). */
 void orc_get_in_edges(const orc* o, uint64_t* ptr, uint32_t* src, float* w0, float* w1, uint8_t* dl);
+
+/* Point evaluations for sampled checks of large runs (FP32 oracle):
+   arrivals A[t*U+u] due at the start of `bin` for each target, from the given
+   spike list (pull form of eq. 3, fixed point), and one Euler step of neuron
+   i at step n from a given state (A is used only when n is a bin start). */
+int orc_point_arrivals(orc* o, uint64_t bin, uint64_t nspk, const uint64_t* spk_steps, const uint32_t* spk_ids,
+                       uint32_t ntargets, const uint32_t* targets, float* A, uint64_t* events);
+int orc_point_step(orc* o, uint32_t i, uint64_t n, const float* A, float* V, float* J, int32_t* ref, int* spiked);
 
 /* Building blocks, exported so that the tests can pin them. */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

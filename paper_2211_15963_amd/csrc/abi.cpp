@@ -1,0 +1,660 @@
+// abi.cpp - the C ABI of libdbsim: handle lifecycle, the bin driver (direct
+// launches or replayed HIP graphs), recording reads and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dbsim.h"
+#include "dbsim_internal.hpp"
+#include "netbuild.hpp"
+
+using namespace dbs;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (dev >= 0 && hipGetDevice(&prev) == hipSuccess && prev != dev) {
+            if (hipSetDevice(dev) != hipSuccess) prev = -1;
+        } else {
+            prev = -1;
+        }
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+constexpr int kGraphBins = 8; // bins captured in one replayable graph
+constexpr int kPhases = 4;    // scatter, gather, neuron, readout+close
+
+} // namespace
+
+struct dbsim {
+    dbsim_desc desc{};
+    std::vector<dbnet_pop> pops;
+    std::vector<dbnet_proj> projs;
+    std::vector<float> xyz;
+    Plan plan;
+    int device = -1;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t cap_stream = nullptr;
+    unsigned char* dev = nullptr;
+    DevNet net{};
+    int scatter_grid = 512;
+    hipGraphExec_t g_multi = nullptr;
+    hipGraphExec_t g_one = nullptr;
+    uint64_t step = 0;
+    int dead = 0; // sticky error code
+    bool timing = false;
+    std::vector<std::array<hipEvent_t, kPhases + 1>> ev_pending;
+    std::vector<std::array<hipEvent_t, kPhases + 1>> ev_pool;
+    double ms[kPhases] = {0, 0, 0, 0};
+    uint64_t timed_bins = 0;
+    double build_seconds = 0.0;
+};
+
+namespace {
+
+int hip_fail(dbsim* h, hipError_t e, const char* what) {
+    if (h) h->dead = DBSIM_EDEVICE;
+    return fail(DBSIM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(h, x, what)                                                                                             \
+    do {                                                                                                               \
+        hipError_t e_ = (x);                                                                                           \
+        if (e_ != hipSuccess) return hip_fail((h), e_, (what));                                                        \
+    } while (0)
+
+template <class T>
+T* at(unsigned char* base, const Plan::Slot& s) {
+    return reinterpret_cast<T*>(base + s.off);
+}
+
+void fill_devnet(dbsim* h) {
+    const Plan& p = h->plan;
+    unsigned char* b = h->dev;
+    DevNet& n = h->net;
+    n.N = p.N;
+    n.U = p.U;
+    n.KW = p.KW;
+    n.S = p.S;
+    n.D = p.D;
+    n.F = p.F;
+    n.tile_bits = p.tile_bits;
+    n.T = p.T;
+    n.n_blocks = p.n_blocks;
+    n.n_regions = p.n_regions;
+    n.RCmask = p.RC - 1;
+    n.MBmask = p.MB - 1;
+    n.net_id = h->desc.net.net_id;
+    n.seed = h->desc.net.seed;
+    n.qscale = std::ldexp(1.0, (int)p.F);
+    n.qinv = std::ldexp(1.0f, -(int)p.F);
+    n.regions_on = p.regions_on ? 1u : 0u;
+    n.V = at<float>(b, p.V);
+    n.J = at<float>(b, p.J);
+    n.ref = at<uint8_t>(b, p.ref);
+    n.pend = at<uint8_t>(b, p.pend);
+    n.A = at<float>(b, p.A);
+    n.pops = at<const PopParams>(b, p.pops);
+    n.ptab = at<const uint32_t>(b, p.ptab);
+    n.blk = at<const uint2>(b, p.blk);
+    n.row_ptr = at<const uint64_t>(b, p.row_ptr);
+    n.seg = at<const uint32_t>(b, p.seg);
+    n.col = at<const uint32_t>(b, p.col);
+    n.w = at<const float>(b, p.w);
+    n.src_inh = at<const uint8_t>(b, p.src_inh);
+    n.ev_tgt = at<uint16_t>(b, p.ev_tgt);
+    n.ev_w = at<float>(b, p.ev_w);
+    n.tile_base = at<const uint64_t>(b, p.tile_base);
+    n.tile_fill = at<uint32_t>(b, p.tile_fill);
+    n.rec = at<uint32_t>(b, p.rec);
+    n.bin_start = at<unsigned long long>(b, p.bin_start);
+    n.bin_cnt = at<uint32_t>(b, p.bin_cnt);
+    n.blk_sig = at<double>(b, p.blk_sig);
+    n.blk_cnt = at<uint32_t>(b, p.blk_cnt);
+    n.reg_blk_ptr = at<const uint32_t>(b, p.reg_blk_ptr);
+    n.reg_blk = at<const uint32_t>(b, p.reg_blk);
+    n.reg_size = at<const uint32_t>(b, p.reg_size);
+    n.sig = at<double>(b, p.sig);
+    n.sig_cnt = at<uint32_t>(b, p.sig_cnt);
+    n.ctl = at<Ctl>(b, p.ctl);
+}
+
+hipError_t enqueue_bin_start(dbsim* h, hipStream_t st) {
+    hipError_t e = launch_scatter(h->net, h->scatter_grid, st);
+    if (e != hipSuccess) return e;
+    return launch_gather(h->net, st);
+}
+
+hipError_t enqueue_bin_end(dbsim* h, hipStream_t st) {
+    if (h->plan.regions_on) {
+        hipError_t e = launch_readout(h->net, st);
+        if (e != hipSuccess) return e;
+    }
+    return launch_close(h->net, st);
+}
+
+hipError_t enqueue_full_bin(dbsim* h, hipStream_t st) {
+    hipError_t e = enqueue_bin_start(h, st);
+    if (e != hipSuccess) return e;
+    e = launch_neuron(h->net, 0, (int)h->plan.S, st);
+    if (e != hipSuccess) return e;
+    return enqueue_bin_end(h, st);
+}
+
+hipError_t capture_graph(dbsim* h, int bins, hipGraphExec_t* out) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    for (int b = 0; b < bins && e == hipSuccess; b++) e = enqueue_full_bin(h, h->cap_stream);
+    hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+}
+
+std::array<hipEvent_t, kPhases + 1> take_events(dbsim* h, hipError_t* e) {
+    std::array<hipEvent_t, kPhases + 1> ev{};
+    *e = hipSuccess;
+    if (!h->ev_pool.empty()) {
+        ev = h->ev_pool.back();
+        h->ev_pool.pop_back();
+        return ev;
+    }
+    for (auto& x : ev) {
+        *e = hipEventCreate(&x);
+        if (*e != hipSuccess) return ev;
+    }
+    return ev;
+}
+
+int resolve_timers(dbsim* h) {
+    for (auto& ev : h->ev_pending) {
+        for (int k = 0; k < kPhases; k++) {
+            float ms = 0.0f;
+            hipError_t e = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+            if (e != hipSuccess) return hip_fail(h, e, "hipEventElapsedTime");
+            h->ms[k] += ms;
+        }
+        h->timed_bins++;
+        h->ev_pool.push_back(ev);
+    }
+    h->ev_pending.clear();
+    return DBSIM_OK;
+}
+
+int check_usable(dbsim* h) {
+    if (!h) return fail(DBSIM_EINVAL, "null handle");
+    if (h->dead) return fail(h->dead, "handle is unusable after an earlier device error: " + g_err);
+    return DBSIM_OK;
+}
+
+int sync_and_check(dbsim* h) {
+    HIPCHK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    Ctl c;
+    HIPCHK(h, hipMemcpy(&c, h->net.ctl, sizeof c, hipMemcpyDeviceToHost), "hipMemcpy(ctl)");
+    if (c.err) {
+        h->dead = DBSIM_EOVERFLOW;
+        return fail(DBSIM_EOVERFLOW, "device-side capacity exceeded (error bits " + std::to_string(c.err) + ")");
+    }
+    return resolve_timers(h);
+}
+
+void release_device(dbsim* h) {
+    if (h->g_multi) (void)hipGraphExecDestroy(h->g_multi);
+    if (h->g_one) (void)hipGraphExecDestroy(h->g_one);
+    h->g_multi = h->g_one = nullptr;
+    for (auto& ev : h->ev_pending)
+        for (auto x : ev) (void)hipEventDestroy(x);
+    for (auto& ev : h->ev_pool)
+        for (auto x : ev) (void)hipEventDestroy(x);
+    h->ev_pending.clear();
+    h->ev_pool.clear();
+    if (h->dev) {
+        if (h->desc.dev_alloc) h->desc.dev_free(h->desc.alloc_ctx, h->dev, h->plan.total);
+        else (void)hipFree(h->dev);
+        h->dev = nullptr;
+    }
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    h->cap_stream = h->stream = nullptr;
+}
+
+} // namespace
+
+extern "C" {
+
+uint32_t dbsim_abi_version(void) { return DBSIM_ABI_VERSION; }
+
+const char* dbsim_last_error(void) { return g_err.c_str(); }
+
+int dbsim_footprint(const dbsim_desc* desc, uint64_t* hbm_bytes) {
+    if (!desc || !hbm_bytes) return fail(DBSIM_EINVAL, "null argument");
+    try {
+        Plan p;
+        std::string m = make_plan(*desc, p);
+        if (!m.empty()) return fail(DBSIM_EINVAL, m);
+        *hbm_bytes = p.total;
+        return DBSIM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(DBSIM_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(DBSIM_EINVAL, "unexpected exception");
+    }
+}
+
+int dbsim_create(const dbsim_desc* desc, dbsim** out) {
+    if (!desc || !out) return fail(DBSIM_EINVAL, "null argument");
+    *out = nullptr;
+    if (desc->dev_alloc && !desc->dev_free) return fail(DBSIM_EINVAL, "dev_alloc given without dev_free");
+    dbsim* h = nullptr;
+    try {
+        h = new dbsim();
+        h->desc = *desc;
+        h->pops.assign(desc->net.pops, desc->net.pops + desc->net.n_pops);
+        if (desc->net.n_projs) h->projs.assign(desc->net.projs, desc->net.projs + desc->net.n_projs);
+        h->desc.net.pops = h->pops.data();
+        h->desc.net.projs = h->projs.empty() ? nullptr : h->projs.data();
+        if (desc->net.region_xyz_mm) {
+            h->xyz.assign(desc->net.region_xyz_mm, desc->net.region_xyz_mm + 3 * (size_t)desc->net.n_regions);
+            h->desc.net.region_xyz_mm = h->xyz.data();
+        }
+        std::string m = make_plan(h->desc, h->plan);
+        if (!m.empty()) {
+            delete h;
+            return fail(DBSIM_EINVAL, m);
+        }
+        h->device = desc->device;
+        if (h->device < 0 && hipGetDevice(&h->device) != hipSuccess) {
+            delete h;
+            return fail(DBSIM_EDEVICE, "no HIP device");
+        }
+        DeviceGuard dg(h->device);
+        const Plan& p = h->plan;
+        // device memory first, so an allocation failure costs no build time
+        if (desc->dev_alloc) {
+            h->dev = (unsigned char*)desc->dev_alloc(desc->alloc_ctx, p.total);
+            if (!h->dev) {
+                delete h;
+                return fail(DBSIM_EHBM, "device allocator returned NULL for " + std::to_string(p.total) + " bytes");
+            }
+        } else {
+            void* ptr = nullptr;
+            if (hipMalloc(&ptr, p.total) != hipSuccess || !ptr) {
+                (void)hipGetLastError();
+                delete h;
+                return fail(DBSIM_EHBM, "hipMalloc failed for " + std::to_string(p.total) + " bytes");
+            }
+            h->dev = (unsigned char*)ptr;
+        }
+        fill_devnet(h);
+        auto t0 = std::chrono::steady_clock::now();
+        HostTables ht;
+        m = build_tables(h->desc, p, desc->host_threads, ht);
+        if (!m.empty()) {
+            release_device(h);
+            delete h;
+            return fail(DBSIM_EINVAL, m);
+        }
+        h->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        // streams
+        if (desc->hip_stream) {
+            h->stream = (hipStream_t)desc->hip_stream;
+        } else {
+            hipError_t se = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+            if (se != hipSuccess) {
+                release_device(h);
+                delete h;
+                return fail(DBSIM_EDEVICE, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(se));
+            }
+            h->own_stream = true;
+        }
+        {
+            hipError_t se = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+            if (se != hipSuccess) {
+                release_device(h);
+                delete h;
+                return fail(DBSIM_EDEVICE, std::string("hipStreamCreateWithFlags (capture): ") + hipGetErrorString(se));
+            }
+        }
+        // upload
+        auto up = [&](const Plan::Slot& s, const void* src, size_t bytes) -> hipError_t {
+            if (!bytes) return hipSuccess;
+            return hipMemcpy(h->dev + s.off, src, bytes, hipMemcpyHostToDevice);
+        };
+        hipError_t e = prepare_kernels();
+        const size_t N = p.N;
+        std::vector<float> zeros((size_t)p.U * N, 0.0f);
+        std::vector<uint8_t> z8(N, 0), pend(N, 0xFF);
+        if (e == hipSuccess) e = up(p.V, ht.V0.data(), 4 * N);
+        if (e == hipSuccess) e = up(p.J, zeros.data(), 4 * (size_t)p.U * N);
+        if (e == hipSuccess) e = up(p.A, zeros.data(), 4 * (size_t)p.U * N);
+        if (e == hipSuccess) e = up(p.ref, z8.data(), N);
+        if (e == hipSuccess) e = up(p.pend, pend.data(), N);
+        if (e == hipSuccess) e = up(p.pops, ht.pops.data(), sizeof(PopParams) * ht.pops.size());
+        if (e == hipSuccess) e = up(p.ptab, ht.ptab.data(), 4 * ht.ptab.size());
+        if (e == hipSuccess) e = up(p.blk, ht.blk.data(), sizeof(uint2) * ht.blk.size());
+        if (e == hipSuccess) e = up(p.row_ptr, ht.row_ptr.data(), 8 * ht.row_ptr.size());
+        if (e == hipSuccess) e = up(p.seg, ht.seg.data(), 4 * ht.seg.size());
+        if (e == hipSuccess) e = up(p.col, ht.col.data(), 4 * ht.col.size());
+        if (e == hipSuccess) e = up(p.w, ht.w.data(), 4 * ht.w.size());
+        if (e == hipSuccess) e = up(p.src_inh, ht.src_inh.data(), ht.src_inh.size());
+        if (e == hipSuccess) e = up(p.tile_base, ht.tile_base.data(), 8 * ht.tile_base.size());
+        if (e == hipSuccess) e = hipMemset(h->dev + p.tile_fill.off, 0, p.tile_fill.bytes);
+        if (e == hipSuccess) e = hipMemset(h->dev + p.bin_start.off, 0, p.bin_start.bytes);
+        if (e == hipSuccess) e = hipMemset(h->dev + p.bin_cnt.off, 0, p.bin_cnt.bytes);
+        if (e == hipSuccess) e = hipMemset(h->dev + p.blk_sig.off, 0, p.blk_sig.bytes);
+        if (e == hipSuccess) e = hipMemset(h->dev + p.blk_cnt.off, 0, p.blk_cnt.bytes);
+        if (e == hipSuccess) e = up(p.reg_blk_ptr, ht.reg_blk_ptr.data(), 4 * ht.reg_blk_ptr.size());
+        if (e == hipSuccess) e = up(p.reg_blk, ht.reg_blk.data(), 4 * ht.reg_blk.size());
+        if (e == hipSuccess) e = up(p.reg_size, ht.reg_size.data(), 4 * ht.reg_size.size());
+        if (e == hipSuccess) e = hipMemset(h->dev + p.sig.off, 0, p.sig.bytes);
+        if (e == hipSuccess) e = hipMemset(h->dev + p.sig_cnt.off, 0, p.sig_cnt.bytes);
+        if (e == hipSuccess) e = hipMemset(h->dev + p.ctl.off, 0, p.ctl.bytes);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            std::string msg = std::string("upload failed: ") + hipGetErrorString(e);
+            release_device(h);
+            delete h;
+            return fail(DBSIM_EDEVICE, msg);
+        }
+        // persistent grid for the scatter kernel: two 1024-thread blocks per CU
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) h->scatter_grid = 2 * prop.multiProcessorCount;
+        *out = h;
+        return DBSIM_OK;
+    } catch (const std::bad_alloc&) {
+        if (h) {
+            release_device(h);
+            delete h;
+        }
+        return fail(DBSIM_ENOMEM, "host allocation failed while building the network");
+    } catch (...) {
+        if (h) {
+            release_device(h);
+            delete h;
+        }
+        return fail(DBSIM_EINVAL, "unexpected exception in dbsim_create");
+    }
+}
+
+int dbsim_get_info(dbsim* h, dbsim_info* info) {
+    if (!h || !info) return fail(DBSIM_EINVAL, "null argument");
+    const Plan& p = h->plan;
+    info->num_neurons = p.N;
+    info->num_edges = p.E;
+    info->receptors = p.U;
+    info->weights_per_edge = p.KW;
+    info->steps_per_bin = p.S;
+    info->max_delay = p.D;
+    info->n_regions = p.n_regions;
+    info->tile_neurons = 1u << p.tile_bits;
+    info->n_tiles = p.T;
+    info->frac_bits = p.F;
+    return DBSIM_OK;
+}
+
+int dbsim_step(dbsim* h, uint64_t n_steps) {
+    int rc = check_usable(h);
+    if (rc) return rc;
+    DeviceGuard dg(h->device);
+    const uint32_t S = h->plan.S;
+    const bool direct = h->timing || (h->desc.flags & DBSIM_F_NO_GRAPH);
+    while (n_steps > 0) {
+        const uint32_t s0 = (uint32_t)(h->step % S);
+        if (s0 == 0 && n_steps >= S) {
+            uint64_t nb = n_steps / S;
+            if (direct) {
+                for (uint64_t b = 0; b < nb; b++) {
+                    if (h->timing) {
+                        hipError_t e;
+                        auto ev = take_events(h, &e);
+                        HIPCHK(h, e, "hipEventCreate");
+                        HIPCHK(h, hipEventRecord(ev[0], h->stream), "hipEventRecord");
+                        HIPCHK(h, launch_scatter(h->net, h->scatter_grid, h->stream), "scatter launch");
+                        HIPCHK(h, hipEventRecord(ev[1], h->stream), "hipEventRecord");
+                        HIPCHK(h, launch_gather(h->net, h->stream), "gather launch");
+                        HIPCHK(h, hipEventRecord(ev[2], h->stream), "hipEventRecord");
+                        HIPCHK(h, launch_neuron(h->net, 0, (int)S, h->stream), "neuron launch");
+                        HIPCHK(h, hipEventRecord(ev[3], h->stream), "hipEventRecord");
+                        HIPCHK(h, enqueue_bin_end(h, h->stream), "readout launch");
+                        HIPCHK(h, hipEventRecord(ev[4], h->stream), "hipEventRecord");
+                        h->ev_pending.push_back(ev);
+                    } else {
+                        HIPCHK(h, enqueue_full_bin(h, h->stream), "bin launch");
+                    }
+                }
+            } else {
+                if (!h->g_multi) HIPCHK(h, capture_graph(h, kGraphBins, &h->g_multi), "graph capture");
+                if (!h->g_one) HIPCHK(h, capture_graph(h, 1, &h->g_one), "graph capture");
+                for (uint64_t b = 0; b + kGraphBins <= nb; b += kGraphBins)
+                    HIPCHK(h, hipGraphLaunch(h->g_multi, h->stream), "hipGraphLaunch");
+                for (uint64_t b = 0; b < nb % kGraphBins; b++)
+                    HIPCHK(h, hipGraphLaunch(h->g_one, h->stream), "hipGraphLaunch");
+            }
+            h->step += nb * S;
+            n_steps -= nb * S;
+        } else {
+            const uint32_t s1 = (uint32_t)std::min<uint64_t>(S, s0 + n_steps);
+            if (s0 == 0) HIPCHK(h, enqueue_bin_start(h, h->stream), "bin start launch");
+            HIPCHK(h, launch_neuron(h->net, (int)s0, (int)s1, h->stream), "neuron launch");
+            if (s1 == S) HIPCHK(h, enqueue_bin_end(h, h->stream), "bin end launch");
+            h->step += s1 - s0;
+            n_steps -= s1 - s0;
+        }
+    }
+    return DBSIM_OK;
+}
+
+int dbsim_sync(dbsim* h) {
+    int rc = check_usable(h);
+    if (rc) return rc;
+    DeviceGuard dg(h->device);
+    return sync_and_check(h);
+}
+
+int dbsim_read_spikes(dbsim* h, uint64_t step_lo, uint64_t step_hi, uint64_t* steps, uint32_t* ids, uint64_t cap,
+                      uint64_t* n_out) {
+    int rc = check_usable(h);
+    if (rc) return rc;
+    if (!n_out) return fail(DBSIM_EINVAL, "n_out is NULL");
+    DeviceGuard dg(h->device);
+    rc = sync_and_check(h);
+    if (rc) return rc;
+    const Plan& p = h->plan;
+    const uint64_t S = p.S, done_bins = h->step / S;
+    step_hi = std::min(step_hi, done_bins * S);
+    *n_out = 0;
+    if (step_lo >= step_hi) return DBSIM_OK;
+    const uint64_t b_lo = step_lo / S, b_hi = (step_hi + S - 1) / S;
+    if (done_bins - b_lo > p.MB - 1) return fail(DBSIM_ERANGE, "requested bins have left the device history");
+    std::vector<unsigned long long> bstart(p.MB);
+    std::vector<uint32_t> bcnt(p.MB);
+    HIPCHK(h, hipMemcpy(bstart.data(), h->net.bin_start, 8 * (size_t)p.MB, hipMemcpyDeviceToHost), "hipMemcpy");
+    HIPCHK(h, hipMemcpy(bcnt.data(), h->net.bin_cnt, 4 * (size_t)p.MB, hipMemcpyDeviceToHost), "hipMemcpy");
+    const uint64_t head = bstart[done_bins & (p.MB - 1)];
+    const uint64_t first = bstart[b_lo & (p.MB - 1)];
+    if (head - first > p.RC) return fail(DBSIM_ERANGE, "requested spikes have been overwritten in the device ring");
+    std::vector<uint32_t> raw(head - first);
+    uint64_t a = first & (p.RC - 1), left = head - first, o = 0;
+    while (left) {
+        const uint64_t n = std::min(left, p.RC - a);
+        HIPCHK(h, hipMemcpy(raw.data() + o, h->net.rec + a, 4 * n, hipMemcpyDeviceToHost), "hipMemcpy");
+        o += n;
+        left -= n;
+        a = 0;
+    }
+    std::vector<std::pair<uint64_t, uint32_t>> out;
+    for (uint64_t b = b_lo; b < b_hi; b++) {
+        const uint64_t s = bstart[b & (p.MB - 1)] - first;
+        const uint32_t c = bcnt[b & (p.MB - 1)];
+        for (uint32_t x = 0; x < c; x++) {
+            const uint32_t v = raw[s + x];
+            const uint64_t st = b * S + (v & 15u);
+            if (st >= step_lo && st < step_hi) out.emplace_back(st, v >> 4);
+        }
+    }
+    std::sort(out.begin(), out.end());
+    *n_out = out.size();
+    if (out.size() > cap) return fail(DBSIM_ETRUNC, "buffer too small; *n_out holds the count needed");
+    if (!out.empty() && (!steps || !ids)) return fail(DBSIM_EINVAL, "output arrays are NULL");
+    for (size_t x = 0; x < out.size(); x++) {
+        steps[x] = out[x].first;
+        ids[x] = out[x].second;
+    }
+    return DBSIM_OK;
+}
+
+int dbsim_read_region_signal(dbsim* h, uint64_t bin_lo, uint64_t bin_hi, double* sig, uint32_t* counts, uint64_t cap,
+                             uint64_t* n_out) {
+    int rc = check_usable(h);
+    if (rc) return rc;
+    if (!n_out) return fail(DBSIM_EINVAL, "n_out is NULL");
+    const Plan& p = h->plan;
+    if (!p.regions_on) return fail(DBSIM_ESTATE, "region recording was not requested (DBSIM_REC_REGIONS)");
+    DeviceGuard dg(h->device);
+    rc = sync_and_check(h);
+    if (rc) return rc;
+    const uint64_t done_bins = h->step / p.S;
+    bin_hi = std::min(bin_hi, done_bins);
+    *n_out = 0;
+    if (bin_lo >= bin_hi) return DBSIM_OK;
+    if (done_bins - bin_lo > p.MB) return fail(DBSIM_ERANGE, "requested bins have left the device history");
+    const uint64_t R = p.n_regions, need = (bin_hi - bin_lo) * R;
+    *n_out = need;
+    if (need > cap) return fail(DBSIM_ETRUNC, "buffer too small; *n_out holds the count needed");
+    if (!sig) return fail(DBSIM_EINVAL, "sig is NULL");
+    for (uint64_t b = bin_lo; b < bin_hi; b++) {
+        const size_t slot = (size_t)(b & (p.MB - 1)) * R;
+        HIPCHK(h, hipMemcpy(sig + (b - bin_lo) * R, h->net.sig + slot, 8 * R, hipMemcpyDeviceToHost), "hipMemcpy");
+        if (counts)
+            HIPCHK(h, hipMemcpy(counts + (b - bin_lo) * R, h->net.sig_cnt + slot, 4 * R, hipMemcpyDeviceToHost),
+                   "hipMemcpy");
+    }
+    return DBSIM_OK;
+}
+
+int dbsim_read_state(dbsim* h, float* V, float* J, int32_t* ref) {
+    int rc = check_usable(h);
+    if (rc) return rc;
+    DeviceGuard dg(h->device);
+    rc = sync_and_check(h);
+    if (rc) return rc;
+    const size_t N = h->plan.N;
+    if (V) HIPCHK(h, hipMemcpy(V, h->net.V, 4 * N, hipMemcpyDeviceToHost), "hipMemcpy");
+    if (J) HIPCHK(h, hipMemcpy(J, h->net.J, 4 * N * h->plan.U, hipMemcpyDeviceToHost), "hipMemcpy");
+    if (ref) {
+        std::vector<uint8_t> r(N);
+        HIPCHK(h, hipMemcpy(r.data(), h->net.ref, N, hipMemcpyDeviceToHost), "hipMemcpy");
+        for (size_t i = 0; i < N; i++) ref[i] = r[i];
+    }
+    return DBSIM_OK;
+}
+
+int dbsim_write_state(dbsim* h, const float* V, const float* J, const int32_t* ref) {
+    int rc = check_usable(h);
+    if (rc) return rc;
+    if (h->step % h->plan.S) return fail(DBSIM_ESTATE, "state can only be written at a bin boundary");
+    DeviceGuard dg(h->device);
+    rc = sync_and_check(h);
+    if (rc) return rc;
+    const size_t N = h->plan.N;
+    if (ref)
+        for (size_t i = 0; i < N; i++)
+            if (ref[i] < 0 || ref[i] > 255) return fail(DBSIM_EINVAL, "ref values must lie in [0, 255]");
+    if (V) HIPCHK(h, hipMemcpy(h->net.V, V, 4 * N, hipMemcpyHostToDevice), "hipMemcpy");
+    if (J) HIPCHK(h, hipMemcpy(h->net.J, J, 4 * N * h->plan.U, hipMemcpyHostToDevice), "hipMemcpy");
+    if (ref) {
+        std::vector<uint8_t> r(N);
+        for (size_t i = 0; i < N; i++) r[i] = (uint8_t)ref[i];
+        HIPCHK(h, hipMemcpy(h->net.ref, r.data(), N, hipMemcpyHostToDevice), "hipMemcpy");
+    }
+    return DBSIM_OK;
+}
+
+int dbsim_export_csr(dbsim* h, uint64_t* row_ptr, uint32_t* seg, uint32_t* tgt, float* w0, float* w1) {
+    int rc = check_usable(h);
+    if (rc) return rc;
+    DeviceGuard dg(h->device);
+    rc = sync_and_check(h);
+    if (rc) return rc;
+    const Plan& p = h->plan;
+    if (row_ptr) HIPCHK(h, hipMemcpy(row_ptr, h->net.row_ptr, 8 * ((size_t)p.N + 1), hipMemcpyDeviceToHost), "hipMemcpy");
+    if (seg) HIPCHK(h, hipMemcpy(seg, h->net.seg, 4 * (size_t)p.N * (p.D + 1), hipMemcpyDeviceToHost), "hipMemcpy");
+    if (tgt) HIPCHK(h, hipMemcpy(tgt, h->net.col, 4 * p.E, hipMemcpyDeviceToHost), "hipMemcpy");
+    if (w0 || w1) {
+        std::vector<float> w((size_t)p.E * p.KW);
+        HIPCHK(h, hipMemcpy(w.data(), h->net.w, 4 * w.size(), hipMemcpyDeviceToHost), "hipMemcpy");
+        for (uint64_t e = 0; e < p.E; e++) {
+            if (w0) w0[e] = w[e * p.KW];
+            if (w1) w1[e] = p.KW == 2 ? w[e * p.KW + 1] : 0.0f;
+        }
+    }
+    return DBSIM_OK;
+}
+
+int dbsim_set_timing(dbsim* h, int on) {
+    int rc = check_usable(h);
+    if (rc) return rc;
+    h->timing = on != 0;
+    return DBSIM_OK;
+}
+
+int dbsim_get_stats(dbsim* h, dbsim_stats* s) {
+    if (!h || !s) return fail(DBSIM_EINVAL, "null argument");
+    std::memset(s, 0, sizeof *s);
+    DeviceGuard dg(h->device);
+    Ctl c{};
+    if (!h->dead) {
+        int rc = sync_and_check(h);
+        if (rc) return rc;
+        HIPCHK(h, hipMemcpy(&c, h->net.ctl, sizeof c, hipMemcpyDeviceToHost), "hipMemcpy(ctl)");
+    }
+    s->steps = h->step;
+    s->bins = c.bin;
+    s->spikes = c.spikes;
+    s->edge_events = c.edge_events;
+    s->num_neurons = h->plan.N;
+    s->num_edges = h->plan.E;
+    s->hbm_bytes = h->plan.total;
+    s->timed_bins = h->timed_bins;
+    s->ms_scatter = h->ms[0];
+    s->ms_gather = h->ms[1];
+    s->ms_neuron = h->ms[2];
+    s->ms_readout = h->ms[3];
+    s->build_seconds = h->build_seconds;
+    return DBSIM_OK;
+}
+
+int dbsim_destroy(dbsim* h) {
+    if (!h) return DBSIM_OK;
+    {
+        DeviceGuard dg(h->device);
+        if (h->stream) (void)hipStreamSynchronize(h->stream);
+        release_device(h);
+    }
+    delete h;
+    return DBSIM_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,119 @@
+// dbsim_internal.hpp - device data layout and kernel interfaces of libdbsim.
+//
+// Layout in HBM (one handle):
+//   neuron state, structure of arrays: V f32[N], J f32[U][N] (receptor-major),
+//     ref u8[N] (refractory steps left), pend u8[N] (spike substep carried
+//     across a bin split over two step calls), A f32[U][N] (arrival sums of the
+//     current bin, already converted from fixed point);
+//   populations: PopParams[n_pops] and Poisson thresholds u32[n_pops][kMaxPoisson];
+//     neuron blocks never straddle populations, so a block's parameters are
+//     uniform (scalar registers);
+//   connection table by presynaptic neuron (Suppl. Table 5's table is stored
+//     by target; the push-based fan-out of Suppl. Algorithm 2 wants it by
+//     source): row_ptr u64[N+1], seg u32[N][D+1] (delay segment offsets inside
+//     the row), col u32[E] (target), w f32[KW][E] interleaved per edge,
+//     src_inh u8[N];
+//   event arena for the bucketed fan-in: ev_tgt u16[E] (target within its tile
+//     | source class << 15), ev_w f32[KW][E] interleaved; tile t owns the slice
+//     tile_base[t] .. tile_base[t+1] whose length is the tile's total in-degree,
+//     the most events a tile can receive in one bin (an edge delivers at most
+//     once per bin);
+//   spike history: rec u32[RC] ring of (id << 4 | substep), per-bin start u64[MB]
+//     and count u32[MB] (rings indexed by bin & (MB-1));
+//   region readout: per-block partial sums f64/u32, per-region block lists,
+//     and a ring of MB bins of region signal f64[MB][n_regions] and counts;
+//   ctl: bin counter, delivered-event counter, sticky error bits.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dbnet.h"
+
+namespace dbs {
+
+constexpr int kMaxPoisson = 64;       // Poisson thresholds per population
+constexpr int kNeuronBlock = 256;     // neurons per block of the neuron kernel
+constexpr int kScatterThreads = 1024; // threads per block of the scatter kernel
+constexpr int kScatterSegs = 1024;    // (spike, delay) segments per scatter chunk
+constexpr int kGatherThreads = 1024;
+constexpr int kMaxTilesLds = 16384;   // tile histogram must fit in LDS
+constexpr uint32_t kTileLdsBytes = 128u * 1024u; // LDS accumulator per tile
+constexpr uint32_t kErrArena = 1u;    // arena slice overflow (cannot happen by construction)
+
+struct PopParams {
+    float k;      // dt / C
+    float gL, VL, Vth, Vr, Iext, wbg;
+    float g[4], Vu[4], dec[4]; // compact receptor order (AMPA, [NMDA], GABA_A, [GABA_B])
+    int32_t r;                  // refractory steps
+    int32_t cmax;               // Poisson table length
+    uint32_t end;               // one past the population's last neuron id
+    uint32_t region;
+};
+
+struct Ctl {
+    unsigned long long bin;         // bin being processed (advanced by k_close)
+    unsigned long long edge_events; // delivered synaptic events
+    unsigned long long spikes;      // spikes emitted in closed bins
+    unsigned int err;               // sticky error bits
+    unsigned int pad;
+};
+
+struct DevNet {
+    uint32_t N, U, KW, S, D, F;
+    uint32_t tile_bits, T, n_blocks, n_regions;
+    uint64_t RCmask;
+    uint32_t MBmask;
+    uint32_t net_id;
+    uint64_t seed;
+    double qscale;   // 2^F
+    float qinv;      // 2^-F
+    uint32_t regions_on;
+    // state
+    float* V;
+    float* J;
+    uint8_t* ref;
+    uint8_t* pend;
+    float* A;
+    // populations and neuron blocks
+    const PopParams* pops;
+    const uint32_t* ptab;
+    const uint2* blk; // (first neuron, population)
+    // connection table
+    const uint64_t* row_ptr;
+    const uint32_t* seg;
+    const uint32_t* col;
+    const float* w;
+    const uint8_t* src_inh;
+    // event arena
+    uint16_t* ev_tgt;
+    float* ev_w;
+    const uint64_t* tile_base;
+    uint32_t* tile_fill;
+    // spikes
+    uint32_t* rec;
+    unsigned long long* bin_start;
+    uint32_t* bin_cnt;
+    // regions
+    double* blk_sig;
+    uint32_t* blk_cnt;
+    const uint32_t* reg_blk_ptr;
+    const uint32_t* reg_blk;
+    const uint32_t* reg_size;
+    double* sig;
+    uint32_t* sig_cnt;
+    Ctl* ctl;
+};
+
+// kernel launchers (kernels.hip); each enqueues on `st` and returns the launch status
+hipError_t prepare_kernels(); // one-time function attributes (LDS opt-in); call outside graph capture
+hipError_t launch_scatter(const DevNet& n, int grid, hipStream_t st);
+hipError_t launch_gather(const DevNet& n, hipStream_t st);
+hipError_t launch_neuron(const DevNet& n, int s0, int s1, hipStream_t st);
+hipError_t launch_readout(const DevNet& n, hipStream_t st);
+hipError_t launch_close(const DevNet& n, hipStream_t st);
+size_t scatter_lds_bytes(const DevNet& n);
+size_t gather_lds_bytes(const DevNet& n);
+
+} // namespace dbs

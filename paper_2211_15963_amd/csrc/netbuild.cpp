@@ -1,0 +1,330 @@
+// netbuild.cpp - validation, memory plan and host construction of the tables.
+//
+// The connection table is generated per target by the seeded generator
+// (fixed in-degree, sources drawn without replacement) and transposed here
+// into rows by presynaptic neuron, each row split into delay segments and
+// sorted by (delay, target) so the layout is deterministic. Two generator
+// passes (count, then fill) avoid holding a by-target copy of the table.
+#include "netbuild.hpp"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <thread>
+
+namespace dbs {
+
+namespace {
+
+template <class F>
+void parallel_chunks(uint64_t n, uint64_t chunk, unsigned nt, F f) {
+    std::atomic<uint64_t> next{0};
+    auto worker = [&](unsigned tid) {
+        for (;;) {
+            const uint64_t a = next.fetch_add(chunk);
+            if (a >= n) break;
+            f(tid, a, std::min(n, a + chunk));
+        }
+    };
+    std::vector<std::thread> th;
+    for (unsigned t = 1; t < nt; t++) th.emplace_back(worker, t);
+    worker(0);
+    for (auto& x : th) x.join();
+}
+
+uint32_t pow2_at_least32(uint64_t x) {
+    uint64_t c = 1;
+    while (c < x) c <<= 1;
+    return (uint32_t)c;
+}
+
+uint64_t pow2_at_least64(uint64_t x) {
+    uint64_t c = 1;
+    while (c < x) c <<= 1;
+    return c;
+}
+
+// Poisson inversion thresholds T_c = floor(2^32 * CDF(c)) of Poisson(lambda),
+// CDF summed in ascending c from p_0 = exp(-lambda), p_c = p_{c-1} lambda / c;
+// stops at the first c whose upper tail is below 2^-32. Returns the length or -1.
+int poisson_thresholds(double lambda, uint32_t* T, int cap) {
+    double p = std::exp(-lambda), F = p;
+    int c = 0;
+    for (;;) {
+        if (1.0 - F < 0x1p-32) return c;
+        if (c >= cap) return -1;
+        T[c] = (uint32_t)std::floor(F * 0x1p32);
+        c++;
+        p = p * lambda / (double)c;
+        F = F + p;
+    }
+}
+
+uint32_t indeg_of_pop(const dbnet_desc& d, uint32_t p) {
+    uint32_t k = 0;
+    for (uint32_t j = 0; j < d.n_projs; j++)
+        if (d.projs[j].dst_pop < 0 || (uint32_t)d.projs[j].dst_pop == p) k += d.projs[j].indegree;
+    return k;
+}
+
+} // namespace
+
+std::string make_plan(const dbsim_desc& d, Plan& p) {
+    if (d.abi_version != DBSIM_ABI_VERSION) return "dbsim_desc.abi_version does not match the library";
+    char err[512];
+    if (dbnet_validate(&d.net, err, sizeof err) != 0) return err;
+    const dbnet_desc& n = d.net;
+    p.N = (uint32_t)dbnet_num_neurons(&n);
+    p.KW = dbnet_weights_per_edge(&n);
+    p.U = 2 * p.KW;
+    p.S = (uint32_t)std::lround((double)n.bin_ms / (double)n.dt_ms);
+    p.D = dbnet_max_delay(&n);
+    p.F = n.frac_bits;
+    p.n_pops = n.n_pops;
+    p.n_regions = n.n_regions;
+    p.regions_on = (d.record_flags & DBSIM_REC_REGIONS) != 0;
+    // tiles: the LDS accumulator of a tile holds tile_neurons * U int64 sums
+    const uint32_t tile_neurons = kTileLdsBytes / (8u * p.U);
+    p.tile_bits = 0;
+    while ((1u << (p.tile_bits + 1)) <= tile_neurons) p.tile_bits++;
+    p.T = (p.N + (1u << p.tile_bits) - 1) >> p.tile_bits;
+    if (p.T > (uint32_t)kMaxTilesLds) return "network too large for the tile histogram (too many neurons)";
+    const double dt = (double)n.dt_ms;
+    p.E = 0;
+    p.n_blocks = 0;
+    for (uint32_t q = 0; q < n.n_pops; q++) {
+        const dbnet_pop& P = n.pops[q];
+        const long r = std::lround((double)P.T_ref / dt);
+        if (r < (long)p.S - 1)
+            return "T_ref must be at least bin_ms - dt_ms so that a neuron spikes at most once per bin";
+        if (r > 255) return "T_ref / dt_ms must not exceed 255 steps";
+        uint32_t T[kMaxPoisson];
+        if (poisson_thresholds((double)P.bg_rate_hz * dt * 1e-3, T, kMaxPoisson) < 0)
+            return "background rate too high for the Poisson table (rate * dt above about 20)";
+        p.E += (uint64_t)P.size * indeg_of_pop(n, q);
+        p.n_blocks += (P.size + kNeuronBlock - 1) / kNeuronBlock;
+    }
+    const uint32_t rb = d.record_bins ? d.record_bins : 4096u;
+    p.MB = pow2_at_least32(std::max<uint64_t>(rb, (uint64_t)p.D + 1));
+    // spike history: at least the last D bins for the fan-in, plus a default reading window
+    const uint64_t want = d.spike_record_capacity ? d.spike_record_capacity : (1ull << 22);
+    p.RC = pow2_at_least64(std::max<uint64_t>(want, ((uint64_t)p.D + 1) * p.N));
+    // tile slices are indexed with 32-bit fill counters
+    for (uint32_t q = 0; q < n.n_pops; q++)
+        if ((uint64_t)indeg_of_pop(n, q) << p.tile_bits >= (1ull << 32)) return "in-degree too large for a tile slice";
+    // memory plan (one allocation, 256-byte aligned slots)
+    size_t off = 0;
+    auto slot = [&](Plan::Slot& s, size_t bytes) {
+        s.off = off;
+        s.bytes = bytes;
+        off += (bytes + 255) & ~(size_t)255;
+    };
+    const size_t N = p.N, U = p.U, E = p.E;
+    slot(p.V, 4 * N);
+    slot(p.J, 4 * U * N);
+    slot(p.ref, N);
+    slot(p.pend, N);
+    slot(p.A, 4 * U * N);
+    slot(p.pops, sizeof(PopParams) * p.n_pops);
+    slot(p.ptab, 4 * (size_t)kMaxPoisson * p.n_pops);
+    slot(p.blk, sizeof(uint2) * p.n_blocks);
+    slot(p.row_ptr, 8 * (N + 1));
+    slot(p.seg, 4 * N * (p.D + 1));
+    slot(p.col, 4 * E);
+    slot(p.w, 4 * (size_t)p.KW * E);
+    slot(p.src_inh, N);
+    slot(p.ev_tgt, 2 * E);
+    slot(p.ev_w, 4 * (size_t)p.KW * E);
+    slot(p.tile_base, 8 * ((size_t)p.T + 1));
+    slot(p.tile_fill, 4 * (size_t)p.T);
+    slot(p.rec, 4 * p.RC);
+    slot(p.bin_start, 8 * (size_t)p.MB);
+    slot(p.bin_cnt, 4 * (size_t)p.MB);
+    slot(p.blk_sig, 8 * (size_t)p.n_blocks);
+    slot(p.blk_cnt, 4 * (size_t)p.n_blocks);
+    slot(p.reg_blk_ptr, 4 * ((size_t)p.n_regions + 1));
+    slot(p.reg_blk, 4 * (size_t)p.n_blocks);
+    slot(p.reg_size, 4 * (size_t)p.n_regions);
+    slot(p.sig, p.regions_on ? 8 * (size_t)p.MB * p.n_regions : 8);
+    slot(p.sig_cnt, p.regions_on ? 4 * (size_t)p.MB * p.n_regions : 4);
+    slot(p.ctl, sizeof(Ctl));
+    p.total = off;
+    return "";
+}
+
+std::string build_tables(const dbsim_desc& desc, const Plan& p, unsigned threads, HostTables& h) {
+    const dbnet_desc& d = desc.net;
+    const unsigned nt = threads ? threads : std::max(1u, std::thread::hardware_concurrency());
+    const uint32_t N = p.N, D = p.D, KW = p.KW;
+    const double dt = (double)d.dt_ms;
+
+    // populations: derived constants, computed in double and rounded once to float
+    h.pops.assign(d.n_pops, PopParams{});
+    h.ptab.assign((size_t)d.n_pops * kMaxPoisson, 0u);
+    static const uint32_t umap2[2] = {DBNET_AMPA, DBNET_GABA_A};
+    static const uint32_t umap4[4] = {DBNET_AMPA, DBNET_NMDA, DBNET_GABA_A, DBNET_GABA_B};
+    const uint32_t* umap = KW == 1 ? umap2 : umap4;
+    uint64_t off = 0;
+    std::vector<uint32_t> pop_indeg(d.n_pops);
+    for (uint32_t q = 0; q < d.n_pops; q++) {
+        const dbnet_pop& Q = d.pops[q];
+        PopParams& P = h.pops[q];
+        P.k = (float)(dt / (double)Q.C);
+        P.gL = Q.g_L;
+        P.VL = Q.V_L;
+        P.Vth = Q.V_th;
+        P.Vr = Q.V_reset;
+        P.Iext = Q.I_ext;
+        P.wbg = Q.w_bg;
+        for (uint32_t c = 0; c < p.U; c++) {
+            const uint32_t u = umap[c];
+            P.g[c] = Q.g[u];
+            P.Vu[c] = Q.V_rev[u];
+            P.dec[c] = (float)std::exp(-dt / (double)Q.tau[u]);
+        }
+        P.r = (int32_t)std::lround((double)Q.T_ref / dt);
+        P.cmax = poisson_thresholds((double)Q.bg_rate_hz * dt * 1e-3, &h.ptab[(size_t)q * kMaxPoisson], kMaxPoisson);
+        off += Q.size;
+        P.end = (uint32_t)off;
+        P.region = Q.region;
+        pop_indeg[q] = indeg_of_pop(d, q);
+    }
+    // neuron blocks never straddle populations; regions list their blocks
+    h.blk.clear();
+    h.reg_size.assign(p.n_regions, 0u);
+    std::vector<std::vector<uint32_t>> rb(p.n_regions);
+    off = 0;
+    for (uint32_t q = 0; q < d.n_pops; q++) {
+        for (uint64_t s = off; s < off + d.pops[q].size; s += kNeuronBlock) {
+            rb[d.pops[q].region].push_back((uint32_t)h.blk.size());
+            h.blk.push_back(make_uint2((uint32_t)s, q));
+        }
+        h.reg_size[d.pops[q].region] += d.pops[q].size;
+        off += d.pops[q].size;
+    }
+    h.reg_blk_ptr.assign(p.n_regions + 1, 0u);
+    h.reg_blk.clear();
+    for (uint32_t r = 0; r < p.n_regions; r++) {
+        h.reg_blk.insert(h.reg_blk.end(), rb[r].begin(), rb[r].end());
+        h.reg_blk_ptr[r + 1] = (uint32_t)h.reg_blk.size();
+    }
+    // per-neuron source class and in-degree prefix by tile
+    h.src_inh.assign(N, 0);
+    std::vector<uint32_t> pop_of(N);
+    off = 0;
+    for (uint32_t q = 0; q < d.n_pops; q++) {
+        for (uint64_t i = off; i < off + d.pops[q].size; i++) {
+            h.src_inh[i] = d.pops[q].exc ? 0 : 1;
+            pop_of[i] = q;
+        }
+        off += d.pops[q].size;
+    }
+    h.tile_base.assign((size_t)p.T + 1, 0ull);
+    for (uint32_t i = 0; i < N; i++) h.tile_base[(i >> p.tile_bits) + 1] += pop_indeg[pop_of[i]];
+    for (uint32_t t = 0; t < p.T; t++) h.tile_base[t + 1] += h.tile_base[t];
+    if (h.tile_base[p.T] != p.E) return "internal error: edge count mismatch";
+
+    // initial membrane potentials
+    h.V0.resize(N);
+    parallel_chunks(N, 1 << 16, nt, [&](unsigned, uint64_t a, uint64_t b) {
+        for (uint64_t i = a; i < b; i++) h.V0[i] = dbnet_v0(&d, (uint32_t)i);
+    });
+
+    // pass 1: out-degree per (source, delay)
+    const size_t scratch_bytes = dbnet_scratch_bytes(&d);
+    const uint32_t kmax = std::max(1u, dbnet_max_indegree(&d));
+    std::unique_ptr<std::atomic<uint32_t>[]> cnt(new std::atomic<uint32_t>[(size_t)N * D]);
+    for (size_t x = 0; x < (size_t)N * D; x++) cnt[x].store(0, std::memory_order_relaxed);
+    std::atomic<int> gen_fail{0};
+    parallel_chunks(N, 256, nt, [&](unsigned, uint64_t a, uint64_t b) {
+        std::vector<uint32_t> src(kmax);
+        std::vector<uint8_t> dl(kmax);
+        std::vector<unsigned char> scratch(scratch_bytes);
+        for (uint64_t i = a; i < b; i++) {
+            const int64_t k = dbnet_in_edges(&d, (uint32_t)i, src.data(), nullptr, nullptr, dl.data(), scratch.data());
+            if (k < 0) {
+                gen_fail.store(1);
+                return;
+            }
+            for (int64_t e = 0; e < k; e++)
+                cnt[(size_t)src[e] * D + dl[e] - 1].fetch_add(1, std::memory_order_relaxed);
+        }
+    });
+    if (gen_fail.load()) return "network generator failed";
+    h.row_ptr.assign((size_t)N + 1, 0ull);
+    h.seg.assign((size_t)N * (D + 1), 0u);
+    for (uint32_t j = 0; j < N; j++) {
+        uint64_t acc = 0;
+        uint32_t* sg = &h.seg[(size_t)j * (D + 1)];
+        sg[0] = 0;
+        for (uint32_t x = 0; x < D; x++) {
+            acc += cnt[(size_t)j * D + x].load(std::memory_order_relaxed);
+            sg[x + 1] = (uint32_t)acc;
+        }
+        if (acc >= (1ull << 32)) return "out-degree too large";
+        h.row_ptr[j + 1] = h.row_ptr[j] + acc;
+    }
+    if (h.row_ptr[N] != p.E) return "internal error: transposed edge count mismatch";
+    // pass 2: fill rows (cursor per (source, delay))
+    std::unique_ptr<std::atomic<uint64_t>[]> cur(new std::atomic<uint64_t>[(size_t)N * D]);
+    for (uint32_t j = 0; j < N; j++)
+        for (uint32_t x = 0; x < D; x++)
+            cur[(size_t)j * D + x].store(h.row_ptr[j] + h.seg[(size_t)j * (D + 1) + x], std::memory_order_relaxed);
+    cnt.reset();
+    h.col.resize(p.E);
+    h.w.resize((size_t)p.E * KW);
+    const double wlim = std::ldexp(1.0, 52 - (int)p.F);
+    std::atomic<int> wbad{0};
+    parallel_chunks(N, 256, nt, [&](unsigned, uint64_t a, uint64_t b) {
+        std::vector<uint32_t> src(kmax);
+        std::vector<float> w0(kmax), w1(kmax);
+        std::vector<uint8_t> dl(kmax);
+        std::vector<unsigned char> scratch(scratch_bytes);
+        for (uint64_t i = a; i < b; i++) {
+            const int64_t k = dbnet_in_edges(&d, (uint32_t)i, src.data(), w0.data(), w1.data(), dl.data(), scratch.data());
+            if (k < 0) {
+                gen_fail.store(1);
+                return;
+            }
+            for (int64_t e = 0; e < k; e++) {
+                const uint64_t pos = cur[(size_t)src[e] * D + dl[e] - 1].fetch_add(1, std::memory_order_relaxed);
+                h.col[pos] = (uint32_t)i;
+                h.w[pos * KW] = w0[e];
+                if (KW == 2) h.w[pos * KW + 1] = w1[e];
+                if (!(std::fabs((double)w0[e]) < wlim) || !(std::fabs((double)w1[e]) < wlim)) wbad.store(1);
+            }
+        }
+    });
+    if (gen_fail.load()) return "network generator failed";
+    if (wbad.load()) return "a weight is too large for the fixed-point format (|w| * 2^frac_bits must stay below 2^52)";
+    cur.reset();
+    // deterministic layout: sort every delay segment by target
+    parallel_chunks(N, 1024, nt, [&](unsigned, uint64_t a, uint64_t b) {
+        struct Ed {
+            uint32_t t;
+            float w0, w1;
+        };
+        std::vector<Ed> tmp;
+        for (uint64_t j = a; j < b; j++) {
+            const uint32_t* sg = &h.seg[(size_t)j * (D + 1)];
+            for (uint32_t x = 0; x < D; x++) {
+                const uint64_t s0 = h.row_ptr[j] + sg[x], s1 = h.row_ptr[j] + sg[x + 1];
+                if (s1 - s0 < 2) continue;
+                tmp.resize(s1 - s0);
+                for (uint64_t e = s0; e < s1; e++)
+                    tmp[e - s0] = Ed{h.col[e], h.w[e * KW], KW == 2 ? h.w[e * KW + 1] : 0.0f};
+                std::sort(tmp.begin(), tmp.end(), [](const Ed& A, const Ed& B) { return A.t < B.t; });
+                for (uint64_t e = s0; e < s1; e++) {
+                    h.col[e] = tmp[e - s0].t;
+                    h.w[e * KW] = tmp[e - s0].w0;
+                    if (KW == 2) h.w[e * KW + 1] = tmp[e - s0].w1;
+                }
+            }
+        }
+    });
+    return "";
+}
+
+} // namespace dbs

@@ -1,0 +1,54 @@
+// netbuild.hpp - host-side construction of the device tables from a description.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "dbnet.h"
+#include "dbsim.h"
+#include "dbsim_internal.hpp"
+
+namespace dbs {
+
+// Sizes derived from a description without generating the network.
+struct Plan {
+    uint32_t N = 0, U = 0, KW = 0, S = 0, D = 0, F = 0;
+    uint32_t tile_bits = 0, T = 0, n_blocks = 0, n_regions = 0, n_pops = 0;
+    uint32_t MB = 0;   // bins kept in the per-bin rings (power of two)
+    uint64_t RC = 0;   // spike-history ring entries (power of two)
+    uint64_t E = 0;    // edges
+    bool regions_on = false;
+    // byte offsets of every device array inside one allocation
+    struct Slot {
+        size_t off = 0, bytes = 0;
+    };
+    Slot V, J, ref, pend, A, pops, ptab, blk, row_ptr, seg, col, w, src_inh, ev_tgt, ev_w, tile_base, tile_fill,
+        rec, bin_start, bin_cnt, blk_sig, blk_cnt, reg_blk_ptr, reg_blk, reg_size, sig, sig_cnt, ctl;
+    size_t total = 0;
+};
+
+// Validates the description for this simulator and fills the plan.
+// Returns an empty string on success, else the reason.
+std::string make_plan(const dbsim_desc& d, Plan& p);
+
+// Host images of every device table.
+struct HostTables {
+    std::vector<float> V0;
+    std::vector<PopParams> pops;
+    std::vector<uint32_t> ptab;
+    std::vector<uint2> blk;
+    std::vector<uint64_t> row_ptr;
+    std::vector<uint32_t> seg;
+    std::vector<uint32_t> col;
+    std::vector<float> w; // KW floats per edge, interleaved
+    std::vector<uint8_t> src_inh;
+    std::vector<uint64_t> tile_base;
+    std::vector<uint32_t> reg_blk_ptr, reg_blk, reg_size;
+};
+
+// Generates the network (threads: 0 = all cores) and builds every host table.
+// Returns an empty string on success, else the reason.
+std::string build_tables(const dbsim_desc& d, const Plan& p, unsigned threads, HostTables& h);
+
+} // namespace dbs

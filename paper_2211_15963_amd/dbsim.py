@@ -1,0 +1,289 @@
+"""ctypes binding of libdbsim.so (include/dbsim.h): argument marshalling only.
+
+Every step of the simulation runs in the library's HIP kernels. PyTorch is used
+only as the source of device memory (its caching allocator, through the
+library's allocator callbacks) and of the HIP stream the work is queued on.
+If the library is missing, importing the binding fails loudly: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import (CFUNCTYPE, POINTER, Structure, byref, c_char_p, c_double, c_float, c_int, c_int32, c_size_t,
+                    c_uint32, c_uint64, c_void_p)
+from typing import Optional
+
+import numpy as np
+
+from netgen.desc import Desc, NetSpec
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdbsim.so")
+
+ABI_VERSION = 1
+REC_REGIONS = 1
+F_NO_GRAPH = 1
+
+OK, EINVAL, ENOMEM, EHBM, EDEVICE, ETRUNC, EOVERFLOW, ESTATE, ERANGE = 0, -1, -2, -3, -4, -5, -6, -7, -8
+_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHBM: "EHBM", EDEVICE: "EDEVICE", ETRUNC: "ETRUNC",
+          EOVERFLOW: "EOVERFLOW", ESTATE: "ESTATE", ERANGE: "ERANGE"}
+
+ALLOC_FN = CFUNCTYPE(c_void_p, c_void_p, c_size_t)
+FREE_FN = CFUNCTYPE(None, c_void_p, c_void_p, c_size_t)
+
+
+class SimDesc(Structure):
+    _fields_ = [("abi_version", c_uint32), ("record_flags", c_uint32), ("net", Desc),
+                ("spike_record_capacity", c_uint64), ("record_bins", c_uint32), ("device", c_int32),
+                ("hip_stream", c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_ctx", c_void_p),
+                ("host_threads", c_uint32), ("flags", c_uint32)]
+
+
+class SimStats(Structure):
+    _fields_ = [("steps", c_uint64), ("bins", c_uint64), ("spikes", c_uint64), ("edge_events", c_uint64),
+                ("num_neurons", c_uint64), ("num_edges", c_uint64), ("hbm_bytes", c_uint64),
+                ("timed_bins", c_uint64), ("ms_scatter", c_double), ("ms_gather", c_double),
+                ("ms_neuron", c_double), ("ms_readout", c_double), ("build_seconds", c_double)]
+
+
+class SimInfo(Structure):
+    _fields_ = [("num_neurons", c_uint64), ("num_edges", c_uint64), ("receptors", c_uint32),
+                ("weights_per_edge", c_uint32), ("steps_per_bin", c_uint32), ("max_delay", c_uint32),
+                ("n_regions", c_uint32), ("tile_neurons", c_uint32), ("n_tiles", c_uint32), ("frac_bits", c_uint32)]
+
+
+class DbsimError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_LIB = None
+
+EXPORTED = ["dbsim_abi_version", "dbsim_last_error", "dbsim_create", "dbsim_footprint", "dbsim_get_info",
+            "dbsim_step", "dbsim_sync", "dbsim_read_spikes", "dbsim_read_region_signal", "dbsim_read_state",
+            "dbsim_write_state", "dbsim_export_csr", "dbsim_set_timing", "dbsim_get_stats", "dbsim_destroy"]
+
+
+def lib():
+    """Loads libdbsim.so; raises if it has not been built (no fallback)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library missing: {LIB_PATH}; build it with paper_2211_15963_amd/build.py")
+    try:
+        # torch ships its own HIP runtime; loading it first makes libdbsim bind to that same
+        # runtime (one HIP runtime per process), so torch's memory and streams are valid here
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    H = c_void_p
+    L.dbsim_abi_version.restype = c_uint32
+    L.dbsim_last_error.restype = c_char_p
+    L.dbsim_create.argtypes = [POINTER(SimDesc), POINTER(c_void_p)]
+    L.dbsim_footprint.argtypes = [POINTER(SimDesc), POINTER(c_uint64)]
+    L.dbsim_get_info.argtypes = [H, POINTER(SimInfo)]
+    L.dbsim_step.argtypes = [H, c_uint64]
+    L.dbsim_sync.argtypes = [H]
+    L.dbsim_read_spikes.argtypes = [H, c_uint64, c_uint64, POINTER(c_uint64), POINTER(c_uint32), c_uint64,
+                                    POINTER(c_uint64)]
+    L.dbsim_read_region_signal.argtypes = [H, c_uint64, c_uint64, POINTER(c_double), POINTER(c_uint32), c_uint64,
+                                           POINTER(c_uint64)]
+    L.dbsim_read_state.argtypes = [H, POINTER(c_float), POINTER(c_float), POINTER(c_int32)]
+    L.dbsim_write_state.argtypes = [H, POINTER(c_float), POINTER(c_float), POINTER(c_int32)]
+    L.dbsim_export_csr.argtypes = [H, POINTER(c_uint64), POINTER(c_uint32), POINTER(c_uint32), POINTER(c_float),
+                                   POINTER(c_float)]
+    L.dbsim_set_timing.argtypes = [H, c_int]
+    L.dbsim_get_stats.argtypes = [H, POINTER(SimStats)]
+    L.dbsim_destroy.argtypes = [H]
+    for nm in EXPORTED:
+        if nm not in ("dbsim_abi_version", "dbsim_last_error"):
+            getattr(L, nm).restype = c_int
+    if L.dbsim_abi_version() != ABI_VERSION:
+        raise RuntimeError("libdbsim ABI version mismatch")
+    _LIB = L
+    return L
+
+
+def _check(rc: int) -> None:
+    if rc != OK:
+        raise DbsimError(rc, lib().dbsim_last_error().decode())
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(POINTER(ct))
+
+
+class _TorchAllocator:
+    """Device memory from torch's caching allocator, handed to the library as callbacks."""
+
+    def __init__(self, device: int, stream_handle: int):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.stream = stream_handle
+        self.alloc = ALLOC_FN(self._alloc)
+        self.free = FREE_FN(self._free)
+
+    def _alloc(self, ctx, nbytes):
+        try:
+            return self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream or None)
+        except Exception:
+            return None
+
+    def _free(self, ctx, ptr, nbytes):
+        try:
+            self.torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:
+            pass
+
+
+def make_desc(spec: NetSpec, record_regions: bool = True, spike_record_capacity: int = 0, record_bins: int = 0,
+              device: int = -1, stream_handle: Optional[int] = None, allocator: Optional[_TorchAllocator] = None,
+              host_threads: int = 0, no_graph: bool = False):
+    holder = spec.to_c()
+    d = SimDesc()
+    d.abi_version = ABI_VERSION
+    d.record_flags = REC_REGIONS if record_regions else 0
+    d.net = holder.desc
+    d.spike_record_capacity = int(spike_record_capacity)
+    d.record_bins = int(record_bins)
+    d.device = int(device)
+    d.hip_stream = c_void_p(stream_handle) if stream_handle else None
+    if allocator is not None:
+        d.dev_alloc = allocator.alloc
+        d.dev_free = allocator.free
+    d.host_threads = int(host_threads)
+    d.flags = F_NO_GRAPH if no_graph else 0
+    return d, holder
+
+
+def footprint(spec: NetSpec, record_regions: bool = True, **kw) -> int:
+    d, holder = make_desc(spec, record_regions=record_regions, **kw)
+    out = c_uint64(0)
+    _check(lib().dbsim_footprint(byref(d), byref(out)))
+    return int(out.value)
+
+
+class Simulator:
+    """One network instance on one GPU, driven through the C ABI.
+
+    use_torch: take device memory from torch's caching allocator and queue work on
+    torch's current HIP stream (otherwise the library uses hipMalloc and its own stream).
+    """
+
+    def __init__(self, spec: NetSpec, record_regions: bool = True, use_torch: bool = True, device: int = 0,
+                 spike_record_capacity: int = 0, record_bins: int = 0, host_threads: Optional[int] = None,
+                 no_graph: bool = False, stream=None):
+        L = lib()
+        if host_threads is None:
+            # the process's CPU share (OMP_NUM_THREADS) rather than every core of the machine
+            host_threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+        self.spec = spec
+        self._alloc = None
+        stream_handle = None
+        if use_torch:
+            import torch
+            if not torch.cuda.is_available():
+                raise RuntimeError("no GPU visible to torch")
+            torch.cuda.set_device(device)
+            st = stream if stream is not None else torch.cuda.current_stream(device)
+            stream_handle = int(st.cuda_stream) or None
+            self._alloc = _TorchAllocator(device, int(st.cuda_stream))
+        self._desc, self._holder = make_desc(spec, record_regions, spike_record_capacity, record_bins, device,
+                                             stream_handle, self._alloc, host_threads, no_graph)
+        h = c_void_p()
+        _check(L.dbsim_create(byref(self._desc), byref(h)))
+        self._h = h
+        info = SimInfo()
+        _check(L.dbsim_get_info(h, byref(info)))
+        self.info = info
+        self.N = int(info.num_neurons)
+        self.U = int(info.receptors)
+        self.S = int(info.steps_per_bin)
+        self.steps_done = 0
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().dbsim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def step(self, n: int) -> None:
+        _check(lib().dbsim_step(self._h, int(n)))
+        self.steps_done += int(n)
+
+    def sync(self) -> None:
+        _check(lib().dbsim_sync(self._h))
+
+    def set_timing(self, on: bool) -> None:
+        _check(lib().dbsim_set_timing(self._h, 1 if on else 0))
+
+    def spikes(self, step_lo: int = 0, step_hi: Optional[int] = None):
+        """(steps uint64, ids uint32) of completed bins, sorted by (step, id)."""
+        hi = (1 << 63) if step_hi is None else int(step_hi)
+        n = c_uint64(0)
+        rc = lib().dbsim_read_spikes(self._h, int(step_lo), hi, None, None, 0, byref(n))
+        if rc not in (OK, ETRUNC):
+            _check(rc)
+        cap = int(n.value)
+        st = np.zeros(max(cap, 1), np.uint64)
+        ids = np.zeros(max(cap, 1), np.uint32)
+        _check(lib().dbsim_read_spikes(self._h, int(step_lo), hi, _p(st, c_uint64), _p(ids, c_uint32), cap, byref(n)))
+        return st[: n.value], ids[: n.value]
+
+    def region_signal(self, bin_lo: int = 0, bin_hi: Optional[int] = None):
+        R = self.spec.n_regions
+        hi = (self.steps_done // self.S) if bin_hi is None else int(bin_hi)
+        nb = max(0, hi - int(bin_lo))
+        sig = np.zeros(max(nb * R, 1), np.float64)
+        cnt = np.zeros(max(nb * R, 1), np.uint32)
+        n = c_uint64(0)
+        _check(lib().dbsim_read_region_signal(self._h, int(bin_lo), hi, _p(sig, c_double), _p(cnt, c_uint32),
+                                              nb * R, byref(n)))
+        k = int(n.value) // R
+        return sig[: k * R].reshape(k, R), cnt[: k * R].reshape(k, R)
+
+    def state(self):
+        V = np.zeros(self.N, np.float32)
+        J = np.zeros(self.U * self.N, np.float32)
+        ref = np.zeros(self.N, np.int32)
+        _check(lib().dbsim_read_state(self._h, _p(V, c_float), _p(J, c_float), _p(ref, c_int32)))
+        return V, J.reshape(self.U, self.N), ref
+
+    def write_state(self, V, J, ref) -> None:
+        V = np.ascontiguousarray(V, np.float32)
+        J = np.ascontiguousarray(J, np.float32).reshape(-1)
+        ref = np.ascontiguousarray(ref, np.int32)
+        _check(lib().dbsim_write_state(self._h, _p(V, c_float), _p(J, c_float), _p(ref, c_int32)))
+
+    def export_csr(self):
+        E = int(self.info.num_edges)
+        D = int(self.info.max_delay)
+        row_ptr = np.zeros(self.N + 1, np.uint64)
+        seg = np.zeros(self.N * (D + 1), np.uint32)
+        tgt = np.zeros(max(E, 1), np.uint32)
+        w0 = np.zeros(max(E, 1), np.float32)
+        w1 = np.zeros(max(E, 1), np.float32)
+        _check(lib().dbsim_export_csr(self._h, _p(row_ptr, c_uint64), _p(seg, c_uint32), _p(tgt, c_uint32),
+                                      _p(w0, c_float), _p(w1, c_float)))
+        return row_ptr, seg.reshape(self.N, D + 1), tgt[:E], w0[:E], w1[:E]
+
+    def stats(self) -> dict:
+        s = SimStats()
+        _check(lib().dbsim_get_stats(self._h, byref(s)))
+        return {f: getattr(s, f) for f, _ in SimStats._fields_}

@@ -1,0 +1,182 @@
+"""GPU path (through the C ABI) vs the FP32 CPU oracle, element by element.
+
+Bar: spike rasters, V, J and refractory counters bit-identical; delivered-event
+counts identical; region signals equal within the rounding bound of two
+different summation orders of the same double terms.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from netgen import configs
+from oracle import Oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def Sim():
+    from paper_2211_15963_amd import Simulator
+    return Simulator
+
+
+def _compare(sim, orc, spec, check_regions=True):
+    st_g, id_g = sim.spikes()
+    st_o, id_o = orc.spikes()
+    assert len(st_o) > 0, "the case produced no spikes"
+    assert len(st_g) == len(st_o), f"spike counts differ: gpu {len(st_g)} oracle {len(st_o)}"
+    assert np.array_equal(st_g, st_o) and np.array_equal(id_g, id_o), "rasters differ"
+    Vg, Jg, rg = sim.state()
+    Vo, Jo, ro = orc.state()
+    assert np.array_equal(Vg.astype(np.float64), Vo), "V differs"
+    assert np.array_equal(Jg.astype(np.float64), Jo), "J differs"
+    assert np.array_equal(rg, ro), "refractory counters differ"
+    assert sim.stats()["edge_events"] == orc.edge_events
+    if check_regions:
+        sg, cg = sim.region_signal()
+        so, co = orc.region_signal()
+        assert sg.shape == so.shape
+        assert np.array_equal(cg, co), "region spike counts differ"
+        # the same double terms summed in two orders differ by at most (n-1) eps sum|terms|;
+        # divided by n and with |current| < 1e5 pA per neuron: n eps 1e5 per region
+        n_reg = np.bincount(spec.region_of_neuron(), minlength=spec.n_regions)
+        bound = n_reg[None, :] * np.finfo(np.float64).eps * 1e5
+        assert np.all(np.abs(sg - so) <= bound)
+
+
+def test_tiny_one_second_bit_exact(Sim):
+    spec = configs.tiny()
+    _say("tiny 1000 neurons, 10000 steps (1 s)")
+    sim = Sim(spec)
+    sim.step(10000)
+    orc = Oracle(spec, 32)
+    orc.step(10000)
+    _compare(sim, orc, spec)
+    sim.close()
+
+
+def test_tiny_partial_bins_and_splits(Sim):
+    spec = configs.tiny(seed=3)
+    chunks = [3, 7, 10, 15, 1, 4, 5, 955, 9, 1, 990]
+    _say(f"tiny seed 3, step chunks {chunks}")
+    sim = Sim(spec)
+    for c in chunks:
+        sim.step(c)
+    orc = Oracle(spec, 32)
+    orc.step(sum(chunks))
+    _compare(sim, orc, spec)
+    sim.close()
+
+
+def test_share_scaled_bit_exact(Sim):
+    spec = configs.share(n=20000, indegree=556, seed=1)
+    _say("share 20000 neurons, in-degree 556, delays 1..10, 400 steps")
+    sim = Sim(spec)
+    sim.step(400)
+    orc = Oracle(spec, 32)
+    orc.step(400)
+    _compare(sim, orc, spec)
+    sim.close()
+
+
+def test_multi_region_scaled_bit_exact(Sim):
+    spec = configs.multi_region(n_regions=20, per_region=1000, seed=2)
+    _say("multi-region 20 x 1000, in-degree 400 + 100 long-range, delays 1..20, 500 steps")
+    sim = Sim(spec)
+    sim.step(500)
+    orc = Oracle(spec, 32)
+    orc.step(500)
+    _compare(sim, orc, spec)
+    sim.close()
+
+
+def test_launch_modes_agree(Sim):
+    spec = configs.share(n=6000, indegree=200, seed=4, bg_rate_hz=6500.0)
+    _say("share 6000 / k200: graph replay vs direct launches vs timed launches")
+    a = Sim(spec)
+    a.step(300)
+    b = Sim(spec, no_graph=True)
+    b.step(300)
+    c = Sim(spec)
+    c.set_timing(True)
+    c.step(300)
+    ra, rb, rc = a.spikes(), b.spikes(), c.spikes()
+    assert len(ra[0]) > 0
+    for x, y in ((ra, rb), (ra, rc)):
+        assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
+    st = c.stats()
+    assert st["timed_bins"] == 30 and st["ms_scatter"] > 0 and st["ms_neuron"] > 0
+    for s in (a, b, c):
+        s.close()
+
+
+def test_exported_table_is_the_generated_network(Sim):
+    from netgen.desc import generate
+    spec = configs.share(n=3000, indegree=50, seed=5)
+    _say("export of the presynaptic table, 3000 neurons")
+    sim = Sim(spec)
+    row_ptr, seg, tgt, w0, w1 = sim.export_csr()
+    net = generate(spec)
+    D = spec.max_delay
+    got = []
+    for j in range(spec.num_neurons):
+        a = int(row_ptr[j])
+        for d in range(1, D + 1):
+            for e in range(a + int(seg[j, d - 1]), a + int(seg[j, d])):
+                got.append((int(tgt[e]), j, d, float(w0[e]), float(w1[e])))
+        # rows sorted by (delay, target)
+        t = tgt[a:int(row_ptr[j + 1])].astype(np.int64)
+        for d in range(1, D + 1):
+            blk = t[int(seg[j, d - 1]):int(seg[j, d])]
+            assert np.all(np.diff(blk) > 0)
+    want = []
+    for i in range(spec.num_neurons):
+        for e in range(int(net["ptr"][i]), int(net["ptr"][i + 1])):
+            want.append((i, int(net["src"][e]), int(net["delay"][e]), float(net["w0"][e]), float(net["w1"][e])))
+    assert sorted(got) == sorted(want)
+    sim.close()
+
+
+def test_state_roundtrip_is_invisible(Sim):
+    spec = configs.tiny(seed=6)
+    _say("tiny seed 6: read/write state at a bin boundary")
+    a = Sim(spec)
+    a.step(2000)
+    b = Sim(spec)
+    b.step(1000)
+    V, J, ref = b.state()
+    b.write_state(V, J, ref)
+    b.step(1000)
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
+    a.close()
+    b.close()
+
+
+def test_spike_read_windows(Sim):
+    spec = configs.tiny(seed=7)
+    _say("tiny seed 7: windowed spike reads and truncation")
+    sim = Sim(spec)
+    sim.step(1234)
+    st, ids = sim.spikes()
+    assert st.max() < 1230  # only completed bins are visible
+    st2, ids2 = sim.spikes(500, 800)
+    sel = (st >= 500) & (st < 800)
+    assert np.array_equal(st2, st[sel]) and np.array_equal(ids2, ids[sel])
+    sim.close()
+
+
+def test_one_hip_runtime_in_process(Sim):
+    import torch
+    _say("HIP runtime libraries mapped in this process")
+    torch.zeros(1, device="cuda")
+    maps = sorted(set(l.split()[-1] for l in open("/proc/self/maps") if "libamdhip64" in l))
+    assert len(maps) == 1, maps

@@ -503,3 +503,23 @@ def test_oracle_regression_fixture():
     stored = json.load(open(os.path.join(here, "oracle_regression.json")))
     for name, (f, steps, prec) in mg.CASES.items():
         assert mg.digest(f(), steps, prec) == stored[name], name
+
+
+def test_point_evaluations_agree_with_full_run():
+    """The sampled-check helpers (arrivals of chosen targets from a spike list, one step
+    of one neuron) reproduce the full oracle run exactly."""
+    spec = configs.share(n=2000, indegree=120, d_max=6, seed=11, bg_rate_hz=7000.0)
+    full = Oracle(spec, 32)
+    K = 25
+    full.step(K * spec.steps_per_bin)
+    st, ids = full.spikes()
+    V, J, ref = full.state()
+    pt = Oracle(spec, 32, params_only=True)
+    targets = np.arange(0, 2000, 37)
+    A, ev = pt.point_arrivals(K, st, ids, targets)
+    assert ev > 0
+    full.step(1)
+    V1, J1, ref1 = full.state()
+    for t, i in enumerate(targets):
+        v, j, r, _ = pt.point_step(int(i), K * spec.steps_per_bin, A[t], V[i], J[:, i], int(ref[i]))
+        assert v == V1[i] and np.array_equal(j.astype(np.float64), J1[:, i]) and r == ref1[i]
