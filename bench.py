@@ -102,6 +102,18 @@ def cpu_baseline(args, budget_s: float):
             "rtf": wall / (bins * 1e-3)}
 
 
+def calibrate_copy(args):
+    """A plain device copy of known size, so that profiler byte counters can be scaled."""
+    import torch
+    n = 1 << 29  # 2 GiB of float32 per buffer
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+
+
 def tune(args):
     """Bisection of the background rate for target population rates (writes nothing)."""
     from netgen import configs
@@ -142,6 +154,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", action="store_true")
     ap.add_argument("--tune-iters", type=int, default=9)
+    ap.add_argument("--calibrate-copy", action="store_true", help="run only a 2 GiB device copy (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU's share of the network; runs on more than one GPU are not supported "
@@ -149,6 +162,9 @@ def main():
         sys.exit(2)
     if args.tune:
         tune(args)
+        return
+    if args.calibrate_copy:
+        calibrate_copy(args)
         return
     g = run_gpu(args)
     spec = g["spec"]

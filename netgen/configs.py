@@ -47,10 +47,10 @@ SHARE_G = (0.20, 0.0096, 0.40, 0.0115)
 SHARE_W_BG = 4.0
 # Poisson background rate (Hz per neuron) per target regime, found by bisection on the
 # population rate of the seeded 'share' recipe (see the benchmark's tuning mode).
-SHARE_BG_HZ = {7: 5200.0, 15: 5600.0, 30: 6200.0}
+SHARE_BG_HZ = {7: 6590.0, 15: 8230.0, 30: 11277.0}
 
 REGION_G = (0.22, 0.0106, 0.44, 0.0126)
-REGION_BG_HZ = 5600.0
+REGION_BG_HZ = 8230.0
 
 
 def tiny(seed: int = 0, dt_ms: float = 0.1, n_exc: int = 800, n_inh: int = 200, indegree: int = 100,

@@ -99,6 +99,8 @@ void fill_devnet(dbsim* h) {
     n.D = p.D;
     n.F = p.F;
     n.tile_bits = p.tile_bits;
+    n.TG = p.TG;
+    n.round_events = p.round_events;
     n.T = p.T;
     n.n_blocks = p.n_blocks;
     n.n_regions = p.n_regions;
@@ -122,10 +124,13 @@ void fill_devnet(dbsim* h) {
     n.col = at<const uint32_t>(b, p.col);
     n.w = at<const float>(b, p.w);
     n.src_inh = at<const uint8_t>(b, p.src_inh);
-    n.ev_tgt = at<uint16_t>(b, p.ev_tgt);
-    n.ev_w = at<float>(b, p.ev_w);
+    n.ev = at<uint32_t>(b, p.ev);
     n.tile_base = at<const uint64_t>(b, p.tile_base);
     n.tile_fill = at<uint32_t>(b, p.tile_fill);
+    n.sq = at<uint32_t>(b, p.sq);
+    n.stage = at<uint32_t>(b, p.stage);
+    n.grp_cnt = at<uint32_t>(b, p.grp_cnt);
+    n.n_grp = p.n_grp;
     n.rec = at<uint32_t>(b, p.rec);
     n.bin_start = at<unsigned long long>(b, p.bin_start);
     n.bin_cnt = at<uint32_t>(b, p.bin_cnt);
@@ -134,6 +139,11 @@ void fill_devnet(dbsim* h) {
     n.reg_blk_ptr = at<const uint32_t>(b, p.reg_blk_ptr);
     n.reg_blk = at<const uint32_t>(b, p.reg_blk);
     n.reg_size = at<const uint32_t>(b, p.reg_size);
+    n.l1_ptr = at<const uint32_t>(b, p.l1_ptr);
+    n.l1_region = at<const uint32_t>(b, p.l1_region);
+    n.l1_sig = at<double>(b, p.l1_sig);
+    n.l1_cnt = at<uint32_t>(b, p.l1_cnt);
+    n.n_l1 = p.n_l1;
     n.sig = at<double>(b, p.sig);
     n.sig_cnt = at<uint32_t>(b, p.sig_cnt);
     n.ctl = at<Ctl>(b, p.ctl);
@@ -146,11 +156,9 @@ hipError_t enqueue_bin_start(dbsim* h, hipStream_t st) {
 }
 
 hipError_t enqueue_bin_end(dbsim* h, hipStream_t st) {
-    if (h->plan.regions_on) {
-        hipError_t e = launch_readout(h->net, st);
-        if (e != hipSuccess) return e;
-    }
-    return launch_close(h->net, st);
+    hipError_t e = launch_compact(h->net, st);
+    if (e != hipSuccess) return e;
+    return launch_readout_close(h->net, st);
 }
 
 hipError_t enqueue_full_bin(dbsim* h, hipStream_t st) {
@@ -355,12 +363,14 @@ int dbsim_create(const dbsim_desc* desc, dbsim** out) {
         if (e == hipSuccess) e = up(p.ptab, ht.ptab.data(), 4 * ht.ptab.size());
         if (e == hipSuccess) e = up(p.blk, ht.blk.data(), sizeof(uint2) * ht.blk.size());
         if (e == hipSuccess) e = up(p.row_ptr, ht.row_ptr.data(), 8 * ht.row_ptr.size());
-        if (e == hipSuccess) e = up(p.seg, ht.seg.data(), 4 * ht.seg.size());
+        if (e == hipSuccess) e = up(p.seg, ht.seg_dg.data(), 4 * ht.seg_dg.size());
         if (e == hipSuccess) e = up(p.col, ht.col.data(), 4 * ht.col.size());
         if (e == hipSuccess) e = up(p.w, ht.w.data(), 4 * ht.w.size());
         if (e == hipSuccess) e = up(p.src_inh, ht.src_inh.data(), ht.src_inh.size());
         if (e == hipSuccess) e = up(p.tile_base, ht.tile_base.data(), 8 * ht.tile_base.size());
         if (e == hipSuccess) e = hipMemset(h->dev + p.tile_fill.off, 0, p.tile_fill.bytes);
+        if (e == hipSuccess) e = hipMemset(h->dev + p.sq.off, 0, p.sq.bytes);
+        if (e == hipSuccess) e = hipMemset(h->dev + p.grp_cnt.off, 0, p.grp_cnt.bytes);
         if (e == hipSuccess) e = hipMemset(h->dev + p.bin_start.off, 0, p.bin_start.bytes);
         if (e == hipSuccess) e = hipMemset(h->dev + p.bin_cnt.off, 0, p.bin_cnt.bytes);
         if (e == hipSuccess) e = hipMemset(h->dev + p.blk_sig.off, 0, p.blk_sig.bytes);
@@ -368,6 +378,8 @@ int dbsim_create(const dbsim_desc* desc, dbsim** out) {
         if (e == hipSuccess) e = up(p.reg_blk_ptr, ht.reg_blk_ptr.data(), 4 * ht.reg_blk_ptr.size());
         if (e == hipSuccess) e = up(p.reg_blk, ht.reg_blk.data(), 4 * ht.reg_blk.size());
         if (e == hipSuccess) e = up(p.reg_size, ht.reg_size.data(), 4 * ht.reg_size.size());
+        if (e == hipSuccess) e = up(p.l1_ptr, ht.l1_ptr.data(), 4 * ht.l1_ptr.size());
+        if (e == hipSuccess) e = up(p.l1_region, ht.l1_region.data(), 4 * ht.l1_region.size());
         if (e == hipSuccess) e = hipMemset(h->dev + p.sig.off, 0, p.sig.bytes);
         if (e == hipSuccess) e = hipMemset(h->dev + p.sig_cnt.off, 0, p.sig_cnt.bytes);
         if (e == hipSuccess) e = hipMemset(h->dev + p.ctl.off, 0, p.ctl.bytes);
@@ -380,7 +392,8 @@ int dbsim_create(const dbsim_desc* desc, dbsim** out) {
         }
         // persistent grid for the scatter kernel: two 1024-thread blocks per CU
         hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) h->scatter_grid = 2 * prop.multiProcessorCount;
+        if (hipGetDeviceProperties(&prop, h->device) == hipSuccess)
+            h->scatter_grid = (int)p.scatter_wgs_per_cu * prop.multiProcessorCount;
         *out = h;
         return DBSIM_OK;
     } catch (const std::bad_alloc&) {
@@ -600,7 +613,13 @@ int dbsim_export_csr(dbsim* h, uint64_t* row_ptr, uint32_t* seg, uint32_t* tgt, 
     if (rc) return rc;
     const Plan& p = h->plan;
     if (row_ptr) HIPCHK(h, hipMemcpy(row_ptr, h->net.row_ptr, 8 * ((size_t)p.N + 1), hipMemcpyDeviceToHost), "hipMemcpy");
-    if (seg) HIPCHK(h, hipMemcpy(seg, h->net.seg, 4 * (size_t)p.N * (p.D + 1), hipMemcpyDeviceToHost), "hipMemcpy");
+    if (seg) {
+        const size_t DG1 = (size_t)p.D * kTileGroups + 1;
+        std::vector<uint32_t> dg((size_t)p.N * DG1);
+        HIPCHK(h, hipMemcpy(dg.data(), h->net.seg, 4 * dg.size(), hipMemcpyDeviceToHost), "hipMemcpy");
+        for (size_t j = 0; j < p.N; j++)
+            for (size_t d = 0; d <= p.D; d++) seg[j * (p.D + 1) + d] = dg[j * DG1 + d * kTileGroups];
+    }
     if (tgt) HIPCHK(h, hipMemcpy(tgt, h->net.col, 4 * p.E, hipMemcpyDeviceToHost), "hipMemcpy");
     if (w0 || w1) {
         std::vector<float> w((size_t)p.E * p.KW);

@@ -10,11 +10,12 @@
 //     uniform (scalar registers);
 //   connection table by presynaptic neuron (Suppl. Table 5's table is stored
 //     by target; the push-based fan-out of Suppl. Algorithm 2 wants it by
-//     source): row_ptr u64[N+1], seg u32[N][D+1] (delay segment offsets inside
-//     the row), col u32[E] (target), w f32[KW][E] interleaved per edge,
-//     src_inh u8[N];
-//   event arena for the bucketed fan-in: ev_tgt u16[E] (target within its tile
-//     | source class << 15), ev_w f32[KW][E] interleaved; tile t owns the slice
+//     source): row_ptr u64[N+1], seg u32[N][D*G+1] (offsets of the (delay,
+//     tile group) sub-segments inside the row; rows are sorted by delay, then
+//     target, so groups of consecutive tiles are contiguous), col u32[E]
+//     (target), w f32[KW][E] interleaved per edge, src_inh u8[N];
+//   event arena for the bucketed fan-in: records of 1 + KW words (target within
+//     its tile | source class << 31, then the weights); tile t owns the slice
 //     tile_base[t] .. tile_base[t+1] whose length is the tile's total in-degree,
 //     the most events a tile can receive in one bin (an edge delivers at most
 //     once per bin);
@@ -41,6 +42,9 @@ constexpr int kGatherThreads = 1024;
 constexpr int kMaxTilesLds = 16384;   // tile histogram must fit in LDS
 constexpr uint32_t kTileLdsBytes = 128u * 1024u; // LDS accumulator per tile
 constexpr uint32_t kErrArena = 1u;    // arena slice overflow (cannot happen by construction)
+constexpr uint32_t kErrLayout = 2u;   // a table entry outside its tile group (cannot happen by construction)
+constexpr uint32_t kTileGroups = 8;   // target tile groups (one per XCC of an MI355X)
+constexpr uint32_t kMaxLdsBytes = 160u * 1024u;
 
 struct PopParams {
     float k;      // dt / C
@@ -53,16 +57,18 @@ struct PopParams {
 };
 
 struct Ctl {
-    unsigned long long bin;         // bin being processed (advanced by k_close)
+    unsigned long long bin;         // bin being processed (advanced at the bin close)
     unsigned long long edge_events; // delivered synaptic events
     unsigned long long spikes;      // spikes emitted in closed bins
     unsigned int err;               // sticky error bits
-    unsigned int pad;
+    unsigned int done;              // readout workgroups finished in the current bin
 };
 
 struct DevNet {
     uint32_t N, U, KW, S, D, F;
     uint32_t tile_bits, T, n_blocks, n_regions;
+    uint32_t TG;           // tiles per tile group
+    uint32_t round_events; // events staged in LDS per scatter round
     uint64_t RCmask;
     uint32_t MBmask;
     uint32_t net_id;
@@ -86,12 +92,16 @@ struct DevNet {
     const uint32_t* col;
     const float* w;
     const uint8_t* src_inh;
-    // event arena
-    uint16_t* ev_tgt;
-    float* ev_w;
+    // event arena: records of (1 + KW) words: target within tile | source class << 31, weights
+    uint32_t* ev;
     const uint64_t* tile_base;
     uint32_t* tile_fill;
-    // spikes
+    uint32_t* sq; // per-group chunk queues of the scatter (reset by the gather)
+    // spikes: per-block staging (256 slots per neuron block), per-group counts (two bin
+    // parities x groups of 256 blocks), then the dense history ring
+    uint32_t* stage;
+    uint32_t* grp_cnt;
+    uint32_t n_grp;
     uint32_t* rec;
     unsigned long long* bin_start;
     uint32_t* bin_cnt;
@@ -101,6 +111,11 @@ struct DevNet {
     const uint32_t* reg_blk_ptr;
     const uint32_t* reg_blk;
     const uint32_t* reg_size;
+    const uint32_t* l1_ptr;    // first level-1 readout group of each region [n_regions + 1]
+    const uint32_t* l1_region; // region of each level-1 group [n_l1]
+    double* l1_sig;
+    uint32_t* l1_cnt;
+    uint32_t n_l1;
     double* sig;
     uint32_t* sig_cnt;
     Ctl* ctl;
@@ -111,9 +126,10 @@ hipError_t prepare_kernels(); // one-time function attributes (LDS opt-in); call
 hipError_t launch_scatter(const DevNet& n, int grid, hipStream_t st);
 hipError_t launch_gather(const DevNet& n, hipStream_t st);
 hipError_t launch_neuron(const DevNet& n, int s0, int s1, hipStream_t st);
-hipError_t launch_readout(const DevNet& n, hipStream_t st);
-hipError_t launch_close(const DevNet& n, hipStream_t st);
+hipError_t launch_compact(const DevNet& n, hipStream_t st);
+hipError_t launch_readout_close(const DevNet& n, hipStream_t st);
 size_t scatter_lds_bytes(const DevNet& n);
+size_t scatter_fixed_lds(uint32_t TG);
 size_t gather_lds_bytes(const DevNet& n);
 
 } // namespace dbs

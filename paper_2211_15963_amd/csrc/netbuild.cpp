@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <thread>
@@ -91,6 +92,16 @@ std::string make_plan(const dbsim_desc& d, Plan& p) {
     while ((1u << (p.tile_bits + 1)) <= tile_neurons) p.tile_bits++;
     p.T = (p.N + (1u << p.tile_bits) - 1) >> p.tile_bits;
     if (p.T > (uint32_t)kMaxTilesLds) return "network too large for the tile histogram (too many neurons)";
+    p.TG = (p.T + kTileGroups - 1) / kTileGroups;
+    // scatter: workgroups per CU (LDS budget each) and the events staged per LDS round
+    {
+        const char* ev = std::getenv("DBSIM_SCATTER_WGS");
+        p.scatter_wgs_per_cu = ev ? (uint32_t)std::max(1, std::min(2, std::atoi(ev))) : 1u;
+        const size_t budget = kMaxLdsBytes / p.scatter_wgs_per_cu - 1024;
+        const size_t fixed = scatter_fixed_lds(p.TG);
+        if (fixed + 14 * 1024 > budget) return "too many tiles per group for the scatter's LDS budget";
+        p.round_events = (uint32_t)std::min<size_t>(16384, ((budget - fixed) / 14) & ~(size_t)1023);
+    }
     const double dt = (double)n.dt_ms;
     p.E = 0;
     p.n_blocks = 0;
@@ -105,6 +116,12 @@ std::string make_plan(const dbsim_desc& d, Plan& p) {
             return "background rate too high for the Poisson table (rate * dt above about 20)";
         p.E += (uint64_t)P.size * indeg_of_pop(n, q);
         p.n_blocks += (P.size + kNeuronBlock - 1) / kNeuronBlock;
+    }
+    {
+        std::vector<uint64_t> rblocks(p.n_regions, 0);
+        for (uint32_t q = 0; q < n.n_pops; q++) rblocks[n.pops[q].region] += (n.pops[q].size + kNeuronBlock - 1) / kNeuronBlock;
+        p.n_l1 = 0;
+        for (uint32_t r = 0; r < p.n_regions; r++) p.n_l1 += (uint32_t)std::max<uint64_t>(1, (rblocks[r] + 255) / 256);
     }
     const uint32_t rb = d.record_bins ? d.record_bins : 4096u;
     p.MB = pow2_at_least32(std::max<uint64_t>(rb, (uint64_t)p.D + 1));
@@ -131,14 +148,17 @@ std::string make_plan(const dbsim_desc& d, Plan& p) {
     slot(p.ptab, 4 * (size_t)kMaxPoisson * p.n_pops);
     slot(p.blk, sizeof(uint2) * p.n_blocks);
     slot(p.row_ptr, 8 * (N + 1));
-    slot(p.seg, 4 * N * (p.D + 1));
+    slot(p.seg, 4 * N * ((size_t)p.D * kTileGroups + 1));
     slot(p.col, 4 * E);
     slot(p.w, 4 * (size_t)p.KW * E);
     slot(p.src_inh, N);
-    slot(p.ev_tgt, 2 * E);
-    slot(p.ev_w, 4 * (size_t)p.KW * E);
+    slot(p.ev, 4 * (size_t)(1 + p.KW) * E);
     slot(p.tile_base, 8 * ((size_t)p.T + 1));
     slot(p.tile_fill, 4 * (size_t)p.T);
+    slot(p.sq, 4 * (size_t)kTileGroups);
+    p.n_grp = (p.n_blocks + 255) / 256;
+    slot(p.stage, 4 * (size_t)p.n_blocks * kNeuronBlock);
+    slot(p.grp_cnt, 4 * 2 * (size_t)p.n_grp);
     slot(p.rec, 4 * p.RC);
     slot(p.bin_start, 8 * (size_t)p.MB);
     slot(p.bin_cnt, 4 * (size_t)p.MB);
@@ -147,6 +167,10 @@ std::string make_plan(const dbsim_desc& d, Plan& p) {
     slot(p.reg_blk_ptr, 4 * ((size_t)p.n_regions + 1));
     slot(p.reg_blk, 4 * (size_t)p.n_blocks);
     slot(p.reg_size, 4 * (size_t)p.n_regions);
+    slot(p.l1_ptr, 4 * ((size_t)p.n_regions + 1));
+    slot(p.l1_region, 4 * (size_t)p.n_l1);
+    slot(p.l1_sig, 8 * (size_t)p.n_l1);
+    slot(p.l1_cnt, 4 * (size_t)p.n_l1);
     slot(p.sig, p.regions_on ? 8 * (size_t)p.MB * p.n_regions : 8);
     slot(p.sig_cnt, p.regions_on ? 4 * (size_t)p.MB * p.n_regions : 4);
     slot(p.ctl, sizeof(Ctl));
@@ -206,10 +230,16 @@ std::string build_tables(const dbsim_desc& desc, const Plan& p, unsigned threads
     }
     h.reg_blk_ptr.assign(p.n_regions + 1, 0u);
     h.reg_blk.clear();
+    h.l1_ptr.assign(p.n_regions + 1, 0u);
+    h.l1_region.clear();
     for (uint32_t r = 0; r < p.n_regions; r++) {
         h.reg_blk.insert(h.reg_blk.end(), rb[r].begin(), rb[r].end());
         h.reg_blk_ptr[r + 1] = (uint32_t)h.reg_blk.size();
+        const uint32_t g = std::max<uint32_t>(1u, ((uint32_t)rb[r].size() + 255u) / 256u);
+        for (uint32_t x = 0; x < g; x++) h.l1_region.push_back(r);
+        h.l1_ptr[r + 1] = (uint32_t)h.l1_region.size();
     }
+    if (h.l1_region.size() != p.n_l1) return "internal error: readout group count mismatch";
     // per-neuron source class and in-degree prefix by tile
     h.src_inh.assign(N, 0);
     std::vector<uint32_t> pop_of(N);
@@ -300,7 +330,8 @@ std::string build_tables(const dbsim_desc& desc, const Plan& p, unsigned threads
     if (gen_fail.load()) return "network generator failed";
     if (wbad.load()) return "a weight is too large for the fixed-point format (|w| * 2^frac_bits must stay below 2^52)";
     cur.reset();
-    // deterministic layout: sort every delay segment by target
+    // deterministic layout: sort every delay segment by target (tile groups are ranges of
+    // consecutive targets, so each delay segment splits into contiguous group sub-segments)
     parallel_chunks(N, 1024, nt, [&](unsigned, uint64_t a, uint64_t b) {
         struct Ed {
             uint32_t t;
@@ -322,6 +353,27 @@ std::string build_tables(const dbsim_desc& desc, const Plan& p, unsigned threads
                     if (KW == 2) h.w[e * KW + 1] = tmp[e - s0].w1;
                 }
             }
+        }
+    });
+    // (delay, tile group) sub-segment offsets: seg_dg[j][(d-1)*G + g] = start, [D*G] = row length
+    const uint32_t G = kTileGroups, DG1 = D * G + 1;
+    const uint64_t group_span = (uint64_t)p.TG << p.tile_bits; // targets per tile group
+    h.seg_dg.resize((size_t)N * DG1);
+    parallel_chunks(N, 4096, nt, [&](unsigned, uint64_t a, uint64_t b) {
+        for (uint64_t j = a; j < b; j++) {
+            const uint32_t* sg = &h.seg[(size_t)j * (D + 1)];
+            uint32_t* out = &h.seg_dg[(size_t)j * DG1];
+            const uint64_t r0 = h.row_ptr[j];
+            for (uint32_t x = 0; x < D; x++) {
+                const uint32_t* c0 = h.col.data() + r0 + sg[x];
+                const uint32_t* c1 = h.col.data() + r0 + sg[x + 1];
+                for (uint32_t g = 0; g < G; g++) {
+                    const uint64_t first = g * group_span;
+                    const uint32_t* it = first >= (1ull << 32) ? c1 : std::lower_bound(c0, c1, (uint32_t)first);
+                    out[x * G + g] = (uint32_t)(it - (h.col.data() + r0));
+                }
+            }
+            out[D * G] = sg[D];
         }
     });
     return "";

@@ -16,6 +16,10 @@ struct Plan {
     uint32_t N = 0, U = 0, KW = 0, S = 0, D = 0, F = 0;
     uint32_t tile_bits = 0, T = 0, n_blocks = 0, n_regions = 0, n_pops = 0;
     uint32_t MB = 0;   // bins kept in the per-bin rings (power of two)
+    uint32_t n_l1 = 0; // level-1 readout groups (256 neuron blocks each, per region)
+    uint32_t n_grp = 0; // compaction groups (256 consecutive neuron blocks each)
+    uint32_t TG = 0;    // tiles per tile group
+    uint32_t round_events = 0, scatter_wgs_per_cu = 0;
     uint64_t RC = 0;   // spike-history ring entries (power of two)
     uint64_t E = 0;    // edges
     bool regions_on = false;
@@ -23,8 +27,9 @@ struct Plan {
     struct Slot {
         size_t off = 0, bytes = 0;
     };
-    Slot V, J, ref, pend, A, pops, ptab, blk, row_ptr, seg, col, w, src_inh, ev_tgt, ev_w, tile_base, tile_fill,
-        rec, bin_start, bin_cnt, blk_sig, blk_cnt, reg_blk_ptr, reg_blk, reg_size, sig, sig_cnt, ctl;
+    Slot V, J, ref, pend, A, pops, ptab, blk, row_ptr, seg, col, w, src_inh, ev, tile_base, tile_fill, sq, stage, grp_cnt, rec,
+        bin_start, bin_cnt, blk_sig, blk_cnt, reg_blk_ptr, reg_blk, reg_size, l1_ptr, l1_region, l1_sig, l1_cnt, sig,
+        sig_cnt, ctl;
     size_t total = 0;
 };
 
@@ -39,12 +44,13 @@ struct HostTables {
     std::vector<uint32_t> ptab;
     std::vector<uint2> blk;
     std::vector<uint64_t> row_ptr;
-    std::vector<uint32_t> seg;
+    std::vector<uint32_t> seg;    // [N][D+1] delay segments
+    std::vector<uint32_t> seg_dg; // [N][D*G+1] (delay, tile group) sub-segments (device layout)
     std::vector<uint32_t> col;
     std::vector<float> w; // KW floats per edge, interleaved
     std::vector<uint8_t> src_inh;
     std::vector<uint64_t> tile_base;
-    std::vector<uint32_t> reg_blk_ptr, reg_blk, reg_size;
+    std::vector<uint32_t> reg_blk_ptr, reg_blk, reg_size, l1_ptr, l1_region;
 };
 
 // Generates the network (threads: 0 = all cores) and builds every host table.

@@ -271,11 +271,15 @@ class Simulator:
         ref = np.ascontiguousarray(ref, np.int32)
         _check(lib().dbsim_write_state(self._h, _p(V, c_float), _p(J, c_float), _p(ref, c_int32)))
 
-    def export_csr(self):
+    def export_csr(self, edges: bool = True):
+        """(row_ptr, seg [N, D+1], tgt, w0, w1); with edges=False only row_ptr and seg."""
         E = int(self.info.num_edges)
         D = int(self.info.max_delay)
         row_ptr = np.zeros(self.N + 1, np.uint64)
         seg = np.zeros(self.N * (D + 1), np.uint32)
+        if not edges:
+            _check(lib().dbsim_export_csr(self._h, _p(row_ptr, c_uint64), _p(seg, c_uint32), None, None, None))
+            return row_ptr, seg.reshape(self.N, D + 1), None, None, None
         tgt = np.zeros(max(E, 1), np.uint32)
         w0 = np.zeros(max(E, 1), np.float32)
         w1 = np.zeros(max(E, 1), np.float32)

@@ -40,7 +40,8 @@ CASES = {
     "tiny_200ms_fp64": (lambda: configs.tiny(), 2000, 64),
     "share_3000_k100_50ms_fp32": (lambda: configs.share(n=3000, indegree=100, bg_rate_hz=7000.0, seed=2), 500, 32),
     "regions_6x100_50ms_fp32": (lambda: configs.multi_region(n_regions=6, per_region=100, intra_indegree=40,
-                                                             long_indegree=10, seed=1), 500, 32),
+                                                             long_indegree=10, seed=1, bg_rate_hz=5600.0),
+                                500, 32),
 }
 
 if __name__ == "__main__":
