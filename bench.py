@@ -2,8 +2,8 @@
 
 One benchmark step is one 1 ms spike bin of the whole hot path: the bucketed
 fan-in of the bin's arrivals (k_scatter + k_gather), ten fused 0.1 ms Euler
-substeps of every neuron with Poisson background and spike compaction
-(k_neuron), and the region readout and bin close (k_readout + k_close).
+substeps of every neuron with Poisson background (k_neuron), the spike-list
+compaction (k_compact), and the region readout and bin close (k_readout_close).
 
 Workload (default): one GPU's share of the whole-brain model, 6.1 M LIF neurons,
 in-degree 556 (3.39e9 synapses, two weights each), 4 receptors, delays uniform in
@@ -11,8 +11,10 @@ in-degree 556 (3.39e9 synapses, two weights each), 4 receptors, delays uniform i
 and seeded (the paper's networks come from private MRI data).
 
 Prints one JSON line: synaptic events/s over the timed bins (inputs resident in
-HBM), the real-time factor, the HBM roofline of the dominant fan-out phase, and
-the CPU oracle's throughput on a bounded sample of the same recipe.
+HBM), the real-time factor, the HBM roofline of the dominant fan-out phase, the
+batched-ensemble comparison (64 uneven networks advanced together vs one after
+another: ensemble sims/s and per-member p50/p99 completion latency), and the CPU
+oracle's throughput on a bounded sample of the same recipe.
 """
 import argparse
 import json
@@ -45,7 +47,15 @@ def run_gpu(args):
     log(f"built in {time.time() - t0:.1f} s (host construction {sim.stats()['build_seconds']:.1f} s), "
         f"device bytes {sim.stats()['hbm_bytes'] / 1e9:.2f} GB")
     S = sim.S
-    sim.step(args.warmup * S)
+    tuned = None
+    if args.autotune:
+        sim.step((args.warmup // 2) * S)
+        from paper_2211_15963_amd.tune import autotune
+        tuned = autotune(sim, bins_per_trial=max(2, args.warmup // 40))
+        log(f"autotuned fan-in schedule: {tuned['chosen']}")
+        sim.step((args.warmup - args.warmup // 2) * S)
+    else:
+        sim.step(args.warmup * S)
     sim.sync()
     log(f"warmup {args.warmup} bins done")
     s0 = sim.stats()
@@ -69,7 +79,7 @@ def run_gpu(args):
         "ms_scatter": s1["ms_scatter"] - s0["ms_scatter"], "ms_gather": s1["ms_gather"] - s0["ms_gather"],
         "ms_neuron": s1["ms_neuron"] - s0["ms_neuron"], "ms_readout": s1["ms_readout"] - s0["ms_readout"],
         "timed_bins": s1["timed_bins"] - s0["timed_bins"], "spec": spec, "build_s": s1["build_seconds"],
-        "hbm_bytes": s1["hbm_bytes"],
+        "hbm_bytes": s1["hbm_bytes"], "tuning": sim.tuning(),
     }
     sim.close()
     return out
@@ -100,6 +110,68 @@ def cpu_baseline(args, budget_s: float):
                       f"{bins} bins ({bins} ms bio) after 20 ms warm-up, FP32 oracle on one host core; "
                       f"real-time factor {wall / (bins * 1e-3):.1f}",
             "rtf": wall / (bins * 1e-3)}
+
+
+def run_ensemble(args):
+    """Batched ensemble: members advanced together vs the same members one after another."""
+    import numpy as np
+    import torch
+    from netgen import configs
+    from paper_2211_15963_amd import Simulator
+
+    members = [configs.ensemble_member(m, seed=args.seed) for m in range(args.members)]
+    nn = sum(s.num_neurons for s in members)
+    ne = sum(s.num_edges() for s in members)
+    bins = args.ensemble_bins
+    log(f"ensemble: {len(members)} members, {nn} neurons, {ne} synapses, {bins} bins each")
+    t0 = time.time()
+    ens = Simulator(members, record_regions=True)
+    log(f"ensemble built in {time.time() - t0:.1f} s")
+    S = ens.S
+    ens.step(args.ensemble_warmup * S)
+    if args.autotune:
+        from paper_2211_15963_amd.tune import autotune
+        autotune(ens, bins_per_trial=4)
+    ens.sync()
+    s0 = ens.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.step(bins * S)
+    ens.sync()
+    torch.cuda.synchronize()
+    wall_ens = time.perf_counter() - t0
+    ev_ens = ens.stats()["edge_events"] - s0["edge_events"]
+    tuning = ens.tuning()
+    ens.close()
+    log(f"ensemble: {bins} bins in {wall_ens:.3f} s")
+    # the same members one after another, each on its own handle
+    walls = []
+    ev_seq = 0
+    for m, spec in enumerate(members):
+        sim = Simulator(spec, record_regions=True)
+        sim.step(args.ensemble_warmup * S)
+        sim.sync()
+        e0 = sim.stats()["edge_events"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(bins * S)
+        sim.sync()
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        ev_seq += sim.stats()["edge_events"] - e0
+        sim.close()
+    wall_seq = float(np.sum(walls))
+    log(f"one after another: {wall_seq:.3f} s")
+    done_seq = np.cumsum(walls)  # completion time of each member when run in sequence
+    return {"members": len(members), "neurons": nn, "synapses": ne, "bio_s": bins * 1e-3,
+            "ensemble": {"wall_s": wall_ens, "sims_per_s": len(members) / wall_ens,
+                         "p50_latency_s": wall_ens, "p99_latency_s": wall_ens, "events_per_s": ev_ens / wall_ens,
+                         "tuning": tuning},
+            "one_after_another": {"wall_s": wall_seq, "sims_per_s": len(members) / wall_seq,
+                                  "p50_latency_s": float(np.percentile(done_seq, 50)),
+                                  "p99_latency_s": float(np.percentile(done_seq, 99)),
+                                  "events_per_s": ev_seq / wall_seq},
+            "speedup": wall_seq / wall_ens}
 
 
 def calibrate_copy(args):
@@ -155,6 +227,11 @@ def main():
     ap.add_argument("--tune", action="store_true")
     ap.add_argument("--tune-iters", type=int, default=9)
     ap.add_argument("--calibrate-copy", action="store_true", help="run only a 2 GiB device copy (counter scaling)")
+    ap.add_argument("--autotune", type=int, default=1, help="autotune the fan-in schedule during warm-up")
+    ap.add_argument("--ensemble", type=int, default=1, help="also run the batched-ensemble comparison")
+    ap.add_argument("--members", type=int, default=64)
+    ap.add_argument("--ensemble-bins", type=int, default=500, help="bins (ms) each member advances")
+    ap.add_argument("--ensemble-warmup", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU's share of the network; runs on more than one GPU are not supported "
@@ -179,6 +256,7 @@ def main():
                 "bytes_per_event": BYTES_PER_EVENT, "events_per_launch": g["events"] / nb,
                 "avg_launch_ms": {"k_scatter": g["ms_scatter"] / nb, "k_gather": g["ms_gather"] / nb,
                                   "k_neuron": g["ms_neuron"] / nb, "readout_close": g["ms_readout"] / nb}}
+    ens = run_ensemble(args) if args.ensemble else None
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, args.cpu_seconds)
@@ -192,7 +270,9 @@ def main():
                    "neurons": spec.num_neurons, "synapses": spec.num_edges(), "dt_ms": spec.dt_ms,
                    "bin_ms": spec.bin_ms, "regime_hz": args.regime, "mean_rate_hz": round(g["rate_hz"], 3),
                    "rtf": g["wall"] / g["bio_s"], "launch": args.mode, "build_s": round(g["build_s"], 1),
-                   "device_gb": round(g["hbm_bytes"] / 1e9, 2)},
+                   "device_gb": round(g["hbm_bytes"] / 1e9, 2), "fanin_schedule": g["tuning"]},
+        "rtf_15hz": g["wall"] / g["bio_s"] if args.regime == 15 else None,
+        "ensemble": ens,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(line))

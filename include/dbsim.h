@@ -107,7 +107,15 @@ typedef struct dbsim_info {
     uint32_t tile_neurons;     /* targets per accumulation tile */
     uint32_t n_tiles;
     uint32_t frac_bits;        /* F of the fixed-point arrival sums */
+    uint32_t n_members;        /* networks in the handle (1 unless an ensemble) */
 } dbsim_info;
+
+typedef struct dbsim_member {
+    uint64_t first_neuron; /* global id of the member's neuron 0 */
+    uint64_t num_neurons;
+    uint32_t first_region; /* global index of the member's region 0 */
+    uint32_t num_regions;
+} dbsim_member;
 
 /* Library ABI version (DBSIM_ABI_VERSION of the build). */
 uint32_t dbsim_abi_version(void);
@@ -127,6 +135,28 @@ int dbsim_create(const dbsim_desc* desc, struct dbsim** out);
 
 /* Exact device bytes dbsim_create would allocate for desc, without building. */
 int dbsim_footprint(const dbsim_desc* desc, uint64_t* hbm_bytes);
+
+/*
+ * Ensemble of independent networks advanced together by the same kernel
+ * launches (the ensemble forward pass of the diffusion ensemble Kalman filter,
+ * Suppl. Algorithm 3, evolves many model instances with their own parameters).
+ * members[m] are full network descriptions (own seed, net_id, populations,
+ * projections, regions); they must share dt_ms, bin_ms, receptor_mask and
+ * frac_bits. Runtime options come from common (its net field is ignored).
+ * Member m's neurons and regions occupy consecutive global ids (see
+ * dbsim_member_info); edges never cross members and each member keeps its own
+ * noise stream, so every member's spikes and state are bit-identical to
+ * running it alone. Reads return global ids; errors as dbsim_create.
+ */
+int dbsim_create_ensemble(const dbsim_desc* common, const dbnet_desc* members, uint32_t n_members,
+                          struct dbsim** out);
+
+/* Exact device bytes dbsim_create_ensemble would allocate (admission control). */
+int dbsim_footprint_ensemble(const dbsim_desc* common, const dbnet_desc* members, uint32_t n_members,
+                             uint64_t* hbm_bytes);
+
+/* Global id range and region range of ensemble member `member` (0 for a single network). */
+int dbsim_member_info(struct dbsim* h, uint32_t member, dbsim_member* info);
 
 /* Queries sizes of a built network. */
 int dbsim_get_info(struct dbsim* h, dbsim_info* info);
@@ -177,6 +207,23 @@ int dbsim_write_state(struct dbsim* h, const float* V, const float* J, const int
  */
 int dbsim_export_csr(struct dbsim* h, uint64_t* row_ptr, uint32_t* seg, uint32_t* tgt, float* w0,
                      float* w1);
+
+/*
+ * Launch schedule of the fan-in scatter kernel. Any valid schedule gives
+ * bit-identical results (the arrival sums are exact integers); it only changes
+ * speed, so an autotuner may try schedules on a live handle.
+ */
+typedef struct dbsim_tuning {
+    uint32_t scatter_wgs_per_cu; /* 1 or 2 resident scatter workgroups per CU (they split the LDS) */
+    uint32_t round_events;       /* events staged in LDS per round, multiple of 1024; 0 = the most that fit */
+    uint32_t chunks_per_wg;      /* target (spike, delay) chunks per scatter workgroup per bin, 1..64 */
+    uint32_t reserved;
+} dbsim_tuning;
+
+/* Reads / sets the schedule (EINVAL if it does not fit the LDS). Takes effect
+   for the next step call; replayed graphs are re-captured. */
+int dbsim_get_tuning(struct dbsim* h, dbsim_tuning* t);
+int dbsim_set_tuning(struct dbsim* h, const dbsim_tuning* t);
 
 /* Turns per-phase kernel timing (HIP events around each phase of every
    bin) on or off; while on, bins are launched directly, not via graphs. */

@@ -47,9 +47,7 @@ constexpr int kPhases = 4;    // scatter, gather, neuron, readout+close
 
 struct dbsim {
     dbsim_desc desc{};
-    std::vector<dbnet_pop> pops;
-    std::vector<dbnet_proj> projs;
-    std::vector<float> xyz;
+    Members mem;
     Plan plan;
     int device = -1;
     hipStream_t stream = nullptr;
@@ -57,7 +55,9 @@ struct dbsim {
     hipStream_t cap_stream = nullptr;
     unsigned char* dev = nullptr;
     DevNet net{};
-    int scatter_grid = 512;
+    int scatter_grid = 256;
+    int num_cus = 256;
+    uint32_t scatter_wgs = 1;
     hipGraphExec_t g_multi = nullptr;
     hipGraphExec_t g_one = nullptr;
     uint64_t step = 0;
@@ -101,13 +101,12 @@ void fill_devnet(dbsim* h) {
     n.tile_bits = p.tile_bits;
     n.TG = p.TG;
     n.round_events = p.round_events;
+    n.chunks_per_wg = 2;
     n.T = p.T;
     n.n_blocks = p.n_blocks;
     n.n_regions = p.n_regions;
     n.RCmask = p.RC - 1;
     n.MBmask = p.MB - 1;
-    n.net_id = h->desc.net.net_id;
-    n.seed = h->desc.net.seed;
     n.qscale = std::ldexp(1.0, (int)p.F);
     n.qinv = std::ldexp(1.0f, -(int)p.F);
     n.regions_on = p.regions_on ? 1u : 0u;
@@ -256,11 +255,13 @@ uint32_t dbsim_abi_version(void) { return DBSIM_ABI_VERSION; }
 
 const char* dbsim_last_error(void) { return g_err.c_str(); }
 
-int dbsim_footprint(const dbsim_desc* desc, uint64_t* hbm_bytes) {
-    if (!desc || !hbm_bytes) return fail(DBSIM_EINVAL, "null argument");
+static int footprint_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32_t n, uint64_t* hbm_bytes) {
+    if (!desc || !hbm_bytes || !members || n == 0) return fail(DBSIM_EINVAL, "null argument or no network");
     try {
+        Members mem;
+        mem.assign(members, n);
         Plan p;
-        std::string m = make_plan(*desc, p);
+        std::string m = make_plan(*desc, mem, p);
         if (!m.empty()) return fail(DBSIM_EINVAL, m);
         *hbm_bytes = p.total;
         return DBSIM_OK;
@@ -271,23 +272,27 @@ int dbsim_footprint(const dbsim_desc* desc, uint64_t* hbm_bytes) {
     }
 }
 
-int dbsim_create(const dbsim_desc* desc, dbsim** out) {
-    if (!desc || !out) return fail(DBSIM_EINVAL, "null argument");
+int dbsim_footprint(const dbsim_desc* desc, uint64_t* hbm_bytes) {
+    if (!desc) return fail(DBSIM_EINVAL, "null argument");
+    return footprint_impl(desc, &desc->net, 1, hbm_bytes);
+}
+
+int dbsim_footprint_ensemble(const dbsim_desc* common, const dbnet_desc* members, uint32_t n_members,
+                             uint64_t* hbm_bytes) {
+    return footprint_impl(common, members, n_members, hbm_bytes);
+}
+
+static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32_t n_members, dbsim** out) {
+    if (!desc || !out || !members || n_members == 0) return fail(DBSIM_EINVAL, "null argument or no network");
     *out = nullptr;
     if (desc->dev_alloc && !desc->dev_free) return fail(DBSIM_EINVAL, "dev_alloc given without dev_free");
     dbsim* h = nullptr;
     try {
         h = new dbsim();
         h->desc = *desc;
-        h->pops.assign(desc->net.pops, desc->net.pops + desc->net.n_pops);
-        if (desc->net.n_projs) h->projs.assign(desc->net.projs, desc->net.projs + desc->net.n_projs);
-        h->desc.net.pops = h->pops.data();
-        h->desc.net.projs = h->projs.empty() ? nullptr : h->projs.data();
-        if (desc->net.region_xyz_mm) {
-            h->xyz.assign(desc->net.region_xyz_mm, desc->net.region_xyz_mm + 3 * (size_t)desc->net.n_regions);
-            h->desc.net.region_xyz_mm = h->xyz.data();
-        }
-        std::string m = make_plan(h->desc, h->plan);
+        h->mem.assign(members, n_members);
+        h->desc.net = h->mem.m[0];
+        std::string m = make_plan(h->desc, h->mem, h->plan);
         if (!m.empty()) {
             delete h;
             return fail(DBSIM_EINVAL, m);
@@ -318,7 +323,7 @@ int dbsim_create(const dbsim_desc* desc, dbsim** out) {
         fill_devnet(h);
         auto t0 = std::chrono::steady_clock::now();
         HostTables ht;
-        m = build_tables(h->desc, p, desc->host_threads, ht);
+        m = build_tables(h->mem, p, desc->host_threads, ht);
         if (!m.empty()) {
             release_device(h);
             delete h;
@@ -392,8 +397,9 @@ int dbsim_create(const dbsim_desc* desc, dbsim** out) {
         }
         // persistent grid for the scatter kernel: two 1024-thread blocks per CU
         hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, h->device) == hipSuccess)
-            h->scatter_grid = (int)p.scatter_wgs_per_cu * prop.multiProcessorCount;
+        if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) h->num_cus = prop.multiProcessorCount;
+        h->scatter_wgs = p.scatter_wgs_per_cu;
+        h->scatter_grid = (int)h->scatter_wgs * h->num_cus;
         *out = h;
         return DBSIM_OK;
     } catch (const std::bad_alloc&) {
@@ -411,6 +417,25 @@ int dbsim_create(const dbsim_desc* desc, dbsim** out) {
     }
 }
 
+int dbsim_create(const dbsim_desc* desc, dbsim** out) {
+    if (!desc) return fail(DBSIM_EINVAL, "null argument");
+    return create_impl(desc, &desc->net, 1, out);
+}
+
+int dbsim_create_ensemble(const dbsim_desc* common, const dbnet_desc* members, uint32_t n_members, dbsim** out) {
+    return create_impl(common, members, n_members, out);
+}
+
+int dbsim_member_info(dbsim* h, uint32_t member, dbsim_member* info) {
+    if (!h || !info) return fail(DBSIM_EINVAL, "null argument");
+    if (member >= h->mem.m.size()) return fail(DBSIM_EINVAL, "member index out of range");
+    info->first_neuron = h->mem.nbase[member];
+    info->num_neurons = h->mem.nbase[member + 1] - h->mem.nbase[member];
+    info->first_region = h->mem.rbase[member];
+    info->num_regions = h->mem.rbase[member + 1] - h->mem.rbase[member];
+    return DBSIM_OK;
+}
+
 int dbsim_get_info(dbsim* h, dbsim_info* info) {
     if (!h || !info) return fail(DBSIM_EINVAL, "null argument");
     const Plan& p = h->plan;
@@ -424,6 +449,7 @@ int dbsim_get_info(dbsim* h, dbsim_info* info) {
     info->tile_neurons = 1u << p.tile_bits;
     info->n_tiles = p.T;
     info->frac_bits = p.F;
+    info->n_members = p.n_members;
     return DBSIM_OK;
 }
 
@@ -629,6 +655,38 @@ int dbsim_export_csr(dbsim* h, uint64_t* row_ptr, uint32_t* seg, uint32_t* tgt, 
             if (w1) w1[e] = p.KW == 2 ? w[e * p.KW + 1] : 0.0f;
         }
     }
+    return DBSIM_OK;
+}
+
+int dbsim_get_tuning(dbsim* h, dbsim_tuning* t) {
+    if (!h || !t) return fail(DBSIM_EINVAL, "null argument");
+    t->scatter_wgs_per_cu = h->scatter_wgs;
+    t->round_events = h->net.round_events;
+    t->chunks_per_wg = h->net.chunks_per_wg;
+    t->reserved = 0;
+    return DBSIM_OK;
+}
+
+int dbsim_set_tuning(dbsim* h, const dbsim_tuning* t) {
+    int rc = check_usable(h);
+    if (rc) return rc;
+    if (!t) return fail(DBSIM_EINVAL, "null argument");
+    if (t->scatter_wgs_per_cu < 1 || t->scatter_wgs_per_cu > 2) return fail(DBSIM_EINVAL, "scatter_wgs_per_cu must be 1 or 2");
+    if (t->chunks_per_wg < 1 || t->chunks_per_wg > 64) return fail(DBSIM_EINVAL, "chunks_per_wg must lie in 1..64");
+    const uint32_t rmax = max_round_events(h->plan.TG, t->scatter_wgs_per_cu);
+    if (rmax == 0) return fail(DBSIM_EINVAL, "this schedule does not fit the LDS");
+    const uint32_t re = t->round_events ? t->round_events : rmax;
+    if (re % 1024 || re > rmax) return fail(DBSIM_EINVAL, "round_events must be a multiple of 1024 that fits the LDS");
+    DeviceGuard dg(h->device);
+    rc = sync_and_check(h);
+    if (rc) return rc;
+    h->scatter_wgs = t->scatter_wgs_per_cu;
+    h->scatter_grid = (int)h->scatter_wgs * h->num_cus;
+    h->net.round_events = re;
+    h->net.chunks_per_wg = t->chunks_per_wg;
+    if (h->g_multi) (void)hipGraphExecDestroy(h->g_multi);
+    if (h->g_one) (void)hipGraphExecDestroy(h->g_one);
+    h->g_multi = h->g_one = nullptr;
     return DBSIM_OK;
 }
 

@@ -54,6 +54,9 @@ struct PopParams {
     int32_t cmax;               // Poisson table length
     uint32_t end;               // one past the population's last neuron id
     uint32_t region;
+    uint32_t net_id;            // noise stream of the population's network
+    uint32_t id_base;           // global id of its network's first neuron (noise counters use local ids)
+    unsigned long long seed;    // its network's seed (Philox key)
 };
 
 struct Ctl {
@@ -69,10 +72,9 @@ struct DevNet {
     uint32_t tile_bits, T, n_blocks, n_regions;
     uint32_t TG;           // tiles per tile group
     uint32_t round_events; // events staged in LDS per scatter round
+    uint32_t chunks_per_wg; // target scatter chunks per workgroup and bin
     uint64_t RCmask;
     uint32_t MBmask;
-    uint32_t net_id;
-    uint64_t seed;
     double qscale;   // 2^F
     float qinv;      // 2^-F
     uint32_t regions_on;

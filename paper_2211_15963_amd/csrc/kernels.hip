@@ -162,8 +162,9 @@ __global__ void __launch_bounds__(kScatterThreads) k_scatter(DevNet net) {
     __syncthreads();
     const unsigned long long total = s_dpre[D];
     if (total == 0) return;
-    // segments per chunk: about two chunks per workgroup over all groups, at most kScatterSegs
-    const unsigned long long want = (total * G + 2ull * gridDim.x - 1) / (2ull * gridDim.x);
+    // segments per chunk: about chunks_per_wg chunks per workgroup over all groups, at most kScatterSegs
+    const unsigned long long cw = (unsigned long long)net.chunks_per_wg * gridDim.x;
+    const unsigned long long want = (total * G + cw - 1) / cw;
     const uint32_t spc = (uint32_t)min((unsigned long long)kScatterSegs, max(32ull, want));
     const uint32_t nchunks = (uint32_t)((total + spc - 1) / spc);
     const uint32_t tb = net.tile_bits, tmask = (1u << tb) - 1u, DG1 = D * G + 1;
@@ -372,8 +373,10 @@ __global__ void __launch_bounds__(kNeuronBlock) k_neuron(DevNet net, int s0, int
         dec[u] = P.dec[u];
     }
     const int rsteps = P.r;
-    const uint32_t key0 = (uint32_t)net.seed, key1 = (uint32_t)(net.seed >> 32);
-    const uint32_t tag = (1u << 24) | (net.net_id & 0xFFFFFFu);
+    const unsigned long long seed = P.seed;
+    const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
+    const uint32_t tag = (1u << 24) | (P.net_id & 0xFFFFFFu);
+    const uint32_t local = i - P.id_base; // neuron index within its own network
     uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
     unsigned long long cur_blk = ~0ull;
 
@@ -383,7 +386,7 @@ __global__ void __launch_bounds__(kNeuronBlock) k_neuron(DevNet net, int s0, int
         if (blk != cur_blk) {
             w0 = (uint32_t)blk;
             w1 = (uint32_t)(blk >> 32);
-            w2 = i;
+            w2 = local;
             w3 = tag;
             philox4x32_10(w0, w1, w2, w3, key0, key1);
             cur_blk = blk;

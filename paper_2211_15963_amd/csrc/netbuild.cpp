@@ -72,20 +72,68 @@ uint32_t indeg_of_pop(const dbnet_desc& d, uint32_t p) {
 
 } // namespace
 
-std::string make_plan(const dbsim_desc& d, Plan& p) {
-    if (d.abi_version != DBSIM_ABI_VERSION) return "dbsim_desc.abi_version does not match the library";
+uint32_t max_round_events(uint32_t TG, uint32_t wgs_per_cu) {
+    const size_t budget = kMaxLdsBytes / wgs_per_cu - 1024;
+    const size_t fixed = scatter_fixed_lds(TG);
+    if (fixed + 14 * 1024 > budget) return 0;
+    return (uint32_t)std::min<size_t>(16384, ((budget - fixed) / 14) & ~(size_t)1023);
+}
+
+void Members::assign(const dbnet_desc* descs, uint32_t n) {
+    m.assign(descs, descs + n);
+    pops.resize(n);
+    projs.resize(n);
+    xyz.resize(n);
+    nbase.assign(n + 1, 0);
+    pbase.assign(n + 1, 0);
+    rbase.assign(n + 1, 0);
+    for (uint32_t k = 0; k < n; k++) {
+        const dbnet_desc& d = descs[k];
+        if (d.pops && d.n_pops) pops[k].assign(d.pops, d.pops + d.n_pops);
+        if (d.projs && d.n_projs) projs[k].assign(d.projs, d.projs + d.n_projs);
+        if (d.region_xyz_mm) xyz[k].assign(d.region_xyz_mm, d.region_xyz_mm + 3 * (size_t)d.n_regions);
+        m[k].pops = pops[k].empty() ? nullptr : pops[k].data();
+        m[k].projs = projs[k].empty() ? nullptr : projs[k].data();
+        m[k].region_xyz_mm = xyz[k].empty() ? nullptr : xyz[k].data();
+        uint64_t nn = 0;
+        for (const auto& q : pops[k]) nn += q.size;
+        nbase[k + 1] = nbase[k] + nn;
+        pbase[k + 1] = pbase[k] + d.n_pops;
+        rbase[k + 1] = rbase[k] + d.n_regions;
+    }
+}
+
+uint32_t Members::member_of(uint64_t i) const {
+    return (uint32_t)(std::upper_bound(nbase.begin(), nbase.end(), i) - nbase.begin()) - 1;
+}
+
+std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
+    if (opts.abi_version != DBSIM_ABI_VERSION) return "dbsim_desc.abi_version does not match the library";
+    if (mem.m.empty()) return "no network given";
     char err[512];
-    if (dbnet_validate(&d.net, err, sizeof err) != 0) return err;
-    const dbnet_desc& n = d.net;
-    p.N = (uint32_t)dbnet_num_neurons(&n);
-    p.KW = dbnet_weights_per_edge(&n);
+    for (size_t k = 0; k < mem.m.size(); k++) {
+        if (dbnet_validate(&mem.m[k], err, sizeof err) != 0)
+            return mem.m.size() > 1 ? "member " + std::to_string(k) + ": " + err : std::string(err);
+    }
+    const dbnet_desc& m0 = mem.m[0];
+    for (size_t k = 1; k < mem.m.size(); k++) {
+        const dbnet_desc& d = mem.m[k];
+        if (d.dt_ms != m0.dt_ms || d.bin_ms != m0.bin_ms || d.receptor_mask != m0.receptor_mask ||
+            d.frac_bits != m0.frac_bits)
+            return "ensemble members must share dt_ms, bin_ms, receptor_mask and frac_bits";
+    }
+    if (mem.nbase.back() >= DBNET_MAX_NEURONS) return "too many neurons in total (ids must fit in 28 bits)";
+    p.n_members = (uint32_t)mem.m.size();
+    p.N = (uint32_t)mem.nbase.back();
+    p.KW = dbnet_weights_per_edge(&m0);
     p.U = 2 * p.KW;
-    p.S = (uint32_t)std::lround((double)n.bin_ms / (double)n.dt_ms);
-    p.D = dbnet_max_delay(&n);
-    p.F = n.frac_bits;
-    p.n_pops = n.n_pops;
-    p.n_regions = n.n_regions;
-    p.regions_on = (d.record_flags & DBSIM_REC_REGIONS) != 0;
+    p.S = (uint32_t)std::lround((double)m0.bin_ms / (double)m0.dt_ms);
+    p.D = 1;
+    for (const auto& d : mem.m) p.D = std::max(p.D, dbnet_max_delay(&d));
+    p.F = m0.frac_bits;
+    p.n_pops = mem.pbase.back();
+    p.n_regions = mem.rbase.back();
+    p.regions_on = (opts.record_flags & DBSIM_REC_REGIONS) != 0;
     // tiles: the LDS accumulator of a tile holds tile_neurons * U int64 sums
     const uint32_t tile_neurons = kTileLdsBytes / (8u * p.U);
     p.tile_bits = 0;
@@ -93,44 +141,41 @@ std::string make_plan(const dbsim_desc& d, Plan& p) {
     p.T = (p.N + (1u << p.tile_bits) - 1) >> p.tile_bits;
     if (p.T > (uint32_t)kMaxTilesLds) return "network too large for the tile histogram (too many neurons)";
     p.TG = (p.T + kTileGroups - 1) / kTileGroups;
-    // scatter: workgroups per CU (LDS budget each) and the events staged per LDS round
-    {
-        const char* ev = std::getenv("DBSIM_SCATTER_WGS");
-        p.scatter_wgs_per_cu = ev ? (uint32_t)std::max(1, std::min(2, std::atoi(ev))) : 1u;
-        const size_t budget = kMaxLdsBytes / p.scatter_wgs_per_cu - 1024;
-        const size_t fixed = scatter_fixed_lds(p.TG);
-        if (fixed + 14 * 1024 > budget) return "too many tiles per group for the scatter's LDS budget";
-        p.round_events = (uint32_t)std::min<size_t>(16384, ((budget - fixed) / 14) & ~(size_t)1023);
-    }
-    const double dt = (double)n.dt_ms;
+    // scatter: default schedule (one workgroup per CU, the largest LDS round that fits)
+    p.scatter_wgs_per_cu = 1;
+    p.round_events = max_round_events(p.TG, 1);
+    if (p.round_events == 0) return "too many tiles per group for the scatter's LDS budget";
+    const double dt = (double)m0.dt_ms;
     p.E = 0;
     p.n_blocks = 0;
-    for (uint32_t q = 0; q < n.n_pops; q++) {
-        const dbnet_pop& P = n.pops[q];
-        const long r = std::lround((double)P.T_ref / dt);
-        if (r < (long)p.S - 1)
-            return "T_ref must be at least bin_ms - dt_ms so that a neuron spikes at most once per bin";
-        if (r > 255) return "T_ref / dt_ms must not exceed 255 steps";
-        uint32_t T[kMaxPoisson];
-        if (poisson_thresholds((double)P.bg_rate_hz * dt * 1e-3, T, kMaxPoisson) < 0)
-            return "background rate too high for the Poisson table (rate * dt above about 20)";
-        p.E += (uint64_t)P.size * indeg_of_pop(n, q);
-        p.n_blocks += (P.size + kNeuronBlock - 1) / kNeuronBlock;
+    std::vector<uint64_t> rblocks(p.n_regions, 0);
+    for (size_t k = 0; k < mem.m.size(); k++) {
+        const dbnet_desc& n = mem.m[k];
+        for (uint32_t q = 0; q < n.n_pops; q++) {
+            const dbnet_pop& P = n.pops[q];
+            const long r = std::lround((double)P.T_ref / dt);
+            if (r < (long)p.S - 1)
+                return "T_ref must be at least bin_ms - dt_ms so that a neuron spikes at most once per bin";
+            if (r > 255) return "T_ref / dt_ms must not exceed 255 steps";
+            uint32_t T[kMaxPoisson];
+            if (poisson_thresholds((double)P.bg_rate_hz * dt * 1e-3, T, kMaxPoisson) < 0)
+                return "background rate too high for the Poisson table (rate * dt above about 20)";
+            const uint32_t kin = indeg_of_pop(n, q);
+            // tile slices are indexed with 32-bit fill counters
+            if ((uint64_t)kin << p.tile_bits >= (1ull << 32)) return "in-degree too large for a tile slice";
+            p.E += (uint64_t)P.size * kin;
+            const uint32_t nb = (P.size + kNeuronBlock - 1) / kNeuronBlock;
+            p.n_blocks += nb;
+            rblocks[mem.rbase[k] + P.region] += nb;
+        }
     }
-    {
-        std::vector<uint64_t> rblocks(p.n_regions, 0);
-        for (uint32_t q = 0; q < n.n_pops; q++) rblocks[n.pops[q].region] += (n.pops[q].size + kNeuronBlock - 1) / kNeuronBlock;
-        p.n_l1 = 0;
-        for (uint32_t r = 0; r < p.n_regions; r++) p.n_l1 += (uint32_t)std::max<uint64_t>(1, (rblocks[r] + 255) / 256);
-    }
-    const uint32_t rb = d.record_bins ? d.record_bins : 4096u;
+    p.n_l1 = 0;
+    for (uint32_t r = 0; r < p.n_regions; r++) p.n_l1 += (uint32_t)std::max<uint64_t>(1, (rblocks[r] + 255) / 256);
+    const uint32_t rb = opts.record_bins ? opts.record_bins : 4096u;
     p.MB = pow2_at_least32(std::max<uint64_t>(rb, (uint64_t)p.D + 1));
     // spike history: at least the last D bins for the fan-in, plus a default reading window
-    const uint64_t want = d.spike_record_capacity ? d.spike_record_capacity : (1ull << 22);
+    const uint64_t want = opts.spike_record_capacity ? opts.spike_record_capacity : (1ull << 22);
     p.RC = pow2_at_least64(std::max<uint64_t>(want, ((uint64_t)p.D + 1) * p.N));
-    // tile slices are indexed with 32-bit fill counters
-    for (uint32_t q = 0; q < n.n_pops; q++)
-        if ((uint64_t)indeg_of_pop(n, q) << p.tile_bits >= (1ull << 32)) return "in-degree too large for a tile slice";
     // memory plan (one allocation, 256-byte aligned slots)
     size_t off = 0;
     auto slot = [&](Plan::Slot& s, size_t bytes) {
@@ -178,55 +223,65 @@ std::string make_plan(const dbsim_desc& d, Plan& p) {
     return "";
 }
 
-std::string build_tables(const dbsim_desc& desc, const Plan& p, unsigned threads, HostTables& h) {
-    const dbnet_desc& d = desc.net;
+std::string build_tables(const Members& mem, const Plan& p, unsigned threads, HostTables& h) {
     const unsigned nt = threads ? threads : std::max(1u, std::thread::hardware_concurrency());
     const uint32_t N = p.N, D = p.D, KW = p.KW;
-    const double dt = (double)d.dt_ms;
+    const uint32_t M = (uint32_t)mem.m.size();
+    const double dt = (double)mem.m[0].dt_ms;
 
     // populations: derived constants, computed in double and rounded once to float
-    h.pops.assign(d.n_pops, PopParams{});
-    h.ptab.assign((size_t)d.n_pops * kMaxPoisson, 0u);
+    h.pops.assign(p.n_pops, PopParams{});
+    h.ptab.assign((size_t)p.n_pops * kMaxPoisson, 0u);
     static const uint32_t umap2[2] = {DBNET_AMPA, DBNET_GABA_A};
     static const uint32_t umap4[4] = {DBNET_AMPA, DBNET_NMDA, DBNET_GABA_A, DBNET_GABA_B};
     const uint32_t* umap = KW == 1 ? umap2 : umap4;
+    std::vector<uint32_t> pop_indeg(p.n_pops);
+    std::vector<uint64_t> pop_first(p.n_pops + 1, 0);
     uint64_t off = 0;
-    std::vector<uint32_t> pop_indeg(d.n_pops);
-    for (uint32_t q = 0; q < d.n_pops; q++) {
-        const dbnet_pop& Q = d.pops[q];
-        PopParams& P = h.pops[q];
-        P.k = (float)(dt / (double)Q.C);
-        P.gL = Q.g_L;
-        P.VL = Q.V_L;
-        P.Vth = Q.V_th;
-        P.Vr = Q.V_reset;
-        P.Iext = Q.I_ext;
-        P.wbg = Q.w_bg;
-        for (uint32_t c = 0; c < p.U; c++) {
-            const uint32_t u = umap[c];
-            P.g[c] = Q.g[u];
-            P.Vu[c] = Q.V_rev[u];
-            P.dec[c] = (float)std::exp(-dt / (double)Q.tau[u]);
+    for (uint32_t m = 0; m < M; m++) {
+        const dbnet_desc& d = mem.m[m];
+        for (uint32_t q = 0; q < d.n_pops; q++) {
+            const uint32_t gq = mem.pbase[m] + q;
+            const dbnet_pop& Q = d.pops[q];
+            PopParams& P = h.pops[gq];
+            P.k = (float)(dt / (double)Q.C);
+            P.gL = Q.g_L;
+            P.VL = Q.V_L;
+            P.Vth = Q.V_th;
+            P.Vr = Q.V_reset;
+            P.Iext = Q.I_ext;
+            P.wbg = Q.w_bg;
+            for (uint32_t c = 0; c < p.U; c++) {
+                const uint32_t u = umap[c];
+                P.g[c] = Q.g[u];
+                P.Vu[c] = Q.V_rev[u];
+                P.dec[c] = (float)std::exp(-dt / (double)Q.tau[u]);
+            }
+            P.r = (int32_t)std::lround((double)Q.T_ref / dt);
+            P.cmax = poisson_thresholds((double)Q.bg_rate_hz * dt * 1e-3, &h.ptab[(size_t)gq * kMaxPoisson],
+                                        kMaxPoisson);
+            pop_first[gq] = off;
+            off += Q.size;
+            P.end = (uint32_t)off;
+            P.region = mem.rbase[m] + Q.region;
+            P.net_id = d.net_id;
+            P.id_base = (uint32_t)mem.nbase[m];
+            P.seed = d.seed;
+            pop_indeg[gq] = indeg_of_pop(d, q);
         }
-        P.r = (int32_t)std::lround((double)Q.T_ref / dt);
-        P.cmax = poisson_thresholds((double)Q.bg_rate_hz * dt * 1e-3, &h.ptab[(size_t)q * kMaxPoisson], kMaxPoisson);
-        off += Q.size;
-        P.end = (uint32_t)off;
-        P.region = Q.region;
-        pop_indeg[q] = indeg_of_pop(d, q);
     }
+    pop_first[p.n_pops] = off;
     // neuron blocks never straddle populations; regions list their blocks
     h.blk.clear();
     h.reg_size.assign(p.n_regions, 0u);
     std::vector<std::vector<uint32_t>> rb(p.n_regions);
-    off = 0;
-    for (uint32_t q = 0; q < d.n_pops; q++) {
-        for (uint64_t s = off; s < off + d.pops[q].size; s += kNeuronBlock) {
-            rb[d.pops[q].region].push_back((uint32_t)h.blk.size());
-            h.blk.push_back(make_uint2((uint32_t)s, q));
+    for (uint32_t gq = 0; gq < p.n_pops; gq++) {
+        const uint32_t r = h.pops[gq].region;
+        for (uint64_t s = pop_first[gq]; s < pop_first[gq + 1]; s += kNeuronBlock) {
+            rb[r].push_back((uint32_t)h.blk.size());
+            h.blk.push_back(make_uint2((uint32_t)s, gq));
         }
-        h.reg_size[d.pops[q].region] += d.pops[q].size;
-        off += d.pops[q].size;
+        h.reg_size[r] += (uint32_t)(pop_first[gq + 1] - pop_first[gq]);
     }
     h.reg_blk_ptr.assign(p.n_regions + 1, 0u);
     h.reg_blk.clear();
@@ -242,29 +297,35 @@ std::string build_tables(const dbsim_desc& desc, const Plan& p, unsigned threads
     if (h.l1_region.size() != p.n_l1) return "internal error: readout group count mismatch";
     // per-neuron source class and in-degree prefix by tile
     h.src_inh.assign(N, 0);
-    std::vector<uint32_t> pop_of(N);
-    off = 0;
-    for (uint32_t q = 0; q < d.n_pops; q++) {
-        for (uint64_t i = off; i < off + d.pops[q].size; i++) {
-            h.src_inh[i] = d.pops[q].exc ? 0 : 1;
-            pop_of[i] = q;
-        }
-        off += d.pops[q].size;
-    }
     h.tile_base.assign((size_t)p.T + 1, 0ull);
-    for (uint32_t i = 0; i < N; i++) h.tile_base[(i >> p.tile_bits) + 1] += pop_indeg[pop_of[i]];
+    for (uint32_t m = 0; m < M; m++)
+        for (uint32_t q = 0; q < mem.m[m].n_pops; q++) {
+            const uint32_t gq = mem.pbase[m] + q;
+            const uint8_t inh = mem.m[m].pops[q].exc ? 0 : 1;
+            for (uint64_t i = pop_first[gq]; i < pop_first[gq + 1]; i++) {
+                h.src_inh[i] = inh;
+                h.tile_base[(i >> p.tile_bits) + 1] += pop_indeg[gq];
+            }
+        }
     for (uint32_t t = 0; t < p.T; t++) h.tile_base[t + 1] += h.tile_base[t];
     if (h.tile_base[p.T] != p.E) return "internal error: edge count mismatch";
 
     // initial membrane potentials
     h.V0.resize(N);
     parallel_chunks(N, 1 << 16, nt, [&](unsigned, uint64_t a, uint64_t b) {
-        for (uint64_t i = a; i < b; i++) h.V0[i] = dbnet_v0(&d, (uint32_t)i);
+        for (uint64_t i = a; i < b; i++) {
+            const uint32_t m = mem.member_of(i);
+            h.V0[i] = dbnet_v0(&mem.m[m], (uint32_t)(i - mem.nbase[m]));
+        }
     });
 
     // pass 1: out-degree per (source, delay)
-    const size_t scratch_bytes = dbnet_scratch_bytes(&d);
-    const uint32_t kmax = std::max(1u, dbnet_max_indegree(&d));
+    size_t scratch_bytes = 0;
+    uint32_t kmax = 1;
+    for (const auto& d : mem.m) {
+        scratch_bytes = std::max(scratch_bytes, dbnet_scratch_bytes(&d));
+        kmax = std::max(kmax, dbnet_max_indegree(&d));
+    }
     std::unique_ptr<std::atomic<uint32_t>[]> cnt(new std::atomic<uint32_t>[(size_t)N * D]);
     for (size_t x = 0; x < (size_t)N * D; x++) cnt[x].store(0, std::memory_order_relaxed);
     std::atomic<int> gen_fail{0};
@@ -273,13 +334,16 @@ std::string build_tables(const dbsim_desc& desc, const Plan& p, unsigned threads
         std::vector<uint8_t> dl(kmax);
         std::vector<unsigned char> scratch(scratch_bytes);
         for (uint64_t i = a; i < b; i++) {
-            const int64_t k = dbnet_in_edges(&d, (uint32_t)i, src.data(), nullptr, nullptr, dl.data(), scratch.data());
+            const uint32_t m = mem.member_of(i);
+            const uint64_t base = mem.nbase[m];
+            const int64_t k = dbnet_in_edges(&mem.m[m], (uint32_t)(i - base), src.data(), nullptr, nullptr, dl.data(),
+                                             scratch.data());
             if (k < 0) {
                 gen_fail.store(1);
                 return;
             }
             for (int64_t e = 0; e < k; e++)
-                cnt[(size_t)src[e] * D + dl[e] - 1].fetch_add(1, std::memory_order_relaxed);
+                cnt[(size_t)(src[e] + base) * D + dl[e] - 1].fetch_add(1, std::memory_order_relaxed);
         }
     });
     if (gen_fail.load()) return "network generator failed";
@@ -313,13 +377,16 @@ std::string build_tables(const dbsim_desc& desc, const Plan& p, unsigned threads
         std::vector<uint8_t> dl(kmax);
         std::vector<unsigned char> scratch(scratch_bytes);
         for (uint64_t i = a; i < b; i++) {
-            const int64_t k = dbnet_in_edges(&d, (uint32_t)i, src.data(), w0.data(), w1.data(), dl.data(), scratch.data());
+            const uint32_t m = mem.member_of(i);
+            const uint64_t base = mem.nbase[m];
+            const int64_t k = dbnet_in_edges(&mem.m[m], (uint32_t)(i - base), src.data(), w0.data(), w1.data(),
+                                             dl.data(), scratch.data());
             if (k < 0) {
                 gen_fail.store(1);
                 return;
             }
             for (int64_t e = 0; e < k; e++) {
-                const uint64_t pos = cur[(size_t)src[e] * D + dl[e] - 1].fetch_add(1, std::memory_order_relaxed);
+                const uint64_t pos = cur[(size_t)(src[e] + base) * D + dl[e] - 1].fetch_add(1, std::memory_order_relaxed);
                 h.col[pos] = (uint32_t)i;
                 h.w[pos * KW] = w0[e];
                 if (KW == 2) h.w[pos * KW + 1] = w1[e];

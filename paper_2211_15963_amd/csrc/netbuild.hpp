@@ -1,4 +1,10 @@
-// netbuild.hpp - host-side construction of the device tables from a description.
+// netbuild.hpp - host-side construction of the device tables from descriptions.
+//
+// A handle simulates one network or an ensemble of independent networks
+// ("members"). Members are laid out one after another: member m owns global
+// neuron ids nbase[m] .. nbase[m+1]-1, populations pbase[m].., regions rbase[m]..
+// Edges never cross members, and each member keeps its own seed and noise
+// stream, so its results do not depend on the other members.
 #pragma once
 
 #include <cstdint>
@@ -11,31 +17,47 @@
 
 namespace dbs {
 
-// Sizes derived from a description without generating the network.
+// Deep copies of the member descriptions (the dbnet_desc pointers point into them).
+struct Members {
+    std::vector<dbnet_desc> m;
+    std::vector<std::vector<dbnet_pop>> pops;
+    std::vector<std::vector<dbnet_proj>> projs;
+    std::vector<std::vector<float>> xyz;
+    std::vector<uint64_t> nbase; // [M+1] first global neuron of each member
+    std::vector<uint32_t> pbase; // [M+1] first global population
+    std::vector<uint32_t> rbase; // [M+1] first global region
+    void assign(const dbnet_desc* descs, uint32_t n);
+    uint32_t member_of(uint64_t i) const;
+};
+
+// Sizes derived from the descriptions without generating the networks.
 struct Plan {
     uint32_t N = 0, U = 0, KW = 0, S = 0, D = 0, F = 0;
-    uint32_t tile_bits = 0, T = 0, n_blocks = 0, n_regions = 0, n_pops = 0;
-    uint32_t MB = 0;   // bins kept in the per-bin rings (power of two)
-    uint32_t n_l1 = 0; // level-1 readout groups (256 neuron blocks each, per region)
+    uint32_t tile_bits = 0, T = 0, n_blocks = 0, n_regions = 0, n_pops = 0, n_members = 0;
+    uint32_t MB = 0;    // bins kept in the per-bin rings (power of two)
+    uint32_t n_l1 = 0;  // level-1 readout groups (256 neuron blocks each, per region)
     uint32_t n_grp = 0; // compaction groups (256 consecutive neuron blocks each)
     uint32_t TG = 0;    // tiles per tile group
     uint32_t round_events = 0, scatter_wgs_per_cu = 0;
-    uint64_t RC = 0;   // spike-history ring entries (power of two)
-    uint64_t E = 0;    // edges
+    uint64_t RC = 0; // spike-history ring entries (power of two)
+    uint64_t E = 0;  // edges
     bool regions_on = false;
     // byte offsets of every device array inside one allocation
     struct Slot {
         size_t off = 0, bytes = 0;
     };
-    Slot V, J, ref, pend, A, pops, ptab, blk, row_ptr, seg, col, w, src_inh, ev, tile_base, tile_fill, sq, stage, grp_cnt, rec,
-        bin_start, bin_cnt, blk_sig, blk_cnt, reg_blk_ptr, reg_blk, reg_size, l1_ptr, l1_region, l1_sig, l1_cnt, sig,
-        sig_cnt, ctl;
+    Slot V, J, ref, pend, A, pops, ptab, blk, row_ptr, seg, col, w, src_inh, ev, tile_base, tile_fill, sq, stage,
+        grp_cnt, rec, bin_start, bin_cnt, blk_sig, blk_cnt, reg_blk_ptr, reg_blk, reg_size, l1_ptr, l1_region, l1_sig,
+        l1_cnt, sig, sig_cnt, ctl;
     size_t total = 0;
 };
 
-// Validates the description for this simulator and fills the plan.
+// Largest multiple of 1024 events a scatter round can stage in LDS (0 if none fits).
+uint32_t max_round_events(uint32_t TG, uint32_t wgs_per_cu);
+
+// Validates the runtime options and the members for this simulator and fills the plan.
 // Returns an empty string on success, else the reason.
-std::string make_plan(const dbsim_desc& d, Plan& p);
+std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p);
 
 // Host images of every device table.
 struct HostTables {
@@ -53,8 +75,8 @@ struct HostTables {
     std::vector<uint32_t> reg_blk_ptr, reg_blk, reg_size, l1_ptr, l1_region;
 };
 
-// Generates the network (threads: 0 = all cores) and builds every host table.
+// Generates the networks (threads: 0 = all cores) and builds every host table.
 // Returns an empty string on success, else the reason.
-std::string build_tables(const dbsim_desc& d, const Plan& p, unsigned threads, HostTables& h);
+std::string build_tables(const Members& mem, const Plan& p, unsigned threads, HostTables& h);
 
 } // namespace dbs

@@ -50,7 +50,18 @@ class SimStats(Structure):
 class SimInfo(Structure):
     _fields_ = [("num_neurons", c_uint64), ("num_edges", c_uint64), ("receptors", c_uint32),
                 ("weights_per_edge", c_uint32), ("steps_per_bin", c_uint32), ("max_delay", c_uint32),
-                ("n_regions", c_uint32), ("tile_neurons", c_uint32), ("n_tiles", c_uint32), ("frac_bits", c_uint32)]
+                ("n_regions", c_uint32), ("tile_neurons", c_uint32), ("n_tiles", c_uint32), ("frac_bits", c_uint32),
+                ("n_members", c_uint32)]
+
+
+class SimMember(Structure):
+    _fields_ = [("first_neuron", c_uint64), ("num_neurons", c_uint64), ("first_region", c_uint32),
+                ("num_regions", c_uint32)]
+
+
+class SimTuning(Structure):
+    _fields_ = [("scatter_wgs_per_cu", c_uint32), ("round_events", c_uint32), ("chunks_per_wg", c_uint32),
+                ("reserved", c_uint32)]
 
 
 class DbsimError(RuntimeError):
@@ -62,6 +73,8 @@ class DbsimError(RuntimeError):
 _LIB = None
 
 EXPORTED = ["dbsim_abi_version", "dbsim_last_error", "dbsim_create", "dbsim_footprint", "dbsim_get_info",
+            "dbsim_create_ensemble", "dbsim_footprint_ensemble", "dbsim_member_info", "dbsim_get_tuning",
+            "dbsim_set_tuning",
             "dbsim_step", "dbsim_sync", "dbsim_read_spikes", "dbsim_read_region_signal", "dbsim_read_state",
             "dbsim_write_state", "dbsim_export_csr", "dbsim_set_timing", "dbsim_get_stats", "dbsim_destroy"]
 
@@ -86,6 +99,11 @@ def lib():
     L.dbsim_create.argtypes = [POINTER(SimDesc), POINTER(c_void_p)]
     L.dbsim_footprint.argtypes = [POINTER(SimDesc), POINTER(c_uint64)]
     L.dbsim_get_info.argtypes = [H, POINTER(SimInfo)]
+    L.dbsim_create_ensemble.argtypes = [POINTER(SimDesc), POINTER(Desc), c_uint32, POINTER(c_void_p)]
+    L.dbsim_footprint_ensemble.argtypes = [POINTER(SimDesc), POINTER(Desc), c_uint32, POINTER(c_uint64)]
+    L.dbsim_member_info.argtypes = [H, c_uint32, POINTER(SimMember)]
+    L.dbsim_get_tuning.argtypes = [H, POINTER(SimTuning)]
+    L.dbsim_set_tuning.argtypes = [H, POINTER(SimTuning)]
     L.dbsim_step.argtypes = [H, c_uint64]
     L.dbsim_sync.argtypes = [H]
     L.dbsim_read_spikes.argtypes = [H, c_uint64, c_uint64, POINTER(c_uint64), POINTER(c_uint32), c_uint64,
@@ -161,18 +179,35 @@ def make_desc(spec: NetSpec, record_regions: bool = True, spike_record_capacity:
     return d, holder
 
 
-def footprint(spec: NetSpec, record_regions: bool = True, **kw) -> int:
-    d, holder = make_desc(spec, record_regions=record_regions, **kw)
+def _member_array(specs):
+    holders = [sp.to_c() for sp in specs]
+    arr = (Desc * len(holders))()
+    for k, h in enumerate(holders):
+        arr[k] = h.desc
+    return arr, holders
+
+
+def footprint(spec, record_regions: bool = True, **kw) -> int:
+    """Device bytes for one network (NetSpec) or an ensemble (list of NetSpec)."""
     out = c_uint64(0)
-    _check(lib().dbsim_footprint(byref(d), byref(out)))
+    if isinstance(spec, (list, tuple)):
+        d, holder = make_desc(spec[0], record_regions=record_regions, **kw)
+        arr, holders = _member_array(spec)
+        _check(lib().dbsim_footprint_ensemble(byref(d), arr, len(spec), byref(out)))
+    else:
+        d, holder = make_desc(spec, record_regions=record_regions, **kw)
+        _check(lib().dbsim_footprint(byref(d), byref(out)))
     return int(out.value)
 
 
 class Simulator:
-    """One network instance on one GPU, driven through the C ABI.
+    """One network (a NetSpec) or an ensemble (a list of NetSpec) on one GPU, driven
+    through the C ABI.
 
     use_torch: take device memory from torch's caching allocator and queue work on
     torch's current HIP stream (otherwise the library uses hipMalloc and its own stream).
+    For an ensemble, reads return global neuron ids; member(m) gives each member's
+    id range and member_spikes / member_state its own view.
     """
 
     def __init__(self, spec: NetSpec, record_regions: bool = True, use_torch: bool = True, device: int = 0,
@@ -193,10 +228,16 @@ class Simulator:
             st = stream if stream is not None else torch.cuda.current_stream(device)
             stream_handle = int(st.cuda_stream) or None
             self._alloc = _TorchAllocator(device, int(st.cuda_stream))
-        self._desc, self._holder = make_desc(spec, record_regions, spike_record_capacity, record_bins, device,
+        self.specs = list(spec) if isinstance(spec, (list, tuple)) else [spec]
+        first = self.specs[0]
+        self._desc, self._holder = make_desc(first, record_regions, spike_record_capacity, record_bins, device,
                                              stream_handle, self._alloc, host_threads, no_graph)
         h = c_void_p()
-        _check(L.dbsim_create(byref(self._desc), byref(h)))
+        if isinstance(spec, (list, tuple)):
+            self._members, self._member_holders = _member_array(self.specs)
+            _check(L.dbsim_create_ensemble(byref(self._desc), self._members, len(self.specs), byref(h)))
+        else:
+            _check(L.dbsim_create(byref(self._desc), byref(h)))
         self._h = h
         info = SimInfo()
         _check(L.dbsim_get_info(h, byref(info)))
@@ -233,6 +274,16 @@ class Simulator:
     def set_timing(self, on: bool) -> None:
         _check(lib().dbsim_set_timing(self._h, 1 if on else 0))
 
+    def tuning(self) -> dict:
+        t = SimTuning()
+        _check(lib().dbsim_get_tuning(self._h, byref(t)))
+        return {"scatter_wgs_per_cu": t.scatter_wgs_per_cu, "round_events": t.round_events,
+                "chunks_per_wg": t.chunks_per_wg}
+
+    def set_tuning(self, scatter_wgs_per_cu: int = 1, round_events: int = 0, chunks_per_wg: int = 2) -> None:
+        t = SimTuning(int(scatter_wgs_per_cu), int(round_events), int(chunks_per_wg), 0)
+        _check(lib().dbsim_set_tuning(self._h, byref(t)))
+
     def spikes(self, step_lo: int = 0, step_hi: Optional[int] = None):
         """(steps uint64, ids uint32) of completed bins, sorted by (step, id)."""
         hi = (1 << 63) if step_hi is None else int(step_hi)
@@ -246,8 +297,26 @@ class Simulator:
         _check(lib().dbsim_read_spikes(self._h, int(step_lo), hi, _p(st, c_uint64), _p(ids, c_uint32), cap, byref(n)))
         return st[: n.value], ids[: n.value]
 
+    def member(self, m: int):
+        """(first global neuron id, neurons, first global region, regions) of member m."""
+        mi = SimMember()
+        _check(lib().dbsim_member_info(self._h, int(m), byref(mi)))
+        return int(mi.first_neuron), int(mi.num_neurons), int(mi.first_region), int(mi.num_regions)
+
+    def member_spikes(self, m: int, step_lo: int = 0, step_hi: Optional[int] = None):
+        """Spikes of member m with member-local neuron ids."""
+        a, n, _, _ = self.member(m)
+        st, ids = self.spikes(step_lo, step_hi)
+        sel = (ids >= a) & (ids < a + n)
+        return st[sel], (ids[sel] - a).astype(np.uint32)
+
+    def member_state(self, m: int):
+        a, n, _, _ = self.member(m)
+        V, J, ref = self.state()
+        return V[a:a + n], J[:, a:a + n], ref[a:a + n]
+
     def region_signal(self, bin_lo: int = 0, bin_hi: Optional[int] = None):
-        R = self.spec.n_regions
+        R = int(self.info.n_regions)
         hi = (self.steps_done // self.S) if bin_hi is None else int(bin_hi)
         nb = max(0, hi - int(bin_lo))
         sig = np.zeros(max(nb * R, 1), np.float64)

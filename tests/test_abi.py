@@ -53,7 +53,8 @@ int main(void) {
   P(dbnet_pop); P(dbnet_proj); P(dbnet_desc); P(dbsim_desc); P(dbsim_stats); P(dbsim_info);
   O(dbnet_desc, seed); O(dbnet_desc, pops); O(dbnet_desc, region_xyz_mm);
   O(dbsim_desc, net); O(dbsim_desc, spike_record_capacity); O(dbsim_desc, hip_stream); O(dbsim_desc, flags);
-  O(dbsim_stats, ms_scatter); O(dbsim_stats, build_seconds); O(dbsim_info, frac_bits);
+  O(dbsim_stats, ms_scatter); O(dbsim_stats, build_seconds); O(dbsim_info, frac_bits); O(dbsim_info, n_members);
+  P(dbsim_member); O(dbsim_member, first_region);
   return 0;
 }
 """
@@ -79,6 +80,9 @@ def test_struct_layouts_match_ctypes(L):
     assert int(out["dbsim_desc.flags"]) == D.SimDesc.flags.offset
     assert int(out["dbsim_stats.ms_scatter"]) == D.SimStats.ms_scatter.offset
     assert int(out["dbsim_info.frac_bits"]) == D.SimInfo.frac_bits.offset
+    assert int(out["dbsim_info.n_members"]) == D.SimInfo.n_members.offset
+    assert int(out["dbsim_member"]) == ctypes.sizeof(D.SimMember)
+    assert int(out["dbsim_member.first_region"]) == D.SimMember.first_region.offset
 
 
 def _create(L, spec, **kw):
@@ -125,3 +129,14 @@ def test_footprint_matches_layout(L):
     # dominant terms: targets (4 B), two weights (8 B) and the event arena record (12 B) per edge
     assert 24 * E < fp < 24 * E + 60 * 100000 + (64 << 20)
     assert D.footprint(configs.tiny()) < 24 << 20   # mostly the default 2^22-entry spike history
+
+
+def test_ensemble_footprint_and_validation(L):
+    from paper_2211_15963_amd import dbsim as D
+    a = configs.share(n=20000, indegree=100, seed=1)
+    b = configs.share(n=30000, indegree=200, seed=2)
+    fa, fb, fab = D.footprint(a), D.footprint(b), D.footprint([a, b])
+    assert fab > max(fa, fb)
+    c = configs.tiny()   # two receptors: cannot share kernels with four-receptor members
+    with pytest.raises(D.DbsimError, match="share dt_ms"):
+        D.footprint([a, c])
