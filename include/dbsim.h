@@ -80,6 +80,9 @@ typedef struct dbsim_desc {
 
 /* flags */
 #define DBSIM_F_NO_GRAPH 1u /* launch kernels directly instead of replaying HIP graphs */
+#define DBSIM_F_TWO_PASS 2u /* fan-in through super-tile streams even where the tiles fit the
+                               single-pass write-combining buffers (same results; for tests
+                               and comparisons) */
 
 typedef struct dbsim_stats {
     uint64_t steps;        /* Euler steps completed (queued) */
@@ -108,6 +111,7 @@ typedef struct dbsim_info {
     uint32_t n_tiles;
     uint32_t frac_bits;        /* F of the fixed-point arrival sums */
     uint32_t n_members;        /* networks in the handle (1 unless an ensemble) */
+    uint32_t fanin_passes;     /* 1: single-pass write-combined fan-in, 2: through super-tile streams */
 } dbsim_info;
 
 typedef struct dbsim_member {
@@ -209,14 +213,15 @@ int dbsim_export_csr(struct dbsim* h, uint64_t* row_ptr, uint32_t* seg, uint32_t
                      float* w1);
 
 /*
- * Launch schedule of the fan-in scatter kernel. Any valid schedule gives
+ * Launch schedule of the fan-in partition kernels. Any valid schedule gives
  * bit-identical results (the arrival sums are exact integers); it only changes
  * speed, so an autotuner may try schedules on a live handle.
  */
 typedef struct dbsim_tuning {
-    uint32_t scatter_wgs_per_cu; /* 1 or 2 resident scatter workgroups per CU (they split the LDS) */
-    uint32_t round_events;       /* events staged in LDS per round, multiple of 1024; 0 = the most that fit */
-    uint32_t chunks_per_wg;      /* target (spike, delay) chunks per scatter workgroup per bin, 1..64 */
+    uint32_t scatter_wgs_per_cu; /* 1..8 partition workgroups per CU (they split the LDS) */
+    uint32_t round_events;       /* events staged in LDS per round, multiple of 256, at most 2048;
+                                    0 = the most that fit */
+    uint32_t chunks_per_wg;      /* target (spike, delay) chunks per partition workgroup per bin, 1..64 */
     uint32_t reserved;
 } dbsim_tuning;
 

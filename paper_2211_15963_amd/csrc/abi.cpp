@@ -99,7 +99,10 @@ void fill_devnet(dbsim* h) {
     n.D = p.D;
     n.F = p.F;
     n.tile_bits = p.tile_bits;
-    n.TG = p.TG;
+    n.wc = p.wc ? 1u : 0u;
+    n.NS = p.NS;
+    n.ts_bits = p.ts_bits;
+    n.HW = p.HW;
     n.round_events = p.round_events;
     n.chunks_per_wg = 2;
     n.T = p.T;
@@ -118,15 +121,15 @@ void fill_devnet(dbsim* h) {
     n.pops = at<const PopParams>(b, p.pops);
     n.ptab = at<const uint32_t>(b, p.ptab);
     n.blk = at<const uint2>(b, p.blk);
-    n.row_ptr = at<const uint64_t>(b, p.row_ptr);
-    n.seg = at<const uint32_t>(b, p.seg);
+    n.hdr = at<const uint32_t>(b, p.hdr);
     n.col = at<const uint32_t>(b, p.col);
     n.w = at<const float>(b, p.w);
-    n.src_inh = at<const uint8_t>(b, p.src_inh);
     n.ev = at<uint32_t>(b, p.ev);
     n.tile_base = at<const uint64_t>(b, p.tile_base);
     n.tile_fill = at<uint32_t>(b, p.tile_fill);
-    n.sq = at<uint32_t>(b, p.sq);
+    n.st_base = at<const uint64_t>(b, p.st_base);
+    n.st_fill = at<uint32_t>(b, p.st_fill);
+    n.sev = at<uint32_t>(b, p.sev);
     n.stage = at<uint32_t>(b, p.stage);
     n.grp_cnt = at<uint32_t>(b, p.grp_cnt);
     n.n_grp = p.n_grp;
@@ -367,14 +370,13 @@ static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32
         if (e == hipSuccess) e = up(p.pops, ht.pops.data(), sizeof(PopParams) * ht.pops.size());
         if (e == hipSuccess) e = up(p.ptab, ht.ptab.data(), 4 * ht.ptab.size());
         if (e == hipSuccess) e = up(p.blk, ht.blk.data(), sizeof(uint2) * ht.blk.size());
-        if (e == hipSuccess) e = up(p.row_ptr, ht.row_ptr.data(), 8 * ht.row_ptr.size());
-        if (e == hipSuccess) e = up(p.seg, ht.seg_dg.data(), 4 * ht.seg_dg.size());
+        if (e == hipSuccess) e = up(p.hdr, ht.hdr.data(), 4 * ht.hdr.size());
+        if (e == hipSuccess) e = up(p.st_base, ht.st_base.data(), 8 * ht.st_base.size());
+        if (e == hipSuccess) e = hipMemset(h->dev + p.st_fill.off, 0, p.st_fill.bytes);
         if (e == hipSuccess) e = up(p.col, ht.col.data(), 4 * ht.col.size());
         if (e == hipSuccess) e = up(p.w, ht.w.data(), 4 * ht.w.size());
-        if (e == hipSuccess) e = up(p.src_inh, ht.src_inh.data(), ht.src_inh.size());
         if (e == hipSuccess) e = up(p.tile_base, ht.tile_base.data(), 8 * ht.tile_base.size());
         if (e == hipSuccess) e = hipMemset(h->dev + p.tile_fill.off, 0, p.tile_fill.bytes);
-        if (e == hipSuccess) e = hipMemset(h->dev + p.sq.off, 0, p.sq.bytes);
         if (e == hipSuccess) e = hipMemset(h->dev + p.grp_cnt.off, 0, p.grp_cnt.bytes);
         if (e == hipSuccess) e = hipMemset(h->dev + p.bin_start.off, 0, p.bin_start.bytes);
         if (e == hipSuccess) e = hipMemset(h->dev + p.bin_cnt.off, 0, p.bin_cnt.bytes);
@@ -399,7 +401,7 @@ static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) h->num_cus = prop.multiProcessorCount;
         h->scatter_wgs = p.scatter_wgs_per_cu;
-        h->scatter_grid = (int)h->scatter_wgs * h->num_cus;
+        h->scatter_grid = std::min((int)kMaxPartGrid, (int)h->scatter_wgs * h->num_cus);
         *out = h;
         return DBSIM_OK;
     } catch (const std::bad_alloc&) {
@@ -450,6 +452,7 @@ int dbsim_get_info(dbsim* h, dbsim_info* info) {
     info->n_tiles = p.T;
     info->frac_bits = p.F;
     info->n_members = p.n_members;
+    info->fanin_passes = p.wc ? 1u : 2u;
     return DBSIM_OK;
 }
 
@@ -638,13 +641,16 @@ int dbsim_export_csr(dbsim* h, uint64_t* row_ptr, uint32_t* seg, uint32_t* tgt, 
     rc = sync_and_check(h);
     if (rc) return rc;
     const Plan& p = h->plan;
-    if (row_ptr) HIPCHK(h, hipMemcpy(row_ptr, h->net.row_ptr, 8 * ((size_t)p.N + 1), hipMemcpyDeviceToHost), "hipMemcpy");
-    if (seg) {
-        const size_t DG1 = (size_t)p.D * kTileGroups + 1;
-        std::vector<uint32_t> dg((size_t)p.N * DG1);
-        HIPCHK(h, hipMemcpy(dg.data(), h->net.seg, 4 * dg.size(), hipMemcpyDeviceToHost), "hipMemcpy");
-        for (size_t j = 0; j < p.N; j++)
-            for (size_t d = 0; d <= p.D; d++) seg[j * (p.D + 1) + d] = dg[j * DG1 + d * kTileGroups];
+    if (row_ptr || seg) { // unpacked from the row headers
+        std::vector<uint32_t> hd((size_t)p.N * p.HW);
+        HIPCHK(h, hipMemcpy(hd.data(), h->net.hdr, 4 * hd.size(), hipMemcpyDeviceToHost), "hipMemcpy");
+        for (size_t j = 0; j < p.N; j++) {
+            const uint32_t* hp = &hd[j * p.HW];
+            if (row_ptr) row_ptr[j] = ((uint64_t)(hp[1] & 0x7FFFFFFFu) << 32) | hp[0];
+            if (seg)
+                for (size_t x = 0; x <= p.D; x++) seg[j * (p.D + 1) + x] = hp[2 + x];
+        }
+        if (row_ptr) row_ptr[p.N] = p.E;
     }
     if (tgt) HIPCHK(h, hipMemcpy(tgt, h->net.col, 4 * p.E, hipMemcpyDeviceToHost), "hipMemcpy");
     if (w0 || w1) {
@@ -671,17 +677,17 @@ int dbsim_set_tuning(dbsim* h, const dbsim_tuning* t) {
     int rc = check_usable(h);
     if (rc) return rc;
     if (!t) return fail(DBSIM_EINVAL, "null argument");
-    if (t->scatter_wgs_per_cu < 1 || t->scatter_wgs_per_cu > 2) return fail(DBSIM_EINVAL, "scatter_wgs_per_cu must be 1 or 2");
+    if (t->scatter_wgs_per_cu < 1 || t->scatter_wgs_per_cu > 8) return fail(DBSIM_EINVAL, "scatter_wgs_per_cu must lie in 1..8");
     if (t->chunks_per_wg < 1 || t->chunks_per_wg > 64) return fail(DBSIM_EINVAL, "chunks_per_wg must lie in 1..64");
-    const uint32_t rmax = max_round_events(h->plan.TG, t->scatter_wgs_per_cu);
+    const uint32_t rmax = max_round_events(h->plan, t->scatter_wgs_per_cu);
     if (rmax == 0) return fail(DBSIM_EINVAL, "this schedule does not fit the LDS");
     const uint32_t re = t->round_events ? t->round_events : rmax;
-    if (re % 1024 || re > rmax) return fail(DBSIM_EINVAL, "round_events must be a multiple of 1024 that fits the LDS");
+    if (re % 256 || re > rmax) return fail(DBSIM_EINVAL, "round_events must be a multiple of 256 that fits the LDS");
     DeviceGuard dg(h->device);
     rc = sync_and_check(h);
     if (rc) return rc;
     h->scatter_wgs = t->scatter_wgs_per_cu;
-    h->scatter_grid = (int)h->scatter_wgs * h->num_cus;
+    h->scatter_grid = std::min((int)kMaxPartGrid, (int)h->scatter_wgs * h->num_cus);
     h->net.round_events = re;
     h->net.chunks_per_wg = t->chunks_per_wg;
     if (h->g_multi) (void)hipGraphExecDestroy(h->g_multi);

@@ -10,15 +10,18 @@
 //     uniform (scalar registers);
 //   connection table by presynaptic neuron (Suppl. Table 5's table is stored
 //     by target; the push-based fan-out of Suppl. Algorithm 2 wants it by
-//     source): row_ptr u64[N+1], seg u32[N][D*G+1] (offsets of the (delay,
-//     tile group) sub-segments inside the row; rows are sorted by delay, then
-//     target, so groups of consecutive tiles are contiguous), col u32[E]
-//     (target), w f32[KW][E] interleaved per edge, src_inh u8[N];
-//   event arena for the bucketed fan-in: records of 1 + KW words (target within
-//     its tile | source class << 31, then the weights); tile t owns the slice
-//     tile_base[t] .. tile_base[t+1] whose length is the tile's total in-degree,
-//     the most events a tile can receive in one bin (an edge delivers at most
-//     once per bin);
+//     source): col u32[E] (target), w f32[KW][E] interleaved per edge, rows
+//     sorted by delay, then target; one row header per neuron, hdr u32[N][HW]
+//     (HW = D + 3 rounded up to 4 words: the row start as u64 with the source
+//     class in bit 63, then the D + 1 delay segment offsets inside the row), so
+//     that one 64-byte read gives everything a (spike, delay) segment needs;
+//   the event arena of the fan-in: records of 1 + KW words (target | source
+//     class << 31, then the weights); tile t owns the slice tile_base[t] ..
+//     tile_base[t+1]: the tile's total in-degree (the most events a tile can
+//     receive in one bin: an edge delivers at most once per bin), plus, when
+//     k_part writes whole chunks, kChunk records of padding per partition
+//     workgroup; the super-tile streams of the two-pass form use the same
+//     record format;
 //   spike history: rec u32[RC] ring of (id << 4 | substep), per-bin start u64[MB]
 //     and count u32[MB] (rings indexed by bin & (MB-1));
 //   region readout: per-block partial sums f64/u32, per-region block lists,
@@ -36,14 +39,18 @@ namespace dbs {
 
 constexpr int kMaxPoisson = 64;       // Poisson thresholds per population
 constexpr int kNeuronBlock = 256;     // neurons per block of the neuron kernel
-constexpr int kScatterThreads = 1024; // threads per block of the scatter kernel
-constexpr int kScatterSegs = 1024;    // (spike, delay) segments per scatter chunk
+constexpr int kScatterThreads = 256;  // threads per block of the partition kernels (several blocks per CU)
+constexpr int kScatterSegs = 256;     // (spike, delay) segments per partition chunk (one per thread)
 constexpr int kGatherThreads = 1024;
-constexpr int kMaxTilesLds = 16384;   // tile histogram must fit in LDS
+constexpr int kMaxTilesLds = 16384;   // most tiles (at most 256 buckets in the second partition pass)
 constexpr uint32_t kTileLdsBytes = 128u * 1024u; // LDS accumulator per tile
 constexpr uint32_t kErrArena = 1u;    // arena slice overflow (cannot happen by construction)
 constexpr uint32_t kErrLayout = 2u;   // a table entry outside its tile group (cannot happen by construction)
-constexpr uint32_t kTileGroups = 8;   // target tile groups (one per XCC of an MI355X)
+constexpr uint32_t kMaxSuperTiles = 64; // buckets of the first partition pass
+constexpr int kLoadBatch = 8;          // gather: records loaded per thread before they are consumed
+constexpr int kMaxBatch = 8;           // partition: events per thread per round (round_events <= 2048)
+constexpr uint32_t kChunk = 16;        // records per write-combined tile chunk (192 B with two weights)
+constexpr uint32_t kMaxPartGrid = 2048; // most partition workgroups (bounds the chunk padding per tile)
 constexpr uint32_t kMaxLdsBytes = 160u * 1024u;
 
 struct PopParams {
@@ -70,8 +77,11 @@ struct Ctl {
 struct DevNet {
     uint32_t N, U, KW, S, D, F;
     uint32_t tile_bits, T, n_blocks, n_regions;
-    uint32_t TG;           // tiles per tile group
-    uint32_t round_events; // events staged in LDS per scatter round
+    uint32_t wc;           // 1: k_part writes the tiles directly (write-combined chunks)
+    uint32_t NS;           // super-tiles (buckets of k_part when wc == 0)
+    uint32_t ts_bits;      // log2(tiles per super-tile)
+    uint32_t HW;           // words per row header
+    uint32_t round_events; // events staged in LDS per partition round
     uint32_t chunks_per_wg; // target scatter chunks per workgroup and bin
     uint64_t RCmask;
     uint32_t MBmask;
@@ -89,16 +99,16 @@ struct DevNet {
     const uint32_t* ptab;
     const uint2* blk; // (first neuron, population)
     // connection table
-    const uint64_t* row_ptr;
-    const uint32_t* seg;
+    const uint32_t* hdr; // [N][HW] row headers
     const uint32_t* col;
     const float* w;
-    const uint8_t* src_inh;
     // event arena: records of (1 + KW) words: target within tile | source class << 31, weights
     uint32_t* ev;
     const uint64_t* tile_base;
     uint32_t* tile_fill;
-    uint32_t* sq; // per-group chunk queues of the scatter (reset by the gather)
+    const uint64_t* st_base; // super-tile stream slices [NS + 1]
+    uint32_t* st_fill;       // records written per super-tile this bin (reset by the gather)
+    uint32_t* sev;           // super-tile stream records (same format as ev)
     // spikes: per-block staging (256 slots per neuron block), per-group counts (two bin
     // parities x groups of 256 blocks), then the dense history ring
     uint32_t* stage;
@@ -130,8 +140,8 @@ hipError_t launch_gather(const DevNet& n, hipStream_t st);
 hipError_t launch_neuron(const DevNet& n, int s0, int s1, hipStream_t st);
 hipError_t launch_compact(const DevNet& n, hipStream_t st);
 hipError_t launch_readout_close(const DevNet& n, hipStream_t st);
-size_t scatter_lds_bytes(const DevNet& n);
-size_t scatter_fixed_lds(uint32_t TG);
+size_t part_lds_bytes(uint32_t nb, uint32_t RE, bool wc, uint32_t D);
+size_t bucket_lds_bytes(uint32_t TS, uint32_t RE);
 size_t gather_lds_bytes(const DevNet& n);
 
 } // namespace dbs

@@ -1,13 +1,16 @@
 // kernels.hip - gfx950 kernels of one spike bin.
 //
 // Per bin k (S Euler steps of dt, SI Section 3):
-//   k_scatter  fan-in of the arrivals due at the start of bin k. Every spike j
-//              of bin k-d (d = 1..D) contributes its delay-d edges (Suppl.
-//              Algorithm 2 pushes a spike list through destination lists;
-//              here the delay ring is read backwards, so all events of a bin
-//              land in one accumulator). Events are bucketed by target tile
-//              into a per-tile arena slice, one reservation atomic per
-//              (chunk, tile) instead of one global atomic per event.
+//   k_part     fan-in of the arrivals due at the start of bin k, pass A. Every
+//              spike j of bin k-d (d = 1..D) contributes its delay-d edges (Suppl.
+//              Algorithm 2 pushes a spike list through destination lists; here
+//              the delay ring is read backwards, so all events of a bin land in
+//              one accumulator). Whole delay segments are read (contiguous table
+//              reads) and their events are partitioned into at most 64
+//              super-tile streams through LDS: one reservation per non-empty
+//              super-tile per round instead of one global atomic per event.
+//   k_bucket   pass B: each super-tile stream is partitioned into its tiles the
+//              same way (skipped when every super-tile is a single tile).
 //   k_gather   one workgroup per tile: sums its events in LDS as int64 fixed
 //              point (exact, so any order gives the same bits), converts once
 //              to float, writes A.
@@ -97,13 +100,9 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
 
 } // namespace
 
-// ------------------------------------------------------------------ scatter
+// ------------------------------------------------------------------ fan-in partition
 
 namespace {
-
-// XCC (accelerator complex die) this wavefront runs on; used only to pick which tile
-// group a workgroup serves first, never for correctness.
-__device__ __forceinline__ uint32_t xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20); }
 
 // exclusive scan of v[0..n) in place (n <= 2 * blockDim.x), returns the total
 __device__ uint32_t block_scan_inplace(uint32_t* v, uint32_t n, uint32_t* s_wave) {
@@ -116,174 +115,479 @@ __device__ uint32_t block_scan_inplace(uint32_t* v, uint32_t n, uint32_t* s_wave
     return tot;
 }
 
-} // namespace
+// bump allocator over the dynamic LDS (host and device compute the same offsets)
+struct LdsLayout {
+    size_t off = 0;
+    __host__ __device__ size_t take(size_t bytes, size_t align) {
+        off = (off + align - 1) & ~(align - 1);
+        const size_t o = off;
+        off += bytes;
+        return o;
+    }
+};
 
-// Fan-in of the arrivals due at the start of bin k (see the file header). Targets are
-// split into kTileGroups groups of consecutive tiles; every (spike, delay) segment of a
-// row is further split by group (rows are sorted by delay, then target). Work items are
-// (group, chunk of segments) taken from one queue per group; a workgroup serves the group
-// of its own XCC first (its arena writes then stay in that XCC's L2) and then helps the
-// others, so the bin completes whatever the placement. Each chunk is processed in rounds
-// that stage the events in LDS, sort them by tile, reserve one slice per non-empty tile
-// and write the records out in runs of consecutive addresses.
-__global__ void __launch_bounds__(kScatterThreads) k_scatter(DevNet net) {
-    extern __shared__ __align__(16) unsigned char dyn[];
-    const uint32_t D = net.D, G = kTileGroups, TG = net.TG, RE = net.round_events;
-    unsigned char* p = dyn;
-    unsigned long long* s_dpre = reinterpret_cast<unsigned long long*>(p); p += 8 * (DBNET_MAX_DELAY + 1);
-    unsigned long long* s_dstart = reinterpret_cast<unsigned long long*>(p); p += 8 * DBNET_MAX_DELAY;
-    unsigned long long* s_sstart = reinterpret_cast<unsigned long long*>(p); p += 8 * kScatterSegs;
-    unsigned long long* gbase = reinterpret_cast<unsigned long long*>(p); p += 8 * ((TG + 1) & ~1u);
-    float2* r_w = reinterpret_cast<float2*>(p); p += 8 * RE;
-    uint32_t* r_col = reinterpret_cast<uint32_t*>(p); p += 4 * RE;
-    uint32_t* s_spre = reinterpret_cast<uint32_t*>(p); p += 4 * (kScatterSegs + 4);
-    uint32_t* hist = reinterpret_cast<uint32_t*>(p); p += 4 * TG;
-    uint32_t* lstart = reinterpret_cast<uint32_t*>(p); p += 4 * TG;
-    uint32_t* lcur = reinterpret_cast<uint32_t*>(p); p += 4 * TG;
-    uint32_t* s_misc = reinterpret_cast<uint32_t*>(p); p += 4 * 20; // [0..15] scan scratch, [16] queue ticket
-    uint16_t* r_idx = reinterpret_cast<uint16_t*>(p); p += 2 * RE;
-    uint8_t* s_scls = reinterpret_cast<uint8_t*>(p);
+// one partition round: the round's events sorted by bucket, per-bucket counts,
+// sorted starts and reserved output positions
+struct RoundLayout {
+    size_t gbase, s_w, s_key, hist, lstart, s_wave;
+    __host__ __device__ void place(LdsLayout& L, uint32_t nb, uint32_t RE) {
+        gbase = L.take(8 * (size_t)nb, 8);
+        s_w = L.take(8 * (size_t)RE, 8);
+        s_key = L.take(4 * (size_t)RE, 4);
+        hist = L.take(4 * (size_t)nb, 4);
+        lstart = L.take(4 * (size_t)nb, 4);
+        s_wave = L.take(4 * 20, 4);
+    }
+};
 
-    const unsigned long long k = net.ctl->bin;
+// write-combining buffers: per bucket up to kChunk - 1 events carried between rounds
+struct WcLayout {
+    size_t bufw, bufk, bcnt, bc, cpre, cmap;
+    __host__ __device__ void place(LdsLayout& L, uint32_t nb, uint32_t RE) {
+        bufw = L.take(8 * (size_t)kChunk * nb, 8);
+        bufk = L.take(4 * (size_t)kChunk * nb, 4);
+        bcnt = L.take(4 * (size_t)nb, 4);
+        bc = L.take(4 * (size_t)nb, 4);
+        cpre = L.take(4 * ((size_t)nb + 1), 4);
+        cmap = L.take(2 * (2 * (size_t)nb + RE / kChunk + 1), 2);
+    }
+};
+
+struct PartLayout {
+    size_t dpre, dstart, sstart, spre, dcnt, smap, scls, total;
+    RoundLayout r;
+    WcLayout w;
+    __host__ __device__ PartLayout(uint32_t nb, uint32_t RE, bool wc, uint32_t D) {
+        LdsLayout L;
+        dpre = L.take(8 * ((size_t)D + 1), 8);
+        dstart = L.take(8 * (size_t)D, 8);
+        sstart = L.take(8 * kScatterSegs, 8);
+        r.place(L, nb, RE);
+        w = WcLayout{};
+        if (wc) w.place(L, nb, RE);
+        spre = L.take(4 * (kScatterSegs + 4), 4);
+        dcnt = L.take(4 * ((size_t)D + 1), 4);
+        smap = L.take(2 * (kScatterSegs + 2), 2);
+        scls = L.take(kScatterSegs, 1);
+        total = L.take(0, 16);
+    }
+};
+
+struct BucketLayout {
+    size_t cpre, ccnt, total;
+    RoundLayout r;
+    __host__ __device__ BucketLayout(uint32_t nb, uint32_t RE) {
+        LdsLayout L;
+        cpre = L.take(8 * (kMaxSuperTiles + 2), 8);
+        ccnt = L.take(4 * (kMaxSuperTiles + 2), 4);
+        r.place(L, nb, RE);
+        total = L.take(0, 16);
+    }
+};
+
+struct Round {
+    unsigned long long* gbase; // reserved output position of each bucket (~0 on overflow)
+    float2* s_w;               // the round's weights, sorted by bucket
+    uint32_t* s_key;           // the round's keys (target | source class << 31), sorted by bucket
+    uint32_t* hist;            // events per bucket
+    uint32_t* lstart;          // first sorted position of each bucket
+    uint32_t* s_wave;
+    __device__ void at(unsigned char* base, const RoundLayout& l) {
+        gbase = reinterpret_cast<unsigned long long*>(base + l.gbase);
+        s_w = reinterpret_cast<float2*>(base + l.s_w);
+        s_key = reinterpret_cast<uint32_t*>(base + l.s_key);
+        hist = reinterpret_cast<uint32_t*>(base + l.hist);
+        lstart = reinterpret_cast<uint32_t*>(base + l.lstart);
+        s_wave = reinterpret_cast<uint32_t*>(base + l.s_wave);
+    }
+};
+
+struct Wc {
+    float2* bufw;    // [nb][kChunk] carried weights
+    uint32_t* bufk;  // [nb][kChunk] carried keys
+    uint32_t* bcnt;  // carried events per bucket
+    uint32_t* bc;    // carried events at the start of the round
+    uint32_t* cpre;  // chunks emitted per bucket this round, exclusive prefix [nb + 1]
+    uint16_t* cmap;  // bucket of every chunk emitted this round
+    __device__ void at(unsigned char* base, const WcLayout& l) {
+        bufw = reinterpret_cast<float2*>(base + l.bufw);
+        bufk = reinterpret_cast<uint32_t*>(base + l.bufk);
+        bcnt = reinterpret_cast<uint32_t*>(base + l.bcnt);
+        bc = reinterpret_cast<uint32_t*>(base + l.bc);
+        cpre = reinterpret_cast<uint32_t*>(base + l.cpre);
+        cmap = reinterpret_cast<uint16_t*>(base + l.cmap);
+    }
+};
+
+// the events of one thread in one round, held in registers from the load to the placement
+struct Batch {
+    uint32_t key[kMaxBatch];
+    float2 w[kMaxBatch];
+    uint32_t br[kMaxBatch]; // bucket << 16 | rank within the bucket
+};
+
+__device__ __forceinline__ uint32_t bucket_of(const DevNet& net, uint32_t key, uint32_t nb, uint32_t b0, uint32_t bshift) {
+    const uint32_t b = ((key & 0x7FFFFFFFu) >> bshift) - b0;
+    return b < nb ? b : 0u;
+}
+
+// counts an event in its bucket; returns bucket << 16 | its rank among the bucket's events
+__device__ __forceinline__ uint32_t rank_event(const DevNet& net, Round& R, uint32_t key, uint32_t nb, uint32_t b0,
+                                               uint32_t bshift) {
+    uint32_t b = ((key & 0x7FFFFFFFu) >> bshift) - b0;
+    if (b >= nb) { // cannot happen for a consistent table
+        atomicOr(&net.ctl->err, kErrLayout);
+        b = 0;
+    }
+    return (b << 16) | atomicAdd(&R.hist[b], 1u);
+}
+
+// moves this thread's events of the round to their sorted LDS positions
+__device__ __forceinline__ void place_batch(Round& R, const Batch& B, uint32_t ne, uint32_t nbt) {
+#pragma unroll
+    for (int u = 0; u < kMaxBatch; u++) {
+        const uint32_t e = u * kScatterThreads + threadIdx.x;
+        if (u < (int)nbt && e < ne) {
+            const uint32_t pos = R.lstart[B.br[u] >> 16] + (B.br[u] & 0xFFFFu);
+            R.s_key[pos] = B.key[u];
+            R.s_w[pos] = B.w[u];
+        }
+    }
+}
+
+template <int KW>
+__device__ __forceinline__ void store_record(uint32_t* out, unsigned long long pos, uint32_t key, float2 w) {
+    if (KW == 2)
+        reinterpret_cast<uint3*>(out)[pos] = make_uint3(key, __float_as_uint(w.x), __float_as_uint(w.y));
+    else
+        reinterpret_cast<uint2*>(out)[pos] = make_uint2(key, __float_as_uint(w.x));
+}
+
+// Runs (unbuffered): one reservation per non-empty bucket in out_fill (slice of bucket b:
+// out_base[b0+b] .. out_base[b0+b+1]); sets gbase and the sorted starts.
+__device__ void reserve_runs(const DevNet& net, Round& R, uint32_t nb, uint32_t b0, const uint64_t* out_base,
+                             uint32_t* out_fill) {
+    for (uint32_t t = threadIdx.x; t < nb; t += blockDim.x) {
+        const uint32_t h = R.hist[t];
+        unsigned long long gb = ~0ull;
+        if (h) {
+            const uint32_t base = atomicAdd(&out_fill[b0 + t], h);
+            const unsigned long long s0 = out_base[b0 + t];
+            if ((unsigned long long)base + h <= out_base[b0 + t + 1] - s0) gb = s0 + base;
+            else atomicOr(&net.ctl->err, kErrArena);
+        }
+        R.gbase[t] = gb;
+        R.lstart[t] = h;
+    }
+    __syncthreads();
+    block_scan_inplace(R.lstart, nb, R.s_wave);
+    __syncthreads();
+}
+
+// consecutive threads write consecutive records of a bucket's run
+template <int KW>
+__device__ void write_runs(const DevNet& net, Round& R, uint32_t ne, uint32_t nb, uint32_t b0, uint32_t bshift,
+                           uint32_t* out) {
+    for (uint32_t q = threadIdx.x; q < ne; q += blockDim.x) {
+        const uint32_t key = R.s_key[q];
+        const uint32_t b = bucket_of(net, key, nb, b0, bshift);
+        const unsigned long long gb = R.gbase[b];
+        if (gb != ~0ull) store_record<KW>(out, gb + (q - R.lstart[b]), key, R.s_w[q]);
+    }
+    __syncthreads();
+}
+
+// Write-combined tile output, first half: per tile, the carried events plus this round's
+// form whole chunks of kChunk records (on the final call the last partial chunk is
+// padded); one reservation of all of a tile's chunks in tile_fill, the sorted starts and
+// the chunk -> tile map.
+__device__ void wc_reserve(const DevNet& net, Round& R, Wc& W, uint32_t nb, bool final) {
     const uint32_t tid = threadIdx.x;
-    if (tid == 0) {
-        unsigned long long tot = 0;
-        for (uint32_t d = 1; d <= D; d++) {
-            s_dpre[d - 1] = tot;
-            s_dstart[d - 1] = 0;
-            if (k >= d) {
-                const uint32_t b = (uint32_t)((k - d) & net.MBmask);
-                s_dstart[d - 1] = net.bin_start[b];
-                tot += net.bin_cnt[b];
+    for (uint32_t t = tid; t < nb; t += blockDim.x) {
+        const uint32_t c = W.bcnt[t], h = R.hist[t], tot = c + h;
+        const uint32_t f = final ? (tot + kChunk - 1) / kChunk : tot / kChunk;
+        unsigned long long gb = ~0ull;
+        if (f) {
+            const uint32_t base = atomicAdd(&net.tile_fill[t], f * kChunk);
+            const unsigned long long s0 = net.tile_base[t];
+            if ((unsigned long long)base + f * kChunk <= net.tile_base[t + 1] - s0) gb = s0 + base;
+            else atomicOr(&net.ctl->err, kErrArena);
+        }
+        R.gbase[t] = gb;
+        R.lstart[t] = h;
+        W.bc[t] = c;
+        W.cpre[t] = f;
+    }
+    __syncthreads();
+    block_scan_inplace(R.lstart, nb, R.s_wave);
+    __syncthreads();
+    const uint32_t nch = block_scan_inplace(W.cpre, nb, R.s_wave);
+    if (tid == 0) W.cpre[nb] = nch;
+    __syncthreads();
+    for (uint32_t t = tid; t < nb; t += blockDim.x)
+        for (uint32_t i = W.cpre[t]; i < W.cpre[t + 1]; i++) W.cmap[i] = (uint16_t)t;
+    __syncthreads();
+}
+
+// Second half, after the round's events are placed: every chunk is written by kChunk
+// consecutive threads (carried records first, then the tile's sorted events, then zero
+// padding, which adds nothing to any sum); the events left over go to the carry buffers.
+template <int KW>
+__device__ void wc_write(const DevNet& net, Round& R, Wc& W, uint32_t ne, uint32_t nb, uint32_t bshift, bool final) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nch = W.cpre[nb];
+    for (uint32_t x = tid; x < nch * kChunk; x += blockDim.x) {
+        const uint32_t ch = x / kChunk, slot = x % kChunk;
+        const uint32_t b = W.cmap[ch];
+        const uint32_t local = (ch - W.cpre[b]) * kChunk + slot, c = W.bc[b];
+        uint32_t key = 0u;
+        float2 w = make_float2(0.0f, 0.0f);
+        if (local < c) {
+            key = W.bufk[b * kChunk + local];
+            w = W.bufw[b * kChunk + local];
+        } else if (local - c < R.hist[b]) {
+            const uint32_t q = R.lstart[b] + (local - c);
+            key = R.s_key[q];
+            w = R.s_w[q];
+        }
+        const unsigned long long gb = R.gbase[b];
+        if (gb != ~0ull) store_record<KW>(net.ev, gb + local, key, w);
+    }
+    __syncthreads();
+    if (!final) {
+        for (uint32_t q = tid; q < ne; q += blockDim.x) {
+            const uint32_t key = R.s_key[q];
+            const uint32_t b = bucket_of(net, key, nb, 0, bshift);
+            const uint32_t local = W.bc[b] + (q - R.lstart[b]);
+            const uint32_t full = (W.cpre[b + 1] - W.cpre[b]) * kChunk;
+            if (local >= full) {
+                W.bufk[b * kChunk + (local - full)] = key;
+                W.bufw[b * kChunk + (local - full)] = R.s_w[q];
             }
         }
-        s_dpre[D] = tot;
     }
+    for (uint32_t t = tid; t < nb; t += blockDim.x)
+        W.bcnt[t] = final ? 0u : W.bc[t] + R.hist[t] - (W.cpre[t + 1] - W.cpre[t]) * kChunk;
+    __syncthreads();
+}
+
+} // namespace
+
+// The fan-in of the arrivals due at the start of bin k: the delay-d segments of the rows of
+// every neuron that spiked in bin k-d, d = 1..D. Workgroups take chunks of these segments
+// (read whole, so the table reads are contiguous) and process them in rounds of up to
+// round_events events: each thread loads its events into registers, ranks them by bucket
+// with LDS counters, the round is placed in LDS sorted by bucket and written out.
+// wc != 0: the buckets are the tiles, written as whole chunks through the carry buffers.
+// wc == 0: the buckets are the super-tile streams (runs), re-bucketed by k_bucket.
+template <int KW>
+__global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net) {
+    extern __shared__ __align__(16) unsigned char dyn[];
+    const uint32_t D = net.D, RE = net.round_events;
+    const bool wc = net.wc != 0;
+    const uint32_t nb = wc ? net.T : net.NS;
+    const PartLayout L(nb, RE, wc, D);
+    unsigned long long* s_dpre = reinterpret_cast<unsigned long long*>(dyn + L.dpre);
+    unsigned long long* s_dstart = reinterpret_cast<unsigned long long*>(dyn + L.dstart);
+    unsigned long long* s_sstart = reinterpret_cast<unsigned long long*>(dyn + L.sstart);
+    uint32_t* s_spre = reinterpret_cast<uint32_t*>(dyn + L.spre);
+    uint8_t* s_scls = reinterpret_cast<uint8_t*>(dyn + L.scls);
+    Round R;
+    R.at(dyn, L.r);
+    Wc W{};
+    if (wc) W.at(dyn, L.w);
+
+    uint32_t* s_dcnt = reinterpret_cast<uint32_t*>(dyn + L.dcnt);
+    uint16_t* s_map = reinterpret_cast<uint16_t*>(dyn + L.smap);
+    const unsigned long long k = net.ctl->bin;
+    const uint32_t tid = threadIdx.x;
+    // spike lists of bins k-1 .. k-D (one thread per delay), then their prefix
+    for (uint32_t x = tid; x < D; x += blockDim.x) {
+        const uint32_t d = x + 1;
+        uint32_t cnt = 0;
+        unsigned long long st = 0;
+        if (k >= d) {
+            const uint32_t b = (uint32_t)((k - d) & net.MBmask);
+            st = net.bin_start[b];
+            cnt = net.bin_cnt[b];
+        }
+        s_dstart[x] = st;
+        s_dcnt[x] = cnt;
+    }
+    __syncthreads();
+    for (uint32_t x = tid; x <= D; x += blockDim.x) {
+        unsigned long long tot = 0;
+        for (uint32_t y = 0; y < x; y++) tot += s_dcnt[y];
+        s_dpre[x] = tot;
+    }
+    if (wc)
+        for (uint32_t t = tid; t < nb; t += blockDim.x) W.bcnt[t] = 0u;
     __syncthreads();
     const unsigned long long total = s_dpre[D];
     if (total == 0) return;
-    // segments per chunk: about chunks_per_wg chunks per workgroup over all groups, at most kScatterSegs
+    // segments per chunk: about chunks_per_wg chunks per workgroup, at most kScatterSegs
     const unsigned long long cw = (unsigned long long)net.chunks_per_wg * gridDim.x;
-    const unsigned long long want = (total * G + cw - 1) / cw;
-    const uint32_t spc = (uint32_t)min((unsigned long long)kScatterSegs, max(32ull, want));
-    const uint32_t nchunks = (uint32_t)((total + spc - 1) / spc);
-    const uint32_t tb = net.tile_bits, tmask = (1u << tb) - 1u, DG1 = D * G + 1;
-    const uint32_t g0 = xcc_id() % G;
+    const uint32_t spc = (uint32_t)min((unsigned long long)kScatterSegs, max(32ull, (total + cw - 1) / cw));
+    const unsigned long long nchunks = (total + spc - 1) / spc;
+    const uint32_t bshift = wc ? net.tile_bits : net.tile_bits + net.ts_bits;
     unsigned long long my_events = 0;
 
-    for (uint32_t gi = 0; gi < G; gi++) {
-        const uint32_t g = (g0 + gi) % G;
-        const uint32_t t0 = g * TG;                       // first tile of the group
-        const uint32_t ntg = t0 < net.T ? min(TG, net.T - t0) : 0u;
-        for (;;) {
-            if (tid == 0) s_misc[16] = atomicAdd(&net.sq[g], 1u);
-            __syncthreads();
-            const uint32_t c = s_misc[16];
-            __syncthreads();
-            if (c >= nchunks || ntg == 0) break;
-            const unsigned long long i0 = (unsigned long long)c * spc;
-            const uint32_t nseg = (uint32_t)min((unsigned long long)spc, total - i0);
-            uint32_t len = 0;
-            if (tid < nseg) {
-                const unsigned long long it = i0 + tid;
-                uint32_t lo = 0, hi = D;
-                while (hi - lo > 1u) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (s_dpre[mid] <= it) lo = mid;
-                    else hi = mid;
-                }
-                const uint32_t d = lo + 1;
-                const uint32_t j = net.rec[(s_dstart[lo] + (it - s_dpre[lo])) & net.RCmask] >> 4;
-                const uint32_t* sg = net.seg + (size_t)j * DG1 + (d - 1) * G + g;
-                const uint32_t so = sg[0], eo = sg[1];
-                s_sstart[tid] = net.row_ptr[j] + so;
-                s_scls[tid] = net.src_inh[j];
-                len = eo - so;
+    for (unsigned long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const unsigned long long i0 = c * spc;
+        const uint32_t nseg = (uint32_t)min((unsigned long long)spc, total - i0);
+        uint32_t len = 0;
+        if (tid < nseg) {
+            const unsigned long long it = i0 + tid;
+            uint32_t lo = 0, hi = D;
+            while (hi - lo > 1u) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (s_dpre[mid] <= it) lo = mid;
+                else hi = mid;
             }
-            uint32_t ec;
-            const uint32_t ex = block_exclusive_scan(len, s_misc, &ec);
-            s_spre[tid] = ex;
-            if (tid == 0) s_spre[kScatterSegs] = ec;
-            __syncthreads();
-            for (uint32_t r0 = 0; r0 < ec; r0 += RE) {
-                const uint32_t ne = min(RE, ec - r0);
-                for (uint32_t t = tid; t < ntg; t += blockDim.x) hist[t] = 0;
-                __syncthreads();
-                // stage the round's events in LDS and count them per tile
-                uint32_t s_lo = 0;
-                for (uint32_t e = tid; e < ne; e += blockDim.x) {
-                    const uint32_t ge = r0 + e;
-                    const uint32_t s = s_lo + seg_search(s_spre + s_lo, nseg - s_lo, ge);
-                    s_lo = s;
-                    const unsigned long long edge = s_sstart[s] + (ge - s_spre[s]);
-                    const uint32_t tgt = net.col[edge];
-                    r_col[e] = tgt | ((uint32_t)s_scls[s] << 31);
-                    r_w[e] = net.KW == 2 ? reinterpret_cast<const float2*>(net.w)[edge] : make_float2(net.w[edge], 0.0f);
-                    uint32_t lt = (tgt >> tb) - t0;
-                    if (lt >= ntg) { // a target outside the group: the table is inconsistent
-                        atomicOr(&net.ctl->err, kErrLayout);
-                        lt = 0;
-                    }
-                    atomicAdd(&hist[lt], 1u);
-                }
-                __syncthreads();
-                // one global reservation per non-empty tile; local offsets by a scan
-                for (uint32_t t = tid; t < ntg; t += blockDim.x) {
-                    const uint32_t h = hist[t];
-                    unsigned long long gb = ~0ull;
-                    if (h) {
-                        const uint32_t base = atomicAdd(&net.tile_fill[t0 + t], h);
-                        const unsigned long long tb0 = net.tile_base[t0 + t];
-                        if ((unsigned long long)base + h <= net.tile_base[t0 + t + 1] - tb0) gb = tb0 + base;
-                        else atomicOr(&net.ctl->err, kErrArena);
-                    }
-                    gbase[t] = gb;
-                    lstart[t] = h;
-                }
-                __syncthreads();
-                block_scan_inplace(lstart, ntg, s_misc);
-                __syncthreads();
-                for (uint32_t t = tid; t < ntg; t += blockDim.x) lcur[t] = lstart[t];
-                __syncthreads();
-                // counting sort of the staged events by tile
-                for (uint32_t e = tid; e < ne; e += blockDim.x) {
-                    uint32_t lt = ((r_col[e] & 0x7FFFFFFFu) >> tb) - t0;
-                    lt = lt < ntg ? lt : 0u;
-                    r_idx[atomicAdd(&lcur[lt], 1u)] = (uint16_t)e;
-                }
-                __syncthreads();
-                // write-out: consecutive threads write consecutive records of a tile's run
-                for (uint32_t q = tid; q < ne; q += blockDim.x) {
-                    const uint32_t e = r_idx[q];
-                    const uint32_t v = r_col[e];
-                    const uint32_t tgt = v & 0x7FFFFFFFu;
-                    uint32_t lt = (tgt >> tb) - t0;
-                    lt = lt < ntg ? lt : 0u;
-                    const unsigned long long gb = gbase[lt];
-                    if (gb != ~0ull) {
-                        const unsigned long long pos = gb + (q - lstart[lt]);
-                        const uint32_t key = (tgt & tmask) | (v & 0x80000000u);
-                        const float2 w = r_w[e];
-                        if (net.KW == 2)
-                            reinterpret_cast<uint3*>(net.ev)[pos] = make_uint3(key, __float_as_uint(w.x), __float_as_uint(w.y));
-                        else
-                            reinterpret_cast<uint2*>(net.ev)[pos] = make_uint2(key, __float_as_uint(w.x));
-                    }
-                }
-                __syncthreads();
-            }
-            my_events += ec;
+            const uint32_t d = lo + 1;
+            const uint32_t j = net.rec[(s_dstart[lo] + (it - s_dpre[lo])) & net.RCmask] >> 4;
+            // row header of j: row start (bit 63: inhibitory source), then the delay segment offsets
+            const uint32_t* hp = net.hdr + (size_t)j * net.HW;
+            const uint2 rs = *reinterpret_cast<const uint2*>(hp);
+            const uint32_t so = hp[1 + d], eo = hp[2 + d];
+            s_sstart[tid] = (((unsigned long long)(rs.y & 0x7FFFFFFFu) << 32) | rs.x) + so;
+            s_scls[tid] = (uint8_t)(rs.y >> 31);
+            len = eo - so;
         }
+        uint32_t ec;
+        const uint32_t ex = block_exclusive_scan(len, R.s_wave, &ec);
+        s_spre[tid] = ex;
+        if (tid == 0) s_spre[kScatterSegs] = ec;
+        // coarse map: the segment holding event m << mb_bits, for the at most
+        // kScatterSegs blocks of 2^mb_bits events of the chunk
+        uint32_t mb_bits = 0;
+        while (((ec + (1u << mb_bits) - 1) >> mb_bits) > (uint32_t)kScatterSegs) mb_bits++;
+        if (len) {
+            const uint32_t m0 = (ex + (1u << mb_bits) - 1) >> mb_bits;
+            const uint32_t m1 = (ex + len + (1u << mb_bits) - 1) >> mb_bits;
+            for (uint32_t m = m0; m < m1; m++) s_map[m] = (uint16_t)tid;
+        }
+        const uint32_t nmap = (ec + (1u << mb_bits) - 1) >> mb_bits;
+        __syncthreads();
+        for (uint32_t r0 = 0; r0 < ec; r0 += RE) {
+            const uint32_t ne = min(RE, ec - r0);
+            const uint32_t nbt = (ne + kScatterThreads - 1) / kScatterThreads;
+            for (uint32_t t = tid; t < nb; t += blockDim.x) R.hist[t] = 0;
+            __syncthreads();
+            Batch B;
+            // all loads of the batch are issued before any is used (latency cover); the
+            // segment of each event is found from the coarse map, independently per event
+#pragma unroll
+            for (int u = 0; u < kMaxBatch; u++) {
+                if (u < (int)nbt) {
+                    const uint32_t ge = r0 + min(u * kScatterThreads + tid, ne - 1);
+                    const uint32_t m = ge >> mb_bits;
+                    const uint32_t lo = s_map[m], hi = m + 1 < nmap ? s_map[m + 1] : nseg - 1;
+                    const uint32_t s = lo + seg_search(s_spre + lo, hi - lo + 1, ge);
+                    const unsigned long long edge = s_sstart[s] + (ge - s_spre[s]);
+                    B.key[u] = net.col[edge] | ((uint32_t)s_scls[s] << 31);
+                    B.w[u] = KW == 2 ? reinterpret_cast<const float2*>(net.w)[edge] : make_float2(net.w[edge], 0.0f);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kMaxBatch; u++)
+                if (u < (int)nbt && u * kScatterThreads + tid < ne) B.br[u] = rank_event(net, R, B.key[u], nb, 0, bshift);
+            __syncthreads();
+            if (wc) wc_reserve(net, R, W, nb, false);
+            else reserve_runs(net, R, nb, 0, net.st_base, net.st_fill);
+            place_batch(R, B, ne, nbt);
+            __syncthreads();
+            if (wc) wc_write<KW>(net, R, W, ne, nb, bshift, false);
+            else write_runs<KW>(net, R, ne, nb, 0, bshift, net.sev);
+        }
+        my_events += ec;
+    }
+    if (wc) { // the carried events of every tile, as padded chunks
+        for (uint32_t t = tid; t < nb; t += blockDim.x) R.hist[t] = 0;
+        __syncthreads();
+        wc_reserve(net, R, W, nb, true);
+        wc_write<KW>(net, R, W, 0, nb, bshift, true);
     }
     if (tid == 0 && my_events) atomicAdd(&net.ctl->edge_events, my_events);
 }
 
-size_t scatter_fixed_lds(uint32_t TG) {
-    return 8 * (DBNET_MAX_DELAY + 1) + 8 * DBNET_MAX_DELAY + 8 * kScatterSegs + 8 * ((TG + 1) & ~1u) +
-           4 * (kScatterSegs + 4) + 12 * (size_t)TG + 4 * 20 + kScatterSegs + 16;
+// Records in super-tile stream st. A stream never holds more than its slice (each edge
+// fires at most once per bin); the clamp keeps the reads inside it even if that
+// invariant were broken (k_part has then raised kErrArena).
+__device__ __forceinline__ uint32_t stream_fill(const DevNet& net, uint32_t st) {
+    return (uint32_t)min((unsigned long long)net.st_fill[st], net.st_base[st + 1] - net.st_base[st]);
 }
 
-size_t scatter_lds_bytes(const DevNet& n) { return scatter_fixed_lds(n.TG) + 14 * (size_t)n.round_events; }
+// Second pass when the tiles are too many for the carry buffers: each super-tile stream is
+// cut into rounds of contiguous records, which are partitioned into the super-tile's tiles.
+template <int KW>
+__global__ void __launch_bounds__(kScatterThreads) k_bucket(DevNet net) {
+    extern __shared__ __align__(16) unsigned char dyn[];
+    const uint32_t RE = net.round_events, NS = net.NS, TS = 1u << net.ts_bits;
+    const BucketLayout L(TS, RE);
+    unsigned long long* s_cpre = reinterpret_cast<unsigned long long*>(dyn + L.cpre);
+    Round R;
+    R.at(dyn, L.r);
+    uint32_t* s_ccnt = reinterpret_cast<uint32_t*>(dyn + L.ccnt);
+    const uint32_t tid = threadIdx.x;
+    // rounds per stream (one thread per stream), then their prefix
+    for (uint32_t st = tid; st < NS; st += blockDim.x) s_ccnt[st] = (stream_fill(net, st) + RE - 1) / RE;
+    __syncthreads();
+    for (uint32_t st = tid; st <= NS; st += blockDim.x) {
+        unsigned long long tot = 0;
+        for (uint32_t y = 0; y < st; y++) tot += s_ccnt[y];
+        s_cpre[st] = tot;
+    }
+    __syncthreads();
+    const unsigned long long nchunks = s_cpre[NS];
+    for (unsigned long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        uint32_t lo = 0, hi = NS;
+        while (hi - lo > 1u) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s_cpre[mid] <= c) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t st = lo;
+        const unsigned long long r0 = (c - s_cpre[st]) * RE;
+        const uint32_t fill = stream_fill(net, st);
+        const uint32_t ne = (uint32_t)min((unsigned long long)RE, fill - r0);
+        const uint32_t nbt = (ne + kScatterThreads - 1) / kScatterThreads;
+        const uint32_t t0 = st * TS;
+        const uint32_t nt = min(TS, net.T - t0);
+        for (uint32_t t = tid; t < nt; t += blockDim.x) R.hist[t] = 0;
+        __syncthreads();
+        const unsigned long long src0 = net.st_base[st] + r0;
+        Batch B;
+#pragma unroll
+        for (int u = 0; u < kMaxBatch; u++) {
+            if (u < (int)nbt) {
+                const uint32_t e = min(u * kScatterThreads + tid, ne - 1); // unconditional loads
+                if (KW == 2) {
+                    const uint3 q = reinterpret_cast<const uint3*>(net.sev)[src0 + e];
+                    B.key[u] = q.x;
+                    B.w[u] = make_float2(__uint_as_float(q.y), __uint_as_float(q.z));
+                } else {
+                    const uint2 q = reinterpret_cast<const uint2*>(net.sev)[src0 + e];
+                    B.key[u] = q.x;
+                    B.w[u] = make_float2(__uint_as_float(q.y), 0.0f);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kMaxBatch; u++)
+            if (u < (int)nbt && u * kScatterThreads + tid < ne)
+                B.br[u] = rank_event(net, R, B.key[u], nt, t0, net.tile_bits);
+        __syncthreads();
+        reserve_runs(net, R, nt, t0, net.tile_base, net.tile_fill);
+        place_batch(R, B, ne, nbt);
+        __syncthreads();
+        write_runs<KW>(net, R, ne, nt, t0, net.tile_bits, net.ev);
+    }
+}
+
+size_t part_lds_bytes(uint32_t nb, uint32_t RE, bool wc, uint32_t D) { return PartLayout(nb, RE, wc, D).total; }
+
+size_t bucket_lds_bytes(uint32_t TS, uint32_t RE) { return BucketLayout(TS, RE).total; }
 
 // ------------------------------------------------------------------ gather
 
@@ -298,25 +602,37 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(DevNet net) {
     for (uint32_t x = threadIdx.x; x < nt * U; x += blockDim.x) acc[x] = 0ull;
     __syncthreads();
     const unsigned long long b0 = net.tile_base[t];
-    const uint32_t cnt = net.tile_fill[t];
+    const uint32_t cnt = (uint32_t)min((unsigned long long)net.tile_fill[t], net.tile_base[t + 1] - b0);
     const double qs = net.qscale;
-    for (uint32_t e = threadIdx.x; e < cnt; e += blockDim.x) {
-        if (KW == 2) {
-            const uint3 r = reinterpret_cast<const uint3*>(net.ev)[b0 + e];
-            const uint32_t lt = r.x & lmask;
-            const uint32_t u0 = (r.x >> 31) ? 2u : 0u;
-            atomicAdd(&acc[lt * U + u0], quant(__uint_as_float(r.y), qs));
-            atomicAdd(&acc[lt * U + u0 + 1], quant(__uint_as_float(r.z), qs));
-        } else {
-            const uint2 r = reinterpret_cast<const uint2*>(net.ev)[b0 + e];
-            const uint32_t lt = r.x & lmask;
-            const uint32_t u0 = (r.x >> 31) ? 1u : 0u;
-            atomicAdd(&acc[lt * U + u0], quant(__uint_as_float(r.y), qs));
+    for (uint32_t eb = 0; eb < cnt; eb += kLoadBatch * blockDim.x) {
+        // load a batch of records first (latency cover), then accumulate them
+        uint3 r[kLoadBatch];
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; u++) {
+            // clamped, so the loads are unconditional (no branch between them)
+            const uint32_t e = min(eb + u * blockDim.x + threadIdx.x, cnt - 1);
+            if (KW == 2) {
+                r[u] = reinterpret_cast<const uint3*>(net.ev)[b0 + e];
+            } else {
+                const uint2 q = reinterpret_cast<const uint2*>(net.ev)[b0 + e];
+                r[u] = make_uint3(q.x, q.y, 0u);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; u++) {
+            const uint32_t e = eb + u * blockDim.x + threadIdx.x;
+            if (e < cnt) {
+                const uint32_t lt = r[u].x & lmask;
+                const uint32_t u0 = (r[u].x >> 31) ? (uint32_t)KW : 0u;
+                atomicAdd(&acc[lt * U + u0], quant(__uint_as_float(r[u].y), qs));
+                if (KW == 2) atomicAdd(&acc[lt * U + u0 + 1], quant(__uint_as_float(r[u].z), qs));
+            }
         }
     }
     __syncthreads();
     if (threadIdx.x == 0) net.tile_fill[t] = 0;
-    if (t == 0 && threadIdx.x < kTileGroups) net.sq[threadIdx.x] = 0;
+    if (t == 0)
+        for (uint32_t x = threadIdx.x; x < net.NS; x += blockDim.x) net.st_fill[x] = 0;
     const float qinv = net.qinv;
     for (uint32_t x = threadIdx.x; x < nt; x += blockDim.x) {
 #pragma unroll
@@ -597,20 +913,36 @@ __global__ void __launch_bounds__(256) k_readout_close(DevNet net) {
 
 size_t gather_lds_bytes(const DevNet& n) { return ((size_t)1 << n.tile_bits) * n.U * 8u; }
 
-hipError_t launch_scatter(const DevNet& n, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(kScatterThreads), scatter_lds_bytes(n), st, n);
-    return hipGetLastError();
-}
 
 hipError_t prepare_kernels() {
-    hipError_t e = hipFuncSetAttribute((const void*)k_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)kMaxLdsBytes);
-    if (e != hipSuccess) return e;
+    const void* big[] = {(const void*)k_part<1>, (const void*)k_part<2>, (const void*)k_bucket<1>,
+                         (const void*)k_bucket<2>};
+    hipError_t e = hipSuccess;
+    for (const void* f : big) {
+        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytes);
+        if (e != hipSuccess) return e;
+    }
     e = hipFuncSetAttribute((const void*)k_gather<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)kTileLdsBytes);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)k_gather<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)kTileLdsBytes);
+}
+
+hipError_t launch_scatter(const DevNet& n, int grid, hipStream_t st) {
+    const size_t la = part_lds_bytes(n.wc ? n.T : n.NS, n.round_events, n.wc != 0, n.D);
+    const size_t lb = bucket_lds_bytes(1u << n.ts_bits, n.round_events);
+    if (n.KW == 2)
+        hipLaunchKernelGGL(k_part<2>, dim3(grid), dim3(kScatterThreads), la, st, n);
+    else
+        hipLaunchKernelGGL(k_part<1>, dim3(grid), dim3(kScatterThreads), la, st, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n.wc) return e;
+    if (n.KW == 2)
+        hipLaunchKernelGGL(k_bucket<2>, dim3(grid), dim3(kScatterThreads), lb, st, n);
+    else
+        hipLaunchKernelGGL(k_bucket<1>, dim3(grid), dim3(kScatterThreads), lb, st, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_gather(const DevNet& n, hipStream_t st) {

@@ -72,11 +72,16 @@ uint32_t indeg_of_pop(const dbnet_desc& d, uint32_t p) {
 
 } // namespace
 
-uint32_t max_round_events(uint32_t TG, uint32_t wgs_per_cu) {
-    const size_t budget = kMaxLdsBytes / wgs_per_cu - 1024;
-    const size_t fixed = scatter_fixed_lds(TG);
-    if (fixed + 14 * 1024 > budget) return 0;
-    return (uint32_t)std::min<size_t>(16384, ((budget - fixed) / 14) & ~(size_t)1023);
+uint32_t max_round_events(const Plan& p, uint32_t wgs_per_cu) {
+    const size_t budget = kMaxLdsBytes / wgs_per_cu - 256;
+    uint32_t best = 0;
+    for (uint32_t re = kScatterThreads; re <= (uint32_t)(kScatterThreads * kMaxBatch); re += kScatterThreads) {
+        const bool fits = p.wc ? part_lds_bytes(p.T, re, true, p.D) <= budget
+                               : part_lds_bytes(p.NS, re, false, p.D) <= budget &&
+                                     bucket_lds_bytes(1u << p.ts_bits, re) <= budget;
+        if (fits) best = re;
+    }
+    return best;
 }
 
 void Members::assign(const dbnet_desc* descs, uint32_t n) {
@@ -140,11 +145,21 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     while ((1u << (p.tile_bits + 1)) <= tile_neurons) p.tile_bits++;
     p.T = (p.N + (1u << p.tile_bits) - 1) >> p.tile_bits;
     if (p.T > (uint32_t)kMaxTilesLds) return "network too large for the tile histogram (too many neurons)";
-    p.TG = (p.T + kTileGroups - 1) / kTileGroups;
-    // scatter: default schedule (one workgroup per CU, the largest LDS round that fits)
-    p.scatter_wgs_per_cu = 1;
-    p.round_events = max_round_events(p.TG, 1);
-    if (p.round_events == 0) return "too many tiles per group for the scatter's LDS budget";
+    // fan-in form: k_part writes the tiles directly when a carry buffer per tile and a
+    // round of 1024 events fit twice in a CU's LDS, else two passes through at most
+    // kMaxSuperTiles super-tile streams of a power-of-two number of tiles each
+    p.wc = !(opts.flags & DBSIM_F_TWO_PASS) && p.T <= 2u * kScatterThreads &&
+           part_lds_bytes(p.T, 1024, true, p.D) <= kMaxLdsBytes / 2 - 256;
+    p.ts_bits = 0;
+    if (!p.wc)
+        while (((p.T + (1u << p.ts_bits) - 1) >> p.ts_bits) > kMaxSuperTiles) p.ts_bits++;
+    p.NS = (p.T + (1u << p.ts_bits) - 1) >> p.ts_bits;
+    p.HW = (p.D + 3 + 3) & ~3u;
+    // default schedule: four partition workgroups per CU (two in the single-pass form),
+    // the largest LDS round that fits
+    p.scatter_wgs_per_cu = p.wc ? 2 : 4;
+    p.round_events = max_round_events(p, p.scatter_wgs_per_cu);
+    if (p.round_events == 0) return "too many tiles per super-tile for the LDS budget";
     const double dt = (double)m0.dt_ms;
     p.E = 0;
     p.n_blocks = 0;
@@ -161,8 +176,9 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
             if (poisson_thresholds((double)P.bg_rate_hz * dt * 1e-3, T, kMaxPoisson) < 0)
                 return "background rate too high for the Poisson table (rate * dt above about 20)";
             const uint32_t kin = indeg_of_pop(n, q);
-            // tile slices are indexed with 32-bit fill counters
-            if ((uint64_t)kin << p.tile_bits >= (1ull << 32)) return "in-degree too large for a tile slice";
+            // super-tile streams and tile slices are indexed with 32-bit fill counters
+            if (((uint64_t)kin << (p.tile_bits + p.ts_bits)) + (uint64_t)kChunk * (kMaxPartGrid + 1) >= (1ull << 32))
+                return "in-degree too large for a super-tile stream";
             p.E += (uint64_t)P.size * kin;
             const uint32_t nb = (P.size + kNeuronBlock - 1) / kNeuronBlock;
             p.n_blocks += nb;
@@ -192,15 +208,17 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     slot(p.pops, sizeof(PopParams) * p.n_pops);
     slot(p.ptab, 4 * (size_t)kMaxPoisson * p.n_pops);
     slot(p.blk, sizeof(uint2) * p.n_blocks);
-    slot(p.row_ptr, 8 * (N + 1));
-    slot(p.seg, 4 * N * ((size_t)p.D * kTileGroups + 1));
+    slot(p.hdr, 4 * N * (size_t)p.HW);
     slot(p.col, 4 * E);
     slot(p.w, 4 * (size_t)p.KW * E);
-    slot(p.src_inh, N);
-    slot(p.ev, 4 * (size_t)(1 + p.KW) * E);
+    // event arena: write-combined tile slices are padded (see build_tables)
+    const size_t arena = p.wc ? E + (size_t)p.T * (kChunk - 1 + (size_t)kChunk * kMaxPartGrid) : E;
+    slot(p.ev, 4 * (size_t)(1 + p.KW) * arena);
     slot(p.tile_base, 8 * ((size_t)p.T + 1));
     slot(p.tile_fill, 4 * (size_t)p.T);
-    slot(p.sq, 4 * (size_t)kTileGroups);
+    slot(p.st_base, 8 * ((size_t)p.NS + 1));
+    slot(p.st_fill, 4 * (size_t)p.NS);
+    slot(p.sev, p.wc ? 16 : 4 * (size_t)(1 + p.KW) * E);
     p.n_grp = (p.n_blocks + 255) / 256;
     slot(p.stage, 4 * (size_t)p.n_blocks * kNeuronBlock);
     slot(p.grp_cnt, 4 * 2 * (size_t)p.n_grp);
@@ -307,8 +325,18 @@ std::string build_tables(const Members& mem, const Plan& p, unsigned threads, Ho
                 h.tile_base[(i >> p.tile_bits) + 1] += pop_indeg[gq];
             }
         }
-    for (uint32_t t = 0; t < p.T; t++) h.tile_base[t + 1] += h.tile_base[t];
-    if (h.tile_base[p.T] != p.E) return "internal error: edge count mismatch";
+    {
+        uint64_t sum = 0;
+        for (uint32_t t = 0; t < p.T; t++) sum += h.tile_base[t + 1];
+        if (sum != p.E) return "internal error: edge count mismatch";
+    }
+    // write-combined form: every slice starts on a whole chunk and holds, besides the
+    // tile's in-degree, one padded chunk per partition workgroup
+    for (uint32_t t = 0; t < p.T; t++) {
+        uint64_t len = h.tile_base[t + 1];
+        if (p.wc) len = (len + kChunk - 1) / kChunk * kChunk + (uint64_t)kChunk * kMaxPartGrid;
+        h.tile_base[t + 1] = h.tile_base[t] + len;
+    }
 
     // initial membrane potentials
     h.V0.resize(N);
@@ -422,27 +450,18 @@ std::string build_tables(const Members& mem, const Plan& p, unsigned threads, Ho
             }
         }
     });
-    // (delay, tile group) sub-segment offsets: seg_dg[j][(d-1)*G + g] = start, [D*G] = row length
-    const uint32_t G = kTileGroups, DG1 = D * G + 1;
-    const uint64_t group_span = (uint64_t)p.TG << p.tile_bits; // targets per tile group
-    h.seg_dg.resize((size_t)N * DG1);
-    parallel_chunks(N, 4096, nt, [&](unsigned, uint64_t a, uint64_t b) {
-        for (uint64_t j = a; j < b; j++) {
-            const uint32_t* sg = &h.seg[(size_t)j * (D + 1)];
-            uint32_t* out = &h.seg_dg[(size_t)j * DG1];
-            const uint64_t r0 = h.row_ptr[j];
-            for (uint32_t x = 0; x < D; x++) {
-                const uint32_t* c0 = h.col.data() + r0 + sg[x];
-                const uint32_t* c1 = h.col.data() + r0 + sg[x + 1];
-                for (uint32_t g = 0; g < G; g++) {
-                    const uint64_t first = g * group_span;
-                    const uint32_t* it = first >= (1ull << 32) ? c1 : std::lower_bound(c0, c1, (uint32_t)first);
-                    out[x * G + g] = (uint32_t)(it - (h.col.data() + r0));
-                }
-            }
-            out[D * G] = sg[D];
-        }
-    });
+    // row headers
+    h.hdr.assign((size_t)N * p.HW, 0u);
+    for (uint32_t j = 0; j < N; j++) {
+        uint32_t* hp = &h.hdr[(size_t)j * p.HW];
+        const uint64_t rs = h.row_ptr[j] | ((uint64_t)h.src_inh[j] << 63);
+        hp[0] = (uint32_t)rs;
+        hp[1] = (uint32_t)(rs >> 32);
+        for (uint32_t x = 0; x <= D; x++) hp[2 + x] = h.seg[(size_t)j * (D + 1) + x];
+    }
+    // super-tile stream slices: the sum of their tiles' slices
+    h.st_base.assign((size_t)p.NS + 1, 0ull);
+    for (uint32_t x = 0; x <= p.NS; x++) h.st_base[x] = h.tile_base[std::min<uint64_t>((uint64_t)x << p.ts_bits, p.T)];
     return "";
 }
 

@@ -37,7 +37,9 @@ struct Plan {
     uint32_t MB = 0;    // bins kept in the per-bin rings (power of two)
     uint32_t n_l1 = 0;  // level-1 readout groups (256 neuron blocks each, per region)
     uint32_t n_grp = 0; // compaction groups (256 consecutive neuron blocks each)
-    uint32_t TG = 0;    // tiles per tile group
+    bool wc = false;              // k_part writes tile chunks directly (else two passes)
+    uint32_t NS = 0, ts_bits = 0; // super-tiles, log2(tiles per super-tile) of the two-pass form
+    uint32_t HW = 0;              // words per row header
     uint32_t round_events = 0, scatter_wgs_per_cu = 0;
     uint64_t RC = 0; // spike-history ring entries (power of two)
     uint64_t E = 0;  // edges
@@ -46,14 +48,15 @@ struct Plan {
     struct Slot {
         size_t off = 0, bytes = 0;
     };
-    Slot V, J, ref, pend, A, pops, ptab, blk, row_ptr, seg, col, w, src_inh, ev, tile_base, tile_fill, sq, stage,
+    Slot V, J, ref, pend, A, pops, ptab, blk, hdr, col, w, ev, tile_base, tile_fill, st_base, st_fill, sev, stage,
         grp_cnt, rec, bin_start, bin_cnt, blk_sig, blk_cnt, reg_blk_ptr, reg_blk, reg_size, l1_ptr, l1_region, l1_sig,
         l1_cnt, sig, sig_cnt, ctl;
     size_t total = 0;
 };
 
-// Largest multiple of 1024 events a scatter round can stage in LDS (0 if none fits).
-uint32_t max_round_events(uint32_t TG, uint32_t wgs_per_cu);
+// Largest multiple of 1024 events (at most 8192) a partition round can stage in LDS for
+// the plan's form (0 if none fits).
+uint32_t max_round_events(const Plan& p, uint32_t wgs_per_cu);
 
 // Validates the runtime options and the members for this simulator and fills the plan.
 // Returns an empty string on success, else the reason.
@@ -66,12 +69,12 @@ struct HostTables {
     std::vector<uint32_t> ptab;
     std::vector<uint2> blk;
     std::vector<uint64_t> row_ptr;
-    std::vector<uint32_t> seg;    // [N][D+1] delay segments
-    std::vector<uint32_t> seg_dg; // [N][D*G+1] (delay, tile group) sub-segments (device layout)
+    std::vector<uint32_t> seg; // [N][D+1] delay segments
     std::vector<uint32_t> col;
     std::vector<float> w; // KW floats per edge, interleaved
     std::vector<uint8_t> src_inh;
-    std::vector<uint64_t> tile_base;
+    std::vector<uint32_t> hdr; // [N][HW] device row headers
+    std::vector<uint64_t> tile_base, st_base;
     std::vector<uint32_t> reg_blk_ptr, reg_blk, reg_size, l1_ptr, l1_region;
 };
 

@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libdbsim.so")
 ABI_VERSION = 1
 REC_REGIONS = 1
 F_NO_GRAPH = 1
+F_TWO_PASS = 2
 
 OK, EINVAL, ENOMEM, EHBM, EDEVICE, ETRUNC, EOVERFLOW, ESTATE, ERANGE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHBM: "EHBM", EDEVICE: "EDEVICE", ETRUNC: "ETRUNC",
@@ -51,7 +52,7 @@ class SimInfo(Structure):
     _fields_ = [("num_neurons", c_uint64), ("num_edges", c_uint64), ("receptors", c_uint32),
                 ("weights_per_edge", c_uint32), ("steps_per_bin", c_uint32), ("max_delay", c_uint32),
                 ("n_regions", c_uint32), ("tile_neurons", c_uint32), ("n_tiles", c_uint32), ("frac_bits", c_uint32),
-                ("n_members", c_uint32)]
+                ("n_members", c_uint32), ("fanin_passes", c_uint32)]
 
 
 class SimMember(Structure):
@@ -161,7 +162,7 @@ class _TorchAllocator:
 
 def make_desc(spec: NetSpec, record_regions: bool = True, spike_record_capacity: int = 0, record_bins: int = 0,
               device: int = -1, stream_handle: Optional[int] = None, allocator: Optional[_TorchAllocator] = None,
-              host_threads: int = 0, no_graph: bool = False):
+              host_threads: int = 0, no_graph: bool = False, two_pass: bool = False):
     holder = spec.to_c()
     d = SimDesc()
     d.abi_version = ABI_VERSION
@@ -175,7 +176,7 @@ def make_desc(spec: NetSpec, record_regions: bool = True, spike_record_capacity:
         d.dev_alloc = allocator.alloc
         d.dev_free = allocator.free
     d.host_threads = int(host_threads)
-    d.flags = F_NO_GRAPH if no_graph else 0
+    d.flags = (F_NO_GRAPH if no_graph else 0) | (F_TWO_PASS if two_pass else 0)
     return d, holder
 
 
@@ -212,7 +213,7 @@ class Simulator:
 
     def __init__(self, spec: NetSpec, record_regions: bool = True, use_torch: bool = True, device: int = 0,
                  spike_record_capacity: int = 0, record_bins: int = 0, host_threads: Optional[int] = None,
-                 no_graph: bool = False, stream=None):
+                 no_graph: bool = False, stream=None, two_pass: bool = False):
         L = lib()
         if host_threads is None:
             # the process's CPU share (OMP_NUM_THREADS) rather than every core of the machine
@@ -231,7 +232,7 @@ class Simulator:
         self.specs = list(spec) if isinstance(spec, (list, tuple)) else [spec]
         first = self.specs[0]
         self._desc, self._holder = make_desc(first, record_regions, spike_record_capacity, record_bins, device,
-                                             stream_handle, self._alloc, host_threads, no_graph)
+                                             stream_handle, self._alloc, host_threads, no_graph, two_pass)
         h = c_void_p()
         if isinstance(spec, (list, tuple)):
             self._members, self._member_holders = _member_array(self.specs)

@@ -15,8 +15,8 @@ from .dbsim import DbsimError, Simulator
 
 def candidates(sim: Simulator) -> List[Tuple[int, int, int]]:
     out = []
-    for wgs in (1, 2):
-        for cpw in (1, 2, 4, 8):
+    for wgs in (2, 4, 6, 8):
+        for cpw in (1, 4):
             for re_div in (1, 2):
                 out.append((wgs, re_div, cpw))
     return out
@@ -33,7 +33,7 @@ def autotune(sim: Simulator, bins_per_trial: int = 10, verbose: bool = False) ->
             sim.set_tuning(scatter_wgs_per_cu=wgs, round_events=0, chunks_per_wg=cpw)
             if re_div > 1:
                 cur = sim.tuning()["round_events"]
-                re = max(1024, (cur // re_div) // 1024 * 1024)
+                re = max(256, (cur // re_div) // 256 * 256)
                 sim.set_tuning(scatter_wgs_per_cu=wgs, round_events=re, chunks_per_wg=cpw)
         except DbsimError:
             continue

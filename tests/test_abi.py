@@ -54,6 +54,7 @@ int main(void) {
   O(dbnet_desc, seed); O(dbnet_desc, pops); O(dbnet_desc, region_xyz_mm);
   O(dbsim_desc, net); O(dbsim_desc, spike_record_capacity); O(dbsim_desc, hip_stream); O(dbsim_desc, flags);
   O(dbsim_stats, ms_scatter); O(dbsim_stats, build_seconds); O(dbsim_info, frac_bits); O(dbsim_info, n_members);
+  O(dbsim_info, fanin_passes);
   P(dbsim_member); O(dbsim_member, first_region);
   return 0;
 }
@@ -81,6 +82,7 @@ def test_struct_layouts_match_ctypes(L):
     assert int(out["dbsim_stats.ms_scatter"]) == D.SimStats.ms_scatter.offset
     assert int(out["dbsim_info.frac_bits"]) == D.SimInfo.frac_bits.offset
     assert int(out["dbsim_info.n_members"]) == D.SimInfo.n_members.offset
+    assert int(out["dbsim_info.fanin_passes"]) == D.SimInfo.fanin_passes.offset
     assert int(out["dbsim_member"]) == ctypes.sizeof(D.SimMember)
     assert int(out["dbsim_member.first_region"]) == D.SimMember.first_region.offset
 
@@ -126,9 +128,18 @@ def test_footprint_matches_layout(L):
     fp = D.footprint(s)
     E = s.num_edges()
     assert E == 100000 * 556
-    # dominant terms: targets (4 B), two weights (8 B) and the event arena record (12 B) per edge
-    assert 24 * E < fp < 24 * E + 60 * 100000 + (64 << 20)
-    assert D.footprint(configs.tiny()) < 24 << 20   # mostly the default 2^22-entry spike history
+    # dominant terms: targets (4 B), two weights (8 B) and the tile arena record (12 B) per
+    # edge; 25 tiles of 4096 neurons are written directly in 16-record chunks, with room
+    # for one padded chunk per partition workgroup (at most 512) in every tile slice
+    pad = 25 * (15 + 16 * 512) * 12
+    assert 24 * E + pad < fp < 24 * E + pad + 60 * 100000 + (64 << 20)
+    # 1490 tiles are too many for the write-combining buffers: two passes, with a 12 B
+    # super-tile stream record per edge as well
+    s = configs.share(n=6100000, indegree=20)
+    fp, E = D.footprint(s), s.num_edges()
+    # per neuron: a 64 B row header, the state, and the spike-history ring of at least
+    # (D + 1) N entries rounded up to a power of two
+    assert 36 * E < fp < 36 * E + 220 * 6100000 + (64 << 20)
 
 
 def test_ensemble_footprint_and_validation(L):

@@ -180,3 +180,53 @@ def test_one_hip_runtime_in_process(Sim):
     torch.zeros(1, device="cuda")
     maps = sorted(set(l.split()[-1] for l in open("/proc/self/maps") if "libamdhip64" in l))
     assert len(maps) == 1, maps
+
+
+def test_two_pass_fanin_bit_exact(Sim):
+    spec = configs.share(n=20000, indegree=556, seed=5)
+    _say("share 20000 / k556 seed 5, fan-in forced through super-tile streams, 400 steps")
+    sim = Sim(spec, two_pass=True)
+    assert sim.info.fanin_passes == 2
+    sim.step(400)
+    orc = Oracle(spec, 32)
+    orc.step(400)
+    _compare(sim, orc, spec)
+    sim.close()
+    spec = configs.multi_region(n_regions=20, per_region=1000, seed=6)
+    _say("multi-region 20 x 1000 seed 6, two-pass fan-in, 300 steps")
+    sim = Sim(spec, two_pass=True)
+    sim.step(300)
+    orc = Oracle(spec, 32)
+    orc.step(300)
+    _compare(sim, orc, spec)
+    sim.close()
+
+
+@pytest.mark.parametrize("two_pass", [False, True])
+def test_fanin_schedules_agree(Sim, two_pass):
+    """Every partition schedule gives the same bits (exact integer arrival sums)."""
+    spec = configs.share(n=60000, indegree=300, seed=7)
+    _say(f"share 60000 / k300, schedules compared, two_pass={two_pass}")
+    ref = Sim(spec, two_pass=two_pass)
+    assert ref.info.fanin_passes == (2 if two_pass else 1)
+    ref.step(200)
+    r_sp, r_st = ref.spikes(), ref.state()
+    r_ev = ref.stats()["edge_events"]
+    assert len(r_sp[0]) > 0
+    ref.close()
+    for wgs, re, cpw in ((1, 0, 1), (2, 256, 64), (3, 512, 2), (8, 0, 8), (4, 1536, 4)):
+        sim = Sim(spec, two_pass=two_pass)
+        try:
+            sim.set_tuning(scatter_wgs_per_cu=wgs, round_events=re, chunks_per_wg=cpw)
+        except Exception as ex:  # a schedule that does not fit the LDS is refused up front
+            assert "LDS" in str(ex)
+            sim.close()
+            continue
+        _say(f"  schedule {sim.tuning()}")
+        sim.step(200)
+        sp, st = sim.spikes(), sim.state()
+        assert np.array_equal(sp[0], r_sp[0]) and np.array_equal(sp[1], r_sp[1])
+        for x, y in zip(st, r_st):
+            assert np.array_equal(x, y)
+        assert sim.stats()["edge_events"] == r_ev
+        sim.close()
