@@ -1,9 +1,10 @@
 """Benchmark of the per-timestep spiking-network step on one MI355X.
 
-One benchmark step is one 1 ms spike bin of the whole hot path: the bucketed
-fan-in of the bin's arrivals (k_scatter + k_gather), ten fused 0.1 ms Euler
-substeps of every neuron with Poisson background (k_neuron), the spike-list
-compaction (k_compact), and the region readout and bin close (k_readout_close).
+One benchmark step is one 1 ms spike bin of the whole hot path: the radix-partitioned
+fan-in of the bin's arrivals (k_part, k_bucket when two passes are needed, k_gather),
+ten fused 0.1 ms Euler substeps of every neuron with Poisson background (k_neuron),
+the spike-list compaction (k_compact), and the region readout and bin close
+(k_readout_close).
 
 Workload (default): one GPU's share of the whole-brain model, 6.1 M LIF neurons,
 in-degree 556 (3.39e9 synapses, two weights each), 4 receptors, delays uniform in
@@ -13,10 +14,13 @@ and seeded (the paper's networks come from private MRI data).
 Prints one JSON line: synaptic events/s over the timed bins (inputs resident in
 HBM), the real-time factor, the HBM roofline of the dominant fan-out phase, the
 batched-ensemble comparison (64 uneven networks advanced together vs one after
-another: ensemble sims/s and per-member p50/p99 completion latency), and the CPU
-oracle's throughput on a bounded sample of the same recipe.
+another: ensemble sims/s and per-member p50/p99 completion latency), the served
+stream (seeded Poisson arrivals of requests admitted by footprint: p50/p99
+latency and sustained events/s, at the offered rate and at a stable rate), and the
+CPU oracle's throughput on a bounded sample of the same recipe.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -31,8 +35,36 @@ BYTES_PER_EVENT = 44.0         # fan-out: 4 B target + 2 x 4 B weights + 2 x (8 
 BYTES_PER_NEURON_BIN = 128.0   # neuron step: V, J[4], ref read+write, g_u[4], arrivals[4] int64 read+clear
 
 
+FANIN_KERNELS = ("k_part", "k_bucket", "k_gather")
+COUNTERS_JSON = os.path.join(ROOT, "profiles", "fanin_share6.1M_15hz_counters.json")
+KERNEL_SOURCES = ("paper_2211_15963_amd/csrc/kernels.hip", "paper_2211_15963_amd/csrc/dbsim_internal.hpp")
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(events_per_bin: float):
+    """HBM bytes per bin of the fan-out phase from the committed counter summary, scaled
+    to this run's events per bin; None when the kernels changed since the counters."""
+    try:
+        with open(COUNTERS_JSON) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    per_bin = sum(c["bytes_per_bin"][k]["read"] + c["bytes_per_bin"][k]["write"]
+                  for k in FANIN_KERNELS if k in c["bytes_per_bin"])
+    return per_bin * events_per_bin / c["edge_events_per_bin"]
 
 
 def run_gpu(args):
@@ -80,9 +112,49 @@ def run_gpu(args):
         "ms_neuron": s1["ms_neuron"] - s0["ms_neuron"], "ms_readout": s1["ms_readout"] - s0["ms_readout"],
         "timed_bins": s1["timed_bins"] - s0["timed_bins"], "spec": spec, "build_s": s1["build_seconds"],
         "hbm_bytes": s1["hbm_bytes"], "tuning": sim.tuning(),
+        "run_totals": {"bins": s1["bins"], "edge_events": s1["edge_events"]},
     }
     sim.close()
     return out
+
+
+def run_served(args):
+    """Served stream: seeded Poisson arrivals of requests of log-uniform size, admitted by
+    footprint, built on host threads and advanced together on the device. First at the
+    offered rate (an overload: network construction on the host bounds the service rate),
+    then at 70% of the sustained completion rate measured there, where queues are stable."""
+    from netgen import configs
+    from paper_2211_15963_amd.serve import Request, Server
+
+    def window(rate, count, seed):
+        t = configs.arrival_times(count, rate, seed=seed)
+        reqs = []
+        for r in range(count):
+            spec, steps = configs.served_request(r, seed=seed)
+            reqs.append(Request(r, spec, steps, arrival_s=float(t[r])))
+        srv = Server(max_active=args.serve_slots, slice_bins=25, build_workers=2, state_digest=False)
+        out = srv.run(reqs)
+        done = [r for r in out["requests"] if r.error is None]
+        return {"offered_per_s": rate, "requests": count, "completed": out["completed"],
+                "wall_s": round(out["wall_s"], 3), "completed_per_s": out["completed"] / out["wall_s"],
+                "p50_latency_s": out["p50_latency_s"], "p99_latency_s": out["p99_latency_s"],
+                "events_per_s": out["events_per_s"], "peak_resident": out["peak_active"],
+                "mean_wait_s": out["mean_wait_s"], "mean_build_s": out["mean_build_s"],
+                "neurons": int(sum(r.spec.num_neurons for r in done)),
+                "synapses": int(sum(r.spec.num_edges() for r in done))}
+
+    log(f"served stream: {args.serve_requests} requests at {args.serve_rate}/s")
+    over = window(args.serve_rate, args.serve_requests, args.seed + 100)
+    log(f"served (offered {args.serve_rate}/s): p50 {over['p50_latency_s']:.2f} s, p99 {over['p99_latency_s']:.2f} s, "
+        f"{over['completed_per_s']:.2f} req/s, {over['events_per_s']:.3g} events/s")
+    stable_rate = 0.7 * over["completed_per_s"]
+    n_stable = max(4, args.serve_requests // 2)
+    stable = window(stable_rate, n_stable, args.seed + 200)
+    log(f"served (offered {stable_rate:.2f}/s): p50 {stable['p50_latency_s']:.2f} s, "
+        f"p99 {stable['p99_latency_s']:.2f} s")
+    return {"offered": over, "stable": stable,
+            "recipe": "sizes log-uniform 1e4..2e6 neurons, in-degree U{200..600}, regime U{7,15,30} Hz, "
+                      "duration U[0.1, 2] s bio; latency = completion - arrival (host build included)"}
 
 
 def cpu_baseline(args, budget_s: float):
@@ -186,6 +258,103 @@ def calibrate_copy(args):
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
 
 
+def _rocpd(db):
+    """Per-kernel dispatch count, mean duration (us) and mean counter values from a rocprofv3 database."""
+    import collections
+    import sqlite3
+    c = sqlite3.connect(db)
+    q = ("select k.kernel_name, d.start, d.end from rocpd_kernel_dispatch d "
+         "join rocpd_info_kernel_symbol k on d.kernel_id = k.id")
+    dur = collections.defaultdict(list)
+    for name, t0, t1 in c.execute(q):
+        dur[name].append((t1 - t0) / 1e3)
+    pmc = collections.defaultdict(lambda: collections.defaultdict(float))
+    try:
+        q = ("select k.kernel_name, d.event_id, p.name, e.value from rocpd_pmc_event e "
+             "join rocpd_info_pmc p on e.pmc_id = p.id join rocpd_kernel_dispatch d on d.event_id = e.event_id "
+             "join rocpd_info_kernel_symbol k on d.kernel_id = k.id")
+        for name, ev, pn, val in c.execute(q):
+            pmc[(name, pn)][ev] += val  # sum over counter instances of one dispatch
+    except sqlite3.Error:
+        pass
+    out = {}
+    for name, v in dur.items():
+        out[name] = {"calls": len(v), "avg_us": sum(v) / len(v)}
+    for (name, pn), per_disp in pmc.items():
+        out.setdefault(name, {})[pn] = sum(per_disp.values()) / len(per_disp)
+    return out
+
+
+def _short(name):
+    for k in ("k_part", "k_bucket", "k_gather", "k_neuron", "k_compact", "k_readout_close", "copyBuffer"):
+        if k in name:
+            return k
+    return name
+
+
+def summarize_profiles(args):
+    """Writes the committed text summary and counter file from a directory of rocprofv3 runs:
+    trace/, fetch/, write/ (the bench command), cal_fetch/, cal_write/ (--calibrate-copy), and
+    fetch.log (the profiled bench run's output, for its event totals)."""
+    d = args.summarize_profiles
+    trace = _rocpd(os.path.join(d, "trace", "run_results.db"))
+    fetch = _rocpd(os.path.join(d, "fetch", "run_results.db"))
+    write = _rocpd(os.path.join(d, "write", "run_results.db"))
+    cf = _rocpd(os.path.join(d, "cal_fetch", "run_results.db"))
+    cw = _rocpd(os.path.join(d, "cal_write", "run_results.db"))
+    copy_bytes = 4 << 29
+    cal_f = next(v["FETCH_SIZE"] for k, v in cf.items() if "copyBuffer" in k and "FETCH_SIZE" in v)
+    cal_w = next(v["WRITE_SIZE"] for k, v in cw.items() if "copyBuffer" in k and "WRITE_SIZE" in v)
+    f_fac, w_fac = copy_bytes / (cal_f * 1024), copy_bytes / (cal_w * 1024)
+    run = None
+    with open(os.path.join(d, "fetch.log")) as f:
+        for line in f:
+            if line.startswith("{"):
+                run = json.loads(line)
+    tot = run["config"]["run_totals"]
+    ev_per_bin = tot["edge_events"] / tot["bins"]
+    per_bin = {}
+    for name in set(fetch) | set(write):
+        if "dbs" not in name:  # the library's kernels only (not the runtime's copy/fill kernels)
+            continue
+        if "FETCH_SIZE" in fetch.get(name, {}) and "WRITE_SIZE" in write.get(name, {}):
+            per_bin[_short(name)] = {"read": fetch[name]["FETCH_SIZE"] * 1024 * f_fac,
+                                     "write": write[name]["WRITE_SIZE"] * 1024 * w_fac}
+    cmd = args.profile_command
+    lines = [f"# Kernel trace and HBM byte counters: {run['config']['workload']}", "",
+             "Commands (from the repository root, PYTHONPATH=., TMPDIR=/tmp):",
+             f"  rocprofv3 --kernel-trace --stats -d OUT/trace -o run -- {cmd}",
+             f"  rocprofv3 --pmc FETCH_SIZE -d OUT/fetch -o run -- {cmd} > OUT/fetch.log",
+             f"  rocprofv3 --pmc WRITE_SIZE -d OUT/write -o run -- {cmd}",
+             "  rocprofv3 --pmc FETCH_SIZE -d OUT/cal_fetch -o run -- python3 bench.py --calibrate-copy",
+             "  rocprofv3 --pmc WRITE_SIZE -d OUT/cal_write -o run -- python3 bench.py --calibrate-copy",
+             "  python3 bench.py --summarize-profiles OUT", "",
+             f"Profiled run: {tot['bins']} bins in all (warm-up included), {ev_per_bin:.4g} edge events per bin "
+             f"on average; fan-in schedule {run['config']['fanin_schedule']}.", "",
+             "Kernel durations (kernel trace, every dispatch of the run):",
+             f"  {'kernel':46s} {'calls':>6s} {'avg us':>10s}"]
+    for name, v in sorted(trace.items(), key=lambda kv: -kv[1]["calls"] * kv[1]["avg_us"]):
+        lines.append(f"  {name[:46]:46s} {v['calls']:6d} {v['avg_us']:10.2f}")
+    lines += ["", f"Counter calibration: a 2 GiB device copy reads FETCH_SIZE {cal_f:.4g} KiB and WRITE_SIZE "
+                  f"{cal_w:.4g} KiB per launch -> scale factors FETCH x{f_fac:.3f}, WRITE x{w_fac:.3f}.", "",
+              "HBM-side bytes per bin (calibrated) and per edge event:"]
+    for k, v in sorted(per_bin.items()):
+        lines.append(f"  {k:18s} read {v['read'] / 1e6:9.1f} MB  write {v['write'] / 1e6:8.1f} MB   "
+                     f"({v['read'] / ev_per_bin:6.2f} + {v['write'] / ev_per_bin:6.2f} B/event)")
+    fan = sum(per_bin[k]["read"] + per_bin[k]["write"] for k in FANIN_KERNELS if k in per_bin)
+    lines.append(f"  fan-out phase total {fan / ev_per_bin:.2f} B per edge event (algorithmic model "
+                 f"{BYTES_PER_EVENT:.0f} B)")
+    base = os.path.join(ROOT, "profiles", "fanin_share6.1M_15hz")
+    with open(base + ".txt", "w") as f:
+        f.write("\n".join(lines) + "\n")
+    with open(base + "_counters.json", "w") as f:
+        json.dump({"kernel_source_hash": kernel_source_hash(), "edge_events_per_bin": ev_per_bin,
+                   "bins": tot["bins"], "copy_factors": {"fetch": f_fac, "write": w_fac},
+                   "bytes_per_bin": per_bin,
+                   "avg_us": {_short(k): v["avg_us"] for k, v in trace.items()}}, f, indent=1)
+    print("\n".join(lines))
+
+
 def tune(args):
     """Bisection of the background rate for target population rates (writes nothing)."""
     from netgen import configs
@@ -227,9 +396,16 @@ def main():
     ap.add_argument("--tune", action="store_true")
     ap.add_argument("--tune-iters", type=int, default=9)
     ap.add_argument("--calibrate-copy", action="store_true", help="run only a 2 GiB device copy (counter scaling)")
+    ap.add_argument("--summarize-profiles", default=None, help="directory of rocprofv3 runs to summarise (CPU only)")
+    ap.add_argument("--profile-command", default="python3 bench.py --steps 100 --warmup 200 --autotune 0 "
+                    "--no-cpu-baseline --ensemble 0", help="the profiled command, quoted in the summary")
     ap.add_argument("--autotune", type=int, default=1, help="autotune the fan-in schedule during warm-up")
     ap.add_argument("--ensemble", type=int, default=1, help="also run the batched-ensemble comparison")
     ap.add_argument("--members", type=int, default=64)
+    ap.add_argument("--serve", type=int, default=1, help="also run the served-stream leg")
+    ap.add_argument("--serve-rate", type=float, default=50.0, help="offered request arrivals per second")
+    ap.add_argument("--serve-requests", type=int, default=24, help="arrivals in the offered-rate window")
+    ap.add_argument("--serve-slots", type=int, default=16, help="most requests resident at once")
     ap.add_argument("--ensemble-bins", type=int, default=500, help="bins (ms) each member advances")
     ap.add_argument("--ensemble-warmup", type=int, default=50)
     args = ap.parse_args()
@@ -243,6 +419,9 @@ def main():
     if args.calibrate_copy:
         calibrate_copy(args)
         return
+    if args.summarize_profiles:
+        summarize_profiles(args)
+        return
     g = run_gpu(args)
     spec = g["spec"]
     value = g["events"] / g["wall"]
@@ -251,12 +430,17 @@ def main():
     roof = None
     if g["timed_bins"]:
         achieved = BYTES_PER_EVENT * g["events"] / (fan_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": "fan-out phase (k_scatter + k_gather)", "achieved": round(achieved, 1),
-                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+        traffic = measured_traffic(g["events"] / nb)
+        roof = {"bound": "hbm", "kernel": "fan-out phase (k_part + k_bucket + k_gather), per bin",
+                "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": None if traffic is None else round(traffic),
+                "traffic_unit": "bytes per bin (FETCH_SIZE x copy factor + WRITE_SIZE x copy factor)",
                 "bytes_per_event": BYTES_PER_EVENT, "events_per_launch": g["events"] / nb,
-                "avg_launch_ms": {"k_scatter": g["ms_scatter"] / nb, "k_gather": g["ms_gather"] / nb,
+                "avg_launch_ms": {"k_part+k_bucket": g["ms_scatter"] / nb, "k_gather": g["ms_gather"] / nb,
                                   "k_neuron": g["ms_neuron"] / nb, "readout_close": g["ms_readout"] / nb}}
     ens = run_ensemble(args) if args.ensemble else None
+    served = run_served(args) if args.serve else None
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, args.cpu_seconds)
@@ -270,9 +454,11 @@ def main():
                    "neurons": spec.num_neurons, "synapses": spec.num_edges(), "dt_ms": spec.dt_ms,
                    "bin_ms": spec.bin_ms, "regime_hz": args.regime, "mean_rate_hz": round(g["rate_hz"], 3),
                    "rtf": g["wall"] / g["bio_s"], "launch": args.mode, "build_s": round(g["build_s"], 1),
-                   "device_gb": round(g["hbm_bytes"] / 1e9, 2), "fanin_schedule": g["tuning"]},
+                   "device_gb": round(g["hbm_bytes"] / 1e9, 2), "fanin_schedule": g["tuning"],
+                   "run_totals": g["run_totals"]},
         "rtf_15hz": g["wall"] / g["bio_s"] if args.regime == 15 else None,
         "ensemble": ens,
+        "served": served,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -198,6 +198,54 @@ int dbsim_read_region_signal(struct dbsim* h, uint64_t bin_lo, uint64_t bin_hi, 
    GABA_A, [GABA_B]), refractory steps left ref[N]. Any pointer may be NULL. */
 int dbsim_read_state(struct dbsim* h, float* V, float* J, int32_t* ref);
 
+/*
+ * Region BOLD signal: the Balloon-Windkessel model of Extended Data Table 4,
+ * one per region, driven by the region's firing rate (Fig. 2a: firing rates from
+ * spike counts feed the haemodynamic model). At the end of every bin k each
+ * region r takes one explicit Euler step of length h = bin_ms / 1000 s (FP64):
+ *   z  = activity_scale * count_r(k) / (N_r * h)          (rate in Hz, scaled)
+ *   s' = s + h * (z - kappa * s - gamma * (f - 1))
+ *   f' = f + h * s
+ *   v' = v + (h / tau) * (f - v^(1/alpha))
+ *   q' = q + (h / tau) * (f * (1 - (1 - rho)^(1/f)) / rho - v^(1/alpha) * q / v)
+ * all right-hand sides at the old state; after every tr_bins bins the sample
+ *   y = V0 * (k1 * (1 - q) + k2 * (1 - q / v) + k3 * (1 - v))
+ * is recorded (a ring of the last 1024 samples per region). The paper gives no
+ * constants; the defaults (dbsim_bold_defaults) are the standard ones of the
+ * Balloon-Windkessel literature. Requires DBSIM_REC_REGIONS.
+ */
+typedef struct dbsim_bold_params {
+    double kappa;          /* 1/s, decay of the vasodilatory signal (0.65) */
+    double gamma;          /* 1/s, autoregulatory feedback (0.41) */
+    double tau;            /* s, haemodynamic transit time (0.98) */
+    double alpha;          /* Grubb's exponent (0.32) */
+    double rho;            /* resting oxygen extraction fraction (0.34) */
+    double V0;             /* resting blood volume fraction (0.02) */
+    double k1, k2, k3;     /* BOLD coefficients (7 rho, 2, 2 rho - 0.2) */
+    double activity_scale; /* z per Hz of region firing rate (0.01) */
+    uint32_t tr_bins;      /* bins per BOLD sample, >= 1 (800: TR = 0.8 s at 1 ms bins) */
+    uint32_t reserved;
+} dbsim_bold_params;
+
+/* Fills the default parameters. */
+void dbsim_bold_defaults(dbsim_bold_params* p);
+
+/* Turns the BOLD model on with these parameters (NULL: off) and resets every
+   region to rest (s = 0, f = v = q = 1) and the sample count to 0; sampling is
+   counted from the next completed bin. EINVAL for non-positive constants or
+   without DBSIM_REC_REGIONS. Synchronises. */
+int dbsim_set_bold(struct dbsim* h, const dbsim_bold_params* p);
+
+/* BOLD samples m with sample_lo <= m < sample_hi: y[(m - sample_lo) * n_regions + r].
+   cap counts entries. ERANGE if part of the range is not (or no longer) recorded;
+   ETRUNC if cap is too small (*n_out = entries needed). Synchronises. */
+int dbsim_read_bold(struct dbsim* h, uint64_t sample_lo, uint64_t sample_hi, double* y, uint64_t cap,
+                    uint64_t* n_out);
+
+/* The Balloon-Windkessel state, sfvq[4 * n_regions]: s, then f, v, q (region-major
+   within each). *n_samples (may be NULL) receives the samples taken so far. */
+int dbsim_read_bold_state(struct dbsim* h, double* sfvq, uint64_t* n_samples);
+
 /* Overwrites the state (checkpoint restore). Only at a bin boundary (ESTATE
    otherwise). ref values must lie in [0, 255]. */
 int dbsim_write_state(struct dbsim* h, const float* V, const float* J, const int32_t* ref);

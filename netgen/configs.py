@@ -22,6 +22,10 @@ multi_region    R regions x M neurons (default 200 x 5,000), 80/20 E/I, intra-re
 ensemble_member member m of a batched ensemble: N log-uniform in [2e4, 5e5],
                 in-degree uniform in 200..600, background rate and per-receptor
                 conductances each scaled by U[0.7, 1.3].
+served_request  request r of a served stream: N log-uniform in [1e4, 2e6], in-degree
+                uniform in 200..600, regime uniform over 7 / 15 / 30 Hz, duration
+                uniform in [0.1, 2] s of biological time (whole 1 ms bins); the
+                arrival times form a seeded Poisson process (arrival_times).
 """
 from __future__ import annotations
 
@@ -116,3 +120,23 @@ def ensemble_member(m: int, seed: int = 0, n_lo: float = 2e4, n_hi: float = 5e5)
                       d_mode=D_UNIFORM, d_min=1, d_max=10)]
     return NetSpec(pops, projs, seed=seed * 1000003 + m, net_id=m, dt_ms=0.1, bin_ms=1.0,
                    receptor_mask=RECEPTORS_4, name=f"member-{m}")
+
+
+def served_request(r: int, seed: int = 0, n_lo: float = 1e4, n_hi: float = 2e6, d_lo_s: float = 0.1,
+                   d_hi_s: float = 2.0):
+    """(network, biological duration in steps) of request r of a served stream."""
+    rng = np.random.default_rng([seed, 0x5E7E, r])
+    n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+    k = int(rng.integers(200, 601))
+    regime = int(rng.choice([7, 15, 30]))
+    bins = int(round(rng.uniform(d_lo_s, d_hi_s) * 1000.0))
+    spec = share(n=n, indegree=k, regime_hz=regime, seed=seed * 1000003 + r)
+    spec.net_id = r & 0xFFFFFF
+    spec.name = f"request-{r}-{n}-k{k}-{regime}hz"
+    return spec, bins * spec.steps_per_bin
+
+
+def arrival_times(count: int, rate_per_s: float, seed: int = 0) -> np.ndarray:
+    """Seeded Poisson arrival process: cumulative exponential gaps (seconds)."""
+    rng = np.random.default_rng([seed, 0xA11E])
+    return np.cumsum(rng.exponential(1.0 / rate_per_s, size=count))

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <array>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -148,6 +149,12 @@ void fill_devnet(dbsim* h) {
     n.n_l1 = p.n_l1;
     n.sig = at<double>(b, p.sig);
     n.sig_cnt = at<uint32_t>(b, p.sig_cnt);
+    n.bold_on = 0;
+    n.tr_bins = 1;
+    n.bold_zs = at<const double>(b, p.bold_zs);
+    n.bold = at<double>(b, p.bold);
+    n.bold_y = at<double>(b, p.bold_y);
+    n.bold_ctl = at<unsigned long long>(b, p.bold_ctl);
     n.ctl = at<Ctl>(b, p.ctl);
 }
 
@@ -356,7 +363,7 @@ static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32
         // upload
         auto up = [&](const Plan::Slot& s, const void* src, size_t bytes) -> hipError_t {
             if (!bytes) return hipSuccess;
-            return hipMemcpy(h->dev + s.off, src, bytes, hipMemcpyHostToDevice);
+            return hipMemcpyAsync(h->dev + s.off, src, bytes, hipMemcpyHostToDevice, h->stream);
         };
         hipError_t e = prepare_kernels();
         const size_t N = p.N;
@@ -372,32 +379,35 @@ static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32
         if (e == hipSuccess) e = up(p.blk, ht.blk.data(), sizeof(uint2) * ht.blk.size());
         if (e == hipSuccess) e = up(p.hdr, ht.hdr.data(), 4 * ht.hdr.size());
         if (e == hipSuccess) e = up(p.st_base, ht.st_base.data(), 8 * ht.st_base.size());
-        if (e == hipSuccess) e = hipMemset(h->dev + p.st_fill.off, 0, p.st_fill.bytes);
+        if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.st_fill.off, 0, p.st_fill.bytes, h->stream);
         if (e == hipSuccess) e = up(p.col, ht.col.data(), 4 * ht.col.size());
         if (e == hipSuccess) e = up(p.w, ht.w.data(), 4 * ht.w.size());
         if (e == hipSuccess) e = up(p.tile_base, ht.tile_base.data(), 8 * ht.tile_base.size());
-        if (e == hipSuccess) e = hipMemset(h->dev + p.tile_fill.off, 0, p.tile_fill.bytes);
-        if (e == hipSuccess) e = hipMemset(h->dev + p.grp_cnt.off, 0, p.grp_cnt.bytes);
-        if (e == hipSuccess) e = hipMemset(h->dev + p.bin_start.off, 0, p.bin_start.bytes);
-        if (e == hipSuccess) e = hipMemset(h->dev + p.bin_cnt.off, 0, p.bin_cnt.bytes);
-        if (e == hipSuccess) e = hipMemset(h->dev + p.blk_sig.off, 0, p.blk_sig.bytes);
-        if (e == hipSuccess) e = hipMemset(h->dev + p.blk_cnt.off, 0, p.blk_cnt.bytes);
+        if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.tile_fill.off, 0, p.tile_fill.bytes, h->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.grp_cnt.off, 0, p.grp_cnt.bytes, h->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.bin_start.off, 0, p.bin_start.bytes, h->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.bin_cnt.off, 0, p.bin_cnt.bytes, h->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.blk_sig.off, 0, p.blk_sig.bytes, h->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.blk_cnt.off, 0, p.blk_cnt.bytes, h->stream);
         if (e == hipSuccess) e = up(p.reg_blk_ptr, ht.reg_blk_ptr.data(), 4 * ht.reg_blk_ptr.size());
         if (e == hipSuccess) e = up(p.reg_blk, ht.reg_blk.data(), 4 * ht.reg_blk.size());
         if (e == hipSuccess) e = up(p.reg_size, ht.reg_size.data(), 4 * ht.reg_size.size());
         if (e == hipSuccess) e = up(p.l1_ptr, ht.l1_ptr.data(), 4 * ht.l1_ptr.size());
         if (e == hipSuccess) e = up(p.l1_region, ht.l1_region.data(), 4 * ht.l1_region.size());
-        if (e == hipSuccess) e = hipMemset(h->dev + p.sig.off, 0, p.sig.bytes);
-        if (e == hipSuccess) e = hipMemset(h->dev + p.sig_cnt.off, 0, p.sig_cnt.bytes);
-        if (e == hipSuccess) e = hipMemset(h->dev + p.ctl.off, 0, p.ctl.bytes);
-        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.sig.off, 0, p.sig.bytes, h->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.sig_cnt.off, 0, p.sig_cnt.bytes, h->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.ctl.off, 0, p.ctl.bytes, h->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.bold_ctl.off, 0, p.bold_ctl.bytes, h->stream);
+        // the host tables die with this call: wait for the copies on this handle's stream
+        // only (other handles keep running on theirs)
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         if (e != hipSuccess) {
             std::string msg = std::string("upload failed: ") + hipGetErrorString(e);
             release_device(h);
             delete h;
             return fail(DBSIM_EDEVICE, msg);
         }
-        // persistent grid for the scatter kernel: two 1024-thread blocks per CU
+        // grid of the partition kernels: scatter_wgs_per_cu blocks per CU
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) h->num_cus = prop.multiProcessorCount;
         h->scatter_wgs = p.scatter_wgs_per_cu;
@@ -660,6 +670,117 @@ int dbsim_export_csr(dbsim* h, uint64_t* row_ptr, uint32_t* seg, uint32_t* tgt, 
             if (w0) w0[e] = w[e * p.KW];
             if (w1) w1[e] = p.KW == 2 ? w[e * p.KW + 1] : 0.0f;
         }
+    }
+    return DBSIM_OK;
+}
+
+void dbsim_bold_defaults(dbsim_bold_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->kappa = 0.65;
+    p->gamma = 0.41;
+    p->tau = 0.98;
+    p->alpha = 0.32;
+    p->rho = 0.34;
+    p->V0 = 0.02;
+    p->k1 = 7.0 * p->rho;
+    p->k2 = 2.0;
+    p->k3 = 2.0 * p->rho - 0.2;
+    p->activity_scale = 0.01;
+    p->tr_bins = 800;
+}
+
+int dbsim_set_bold(dbsim* h, const dbsim_bold_params* bp) {
+    int rc = check_usable(h);
+    if (rc) return rc;
+    const Plan& p = h->plan;
+    if (bp) {
+        if (!p.regions_on) return fail(DBSIM_EINVAL, "the BOLD model needs DBSIM_REC_REGIONS");
+        const double v[] = {bp->kappa, bp->gamma, bp->tau, bp->alpha, bp->rho, bp->V0,
+                            bp->k1, bp->k2, bp->k3, bp->activity_scale};
+        for (double x : v)
+            if (!std::isfinite(x)) return fail(DBSIM_EINVAL, "BOLD parameters must be finite");
+        if (!(bp->tau > 0) || !(bp->alpha > 0) || !(bp->rho > 0 && bp->rho < 1) || bp->kappa < 0 ||
+            bp->gamma < 0 || bp->activity_scale < 0 || bp->tr_bins < 1)
+            return fail(DBSIM_EINVAL, "BOLD parameters out of range (tau, alpha > 0; 0 < rho < 1; kappa, gamma, "
+                                      "activity_scale >= 0; tr_bins >= 1)");
+    }
+    DeviceGuard dg(h->device);
+    rc = sync_and_check(h);
+    if (rc) return rc;
+    DevNet& n = h->net;
+    if (bp) {
+        const double hs = (double)h->mem.m[0].bin_ms * 1e-3;
+        std::vector<uint32_t> rs(p.n_regions);
+        HIPCHK(h, hipMemcpy(rs.data(), n.reg_size, 4 * rs.size(), hipMemcpyDeviceToHost), "hipMemcpy");
+        std::vector<double> zs(p.n_regions), st(4 * (size_t)p.n_regions, 1.0);
+        for (uint32_t r = 0; r < p.n_regions; r++) {
+            zs[r] = rs[r] ? bp->activity_scale / ((double)rs[r] * hs) : 0.0;
+            st[r] = 0.0; // s = 0, f = v = q = 1
+        }
+        const unsigned long long zero[2] = {0ull, 0ull};
+        HIPCHK(h, hipMemcpy((void*)n.bold_zs, zs.data(), 8 * zs.size(), hipMemcpyHostToDevice), "hipMemcpy");
+        HIPCHK(h, hipMemcpy(n.bold, st.data(), 8 * st.size(), hipMemcpyHostToDevice), "hipMemcpy");
+        HIPCHK(h, hipMemcpy(n.bold_ctl, zero, sizeof zero, hipMemcpyHostToDevice), "hipMemcpy");
+        n.bw_h = hs;
+        n.bw_htau = hs / bp->tau;
+        n.bw_kappa = bp->kappa;
+        n.bw_gamma = bp->gamma;
+        n.bw_inv_alpha = 1.0 / bp->alpha;
+        n.bw_rho = bp->rho;
+        n.bw_V0 = bp->V0;
+        n.bw_k1 = bp->k1;
+        n.bw_k2 = bp->k2;
+        n.bw_k3 = bp->k3;
+        n.tr_bins = bp->tr_bins;
+        n.bold_on = 1;
+    } else {
+        n.bold_on = 0;
+    }
+    // the kernels take the network descriptor by value: re-capture the graphs
+    if (h->g_multi) (void)hipGraphExecDestroy(h->g_multi);
+    if (h->g_one) (void)hipGraphExecDestroy(h->g_one);
+    h->g_multi = h->g_one = nullptr;
+    return DBSIM_OK;
+}
+
+int dbsim_read_bold(dbsim* h, uint64_t sample_lo, uint64_t sample_hi, double* y, uint64_t cap, uint64_t* n_out) {
+    int rc = check_usable(h);
+    if (rc) return rc;
+    if (!n_out || sample_hi < sample_lo) return fail(DBSIM_EINVAL, "bad arguments");
+    const Plan& p = h->plan;
+    if (!p.regions_on) return fail(DBSIM_EINVAL, "the BOLD model needs DBSIM_REC_REGIONS");
+    DeviceGuard dg(h->device);
+    rc = sync_and_check(h);
+    if (rc) return rc;
+    unsigned long long c[2];
+    HIPCHK(h, hipMemcpy(c, h->net.bold_ctl, sizeof c, hipMemcpyDeviceToHost), "hipMemcpy");
+    const uint64_t have = c[1], first = have > kBoldRing ? have - kBoldRing : 0;
+    if (sample_hi > have || sample_lo < first)
+        return fail(DBSIM_ERANGE, "BOLD samples " + std::to_string(sample_lo) + ".." + std::to_string(sample_hi) +
+                                      " not recorded (have " + std::to_string(first) + ".." + std::to_string(have) + ")");
+    const uint64_t R = p.n_regions, need = (sample_hi - sample_lo) * R;
+    *n_out = need;
+    if (!y || cap < need) return need ? fail(DBSIM_ETRUNC, "output buffer too small") : DBSIM_OK;
+    for (uint64_t m = sample_lo; m < sample_hi; m++)
+        HIPCHK(h, hipMemcpy(y + (m - sample_lo) * R, h->net.bold_y + (m & (kBoldRing - 1)) * R, 8 * R,
+                            hipMemcpyDeviceToHost), "hipMemcpy");
+    return DBSIM_OK;
+}
+
+int dbsim_read_bold_state(dbsim* h, double* sfvq, uint64_t* n_samples) {
+    int rc = check_usable(h);
+    if (rc) return rc;
+    const Plan& p = h->plan;
+    if (!p.regions_on) return fail(DBSIM_EINVAL, "the BOLD model needs DBSIM_REC_REGIONS");
+    DeviceGuard dg(h->device);
+    rc = sync_and_check(h);
+    if (rc) return rc;
+    if (sfvq) HIPCHK(h, hipMemcpy(sfvq, h->net.bold, 8 * 4 * (size_t)p.n_regions, hipMemcpyDeviceToHost), "hipMemcpy");
+    if (n_samples) {
+        unsigned long long c[2];
+        HIPCHK(h, hipMemcpy(c, h->net.bold_ctl, sizeof c, hipMemcpyDeviceToHost), "hipMemcpy");
+        *n_samples = c[1];
     }
     return DBSIM_OK;
 }

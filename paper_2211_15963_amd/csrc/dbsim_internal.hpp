@@ -26,6 +26,8 @@
 //     and count u32[MB] (rings indexed by bin & (MB-1));
 //   region readout: per-block partial sums f64/u32, per-region block lists,
 //     and a ring of MB bins of region signal f64[MB][n_regions] and counts;
+//   region BOLD: per-region activity scale f64[n_regions], Balloon-Windkessel state
+//     f64[4][n_regions] and a ring of kBoldRing samples f64[kBoldRing][n_regions];
 //   ctl: bin counter, delivered-event counter, sticky error bits.
 #pragma once
 
@@ -47,6 +49,7 @@ constexpr uint32_t kTileLdsBytes = 128u * 1024u; // LDS accumulator per tile
 constexpr uint32_t kErrArena = 1u;    // arena slice overflow (cannot happen by construction)
 constexpr uint32_t kErrLayout = 2u;   // a table entry outside its tile group (cannot happen by construction)
 constexpr uint32_t kMaxSuperTiles = 64; // buckets of the first partition pass
+constexpr uint32_t kBoldRing = 1024;     // BOLD samples kept per region (power of two)
 constexpr int kLoadBatch = 8;          // gather: records loaded per thread before they are consumed
 constexpr int kMaxBatch = 8;           // partition: events per thread per round (round_events <= 2048)
 constexpr uint32_t kChunk = 16;        // records per write-combined tile chunk (192 B with two weights)
@@ -130,6 +133,13 @@ struct DevNet {
     uint32_t n_l1;
     double* sig;
     uint32_t* sig_cnt;
+    // region BOLD (Balloon-Windkessel, Extended Data Table 4), stepped at every bin end
+    uint32_t bold_on, tr_bins;
+    double bw_h, bw_htau, bw_kappa, bw_gamma, bw_inv_alpha, bw_rho, bw_V0, bw_k1, bw_k2, bw_k3;
+    const double* bold_zs;           // per region: activity_scale / (N_r * h)
+    double* bold;                    // [4][n_regions]: s, f, v, q
+    double* bold_y;                  // [kBoldRing][n_regions] samples
+    unsigned long long* bold_ctl;    // [0] bins since enabled, [1] samples taken
     Ctl* ctl;
 };
 

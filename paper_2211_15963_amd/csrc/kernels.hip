@@ -856,6 +856,33 @@ __global__ void __launch_bounds__(256) k_compact(DevNet net) {
 // region r in a fixed tree. The last workgroup to finish sums each region's level-1
 // partials in ascending g (so the result does not depend on which workgroup is last),
 // then closes the bin: advances the spike-history ring and the bin counter.
+// One explicit Euler step (h = one bin) of region r's Balloon-Windkessel model driven by
+// the bin's spike count c, in the order of the equations of Extended Data Table 4 (all
+// right-hand sides at the old state), and the BOLD sample when a TR is complete.
+__device__ void bold_step(const DevNet& net, uint32_t r, uint32_t c) {
+    const uint32_t R = net.n_regions;
+    double* B = net.bold;
+    const double z = net.bold_zs[r] * (double)c;
+    const double s = B[r], f = B[R + r], v = B[2 * R + r], q = B[3 * R + r];
+    const double h = net.bw_h, ht = net.bw_htau, rho = net.bw_rho;
+    const double fout = pow(v, net.bw_inv_alpha);
+    const double E = 1.0 - pow(1.0 - rho, 1.0 / f);
+    const double s1 = s + h * (z - net.bw_kappa * s - net.bw_gamma * (f - 1.0));
+    const double f1 = f + h * s;
+    const double v1 = v + ht * (f - fout);
+    const double q1 = q + ht * (f * E / rho - fout * q / v);
+    B[r] = s1;
+    B[R + r] = f1;
+    B[2 * R + r] = v1;
+    B[3 * R + r] = q1;
+    const unsigned long long bb = net.bold_ctl[0] + 1; // bins stepped including this one
+    if (bb % net.tr_bins == 0) {
+        const unsigned long long m = bb / net.tr_bins - 1;
+        const double y = net.bw_V0 * (net.bw_k1 * (1.0 - q1) + net.bw_k2 * (1.0 - q1 / v1) + net.bw_k3 * (1.0 - v1));
+        net.bold_y[(size_t)(m & (kBoldRing - 1)) * R + r] = y;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_readout_close(DevNet net) {
     __shared__ double s[256];
     __shared__ uint32_t sc[256];
@@ -896,6 +923,13 @@ __global__ void __launch_bounds__(256) k_readout_close(DevNet net) {
             const size_t o = (size_t)(k & net.MBmask) * net.n_regions + rr;
             net.sig[o] = net.reg_size[rr] ? a / (double)net.reg_size[rr] : 0.0;
             net.sig_cnt[o] = c;
+            if (net.bold_on) bold_step(net, rr, c);
+        }
+        __syncthreads(); // every region has read the BOLD bin counter
+        if (net.bold_on && threadIdx.x == 0) {
+            const unsigned long long bb = net.bold_ctl[0] + 1;
+            net.bold_ctl[0] = bb;
+            if (bb % net.tr_bins == 0) net.bold_ctl[1] = bb / net.tr_bins;
         }
     }
     if (threadIdx.x == 0) {

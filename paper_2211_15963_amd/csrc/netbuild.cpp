@@ -236,6 +236,11 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     slot(p.l1_cnt, 4 * (size_t)p.n_l1);
     slot(p.sig, p.regions_on ? 8 * (size_t)p.MB * p.n_regions : 8);
     slot(p.sig_cnt, p.regions_on ? 4 * (size_t)p.MB * p.n_regions : 4);
+    const size_t RB = p.regions_on ? p.n_regions : 1;
+    slot(p.bold_zs, 8 * RB);
+    slot(p.bold, 8 * 4 * RB);
+    slot(p.bold_y, 8 * (size_t)kBoldRing * RB);
+    slot(p.bold_ctl, 16);
     slot(p.ctl, sizeof(Ctl));
     p.total = off;
     return "";

@@ -65,6 +65,23 @@ class SimTuning(Structure):
                 ("reserved", c_uint32)]
 
 
+class BoldParams(Structure):
+    _fields_ = [("kappa", c_double), ("gamma", c_double), ("tau", c_double), ("alpha", c_double),
+                ("rho", c_double), ("V0", c_double), ("k1", c_double), ("k2", c_double), ("k3", c_double),
+                ("activity_scale", c_double), ("tr_bins", c_uint32), ("reserved", c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+def bold_defaults(**overrides) -> BoldParams:
+    p = BoldParams()
+    lib().dbsim_bold_defaults(byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
 class DbsimError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{_NAMES.get(code, code)}: {msg}")
@@ -118,6 +135,11 @@ def lib():
     L.dbsim_set_timing.argtypes = [H, c_int]
     L.dbsim_get_stats.argtypes = [H, POINTER(SimStats)]
     L.dbsim_destroy.argtypes = [H]
+    L.dbsim_bold_defaults.argtypes = [POINTER(BoldParams)]
+    L.dbsim_bold_defaults.restype = None
+    L.dbsim_set_bold.argtypes = [H, POINTER(BoldParams)]
+    L.dbsim_read_bold.argtypes = [H, c_uint64, c_uint64, POINTER(c_double), c_uint64, POINTER(c_uint64)]
+    L.dbsim_read_bold_state.argtypes = [H, POINTER(c_double), POINTER(c_uint64)]
     for nm in EXPORTED:
         if nm not in ("dbsim_abi_version", "dbsim_last_error"):
             getattr(L, nm).restype = c_int
@@ -315,6 +337,36 @@ class Simulator:
         a, n, _, _ = self.member(m)
         V, J, ref = self.state()
         return V[a:a + n], J[:, a:a + n], ref[a:a + n]
+
+    def set_bold(self, params: Optional[BoldParams] = None, **overrides) -> None:
+        """Turns the region BOLD model on (defaults, optionally overridden) and resets it
+        to rest; set_bold(False) turns it off."""
+        if params is False:
+            _check(lib().dbsim_set_bold(self._h, None))
+            return
+        p = params if params is not None else bold_defaults()
+        for k, v in overrides.items():
+            setattr(p, k, v)
+        _check(lib().dbsim_set_bold(self._h, byref(p)))
+
+    def bold(self, sample_lo: int = 0, sample_hi: Optional[int] = None) -> np.ndarray:
+        """BOLD samples [samples][regions]."""
+        R = int(self.info.n_regions)
+        if sample_hi is None:
+            sample_hi = self.bold_state()[1]
+        nb = max(0, int(sample_hi) - int(sample_lo))
+        y = np.zeros(max(nb * R, 1), np.float64)
+        n = c_uint64(0)
+        _check(lib().dbsim_read_bold(self._h, int(sample_lo), int(sample_hi), _p(y, c_double), nb * R, byref(n)))
+        return y[: nb * R].reshape(nb, R)
+
+    def bold_state(self):
+        """(state [4][regions]: s, f, v, q; samples taken)."""
+        R = int(self.info.n_regions)
+        st = np.zeros(4 * R, np.float64)
+        n = c_uint64(0)
+        _check(lib().dbsim_read_bold_state(self._h, _p(st, c_double), byref(n)))
+        return st.reshape(4, R), int(n.value)
 
     def region_signal(self, bin_lo: int = 0, bin_hi: Optional[int] = None):
         R = int(self.info.n_regions)

@@ -56,6 +56,7 @@ int main(void) {
   O(dbsim_stats, ms_scatter); O(dbsim_stats, build_seconds); O(dbsim_info, frac_bits); O(dbsim_info, n_members);
   O(dbsim_info, fanin_passes);
   P(dbsim_member); O(dbsim_member, first_region);
+  P(dbsim_bold_params); O(dbsim_bold_params, activity_scale); O(dbsim_bold_params, tr_bins);
   return 0;
 }
 """
@@ -85,6 +86,9 @@ def test_struct_layouts_match_ctypes(L):
     assert int(out["dbsim_info.fanin_passes"]) == D.SimInfo.fanin_passes.offset
     assert int(out["dbsim_member"]) == ctypes.sizeof(D.SimMember)
     assert int(out["dbsim_member.first_region"]) == D.SimMember.first_region.offset
+    assert int(out["dbsim_bold_params"]) == ctypes.sizeof(D.BoldParams)
+    assert int(out["dbsim_bold_params.activity_scale"]) == D.BoldParams.activity_scale.offset
+    assert int(out["dbsim_bold_params.tr_bins"]) == D.BoldParams.tr_bins.offset
 
 
 def _create(L, spec, **kw):

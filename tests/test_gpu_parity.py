@@ -230,3 +230,26 @@ def test_fanin_schedules_agree(Sim, two_pass):
             assert np.array_equal(x, y)
         assert sim.stats()["edge_events"] == r_ev
         sim.close()
+
+
+def test_one_ms_euler_step_bit_exact(Sim):
+    """The paper's Delta_t = 1 ms setting (one Euler step per bin, S = 1)."""
+    spec = configs.tiny(dt_ms=1.0, seed=8)
+    _say("tiny with dt = bin = 1 ms (S = 1), 1000 steps")
+    sim = Sim(spec)
+    assert sim.S == 1
+    sim.step(1000)
+    orc = Oracle(spec, 32)
+    orc.step(1000)
+    _compare(sim, orc, spec)
+    sim.close()
+    spec = configs.share(n=20000, indegree=300, seed=9)
+    spec.dt_ms = 1.0
+    spec.pops[0].T_ref = spec.pops[1].T_ref = 2.0
+    _say("share 20000 / k300 with dt = 1 ms, 300 steps")
+    sim = Sim(spec)
+    sim.step(300)
+    orc = Oracle(spec, 32)
+    orc.step(300)
+    _compare(sim, orc, spec)
+    sim.close()

@@ -1,0 +1,82 @@
+"""Served stream: requests admitted by footprint and overlapped on the device give
+the same bits as each request run alone (every handle is independent and
+deterministic), and admission respects the HBM budget and the slot limit."""
+import sys
+
+import numpy as np
+import pytest
+
+from netgen import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _requests(count, seed, n_hi, d_hi_s, gap_s):
+    from paper_2211_15963_amd.serve import Request
+    out = []
+    for r in range(count):
+        spec, steps = configs.served_request(r, seed=seed, n_lo=1e4, n_hi=n_hi, d_lo_s=0.05, d_hi_s=d_hi_s)
+        out.append(Request(r, spec, steps, arrival_s=r * gap_s))
+    return out
+
+
+def _alone(req):
+    from paper_2211_15963_amd import Simulator
+    from paper_2211_15963_amd.serve import summarize
+    bins = -(-req.n_steps // req.spec.steps_per_bin)
+    sim = Simulator(req.spec, record_regions=True, record_bins=max(4096, bins))
+    sim.step(req.n_steps)
+    sim.sync()
+    out = summarize(sim)
+    sim.close()
+    return out
+
+
+def _same(a, b):
+    assert a["steps"] == b["steps"] and a["bins"] == b["bins"]
+    assert a["spikes"] == b["spikes"] and a["edge_events"] == b["edge_events"]
+    assert np.array_equal(a["bin_spikes"], b["bin_spikes"])
+    assert a["state_sha256"] == b["state_sha256"]
+
+
+def test_served_results_equal_alone():
+    from paper_2211_15963_amd.serve import Server
+    reqs = _requests(8, seed=11, n_hi=8e4, d_hi_s=0.2, gap_s=0.02)
+    _say(f"serve 8 requests, sizes {[r.spec.num_neurons for r in reqs]}, steps {[r.n_steps for r in reqs]}")
+    srv = Server(max_active=4, slice_bins=10, build_workers=2)
+    out = srv.run(reqs)
+    assert out["completed"] == 8 and out["failed"] == 0
+    assert 1 <= out["peak_active"] <= 4
+    for r in out["requests"]:
+        assert r.result["spikes"] > 0
+        assert r.t_admit >= r.arrival_s - 1e-9 and r.t_built >= r.t_admit and r.t_done >= r.t_built
+    for r in sorted(out["requests"], key=lambda r: r.rid):
+        _say(f"  request {r.rid}: {r.spec.num_neurons} neurons, latency {r.latency_s:.3f} s; alone run")
+        _same(r.result, _alone(r))
+
+
+def test_admission_by_footprint():
+    from paper_2211_15963_amd.dbsim import footprint
+    from paper_2211_15963_amd.serve import Server
+    reqs = _requests(6, seed=12, n_hi=5e4, d_hi_s=0.1, gap_s=0.0)
+    fps = sorted(footprint(r.spec, record_regions=True) for r in reqs)
+    budget = fps[-1] + fps[-2]  # room for two of the largest at most
+    _say(f"serve 6 requests with an HBM budget of {budget} B")
+    srv = Server(hbm_budget=budget, max_active=16, slice_bins=5, build_workers=2)
+    out = srv.run(reqs)
+    assert out["completed"] == 6
+    # no more than the budget resident at once: replay admissions and retirements
+    events = sorted([(r.t_admit, r.footprint) for r in out["requests"]] +
+                    [(r.t_done, -r.footprint) for r in out["requests"]], key=lambda e: (e[0], e[1]))
+    use = 0
+    for _, d in events:
+        use += d
+        assert use <= budget
+    too_big = _requests(1, seed=13, n_hi=2e4, d_hi_s=0.06, gap_s=0.0)
+    out = Server(hbm_budget=1 << 20, max_active=2).run(too_big)
+    assert out["completed"] == 0 and out["failed"] == 1 and "exceeds" in out["requests"][0].error
