@@ -36,6 +36,7 @@ BYTES_PER_NEURON_BIN = 128.0   # neuron step: V, J[4], ref read+write, g_u[4], a
 
 
 FANIN_KERNELS = ("k_part", "k_bucket", "k_gather")
+PHASES = ("ms_scatter", "ms_gather", "ms_neuron", "ms_readout")
 COUNTERS_JSON = os.path.join(ROOT, "profiles", "fanin_share6.1M_15hz_counters.json")
 KERNEL_SOURCES = ("paper_2211_15963_amd/csrc/kernels.hip", "paper_2211_15963_amd/csrc/dbsim_internal.hpp")
 
@@ -101,18 +102,33 @@ def run_gpu(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     s1 = sim.stats()
-    log(f"timed {args.steps} bins in {wall:.3f} s")
+    log(f"timed {args.steps} bins in {wall:.3f} s ({args.mode} launches)")
     events = s1["edge_events"] - s0["edge_events"]
     spikes = s1["spikes"] - s0["spikes"]
     bio_s = args.steps * spec.bin_ms * 1e-3
+    # per-kernel durations: HIP events between the phases on the handle's stream (one
+    # stream, nothing overlapped), over a further window of the same run
+    p0, p1, pbins = s0, s1, args.steps
+    if args.mode == "graph" and args.phase_bins > 0:
+        sim.set_timing(True)
+        p0 = sim.stats()
+        sim.step(args.phase_bins * S)
+        sim.sync()
+        p1 = sim.stats()
+        sim.set_timing(False)
+        pbins = args.phase_bins
+        log(f"phase timing window: {pbins} bins, {sum(p1[k] - p0[k] for k in PHASES) / pbins:.3f} ms per bin "
+            f"without overlap")
+    s2 = sim.stats()
     out = {
         "events": events, "spikes": spikes, "wall": wall, "bio_s": bio_s,
         "rate_hz": spikes / (spec.num_neurons * bio_s),
-        "ms_scatter": s1["ms_scatter"] - s0["ms_scatter"], "ms_gather": s1["ms_gather"] - s0["ms_gather"],
-        "ms_neuron": s1["ms_neuron"] - s0["ms_neuron"], "ms_readout": s1["ms_readout"] - s0["ms_readout"],
-        "timed_bins": s1["timed_bins"] - s0["timed_bins"], "spec": spec, "build_s": s1["build_seconds"],
+        "phase_events": p1["edge_events"] - p0["edge_events"],
+        "ms_scatter": p1["ms_scatter"] - p0["ms_scatter"], "ms_gather": p1["ms_gather"] - p0["ms_gather"],
+        "ms_neuron": p1["ms_neuron"] - p0["ms_neuron"], "ms_readout": p1["ms_readout"] - p0["ms_readout"],
+        "timed_bins": p1["timed_bins"] - p0["timed_bins"], "spec": spec, "build_s": s1["build_seconds"],
         "hbm_bytes": s1["hbm_bytes"], "tuning": sim.tuning(),
-        "run_totals": {"bins": s1["bins"], "edge_events": s1["edge_events"]},
+        "run_totals": {"bins": s2["bins"], "edge_events": s2["edge_events"]},
     }
     sim.close()
     return out
@@ -390,7 +406,10 @@ def main():
     ap.add_argument("--indegree", type=int, default=556)
     ap.add_argument("--regime", type=int, default=15, choices=[7, 15, 30])
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--mode", default="timed", choices=["timed", "graph", "direct"])
+    ap.add_argument("--mode", default="graph", choices=["graph", "timed", "direct"],
+                    help="graph: replayed HIP graphs with the next bin's fan-in overlapped (headline), then a "
+                         "window of timed phases for the roofline; timed: timed phases only")
+    ap.add_argument("--phase-bins", type=int, default=300, help="bins of the per-kernel timing window")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", action="store_true")
@@ -429,14 +448,15 @@ def main():
     nb = max(1, g["timed_bins"])
     roof = None
     if g["timed_bins"]:
-        achieved = BYTES_PER_EVENT * g["events"] / (fan_ms * 1e-3) / 1e9
-        traffic = measured_traffic(g["events"] / nb)
+        achieved = BYTES_PER_EVENT * g["phase_events"] / (fan_ms * 1e-3) / 1e9
+        traffic = measured_traffic(g["phase_events"] / nb)
         roof = {"bound": "hbm", "kernel": "fan-out phase (k_part + k_bucket + k_gather), per bin",
                 "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": None if traffic is None else round(traffic),
                 "traffic_unit": "bytes per bin (FETCH_SIZE x copy factor + WRITE_SIZE x copy factor)",
-                "bytes_per_event": BYTES_PER_EVENT, "events_per_launch": g["events"] / nb,
+                "bytes_per_event": BYTES_PER_EVENT, "events_per_launch": g["phase_events"] / nb,
+                "phase_window_bins": nb,
                 "avg_launch_ms": {"k_part+k_bucket": g["ms_scatter"] / nb, "k_gather": g["ms_gather"] / nb,
                                   "k_neuron": g["ms_neuron"] / nb, "readout_close": g["ms_readout"] / nb}}
     ens = run_ensemble(args) if args.ensemble else None

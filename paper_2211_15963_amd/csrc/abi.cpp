@@ -42,7 +42,8 @@ struct DeviceGuard {
 };
 
 constexpr int kGraphBins = 8; // bins captured in one replayable graph
-constexpr int kPhases = 4;    // scatter, gather, neuron, readout+close
+constexpr int kPhases = 4;    // reported phases: scatter (partition), gather, neuron, bin end
+constexpr int kMarks = 7;     // events per timed bin (six intervals, see resolve_timers)
 
 } // namespace
 
@@ -54,6 +55,8 @@ struct dbsim {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipStream_t cap_stream = nullptr;
+    hipStream_t side_stream = nullptr; // the next bin's delay >= 2 fan-in, beside the neuron step
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     unsigned char* dev = nullptr;
     DevNet net{};
     int scatter_grid = 256;
@@ -64,8 +67,8 @@ struct dbsim {
     uint64_t step = 0;
     int dead = 0; // sticky error code
     bool timing = false;
-    std::vector<std::array<hipEvent_t, kPhases + 1>> ev_pending;
-    std::vector<std::array<hipEvent_t, kPhases + 1>> ev_pool;
+    std::vector<std::array<hipEvent_t, kMarks>> ev_pending;
+    std::vector<std::array<hipEvent_t, kMarks>> ev_pool;
     double ms[kPhases] = {0, 0, 0, 0};
     uint64_t timed_bins = 0;
     double build_seconds = 0.0;
@@ -158,31 +161,54 @@ void fill_devnet(dbsim* h) {
     n.ctl = at<Ctl>(b, p.ctl);
 }
 
+// Bin schedule. The arrivals due at the start of bin k come from the spikes of bins k-d,
+// d = 1..D. Those with d >= 2 only need bins that are already complete while bin k-1's
+// neurons are being stepped, so they are assembled then ("ahead", on a side stream when
+// the bin runs as a whole); at the start of bin k only the delay-1 part is left. Bin 0
+// has nothing to assemble ahead. Order per bin k:
+//   start: partition d = 1 (bin k) -> gather (A for bin k)
+//   step:  neuron (bin k)                 | side: partition d = 2..D (bin k+1)
+//   end:   compact (bin k) -> join side -> readout and bin close (resets the streams)
 hipError_t enqueue_bin_start(dbsim* h, hipStream_t st) {
-    hipError_t e = launch_scatter(h->net, h->scatter_grid, st);
+    hipError_t e = launch_scatter(h->net, h->scatter_grid, st, 1, 1, 0);
     if (e != hipSuccess) return e;
     return launch_gather(h->net, st);
 }
 
+hipError_t enqueue_ahead(dbsim* h, hipStream_t st) {
+    if (h->plan.D < 2) return hipSuccess;
+    return launch_scatter(h->net, h->scatter_grid, st, 2, h->plan.D, 1);
+}
+
 hipError_t enqueue_bin_end(dbsim* h, hipStream_t st) {
     hipError_t e = launch_compact(h->net, st);
+    if (e == hipSuccess) e = enqueue_ahead(h, st);
     if (e != hipSuccess) return e;
     return launch_readout_close(h->net, st);
 }
 
-hipError_t enqueue_full_bin(dbsim* h, hipStream_t st) {
+// One whole bin with the next bin's delay >= 2 fan-in forked onto the side stream right
+// after the gather (it touches neither the neuron state nor this bin's spike list) and
+// joined before the bin close.
+hipError_t enqueue_full_bin(dbsim* h, hipStream_t st, hipStream_t side) {
     hipError_t e = enqueue_bin_start(h, st);
+    const bool fork = h->plan.D >= 2;
+    if (e == hipSuccess && fork) e = hipEventRecord(h->ev_fork, st);
+    if (e == hipSuccess && fork) e = hipStreamWaitEvent(side, h->ev_fork, 0);
+    if (e == hipSuccess && fork) e = enqueue_ahead(h, side);
+    if (e == hipSuccess && fork) e = hipEventRecord(h->ev_join, side);
+    if (e == hipSuccess) e = launch_neuron(h->net, 0, (int)h->plan.S, st);
+    if (e == hipSuccess) e = launch_compact(h->net, st);
+    if (e == hipSuccess && fork) e = hipStreamWaitEvent(st, h->ev_join, 0);
     if (e != hipSuccess) return e;
-    e = launch_neuron(h->net, 0, (int)h->plan.S, st);
-    if (e != hipSuccess) return e;
-    return enqueue_bin_end(h, st);
+    return launch_readout_close(h->net, st);
 }
 
 hipError_t capture_graph(dbsim* h, int bins, hipGraphExec_t* out) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    for (int b = 0; b < bins && e == hipSuccess; b++) e = enqueue_full_bin(h, h->cap_stream);
+    for (int b = 0; b < bins && e == hipSuccess; b++) e = enqueue_full_bin(h, h->cap_stream, h->side_stream);
     hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
     if (e == hipSuccess) e = e2;
     if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -190,8 +216,8 @@ hipError_t capture_graph(dbsim* h, int bins, hipGraphExec_t* out) {
     return e;
 }
 
-std::array<hipEvent_t, kPhases + 1> take_events(dbsim* h, hipError_t* e) {
-    std::array<hipEvent_t, kPhases + 1> ev{};
+std::array<hipEvent_t, kMarks> take_events(dbsim* h, hipError_t* e) {
+    std::array<hipEvent_t, kMarks> ev{};
     *e = hipSuccess;
     if (!h->ev_pool.empty()) {
         ev = h->ev_pool.back();
@@ -206,12 +232,16 @@ std::array<hipEvent_t, kPhases + 1> take_events(dbsim* h, hipError_t* e) {
 }
 
 int resolve_timers(dbsim* h) {
+    // marks of a timed bin: 0 partition d=1 | 1 gather | 2 neuron | 3 compact | 4 partition
+    // d>=2 of the next bin | 5 readout and close | 6; the partition intervals add up to the
+    // scatter phase, compact and readout to the bin-end phase
+    static const int phase_of[kMarks - 1] = {0, 1, 2, 3, 0, 3};
     for (auto& ev : h->ev_pending) {
-        for (int k = 0; k < kPhases; k++) {
+        for (int k = 0; k < kMarks - 1; k++) {
             float ms = 0.0f;
             hipError_t e = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
             if (e != hipSuccess) return hip_fail(h, e, "hipEventElapsedTime");
-            h->ms[k] += ms;
+            h->ms[phase_of[k]] += ms;
         }
         h->timed_bins++;
         h->ev_pool.push_back(ev);
@@ -253,8 +283,12 @@ void release_device(dbsim* h) {
         h->dev = nullptr;
     }
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->side_stream) (void)hipStreamDestroy(h->side_stream);
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
-    h->cap_stream = h->stream = nullptr;
+    h->cap_stream = h->side_stream = h->stream = nullptr;
+    h->ev_fork = h->ev_join = nullptr;
 }
 
 } // namespace
@@ -354,10 +388,13 @@ static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32
         }
         {
             hipError_t se = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+            if (se == hipSuccess) se = hipStreamCreateWithFlags(&h->side_stream, hipStreamNonBlocking);
+            if (se == hipSuccess) se = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
+            if (se == hipSuccess) se = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming);
             if (se != hipSuccess) {
                 release_device(h);
                 delete h;
-                return fail(DBSIM_EDEVICE, std::string("hipStreamCreateWithFlags (capture): ") + hipGetErrorString(se));
+                return fail(DBSIM_EDEVICE, std::string("stream/event creation: ") + hipGetErrorString(se));
             }
         }
         // upload
@@ -482,18 +519,25 @@ int dbsim_step(dbsim* h, uint64_t n_steps) {
                         hipError_t e;
                         auto ev = take_events(h, &e);
                         HIPCHK(h, e, "hipEventCreate");
-                        HIPCHK(h, hipEventRecord(ev[0], h->stream), "hipEventRecord");
-                        HIPCHK(h, launch_scatter(h->net, h->scatter_grid, h->stream), "scatter launch");
-                        HIPCHK(h, hipEventRecord(ev[1], h->stream), "hipEventRecord");
-                        HIPCHK(h, launch_gather(h->net, h->stream), "gather launch");
-                        HIPCHK(h, hipEventRecord(ev[2], h->stream), "hipEventRecord");
-                        HIPCHK(h, launch_neuron(h->net, 0, (int)S, h->stream), "neuron launch");
-                        HIPCHK(h, hipEventRecord(ev[3], h->stream), "hipEventRecord");
-                        HIPCHK(h, enqueue_bin_end(h, h->stream), "readout launch");
-                        HIPCHK(h, hipEventRecord(ev[4], h->stream), "hipEventRecord");
+                        // one stream, an event between phases (no overlap, so that each
+                        // kernel's duration is its own)
+                        hipStream_t st = h->stream;
+                        HIPCHK(h, hipEventRecord(ev[0], st), "hipEventRecord");
+                        HIPCHK(h, launch_scatter(h->net, h->scatter_grid, st, 1, 1, 0), "partition launch");
+                        HIPCHK(h, hipEventRecord(ev[1], st), "hipEventRecord");
+                        HIPCHK(h, launch_gather(h->net, st), "gather launch");
+                        HIPCHK(h, hipEventRecord(ev[2], st), "hipEventRecord");
+                        HIPCHK(h, launch_neuron(h->net, 0, (int)S, st), "neuron launch");
+                        HIPCHK(h, hipEventRecord(ev[3], st), "hipEventRecord");
+                        HIPCHK(h, launch_compact(h->net, st), "compact launch");
+                        HIPCHK(h, hipEventRecord(ev[4], st), "hipEventRecord");
+                        HIPCHK(h, enqueue_ahead(h, st), "partition launch");
+                        HIPCHK(h, hipEventRecord(ev[5], st), "hipEventRecord");
+                        HIPCHK(h, launch_readout_close(h->net, st), "readout launch");
+                        HIPCHK(h, hipEventRecord(ev[6], st), "hipEventRecord");
                         h->ev_pending.push_back(ev);
                     } else {
-                        HIPCHK(h, enqueue_full_bin(h, h->stream), "bin launch");
+                        HIPCHK(h, enqueue_full_bin(h, h->stream, h->side_stream), "bin launch");
                     }
                 }
             } else {

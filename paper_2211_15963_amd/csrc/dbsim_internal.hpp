@@ -20,8 +20,8 @@
 //     tile_base[t+1]: the tile's total in-degree (the most events a tile can
 //     receive in one bin: an edge delivers at most once per bin), plus, when
 //     k_part writes whole chunks, kChunk records of padding per partition
-//     workgroup; the super-tile streams of the two-pass form use the same
-//     record format;
+//     workgroup and partition launch (two per bin); the super-tile streams of
+//     the two-pass form use the same record format;
 //   spike history: rec u32[RC] ring of (id << 4 | substep), per-bin start u64[MB]
 //     and count u32[MB] (rings indexed by bin & (MB-1));
 //   region readout: per-block partial sums f64/u32, per-region block lists,
@@ -75,6 +75,7 @@ struct Ctl {
     unsigned long long spikes;      // spikes emitted in closed bins
     unsigned int err;               // sticky error bits
     unsigned int done;              // readout workgroups finished in the current bin
+    unsigned long long ahead_events; // events of the next bin assembled ahead, not yet delivered
 };
 
 struct DevNet {
@@ -145,7 +146,8 @@ struct DevNet {
 
 // kernel launchers (kernels.hip); each enqueues on `st` and returns the launch status
 hipError_t prepare_kernels(); // one-time function attributes (LDS opt-in); call outside graph capture
-hipError_t launch_scatter(const DevNet& n, int grid, hipStream_t st);
+// fan-in of the delays d_lo..d_hi of the current bin (ahead = 0) or of the next one (ahead = 1)
+hipError_t launch_scatter(const DevNet& n, int grid, hipStream_t st, uint32_t d_lo, uint32_t d_hi, uint32_t ahead);
 hipError_t launch_gather(const DevNet& n, hipStream_t st);
 hipError_t launch_neuron(const DevNet& n, int s0, int s1, hipStream_t st);
 hipError_t launch_compact(const DevNet& n, hipStream_t st);

@@ -381,7 +381,7 @@ __device__ void wc_write(const DevNet& net, Round& R, Wc& W, uint32_t ne, uint32
 // wc != 0: the buckets are the tiles, written as whole chunks through the carry buffers.
 // wc == 0: the buckets are the super-tile streams (runs), re-bucketed by k_bucket.
 template <int KW>
-__global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net) {
+__global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d_lo, uint32_t d_hi, uint32_t ahead) {
     extern __shared__ __align__(16) unsigned char dyn[];
     const uint32_t D = net.D, RE = net.round_events;
     const bool wc = net.wc != 0;
@@ -399,14 +399,17 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net) {
 
     uint32_t* s_dcnt = reinterpret_cast<uint32_t*>(dyn + L.dcnt);
     uint16_t* s_map = reinterpret_cast<uint16_t*>(dyn + L.smap);
-    const unsigned long long k = net.ctl->bin;
+    // the bin whose arrivals are assembled: the current one, or (ahead = 1, while the
+    // current bin's neurons are still being stepped) the next one
+    const unsigned long long k = net.ctl->bin + ahead;
     const uint32_t tid = threadIdx.x;
-    // spike lists of bins k-1 .. k-D (one thread per delay), then their prefix
+    // spike lists of bins k-d for the delays d_lo <= d <= d_hi (one thread per delay),
+    // then their prefix over all D delays (the other delays contribute nothing)
     for (uint32_t x = tid; x < D; x += blockDim.x) {
         const uint32_t d = x + 1;
         uint32_t cnt = 0;
         unsigned long long st = 0;
-        if (k >= d) {
+        if (k >= d && d >= d_lo && d <= d_hi) {
             const uint32_t b = (uint32_t)((k - d) & net.MBmask);
             st = net.bin_start[b];
             cnt = net.bin_cnt[b];
@@ -508,7 +511,9 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net) {
         wc_reserve(net, R, W, nb, true);
         wc_write<KW>(net, R, W, 0, nb, bshift, true);
     }
-    if (tid == 0 && my_events) atomicAdd(&net.ctl->edge_events, my_events);
+    // events count as delivered when their bin's arrivals are consumed (the gather moves
+    // the ahead count over)
+    if (tid == 0 && my_events) atomicAdd(ahead ? &net.ctl->ahead_events : &net.ctl->edge_events, my_events);
 }
 
 // Records in super-tile stream st. A stream never holds more than its slice (each edge
@@ -631,8 +636,17 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(DevNet net) {
     }
     __syncthreads();
     if (threadIdx.x == 0) net.tile_fill[t] = 0;
+    // the super-tile streams are empty again: this bin's delay-1 records are in the tile
+    // arena, and the next bin's delay >= 2 records start from the front (the bin close
+    // clears them again after those have been bucketed)
     if (t == 0)
         for (uint32_t x = threadIdx.x; x < net.NS; x += blockDim.x) net.st_fill[x] = 0;
+    // this bin's events assembled ahead are delivered now (no partition of the next bin
+    // runs before the gather has finished)
+    if (t == 0 && threadIdx.x == 0) {
+        net.ctl->edge_events += net.ctl->ahead_events;
+        net.ctl->ahead_events = 0;
+    }
     const float qinv = net.qinv;
     for (uint32_t x = threadIdx.x; x < nt; x += blockDim.x) {
 #pragma unroll
@@ -932,6 +946,9 @@ __global__ void __launch_bounds__(256) k_readout_close(DevNet net) {
             if (bb % net.tr_bins == 0) net.bold_ctl[1] = bb / net.tr_bins;
         }
     }
+    // the super-tile streams are empty again: the next bin's delay >= 2 records have been
+    // bucketed before this kernel starts, its delay-1 records come next
+    for (uint32_t x = threadIdx.x; x < net.NS; x += blockDim.x) net.st_fill[x] = 0;
     if (threadIdx.x == 0) {
         const uint32_t m = net.MBmask;
         const uint32_t c = net.bin_cnt[k & m];
@@ -963,13 +980,13 @@ hipError_t prepare_kernels() {
                                (int)kTileLdsBytes);
 }
 
-hipError_t launch_scatter(const DevNet& n, int grid, hipStream_t st) {
+hipError_t launch_scatter(const DevNet& n, int grid, hipStream_t st, uint32_t d_lo, uint32_t d_hi, uint32_t ahead) {
     const size_t la = part_lds_bytes(n.wc ? n.T : n.NS, n.round_events, n.wc != 0, n.D);
     const size_t lb = bucket_lds_bytes(1u << n.ts_bits, n.round_events);
     if (n.KW == 2)
-        hipLaunchKernelGGL(k_part<2>, dim3(grid), dim3(kScatterThreads), la, st, n);
+        hipLaunchKernelGGL(k_part<2>, dim3(grid), dim3(kScatterThreads), la, st, n, d_lo, d_hi, ahead);
     else
-        hipLaunchKernelGGL(k_part<1>, dim3(grid), dim3(kScatterThreads), la, st, n);
+        hipLaunchKernelGGL(k_part<1>, dim3(grid), dim3(kScatterThreads), la, st, n, d_lo, d_hi, ahead);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || n.wc) return e;
     if (n.KW == 2)

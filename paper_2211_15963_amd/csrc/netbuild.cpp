@@ -177,7 +177,7 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
                 return "background rate too high for the Poisson table (rate * dt above about 20)";
             const uint32_t kin = indeg_of_pop(n, q);
             // super-tile streams and tile slices are indexed with 32-bit fill counters
-            if (((uint64_t)kin << (p.tile_bits + p.ts_bits)) + (uint64_t)kChunk * (kMaxPartGrid + 1) >= (1ull << 32))
+            if (((uint64_t)kin << (p.tile_bits + p.ts_bits)) + (uint64_t)kChunk * (2 * kMaxPartGrid + 1) >= (1ull << 32))
                 return "in-degree too large for a super-tile stream";
             p.E += (uint64_t)P.size * kin;
             const uint32_t nb = (P.size + kNeuronBlock - 1) / kNeuronBlock;
@@ -212,7 +212,7 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     slot(p.col, 4 * E);
     slot(p.w, 4 * (size_t)p.KW * E);
     // event arena: write-combined tile slices are padded (see build_tables)
-    const size_t arena = p.wc ? E + (size_t)p.T * (kChunk - 1 + (size_t)kChunk * kMaxPartGrid) : E;
+    const size_t arena = p.wc ? E + (size_t)p.T * (kChunk - 1 + 2 * (size_t)kChunk * kMaxPartGrid) : E;
     slot(p.ev, 4 * (size_t)(1 + p.KW) * arena);
     slot(p.tile_base, 8 * ((size_t)p.T + 1));
     slot(p.tile_fill, 4 * (size_t)p.T);
@@ -336,10 +336,11 @@ std::string build_tables(const Members& mem, const Plan& p, unsigned threads, Ho
         if (sum != p.E) return "internal error: edge count mismatch";
     }
     // write-combined form: every slice starts on a whole chunk and holds, besides the
-    // tile's in-degree, one padded chunk per partition workgroup
+    // tile's in-degree, one padded chunk per partition workgroup and partition launch
+    // (two launches per bin: delay 1, and delays 2..D)
     for (uint32_t t = 0; t < p.T; t++) {
         uint64_t len = h.tile_base[t + 1];
-        if (p.wc) len = (len + kChunk - 1) / kChunk * kChunk + (uint64_t)kChunk * kMaxPartGrid;
+        if (p.wc) len = (len + kChunk - 1) / kChunk * kChunk + 2ull * kChunk * kMaxPartGrid;
         h.tile_base[t + 1] = h.tile_base[t] + len;
     }
 

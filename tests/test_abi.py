@@ -134,8 +134,9 @@ def test_footprint_matches_layout(L):
     assert E == 100000 * 556
     # dominant terms: targets (4 B), two weights (8 B) and the tile arena record (12 B) per
     # edge; 25 tiles of 4096 neurons are written directly in 16-record chunks, with room
-    # for one padded chunk per partition workgroup (at most 512) in every tile slice
-    pad = 25 * (15 + 16 * 512) * 12
+    # for one padded chunk per partition workgroup (at most 2048) and launch (two per bin)
+    # in every tile slice
+    pad = 25 * (15 + 2 * 16 * 2048) * 12
     assert 24 * E + pad < fp < 24 * E + pad + 60 * 100000 + (64 << 20)
     # 1490 tiles are too many for the write-combining buffers: two passes, with a 12 B
     # super-tile stream record per edge as well
