@@ -126,8 +126,7 @@ void fill_devnet(dbsim* h) {
     n.ptab = at<const uint32_t>(b, p.ptab);
     n.blk = at<const uint2>(b, p.blk);
     n.hdr = at<const uint32_t>(b, p.hdr);
-    n.col = at<const uint32_t>(b, p.col);
-    n.w = at<const float>(b, p.w);
+    n.edge = at<const uint32_t>(b, p.edge);
     n.ev = at<uint32_t>(b, p.ev);
     n.tile_base = at<const uint64_t>(b, p.tile_base);
     n.tile_fill = at<uint32_t>(b, p.tile_fill);
@@ -417,8 +416,7 @@ static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32
         if (e == hipSuccess) e = up(p.hdr, ht.hdr.data(), 4 * ht.hdr.size());
         if (e == hipSuccess) e = up(p.st_base, ht.st_base.data(), 8 * ht.st_base.size());
         if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.st_fill.off, 0, p.st_fill.bytes, h->stream);
-        if (e == hipSuccess) e = up(p.col, ht.col.data(), 4 * ht.col.size());
-        if (e == hipSuccess) e = up(p.w, ht.w.data(), 4 * ht.w.size());
+        if (e == hipSuccess) e = up(p.edge, ht.edge.data(), 4 * ht.edge.size());
         if (e == hipSuccess) e = up(p.tile_base, ht.tile_base.data(), 8 * ht.tile_base.size());
         if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.tile_fill.off, 0, p.tile_fill.bytes, h->stream);
         if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.grp_cnt.off, 0, p.grp_cnt.bytes, h->stream);
@@ -706,13 +704,17 @@ int dbsim_export_csr(dbsim* h, uint64_t* row_ptr, uint32_t* seg, uint32_t* tgt, 
         }
         if (row_ptr) row_ptr[p.N] = p.E;
     }
-    if (tgt) HIPCHK(h, hipMemcpy(tgt, h->net.col, 4 * p.E, hipMemcpyDeviceToHost), "hipMemcpy");
-    if (w0 || w1) {
-        std::vector<float> w((size_t)p.E * p.KW);
-        HIPCHK(h, hipMemcpy(w.data(), h->net.w, 4 * w.size(), hipMemcpyDeviceToHost), "hipMemcpy");
+    if (tgt || w0 || w1) { // split the edge records
+        const size_t RW = 1 + p.KW;
+        std::vector<uint32_t> rec((size_t)p.E * RW);
+        HIPCHK(h, hipMemcpy(rec.data(), h->net.edge, 4 * rec.size(), hipMemcpyDeviceToHost), "hipMemcpy");
         for (uint64_t e = 0; e < p.E; e++) {
-            if (w0) w0[e] = w[e * p.KW];
-            if (w1) w1[e] = p.KW == 2 ? w[e * p.KW + 1] : 0.0f;
+            if (tgt) tgt[e] = rec[e * RW];
+            if (w0) std::memcpy(&w0[e], &rec[e * RW + 1], 4);
+            if (w1) {
+                if (p.KW == 2) std::memcpy(&w1[e], &rec[e * RW + 2], 4);
+                else w1[e] = 0.0f;
+            }
         }
     }
     return DBSIM_OK;

@@ -10,8 +10,9 @@
 //     uniform (scalar registers);
 //   connection table by presynaptic neuron (Suppl. Table 5's table is stored
 //     by target; the push-based fan-out of Suppl. Algorithm 2 wants it by
-//     source): col u32[E] (target), w f32[KW][E] interleaved per edge, rows
-//     sorted by delay, then target; one row header per neuron, hdr u32[N][HW]
+//     source): one record of 1 + KW words per edge (target, then the weights),
+//     so that a (spike, delay) segment is one contiguous run; rows sorted by
+//     delay, then target; one row header per neuron, hdr u32[N][HW]
 //     (HW = D + 3 rounded up to 4 words: the row start as u64 with the source
 //     class in bit 63, then the D + 1 delay segment offsets inside the row), so
 //     that one 64-byte read gives everything a (spike, delay) segment needs;
@@ -103,9 +104,8 @@ struct DevNet {
     const uint32_t* ptab;
     const uint2* blk; // (first neuron, population)
     // connection table
-    const uint32_t* hdr; // [N][HW] row headers
-    const uint32_t* col;
-    const float* w;
+    const uint32_t* hdr;  // [N][HW] row headers
+    const uint32_t* edge; // [E][1 + KW] records: target, then the weights
     // event arena: records of (1 + KW) words: target within tile | source class << 31, weights
     uint32_t* ev;
     const uint64_t* tile_base;

@@ -488,8 +488,15 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
                     const uint32_t lo = s_map[m], hi = m + 1 < nmap ? s_map[m + 1] : nseg - 1;
                     const uint32_t s = lo + seg_search(s_spre + lo, hi - lo + 1, ge);
                     const unsigned long long edge = s_sstart[s] + (ge - s_spre[s]);
-                    B.key[u] = net.col[edge] | ((uint32_t)s_scls[s] << 31);
-                    B.w[u] = KW == 2 ? reinterpret_cast<const float2*>(net.w)[edge] : make_float2(net.w[edge], 0.0f);
+                    if (KW == 2) {
+                        const uint3 r = reinterpret_cast<const uint3*>(net.edge)[edge];
+                        B.key[u] = r.x | ((uint32_t)s_scls[s] << 31);
+                        B.w[u] = make_float2(__uint_as_float(r.y), __uint_as_float(r.z));
+                    } else {
+                        const uint2 r = reinterpret_cast<const uint2*>(net.edge)[edge];
+                        B.key[u] = r.x | ((uint32_t)s_scls[s] << 31);
+                        B.w[u] = make_float2(__uint_as_float(r.y), 0.0f);
+                    }
                 }
             }
 #pragma unroll

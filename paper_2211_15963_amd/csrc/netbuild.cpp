@@ -209,8 +209,7 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     slot(p.ptab, 4 * (size_t)kMaxPoisson * p.n_pops);
     slot(p.blk, sizeof(uint2) * p.n_blocks);
     slot(p.hdr, 4 * N * (size_t)p.HW);
-    slot(p.col, 4 * E);
-    slot(p.w, 4 * (size_t)p.KW * E);
+    slot(p.edge, 4 * (size_t)(1 + p.KW) * E);
     // event arena: write-combined tile slices are padded (see build_tables)
     const size_t arena = p.wc ? E + (size_t)p.T * (kChunk - 1 + 2 * (size_t)kChunk * kMaxPartGrid) : E;
     slot(p.ev, 4 * (size_t)(1 + p.KW) * arena);
@@ -401,8 +400,8 @@ std::string build_tables(const Members& mem, const Plan& p, unsigned threads, Ho
         for (uint32_t x = 0; x < D; x++)
             cur[(size_t)j * D + x].store(h.row_ptr[j] + h.seg[(size_t)j * (D + 1) + x], std::memory_order_relaxed);
     cnt.reset();
-    h.col.resize(p.E);
-    h.w.resize((size_t)p.E * KW);
+    const size_t RW = 1 + KW; // words per edge record: target, then the weights
+    h.edge.resize((size_t)p.E * RW);
     const double wlim = std::ldexp(1.0, 52 - (int)p.F);
     std::atomic<int> wbad{0};
     parallel_chunks(N, 256, nt, [&](unsigned, uint64_t a, uint64_t b) {
@@ -421,9 +420,10 @@ std::string build_tables(const Members& mem, const Plan& p, unsigned threads, Ho
             }
             for (int64_t e = 0; e < k; e++) {
                 const uint64_t pos = cur[(size_t)(src[e] + base) * D + dl[e] - 1].fetch_add(1, std::memory_order_relaxed);
-                h.col[pos] = (uint32_t)i;
-                h.w[pos * KW] = w0[e];
-                if (KW == 2) h.w[pos * KW + 1] = w1[e];
+                uint32_t* rec = &h.edge[pos * RW];
+                rec[0] = (uint32_t)i;
+                std::memcpy(&rec[1], &w0[e], 4);
+                if (KW == 2) std::memcpy(&rec[2], &w1[e], 4);
                 if (!(std::fabs((double)w0[e]) < wlim) || !(std::fabs((double)w1[e]) < wlim)) wbad.store(1);
             }
         }
@@ -435,8 +435,7 @@ std::string build_tables(const Members& mem, const Plan& p, unsigned threads, Ho
     // consecutive targets, so each delay segment splits into contiguous group sub-segments)
     parallel_chunks(N, 1024, nt, [&](unsigned, uint64_t a, uint64_t b) {
         struct Ed {
-            uint32_t t;
-            float w0, w1;
+            uint32_t t, w0, w1; // target and the weights' bit patterns
         };
         std::vector<Ed> tmp;
         for (uint64_t j = a; j < b; j++) {
@@ -446,12 +445,12 @@ std::string build_tables(const Members& mem, const Plan& p, unsigned threads, Ho
                 if (s1 - s0 < 2) continue;
                 tmp.resize(s1 - s0);
                 for (uint64_t e = s0; e < s1; e++)
-                    tmp[e - s0] = Ed{h.col[e], h.w[e * KW], KW == 2 ? h.w[e * KW + 1] : 0.0f};
+                    tmp[e - s0] = Ed{h.edge[e * RW], h.edge[e * RW + 1], KW == 2 ? h.edge[e * RW + 2] : 0u};
                 std::sort(tmp.begin(), tmp.end(), [](const Ed& A, const Ed& B) { return A.t < B.t; });
                 for (uint64_t e = s0; e < s1; e++) {
-                    h.col[e] = tmp[e - s0].t;
-                    h.w[e * KW] = tmp[e - s0].w0;
-                    if (KW == 2) h.w[e * KW + 1] = tmp[e - s0].w1;
+                    h.edge[e * RW] = tmp[e - s0].t;
+                    h.edge[e * RW + 1] = tmp[e - s0].w0;
+                    if (KW == 2) h.edge[e * RW + 2] = tmp[e - s0].w1;
                 }
             }
         }

@@ -48,7 +48,7 @@ struct Plan {
     struct Slot {
         size_t off = 0, bytes = 0;
     };
-    Slot V, J, ref, pend, A, pops, ptab, blk, hdr, col, w, ev, tile_base, tile_fill, st_base, st_fill, sev, stage,
+    Slot V, J, ref, pend, A, pops, ptab, blk, hdr, edge, ev, tile_base, tile_fill, st_base, st_fill, sev, stage,
         grp_cnt, rec, bin_start, bin_cnt, blk_sig, blk_cnt, reg_blk_ptr, reg_blk, reg_size, l1_ptr, l1_region, l1_sig,
         l1_cnt, sig, sig_cnt, bold_zs, bold, bold_y, bold_ctl, ctl;
     size_t total = 0;
@@ -70,8 +70,7 @@ struct HostTables {
     std::vector<uint2> blk;
     std::vector<uint64_t> row_ptr;
     std::vector<uint32_t> seg; // [N][D+1] delay segments
-    std::vector<uint32_t> col;
-    std::vector<float> w; // KW floats per edge, interleaved
+    std::vector<uint32_t> edge; // [E][1 + KW]: target, then the weights (bit patterns)
     std::vector<uint8_t> src_inh;
     std::vector<uint32_t> hdr; // [N][HW] device row headers
     std::vector<uint64_t> tile_base, st_base;
