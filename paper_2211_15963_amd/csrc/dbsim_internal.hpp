@@ -42,8 +42,8 @@ namespace dbs {
 
 constexpr int kMaxPoisson = 64;       // Poisson thresholds per population
 constexpr int kNeuronBlock = 256;     // neurons per block of the neuron kernel
-constexpr int kScatterThreads = 256;  // threads per block of the partition kernels (several blocks per CU)
-constexpr int kScatterSegs = 256;     // (spike, delay) segments per partition chunk (one per thread)
+constexpr int kScatterThreads = 512;  // threads per block of the partition kernels (several blocks per CU)
+constexpr int kScatterSegs = 512;     // (spike, delay) segments per partition chunk (one per thread)
 constexpr int kGatherThreads = 1024;
 constexpr int kMaxTilesLds = 16384;   // most tiles (at most 256 buckets in the second partition pass)
 constexpr uint32_t kTileLdsBytes = 128u * 1024u; // LDS accumulator per tile
@@ -52,7 +52,7 @@ constexpr uint32_t kErrLayout = 2u;   // a table entry outside its tile group (c
 constexpr uint32_t kMaxSuperTiles = 64; // buckets of the first partition pass
 constexpr uint32_t kBoldRing = 1024;     // BOLD samples kept per region (power of two)
 constexpr int kLoadBatch = 8;          // gather: records loaded per thread before they are consumed
-constexpr int kMaxBatch = 8;           // partition: events per thread per round (round_events <= 2048)
+constexpr int kMaxBatch = 8;           // partition: events per thread per round (round_events <= 4096)
 constexpr uint32_t kChunk = 16;        // records per write-combined tile chunk (192 B with two weights)
 constexpr uint32_t kMaxPartGrid = 2048; // most partition workgroups (bounds the chunk padding per tile)
 constexpr uint32_t kMaxLdsBytes = 160u * 1024u;
@@ -77,6 +77,7 @@ struct Ctl {
     unsigned int err;               // sticky error bits
     unsigned int done;              // readout workgroups finished in the current bin
     unsigned long long ahead_events; // events of the next bin assembled ahead, not yet delivered
+    unsigned int bdone;              // k_bucket workgroups finished in the current launch
 };
 
 struct DevNet {
@@ -88,6 +89,7 @@ struct DevNet {
     uint32_t HW;           // words per row header
     uint32_t round_events; // events staged in LDS per partition round
     uint32_t chunks_per_wg; // target scatter chunks per workgroup and bin
+    uint32_t ahead_passes;  // partition passes of the next bin's delay >= 2 fan-in (two-pass form)
     uint64_t RCmask;
     uint32_t MBmask;
     double qscale;   // 2^F

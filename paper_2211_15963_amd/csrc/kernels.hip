@@ -1,16 +1,19 @@
 // kernels.hip - gfx950 kernels of one spike bin.
 //
 // Per bin k (S Euler steps of dt, SI Section 3):
-//   k_part     fan-in of the arrivals due at the start of bin k, pass A. Every
-//              spike j of bin k-d (d = 1..D) contributes its delay-d edges (Suppl.
-//              Algorithm 2 pushes a spike list through destination lists; here
-//              the delay ring is read backwards, so all events of a bin land in
-//              one accumulator). Whole delay segments are read (contiguous table
-//              reads) and their events are partitioned into at most 64
-//              super-tile streams through LDS: one reservation per non-empty
-//              super-tile per round instead of one global atomic per event.
-//   k_bucket   pass B: each super-tile stream is partitioned into its tiles the
-//              same way (skipped when every super-tile is a single tile).
+//   k_part     fan-in of the arrivals due at the start of bin k: every spike j of
+//              bin k-d (d = 1..D) contributes its delay-d edges (Suppl. Algorithm 2
+//              pushes a spike list through destination lists; here the delay ring
+//              is read backwards, so all events of a bin land in one accumulator).
+//              Whole delay segments are read (contiguous 12-byte edge records) and
+//              their events are radix-partitioned through LDS, with one global
+//              reservation per non-empty bucket per round instead of one atomic per
+//              event: straight into the target tiles in whole chunks (carry buffers
+//              per tile) when the tiles are few, else into at most 64 super-tile
+//              streams. Launched twice per bin: delays 2..D of bin k+1 while bin k's
+//              neurons are stepped (side stream), delay 1 at the start of bin k+1.
+//   k_bucket   second pass of the two-pass form: each super-tile stream is
+//              partitioned into its tiles the same way.
 //   k_gather   one workgroup per tile: sums its events in LDS as int64 fixed
 //              point (exact, so any order gives the same bits), converts once
 //              to float, writes A.
@@ -19,9 +22,10 @@
 //              reset and refractory clamp, receptor decay (eq. 3); at the bin
 //              end, wavefront-ballot compaction of the spike list and the
 //              per-block region partial sums.
-//   k_readout  per-region mean synaptic current and spike count (fixed-order
-//              tree over the region's block partials).
-//   k_close    advances the bin counter and the spike-history ring.
+//   k_compact  places every block's staged spikes in the bin's dense spike list.
+//   k_readout_close  per-region mean synaptic current and spike count (fixed-order
+//              tree over the region's block partials), the region BOLD step
+//              (Extended Data Table 4), and the bin close (bin counter, spike ring).
 //
 // All float arithmetic is single IEEE operations in a fixed order (the file
 // is built with -ffp-contract=off and f32 denormals preserved) so the result
@@ -595,6 +599,19 @@ __global__ void __launch_bounds__(kScatterThreads) k_bucket(DevNet net) {
         __syncthreads();
         write_runs<KW>(net, R, ne, nt, t0, net.tile_bits, net.ev);
     }
+    // the last workgroup to finish empties the streams for the next partition pass (every
+    // workgroup read the fill counts in its prologue, before it got here)
+    __shared__ bool last;
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();
+        last = atomicAdd(&net.ctl->bdone, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last) {
+        for (uint32_t st = tid; st < NS; st += blockDim.x) net.st_fill[st] = 0;
+        if (tid == 0) net.ctl->bdone = 0;
+    }
 }
 
 size_t part_lds_bytes(uint32_t nb, uint32_t RE, bool wc, uint32_t D) { return PartLayout(nb, RE, wc, D).total; }
@@ -976,8 +993,8 @@ hipError_t prepare_kernels() {
     const void* big[] = {(const void*)k_part<1>, (const void*)k_part<2>, (const void*)k_bucket<1>,
                          (const void*)k_bucket<2>};
     hipError_t e = hipSuccess;
-    for (const void* f : big) {
-        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytes);
+    for (const void* f : big) { // leave room for the kernels' few static LDS bytes
+        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytes - 256);
         if (e != hipSuccess) return e;
     }
     e = hipFuncSetAttribute((const void*)k_gather<1>, hipFuncAttributeMaxDynamicSharedMemorySize,

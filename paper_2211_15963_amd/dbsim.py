@@ -62,7 +62,7 @@ class SimMember(Structure):
 
 class SimTuning(Structure):
     _fields_ = [("scatter_wgs_per_cu", c_uint32), ("round_events", c_uint32), ("chunks_per_wg", c_uint32),
-                ("reserved", c_uint32)]
+                ("ahead_passes", c_uint32)]
 
 
 class BoldParams(Structure):
@@ -301,10 +301,11 @@ class Simulator:
         t = SimTuning()
         _check(lib().dbsim_get_tuning(self._h, byref(t)))
         return {"scatter_wgs_per_cu": t.scatter_wgs_per_cu, "round_events": t.round_events,
-                "chunks_per_wg": t.chunks_per_wg}
+                "chunks_per_wg": t.chunks_per_wg, "ahead_passes": t.ahead_passes}
 
-    def set_tuning(self, scatter_wgs_per_cu: int = 1, round_events: int = 0, chunks_per_wg: int = 2) -> None:
-        t = SimTuning(int(scatter_wgs_per_cu), int(round_events), int(chunks_per_wg), 0)
+    def set_tuning(self, scatter_wgs_per_cu: int = 1, round_events: int = 0, chunks_per_wg: int = 2,
+                   ahead_passes: int = 0) -> None:
+        t = SimTuning(int(scatter_wgs_per_cu), int(round_events), int(chunks_per_wg), int(ahead_passes))
         _check(lib().dbsim_set_tuning(self._h, byref(t)))
 
     def spikes(self, step_lo: int = 0, step_hi: Optional[int] = None):

@@ -214,10 +214,10 @@ def test_fanin_schedules_agree(Sim, two_pass):
     r_ev = ref.stats()["edge_events"]
     assert len(r_sp[0]) > 0
     ref.close()
-    for wgs, re, cpw in ((1, 0, 1), (2, 256, 64), (3, 512, 2), (8, 0, 8), (4, 1536, 4)):
+    for wgs, re, cpw, ap in ((1, 0, 1, 1), (2, 256, 64, 9), (3, 512, 2, 2), (8, 0, 8, 0), (4, 1536, 4, 5)):
         sim = Sim(spec, two_pass=two_pass)
         try:
-            sim.set_tuning(scatter_wgs_per_cu=wgs, round_events=re, chunks_per_wg=cpw)
+            sim.set_tuning(scatter_wgs_per_cu=wgs, round_events=re, chunks_per_wg=cpw, ahead_passes=ap)
         except Exception as ex:  # a schedule that does not fit the LDS is refused up front
             assert "LDS" in str(ex)
             sim.close()
