@@ -25,12 +25,20 @@ static inline uint64_t mix64(uint64_t z) {
     return z ^ (z >> 31);
 }
 
+/* the draws of one (stream, target): key = the first two rounds, which do not depend on
+   the projection and index; draw = the third */
+static inline uint64_t stream_key(const dbnet_desc* d, uint32_t stream, uint32_t target) {
+    uint64_t h = mix64(d->seed + 0x9E3779B97F4A7C15ULL * (uint64_t)(1u + stream));
+    return mix64(h ^ (((uint64_t)d->net_id << 32) | target));
+}
+
+static inline uint64_t draw_k(uint64_t key, uint32_t proj, uint64_t idx) {
+    return mix64(key ^ ((uint64_t)proj << 48) ^ idx);
+}
+
 static inline uint64_t draw(const dbnet_desc* d, uint32_t stream, uint32_t target, uint32_t proj,
                             uint64_t idx) {
-    uint64_t h = mix64(d->seed + 0x9E3779B97F4A7C15ULL * (uint64_t)(1u + stream));
-    h = mix64(h ^ (((uint64_t)d->net_id << 32) | target));
-    h = mix64(h ^ ((uint64_t)proj << 48) ^ idx);
-    return h;
+    return draw_k(stream_key(d, stream, target), proj, idx);
 }
 
 /* uniform double in [0,1) from the top 53 bits */
@@ -243,14 +251,14 @@ static int set_insert(uint64_t* tab, uint32_t cap, uint64_t key) {
     }
 }
 
-static double weight_draw(const dbnet_desc* d, const dbnet_proj* pr, uint32_t st_a, uint32_t st_b,
-                          uint32_t i, uint32_t j, uint64_t e) {
+/* key_a / key_b: stream keys of the weight's two streams for this target */
+static double weight_draw(const dbnet_proj* pr, uint64_t key_a, uint64_t key_b, uint32_t j, uint64_t e) {
     switch (pr->w_dist) {
-    case DBNET_W_UNIFORM: return (double)pr->w_a + ((double)pr->w_b - (double)pr->w_a) * u01(draw(d, st_a, i, j, e));
+    case DBNET_W_UNIFORM: return (double)pr->w_a + ((double)pr->w_b - (double)pr->w_a) * u01(draw_k(key_a, j, e));
     case DBNET_W_LOGNORMAL: {
         /* Box-Muller normal deviate */
-        double r = sqrt(-2.0 * log(u01_open0(draw(d, st_a, i, j, e))));
-        double z = r * cos(6.283185307179586 * u01(draw(d, st_b, i, j, e)));
+        double r = sqrt(-2.0 * log(u01_open0(draw_k(key_a, j, e))));
+        double z = r * cos(6.283185307179586 * u01(draw_k(key_b, j, e)));
         return exp((double)pr->w_a + (double)pr->w_b * z);
     }
     default: return (double)pr->w_a;
@@ -275,6 +283,9 @@ int64_t dbnet_in_edges(const dbnet_desc* d, uint32_t i, uint32_t* src, float* w0
     const uint32_t kw = dbnet_weights_per_edge(d);
     const dbnet_pop* T = &d->pops[tp];
     int64_t out = 0;
+    const uint64_t k_sample = stream_key(d, ST_SAMPLE, i), k_delay = stream_key(d, ST_DELAY, i);
+    const uint64_t k_w0 = stream_key(d, ST_W0, i), k_w0b = stream_key(d, ST_W0B, i);
+    const uint64_t k_w1 = stream_key(d, ST_W1, i), k_w1b = stream_key(d, ST_W1B, i);
 
     for (uint32_t j = 0; j < d->n_projs; j++) {
         const dbnet_proj* pr = &d->projs[j];
@@ -298,7 +309,7 @@ int64_t dbnet_in_edges(const dbnet_desc* d, uint32_t i, uint32_t* src, float* w0
         memset(hash, 0, (size_t)hcap * 8);
         uint32_t np = 0;
         for (uint64_t t = M - k; t < M; t++) {
-            uint64_t r = below(draw(d, ST_SAMPLE, i, j, t), t + 1);
+            uint64_t r = below(draw_k(k_sample, j, t), t + 1);
             if (set_insert(hash, hcap, r)) picked[np++] = r;
             else { set_insert(hash, hcap, t); picked[np++] = t; }
         }
@@ -325,13 +336,13 @@ int64_t dbnet_in_edges(const dbnet_desc* d, uint32_t i, uint32_t* src, float* w0
             const dbnet_pop* Sp = &d->pops[q];
             double scale = Sp->exc ? (double)pr->w_scale_exc : (double)pr->w_scale_inh;
             src[out] = s;
-            if (w0) w0[out] = (float)(scale * weight_draw(d, pr, ST_W0, ST_W0B, i, j, a));
-            if (w1) w1[out] = kw == 2 ? (float)(scale * weight_draw(d, pr, ST_W1, ST_W1B, i, j, a)) : 0.0f;
+            if (w0) w0[out] = (float)(scale * weight_draw(pr, k_w0, k_w0b, j, a));
+            if (w1) w1[out] = kw == 2 ? (float)(scale * weight_draw(pr, k_w1, k_w1b, j, a)) : 0.0f;
             uint32_t dl;
             if (pr->d_mode == DBNET_D_FIXED) {
                 dl = pr->d_min;
             } else if (pr->d_mode == DBNET_D_UNIFORM) {
-                dl = pr->d_min + (uint32_t)below(draw(d, ST_DELAY, i, j, a), pr->d_max - pr->d_min + 1);
+                dl = pr->d_min + (uint32_t)below(draw_k(k_delay, j, a), pr->d_max - pr->d_min + 1);
             } else {
                 const float* xs = d->region_xyz_mm + 3 * Sp->region;
                 const float* xt = d->region_xyz_mm + 3 * T->region;

@@ -431,7 +431,7 @@ static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32
         if (e == hipSuccess) e = up(p.hdr, ht.hdr.data(), 4 * ht.hdr.size());
         if (e == hipSuccess) e = up(p.st_base, ht.st_base.data(), 8 * ht.st_base.size());
         if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.st_fill.off, 0, p.st_fill.bytes, h->stream);
-        if (e == hipSuccess) e = up(p.edge, ht.edge.data(), 4 * ht.edge.size());
+        if (e == hipSuccess) e = up(p.edge, ht.edge.get(), 4 * ht.edge_words);
         if (e == hipSuccess) e = up(p.tile_base, ht.tile_base.data(), 8 * ht.tile_base.size());
         if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.tile_fill.off, 0, p.tile_fill.bytes, h->stream);
         if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.grp_cnt.off, 0, p.grp_cnt.bytes, h->stream);

@@ -15,6 +15,8 @@
 #include <memory>
 #include <thread>
 
+#include <unistd.h>
+
 namespace dbs {
 
 namespace {
@@ -71,6 +73,20 @@ uint32_t indeg_of_pop(const dbnet_desc& d, uint32_t p) {
 }
 
 } // namespace
+
+// one edge on its way from its target to its source's row (bucketed construction)
+struct BucketEdge {
+    uint32_t src_dl; // source index within its block << 8 | delay
+    uint32_t tgt;
+    uint32_t w0, w1; // weight bit patterns
+};
+// host memory the bucketed construction may hold: 30 % of the machine's memory, at most
+// 64 GiB (larger networks take the two-pass construction)
+static double bucket_build_bytes() {
+    const long pages = sysconf(_SC_PHYS_PAGES), psz = sysconf(_SC_PAGE_SIZE);
+    const double phys = pages > 0 && psz > 0 ? (double)pages * (double)psz : 16.0 * (1ull << 30);
+    return std::min(0.3 * phys, 64.0 * (1ull << 30));
+}
 
 uint32_t max_round_events(const Plan& p, uint32_t wgs_per_cu) {
     const size_t budget = kMaxLdsBytes / wgs_per_cu - 256;
@@ -352,109 +368,210 @@ std::string build_tables(const Members& mem, const Plan& p, unsigned threads, Ho
         }
     });
 
-    // pass 1: out-degree per (source, delay)
     size_t scratch_bytes = 0;
     uint32_t kmax = 1;
     for (const auto& d : mem.m) {
         scratch_bytes = std::max(scratch_bytes, dbnet_scratch_bytes(&d));
         kmax = std::max(kmax, dbnet_max_indegree(&d));
     }
-    std::unique_ptr<std::atomic<uint32_t>[]> cnt(new std::atomic<uint32_t>[(size_t)N * D]);
-    for (size_t x = 0; x < (size_t)N * D; x++) cnt[x].store(0, std::memory_order_relaxed);
-    std::atomic<int> gen_fail{0};
-    parallel_chunks(N, 256, nt, [&](unsigned, uint64_t a, uint64_t b) {
-        std::vector<uint32_t> src(kmax);
-        std::vector<uint8_t> dl(kmax);
-        std::vector<unsigned char> scratch(scratch_bytes);
-        for (uint64_t i = a; i < b; i++) {
-            const uint32_t m = mem.member_of(i);
-            const uint64_t base = mem.nbase[m];
-            const int64_t k = dbnet_in_edges(&mem.m[m], (uint32_t)(i - base), src.data(), nullptr, nullptr, dl.data(),
-                                             scratch.data());
-            if (k < 0) {
-                gen_fail.store(1);
-                return;
-            }
-            for (int64_t e = 0; e < k; e++)
-                cnt[(size_t)(src[e] + base) * D + dl[e] - 1].fetch_add(1, std::memory_order_relaxed);
-        }
-    });
-    if (gen_fail.load()) return "network generator failed";
-    h.row_ptr.assign((size_t)N + 1, 0ull);
-    h.seg.assign((size_t)N * (D + 1), 0u);
-    for (uint32_t j = 0; j < N; j++) {
-        uint64_t acc = 0;
-        uint32_t* sg = &h.seg[(size_t)j * (D + 1)];
-        sg[0] = 0;
-        for (uint32_t x = 0; x < D; x++) {
-            acc += cnt[(size_t)j * D + x].load(std::memory_order_relaxed);
-            sg[x + 1] = (uint32_t)acc;
-        }
-        if (acc >= (1ull << 32)) return "out-degree too large";
-        h.row_ptr[j + 1] = h.row_ptr[j] + acc;
-    }
-    if (h.row_ptr[N] != p.E) return "internal error: transposed edge count mismatch";
-    // pass 2: fill rows (cursor per (source, delay))
-    std::unique_ptr<std::atomic<uint64_t>[]> cur(new std::atomic<uint64_t>[(size_t)N * D]);
-    for (uint32_t j = 0; j < N; j++)
-        for (uint32_t x = 0; x < D; x++)
-            cur[(size_t)j * D + x].store(h.row_ptr[j] + h.seg[(size_t)j * (D + 1) + x], std::memory_order_relaxed);
-    cnt.reset();
     const size_t RW = 1 + KW; // words per edge record: target, then the weights
-    h.edge.resize((size_t)p.E * RW);
     const double wlim = std::ldexp(1.0, 52 - (int)p.F);
-    std::atomic<int> wbad{0};
-    parallel_chunks(N, 256, nt, [&](unsigned, uint64_t a, uint64_t b) {
-        std::vector<uint32_t> src(kmax);
-        std::vector<float> w0(kmax), w1(kmax);
-        std::vector<uint8_t> dl(kmax);
-        std::vector<unsigned char> scratch(scratch_bytes);
-        for (uint64_t i = a; i < b; i++) {
-            const uint32_t m = mem.member_of(i);
-            const uint64_t base = mem.nbase[m];
-            const int64_t k = dbnet_in_edges(&mem.m[m], (uint32_t)(i - base), src.data(), w0.data(), w1.data(),
-                                             dl.data(), scratch.data());
-            if (k < 0) {
-                gen_fail.store(1);
-                return;
-            }
-            for (int64_t e = 0; e < k; e++) {
-                const uint64_t pos = cur[(size_t)(src[e] + base) * D + dl[e] - 1].fetch_add(1, std::memory_order_relaxed);
-                uint32_t* rec = &h.edge[pos * RW];
-                rec[0] = (uint32_t)i;
-                std::memcpy(&rec[1], &w0[e], 4);
-                if (KW == 2) std::memcpy(&rec[2], &w1[e], 4);
-                if (!(std::fabs((double)w0[e]) < wlim) || !(std::fabs((double)w1[e]) < wlim)) wbad.store(1);
-            }
-        }
-    });
-    if (gen_fail.load()) return "network generator failed";
-    if (wbad.load()) return "a weight is too large for the fixed-point format (|w| * 2^frac_bits must stay below 2^52)";
-    cur.reset();
-    // deterministic layout: sort every delay segment by target (tile groups are ranges of
-    // consecutive targets, so each delay segment splits into contiguous group sub-segments)
-    parallel_chunks(N, 1024, nt, [&](unsigned, uint64_t a, uint64_t b) {
-        struct Ed {
-            uint32_t t, w0, w1; // target and the weights' bit patterns
-        };
-        std::vector<Ed> tmp;
-        for (uint64_t j = a; j < b; j++) {
-            const uint32_t* sg = &h.seg[(size_t)j * (D + 1)];
-            for (uint32_t x = 0; x < D; x++) {
-                const uint64_t s0 = h.row_ptr[j] + sg[x], s1 = h.row_ptr[j] + sg[x + 1];
-                if (s1 - s0 < 2) continue;
-                tmp.resize(s1 - s0);
-                for (uint64_t e = s0; e < s1; e++)
-                    tmp[e - s0] = Ed{h.edge[e * RW], h.edge[e * RW + 1], KW == 2 ? h.edge[e * RW + 2] : 0u};
-                std::sort(tmp.begin(), tmp.end(), [](const Ed& A, const Ed& B) { return A.t < B.t; });
-                for (uint64_t e = s0; e < s1; e++) {
-                    h.edge[e * RW] = tmp[e - s0].t;
-                    h.edge[e * RW + 1] = tmp[e - s0].w0;
-                    if (KW == 2) h.edge[e * RW + 2] = tmp[e - s0].w1;
+    std::atomic<int> gen_fail{0}, wbad{0};
+    if ((double)p.E * sizeof(BucketEdge) <= bucket_build_bytes()) {
+        // Bucketed transposition. The edges are generated by target and stored by source.
+        // Phase 1: thread t generates the targets of its static range in ascending order and
+        // appends each edge to its bucket of the source's block. Phase 2: every source block
+        // is placed on its own: counts per (source, delay), block-local offsets, then the
+        // block's buckets in thread order, which is ascending target order, so every delay
+        // segment comes out sorted by target. No atomics, no random writes across the table.
+        const uint32_t SB = std::max<uint32_t>(1, std::min<uint32_t>(4096, N / 2048)); // source blocks
+        const uint32_t bsz = (N + SB - 1) / SB;                                        // sources per block
+        const unsigned T = nt;
+        std::vector<std::vector<BucketEdge>> bucket((size_t)T * SB);
+        std::vector<std::thread> th;
+        auto gen = [&](unsigned t) {
+            const uint64_t i0 = (uint64_t)N * t / T, i1 = (uint64_t)N * (t + 1) / T;
+            // room for this thread's share of every block with sources drawn uniformly (a
+            // bucket that outgrows it still grows)
+            const double share = (double)p.E / T / SB;
+            for (uint32_t b = 0; b < SB; b++) bucket[(size_t)t * SB + b].reserve((size_t)(1.15 * share) + 256);
+            std::vector<uint32_t> src(kmax);
+            std::vector<float> w0(kmax), w1(kmax);
+            std::vector<uint8_t> dl(kmax);
+            std::vector<unsigned char> scratch(scratch_bytes);
+            for (uint64_t i = i0; i < i1; i++) {
+                const uint32_t m = mem.member_of(i);
+                const uint64_t base = mem.nbase[m];
+                const int64_t k = dbnet_in_edges(&mem.m[m], (uint32_t)(i - base), src.data(), w0.data(), w1.data(),
+                                                 dl.data(), scratch.data());
+                if (k < 0) {
+                    gen_fail.store(1);
+                    return;
+                }
+                for (int64_t e = 0; e < k; e++) {
+                    const uint32_t s = (uint32_t)(src[e] + base);
+                    BucketEdge be;
+                    be.src_dl = ((s % bsz) << 8) | dl[e];
+                    be.tgt = (uint32_t)i;
+                    std::memcpy(&be.w0, &w0[e], 4);
+                    std::memcpy(&be.w1, &w1[e], 4);
+                    if (!(std::fabs((double)w0[e]) < wlim) || !(std::fabs((double)w1[e]) < wlim)) wbad.store(1);
+                    bucket[(size_t)t * SB + s / bsz].push_back(be);
                 }
             }
+        };
+        for (unsigned t = 1; t < T; t++) th.emplace_back(gen, t);
+        gen(0);
+        for (auto& x : th) x.join();
+        if (gen_fail.load()) return "network generator failed";
+        if (wbad.load()) return "a weight is too large for the fixed-point format (|w| * 2^frac_bits must stay below 2^52)";
+        std::vector<uint64_t> bbase((size_t)SB + 1, 0ull); // first edge of every source block
+        for (uint32_t b = 0; b < SB; b++) {
+            uint64_t n = 0;
+            for (unsigned t = 0; t < T; t++) n += bucket[(size_t)t * SB + b].size();
+            bbase[b + 1] = bbase[b] + n;
         }
-    });
+        if (bbase[SB] != p.E) return "internal error: transposed edge count mismatch";
+        h.row_ptr.assign((size_t)N + 1, 0ull);
+        h.seg.assign((size_t)N * (D + 1), 0u);
+        h.edge.reset(new uint32_t[(size_t)p.E * RW]);
+        h.edge_words = (size_t)p.E * RW;
+        std::atomic<int> too_big{0};
+        parallel_chunks(SB, 1, nt, [&](unsigned, uint64_t b0, uint64_t b1) {
+            std::vector<uint64_t> cur;
+            for (uint64_t b = b0; b < b1; b++) {
+                const uint32_t j0 = (uint32_t)(b * bsz), j1 = std::min<uint32_t>(N, j0 + bsz);
+                const uint32_t nj = j1 - j0;
+                cur.assign((size_t)nj * D, 0ull);
+                for (unsigned t = 0; t < T; t++)
+                    for (const BucketEdge& be : bucket[(size_t)t * SB + b]) cur[(size_t)(be.src_dl >> 8) * D + (be.src_dl & 0xFF) - 1]++;
+                uint64_t pos = bbase[b];
+                for (uint32_t jl = 0; jl < nj; jl++) {
+                    const uint32_t j = j0 + jl;
+                    h.row_ptr[j] = pos;
+                    uint32_t* sg = &h.seg[(size_t)j * (D + 1)];
+                    uint64_t acc = 0;
+                    sg[0] = 0;
+                    for (uint32_t x = 0; x < D; x++) {
+                        const uint64_t c = cur[(size_t)jl * D + x];
+                        cur[(size_t)jl * D + x] = pos + acc; // cursor of (j, delay x + 1)
+                        acc += c;
+                        sg[x + 1] = (uint32_t)acc;
+                    }
+                    if (acc >= (1ull << 32)) too_big.store(1);
+                    pos += acc;
+                }
+                for (unsigned t = 0; t < T; t++)
+                    for (const BucketEdge& be : bucket[(size_t)t * SB + b]) {
+                        const uint64_t e = cur[(size_t)(be.src_dl >> 8) * D + (be.src_dl & 0xFF) - 1]++;
+                        uint32_t* rec = &h.edge[e * RW];
+                        rec[0] = be.tgt;
+                        rec[1] = be.w0;
+                        if (KW == 2) rec[2] = be.w1;
+                    }
+                for (unsigned t = 0; t < T; t++) std::vector<BucketEdge>().swap(bucket[(size_t)t * SB + b]);
+            }
+        });
+        if (too_big.load()) return "out-degree too large";
+        h.row_ptr[N] = p.E;
+    } else {
+        // Two generation passes for networks whose buckets would not fit in host memory:
+        // count per (source, delay), then fill through atomic cursors, then sort every
+        // delay segment by target.
+        std::unique_ptr<std::atomic<uint32_t>[]> cnt(new std::atomic<uint32_t>[(size_t)N * D]);
+        for (size_t x = 0; x < (size_t)N * D; x++) cnt[x].store(0, std::memory_order_relaxed);
+        parallel_chunks(N, 256, nt, [&](unsigned, uint64_t a, uint64_t b) {
+            std::vector<uint32_t> src(kmax);
+            std::vector<uint8_t> dl(kmax);
+            std::vector<unsigned char> scratch(scratch_bytes);
+            for (uint64_t i = a; i < b; i++) {
+                const uint32_t m = mem.member_of(i);
+                const uint64_t base = mem.nbase[m];
+                const int64_t k = dbnet_in_edges(&mem.m[m], (uint32_t)(i - base), src.data(), nullptr, nullptr, dl.data(),
+                                                 scratch.data());
+                if (k < 0) {
+                    gen_fail.store(1);
+                    return;
+                }
+                for (int64_t e = 0; e < k; e++)
+                    cnt[(size_t)(src[e] + base) * D + dl[e] - 1].fetch_add(1, std::memory_order_relaxed);
+            }
+        });
+        if (gen_fail.load()) return "network generator failed";
+        h.row_ptr.assign((size_t)N + 1, 0ull);
+        h.seg.assign((size_t)N * (D + 1), 0u);
+        for (uint32_t j = 0; j < N; j++) {
+            uint64_t acc = 0;
+            uint32_t* sg = &h.seg[(size_t)j * (D + 1)];
+            sg[0] = 0;
+            for (uint32_t x = 0; x < D; x++) {
+                acc += cnt[(size_t)j * D + x].load(std::memory_order_relaxed);
+                sg[x + 1] = (uint32_t)acc;
+            }
+            if (acc >= (1ull << 32)) return "out-degree too large";
+            h.row_ptr[j + 1] = h.row_ptr[j] + acc;
+        }
+        if (h.row_ptr[N] != p.E) return "internal error: transposed edge count mismatch";
+        // pass 2: fill rows (cursor per (source, delay))
+        std::unique_ptr<std::atomic<uint64_t>[]> cur(new std::atomic<uint64_t>[(size_t)N * D]);
+        for (uint32_t j = 0; j < N; j++)
+            for (uint32_t x = 0; x < D; x++)
+                cur[(size_t)j * D + x].store(h.row_ptr[j] + h.seg[(size_t)j * (D + 1) + x], std::memory_order_relaxed);
+        cnt.reset();
+            h.edge.reset(new uint32_t[(size_t)p.E * RW]);
+            h.edge_words = (size_t)p.E * RW;
+            parallel_chunks(N, 256, nt, [&](unsigned, uint64_t a, uint64_t b) {
+            std::vector<uint32_t> src(kmax);
+            std::vector<float> w0(kmax), w1(kmax);
+            std::vector<uint8_t> dl(kmax);
+            std::vector<unsigned char> scratch(scratch_bytes);
+            for (uint64_t i = a; i < b; i++) {
+                const uint32_t m = mem.member_of(i);
+                const uint64_t base = mem.nbase[m];
+                const int64_t k = dbnet_in_edges(&mem.m[m], (uint32_t)(i - base), src.data(), w0.data(), w1.data(),
+                                                 dl.data(), scratch.data());
+                if (k < 0) {
+                    gen_fail.store(1);
+                    return;
+                }
+                for (int64_t e = 0; e < k; e++) {
+                    const uint64_t pos = cur[(size_t)(src[e] + base) * D + dl[e] - 1].fetch_add(1, std::memory_order_relaxed);
+                    uint32_t* rec = &h.edge[pos * RW];
+                    rec[0] = (uint32_t)i;
+                    std::memcpy(&rec[1], &w0[e], 4);
+                    if (KW == 2) std::memcpy(&rec[2], &w1[e], 4);
+                    if (!(std::fabs((double)w0[e]) < wlim) || !(std::fabs((double)w1[e]) < wlim)) wbad.store(1);
+                }
+            }
+        });
+        if (gen_fail.load()) return "network generator failed";
+        if (wbad.load()) return "a weight is too large for the fixed-point format (|w| * 2^frac_bits must stay below 2^52)";
+        cur.reset();
+        // deterministic layout: sort every delay segment by target (tile groups are ranges of
+        // consecutive targets, so each delay segment splits into contiguous group sub-segments)
+        parallel_chunks(N, 1024, nt, [&](unsigned, uint64_t a, uint64_t b) {
+            struct Ed {
+                uint32_t t, w0, w1; // target and the weights' bit patterns
+            };
+            std::vector<Ed> tmp;
+            for (uint64_t j = a; j < b; j++) {
+                const uint32_t* sg = &h.seg[(size_t)j * (D + 1)];
+                for (uint32_t x = 0; x < D; x++) {
+                    const uint64_t s0 = h.row_ptr[j] + sg[x], s1 = h.row_ptr[j] + sg[x + 1];
+                    if (s1 - s0 < 2) continue;
+                    tmp.resize(s1 - s0);
+                    for (uint64_t e = s0; e < s1; e++)
+                        tmp[e - s0] = Ed{h.edge[e * RW], h.edge[e * RW + 1], KW == 2 ? h.edge[e * RW + 2] : 0u};
+                    std::sort(tmp.begin(), tmp.end(), [](const Ed& A, const Ed& B) { return A.t < B.t; });
+                    for (uint64_t e = s0; e < s1; e++) {
+                        h.edge[e * RW] = tmp[e - s0].t;
+                        h.edge[e * RW + 1] = tmp[e - s0].w0;
+                        if (KW == 2) h.edge[e * RW + 2] = tmp[e - s0].w1;
+                    }
+                }
+            }
+        });
+    }
     // row headers
     h.hdr.assign((size_t)N * p.HW, 0u);
     for (uint32_t j = 0; j < N; j++) {

@@ -8,6 +8,7 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -70,7 +71,10 @@ struct HostTables {
     std::vector<uint2> blk;
     std::vector<uint64_t> row_ptr;
     std::vector<uint32_t> seg; // [N][D+1] delay segments
-    std::vector<uint32_t> edge; // [E][1 + KW]: target, then the weights (bit patterns)
+    // [E][1 + KW]: target, then the weights (bit patterns); left uninitialised at allocation
+    // so that the parallel placement threads touch its pages first
+    std::unique_ptr<uint32_t[]> edge;
+    size_t edge_words = 0;
     std::vector<uint8_t> src_inh;
     std::vector<uint32_t> hdr; // [N][HW] device row headers
     std::vector<uint64_t> tile_base, st_base;
