@@ -334,8 +334,11 @@ def summarize_profiles(args):
         if "dbs" not in name:  # the library's kernels only (not the runtime's copy/fill kernels)
             continue
         if "FETCH_SIZE" in fetch.get(name, {}) and "WRITE_SIZE" in write.get(name, {}):
-            per_bin[_short(name)] = {"read": fetch[name]["FETCH_SIZE"] * 1024 * f_fac,
-                                     "write": write[name]["WRITE_SIZE"] * 1024 * w_fac}
+            # mean per dispatch x dispatches per bin (the partition kernels run twice a bin)
+            fr, wr = fetch[name]["calls"] / tot["bins"], write[name]["calls"] / tot["bins"]
+            per_bin[_short(name)] = {"read": fetch[name]["FETCH_SIZE"] * 1024 * f_fac * fr,
+                                     "write": write[name]["WRITE_SIZE"] * 1024 * w_fac * wr,
+                                     "dispatches_per_bin": fr}
     cmd = args.profile_command
     lines = [f"# Kernel trace and HBM byte counters: {run['config']['workload']}", "",
              "Commands (from the repository root, PYTHONPATH=., TMPDIR=/tmp):",
@@ -347,10 +350,12 @@ def summarize_profiles(args):
              "  python3 bench.py --summarize-profiles OUT", "",
              f"Profiled run: {tot['bins']} bins in all (warm-up included), {ev_per_bin:.4g} edge events per bin "
              f"on average; fan-in schedule {run['config']['fanin_schedule']}.", "",
-             "Kernel durations (kernel trace, every dispatch of the run):",
+             "Kernel durations (kernel trace, every dispatch of the run; the next bin's delay >= 2 "
+             "partition overlaps the neuron step on a second stream, so per-bin sums exceed the bin time):",
              f"  {'kernel':46s} {'calls':>6s} {'avg us':>10s}"]
     for name, v in sorted(trace.items(), key=lambda kv: -kv[1]["calls"] * kv[1]["avg_us"]):
-        lines.append(f"  {name[:46]:46s} {v['calls']:6d} {v['avg_us']:10.2f}")
+        lines.append(f"  {name[:46]:46s} {v['calls']:6d} {v['avg_us']:10.2f}  "
+                     f"({v['calls'] * v['avg_us'] / tot['bins']:8.2f} us per bin)")
     lines += ["", f"Counter calibration: a 2 GiB device copy reads FETCH_SIZE {cal_f:.4g} KiB and WRITE_SIZE "
                   f"{cal_w:.4g} KiB per launch -> scale factors FETCH x{f_fac:.3f}, WRITE x{w_fac:.3f}.", "",
               "HBM-side bytes per bin (calibrated) and per edge event:"]
