@@ -112,7 +112,7 @@ void fill_devnet(dbsim* h) {
     n.ts_bits = p.ts_bits;
     n.HW = p.HW;
     n.round_events = p.round_events;
-    n.chunks_per_wg = 2;
+    n.chunks_per_wg = 4;
     n.ahead_passes = default_ahead_passes(p);
     n.T = p.T;
     n.n_blocks = p.n_blocks;

@@ -171,9 +171,9 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
         while (((p.T + (1u << p.ts_bits) - 1) >> p.ts_bits) > kMaxSuperTiles) p.ts_bits++;
     p.NS = (p.T + (1u << p.ts_bits) - 1) >> p.ts_bits;
     p.HW = (p.D + 3 + 3) & ~3u;
-    // default schedule: four partition workgroups per CU (two in the single-pass form),
-    // the largest LDS round that fits
-    p.scatter_wgs_per_cu = p.wc ? 2 : 4;
+    // default schedule (what the autotuner settles on for the 6.1 M share): two partition
+    // workgroups per CU, the largest LDS round that fits
+    p.scatter_wgs_per_cu = 2;
     p.round_events = max_round_events(p, p.scatter_wgs_per_cu);
     if (p.round_events == 0) return "too many tiles per super-tile for the LDS budget";
     const double dt = (double)m0.dt_ms;

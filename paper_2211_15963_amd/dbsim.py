@@ -303,7 +303,7 @@ class Simulator:
         return {"scatter_wgs_per_cu": t.scatter_wgs_per_cu, "round_events": t.round_events,
                 "chunks_per_wg": t.chunks_per_wg, "ahead_passes": t.ahead_passes}
 
-    def set_tuning(self, scatter_wgs_per_cu: int = 1, round_events: int = 0, chunks_per_wg: int = 2,
+    def set_tuning(self, scatter_wgs_per_cu: int = 2, round_events: int = 0, chunks_per_wg: int = 4,
                    ahead_passes: int = 0) -> None:
         t = SimTuning(int(scatter_wgs_per_cu), int(round_events), int(chunks_per_wg), int(ahead_passes))
         _check(lib().dbsim_set_tuning(self._h, byref(t)))
