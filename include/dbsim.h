@@ -246,6 +246,19 @@ int dbsim_read_bold(struct dbsim* h, uint64_t sample_lo, uint64_t sample_hi, dou
    within each). *n_samples (may be NULL) receives the samples taken so far. */
 int dbsim_read_bold_state(struct dbsim* h, double* sfvq, uint64_t* n_samples);
 
+/*
+ * Initial spike injection (Methods, initialisation of the spike trains): during the next
+ * `bins` bins, the output spike train of every neuron of population p carries a spike in
+ * a bin with probability prob[p] (the neuron's own draw: word 0 of Philox4x32-10 with key =
+ * its network's seed and counter (bin, bin >> 32, local neuron id, 2 << 24 | net_id), below
+ * floor(prob * 2^32)). An injected spike is delivered through the neuron's edges like any
+ * other and recorded (at the bin's last step when the neuron did not fire itself), but it
+ * does not reset the neuron. prob[n_pops] over all populations of the handle (members of an
+ * ensemble one after another), each in [0, 1); n_pops must match; bins = 0 turns injection
+ * off. Call at a bin boundary (ESTATE otherwise); takes effect from the next bin. Synchronises.
+ */
+int dbsim_set_spike_injection(struct dbsim* h, const float* prob, uint32_t n_pops, uint64_t bins);
+
 /* Overwrites the state (checkpoint restore). Only at a bin boundary (ESTATE
    otherwise). ref values must lie in [0, 255]. */
 int dbsim_write_state(struct dbsim* h, const float* V, const float* J, const int32_t* ref);

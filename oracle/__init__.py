@@ -43,6 +43,7 @@ def lib():
     L.orc_point_step.restype = c_int
     L.orc_destroy.argtypes = [c_void_p]
     L.orc_step.argtypes = [c_void_p, c_uint64]
+    L.orc_set_injection.argtypes = [c_void_p, POINTER(c_float), c_uint32, c_uint64]
     L.orc_step.restype = c_int
     for nm, rt in [("orc_num_neurons", c_uint32), ("orc_num_receptors", c_uint32), ("orc_steps_per_bin", c_uint32),
                    ("orc_steps_done", c_uint64), ("orc_num_edges", c_uint64), ("orc_edge_events", c_uint64),
@@ -100,6 +101,14 @@ class Oracle:
     def step(self, n: int) -> None:
         if lib().orc_step(self._h, int(n)) != 0:
             raise MemoryError("oracle ran out of host memory")
+
+    def set_injection(self, prob, until_bin: int) -> None:
+        """Initial spike injection in bins below until_bin (absolute bin index), per-population
+        probability per bin (a scalar applies to every population)."""
+        n = len(self.spec.pops)
+        pr = np.broadcast_to(np.asarray(prob, np.float32), (n,)).copy()
+        if lib().orc_set_injection(self._h, pr.ctypes.data_as(POINTER(c_float)), n, int(until_bin)) != 0:
+            raise ValueError("bad injection arguments")
 
     @property
     def steps_done(self) -> int:

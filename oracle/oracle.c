@@ -163,6 +163,9 @@ struct orc {
     uint64_t nbins_rec, capbins;
     double* sig; uint32_t* cnt;
     int params_only;
+    /* initial spike injection (Methods): per-population threshold, active below inj_until */
+    uint32_t* inj_T;
+    uint64_t inj_until;
 };
 
 static void* xcalloc(size_t n, size_t s) {
@@ -172,6 +175,7 @@ static void* xcalloc(size_t n, size_t s) {
 
 void orc_destroy(orc* o) {
     if (!o) return;
+    free(o->inj_T);
     free(o->pops); free(o->projs); free(o->xyz);
     free(o->pop_of); free(o->is_exc); free(o->region_of); free(o->region_size); free(o->P);
     free(o->in_ptr); free(o->in_src); free(o->in_w0); free(o->in_w1); free(o->in_d);
@@ -449,6 +453,32 @@ static int neuron_step64(const orc_pop* P, uint32_t U, uint32_t c, const double*
     return spiked;
 }
 
+/* Initial spike injection (Methods: to start the spike trains without synchrony, every
+   neuron's output train gets a spike with a small probability): in bins k < inj_until
+   neuron i's train carries a spike when word 0 of Philox4x32-10 with key = seed and
+   counter (k, k >> 32, i, 2 << 24 | net_id) is below floor(p * 2^32). */
+static int injected(const orc* o, uint64_t k, uint32_t i) {
+    if (!o->inj_T || k >= o->inj_until) return 0;
+    const uint32_t T = o->inj_T[o->pop_of[i]];
+    if (T == 0) return 0;
+    uint32_t ctr[4] = {(uint32_t)k, (uint32_t)(k >> 32), i, (2u << 24) | (o->d.net_id & 0xFFFFFFu)};
+    uint32_t key[2] = {(uint32_t)o->d.seed, (uint32_t)(o->d.seed >> 32)};
+    uint32_t out[4];
+    orc_philox4x32_10(ctr, key, out);
+    return out[0] < T;
+}
+
+int orc_set_injection(orc* o, const float* p, uint32_t npops, uint64_t until_bin) {
+    if (!o || npops != o->d.n_pops || (until_bin && !p)) return -1;
+    if (!o->inj_T) o->inj_T = (uint32_t*)xcalloc(npops, sizeof(uint32_t));
+    for (uint32_t q = 0; q < npops; q++) {
+        if (until_bin && !(p[q] >= 0.0f && p[q] < 1.0f)) return -1;
+        o->inj_T[q] = until_bin ? (uint32_t)floor((double)p[q] * 4294967296.0) : 0u;
+    }
+    o->inj_until = until_bin;
+    return 0;
+}
+
 int orc_step(orc* o, uint64_t nsteps) {
     const uint32_t N = o->N, U = o->U, S = o->S;
     if (o->params_only) return -2;
@@ -484,6 +514,10 @@ int orc_step(orc* o, uint64_t nsteps) {
                 for (uint32_t u = 0; u < U; u++) o->J64[(size_t)u * N + i] = J[u];
             }
             if (spiked) {
+                o->binspk[i] = 1;
+                if (record_spike(o, n, i)) return -1;
+            } else if (s == S - 1 && !o->binspk[i] && injected(o, k, i)) {
+                /* an injected output spike: delivered and recorded, the neuron is not reset */
                 o->binspk[i] = 1;
                 if (record_spike(o, n, i)) return -1;
             }

@@ -54,6 +54,11 @@ int orc_set_state(orc* o, const double* V, const double* J, const int32_t* ref);
 /* The incoming-edge table the oracle works from (ptr[N+1], then E entries). */
 void orc_get_in_edges(const orc* o, uint64_t* ptr, uint32_t* src, float* w0, float* w1, uint8_t* dl);
 
+/* Initial spike injection: in bins k < until_bin the output train of every neuron of
+   population q carries a spike with probability p[q] per bin (see oracle.c); npops must
+   equal the description's. Returns 0, or -1 on bad arguments. */
+int orc_set_injection(orc* o, const float* p, uint32_t npops, uint64_t until_bin);
+
 /* Point evaluations for sampled checks of large runs (FP32 oracle):
    arrivals A[t*U+u] due at the start of `bin` for each target, from the given
    spike list (pull form of eq. 3, fixed point), and one Euler step of neuron

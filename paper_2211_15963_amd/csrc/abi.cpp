@@ -846,6 +846,31 @@ int dbsim_read_bold_state(dbsim* h, double* sfvq, uint64_t* n_samples) {
     return DBSIM_OK;
 }
 
+int dbsim_set_spike_injection(dbsim* h, const float* prob, uint32_t n_pops, uint64_t bins) {
+    int rc = check_usable(h);
+    if (rc) return rc;
+    const Plan& p = h->plan;
+    if (bins && !prob) return fail(DBSIM_EINVAL, "prob is NULL");
+    if (bins && n_pops != p.n_pops)
+        return fail(DBSIM_EINVAL, "n_pops must equal the handle's " + std::to_string(p.n_pops) + " populations");
+    if (h->step % p.S) return fail(DBSIM_ESTATE, "spike injection can only be set at a bin boundary");
+    std::vector<uint32_t> thr(p.n_pops, 0u);
+    for (uint32_t q = 0; bins && q < p.n_pops; q++) {
+        if (!(prob[q] >= 0.0f && prob[q] < 1.0f)) return fail(DBSIM_EINVAL, "injection probabilities must lie in [0, 1)");
+        thr[q] = (uint32_t)std::floor((double)prob[q] * 4294967296.0);
+    }
+    DeviceGuard dg(h->device);
+    rc = sync_and_check(h);
+    if (rc) return rc;
+    std::vector<PopParams> pp(p.n_pops);
+    HIPCHK(h, hipMemcpy(pp.data(), h->net.pops, sizeof(PopParams) * pp.size(), hipMemcpyDeviceToHost), "hipMemcpy");
+    for (uint32_t q = 0; q < p.n_pops; q++) pp[q].inject_t = thr[q];
+    HIPCHK(h, hipMemcpy((void*)h->net.pops, pp.data(), sizeof(PopParams) * pp.size(), hipMemcpyHostToDevice), "hipMemcpy");
+    const unsigned long long until = bins ? h->step / p.S + bins : 0ull;
+    HIPCHK(h, hipMemcpy(&h->net.ctl->inject_until, &until, sizeof until, hipMemcpyHostToDevice), "hipMemcpy");
+    return DBSIM_OK;
+}
+
 int dbsim_get_tuning(dbsim* h, dbsim_tuning* t) {
     if (!h || !t) return fail(DBSIM_EINVAL, "null argument");
     t->scatter_wgs_per_cu = h->scatter_wgs;

@@ -68,6 +68,8 @@ struct PopParams {
     uint32_t net_id;            // noise stream of the population's network
     uint32_t id_base;           // global id of its network's first neuron (noise counters use local ids)
     unsigned long long seed;    // its network's seed (Philox key)
+    uint32_t inject_t;          // injected output spike when a Philox word < inject_t (0: none)
+    uint32_t pad;
 };
 
 struct Ctl {
@@ -78,6 +80,7 @@ struct Ctl {
     unsigned int done;              // readout workgroups finished in the current bin
     unsigned long long ahead_events; // events of the next bin assembled ahead, not yet delivered
     unsigned int bdone;              // k_bucket workgroups finished in the current launch
+    unsigned long long inject_until; // output spikes are injected in bins below this one
 };
 
 struct DevNet {

@@ -793,6 +793,15 @@ __global__ void __launch_bounds__(kNeuronBlock) k_neuron(DevNet net, int s0, int
     }
     if (s1 < (int)S) return; // block-uniform: the bin continues in a later launch
 
+    // initial spike injection (Methods): in the bins below inject_until the output train
+    // of a neuron carries a spike with probability inject_t / 2^32 per bin (its own Philox
+    // stream, word 0 of counter (k, local id, 2 << 24 | net_id)); the spike is delivered
+    // like any other but does not reset the neuron; alone it is stamped at the bin's last step
+    if (active && P.inject_t != 0u && k < net.ctl->inject_until && sub == 0xFFu) {
+        uint32_t x0 = (uint32_t)k, x1 = (uint32_t)(k >> 32), x2 = local, x3 = (2u << 24) | (P.net_id & 0xFFFFFFu);
+        philox4x32_10(x0, x1, x2, x3, key0, key1);
+        if (x0 < P.inject_t) sub = S - 1;
+    }
     // bin end: compact this block's spikes into its own staging slots (no global atomics
     // per wavefront); k_compact then places every block's spikes in the bin's dense list
     const bool spiked = active && sub != 0xFFu;

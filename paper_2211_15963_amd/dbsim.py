@@ -140,6 +140,7 @@ def lib():
     L.dbsim_set_bold.argtypes = [H, POINTER(BoldParams)]
     L.dbsim_read_bold.argtypes = [H, c_uint64, c_uint64, POINTER(c_double), c_uint64, POINTER(c_uint64)]
     L.dbsim_read_bold_state.argtypes = [H, POINTER(c_double), POINTER(c_uint64)]
+    L.dbsim_set_spike_injection.argtypes = [H, POINTER(c_float), c_uint32, c_uint64]
     for nm in EXPORTED:
         if nm not in ("dbsim_abi_version", "dbsim_last_error"):
             getattr(L, nm).restype = c_int
@@ -349,6 +350,13 @@ class Simulator:
         for k, v in overrides.items():
             setattr(p, k, v)
         _check(lib().dbsim_set_bold(self._h, byref(p)))
+
+    def set_spike_injection(self, prob, bins: int) -> None:
+        """Initial spike injection for the next `bins` bins: per-population probability per
+        bin (a scalar applies to every population); bins = 0 turns it off."""
+        n = sum(len(sp.pops) for sp in self.specs)
+        pr = np.broadcast_to(np.asarray(prob, np.float32), (n,)).copy()
+        _check(lib().dbsim_set_spike_injection(self._h, _p(pr, c_float), n, int(bins)))
 
     def bold(self, sample_lo: int = 0, sample_hi: Optional[int] = None) -> np.ndarray:
         """BOLD samples [samples][regions]."""

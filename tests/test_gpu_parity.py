@@ -253,3 +253,32 @@ def test_one_ms_euler_step_bit_exact(Sim):
     orc.step(300)
     _compare(sim, orc, spec)
     sim.close()
+
+
+def test_spike_injection_bit_exact(Sim):
+    """Initial spike injection (Methods) on the GPU vs the oracle: injected output spikes,
+    their delivery and the rest of the trajectory."""
+    spec = configs.tiny(seed=12)
+    S = spec.steps_per_bin
+    _say("tiny seed 12: injection p = (0.01, 0.005) for 200 bins, 400 bins run")
+    sim = Sim(spec)
+    sim.set_spike_injection([0.01, 0.005], 200)
+    sim.step(400 * S)
+    orc = Oracle(spec, 32)
+    orc.set_injection([0.01, 0.005], 200)
+    orc.step(400 * S)
+    _compare(sim, orc, spec)
+    sim.close()
+    spec = configs.share(n=20000, indegree=300, seed=13)
+    for two_pass in (False, True):
+        _say(f"share 20000 / k300 seed 13: injection 0.02 for 20 bins from bin 10, two_pass={two_pass}")
+        sim = Sim(spec, two_pass=two_pass)
+        sim.step(10 * S)
+        sim.set_spike_injection(0.02, 20)
+        sim.step(30 * S)
+        orc = Oracle(spec, 32)
+        orc.step(10 * S)
+        orc.set_injection(0.02, 30)  # absolute bin index: bins 10..29
+        orc.step(30 * S)
+        _compare(sim, orc, spec)
+        sim.close()
