@@ -259,6 +259,21 @@ int dbsim_read_bold_state(struct dbsim* h, double* sfvq, uint64_t* n_samples);
  */
 int dbsim_set_spike_injection(struct dbsim* h, const float* prob, uint32_t n_pops, uint64_t bins);
 
+/*
+ * Ornstein-Uhlenbeck background current (eq. 1; eq. 4 discretised with the noise scaled as
+ * the continuous process requires): for the neurons of population p with tau_ms[p] > 0,
+ *   I_bg' = I_bg + c1 (mu - I_bg),   I_bg'' = I_bg' + c2 z,
+ * c1 = dt / tau, c2 = sigma sqrt(2 dt / tau) (rounded once to f32), z the standardised sum of
+ * twelve 10-bit fields of one Philox4x32-10 block (counter (n, n >> 32, local id,
+ * 3 << 24 | net_id)): an exact integer, variance 1 - 2^-20. I_bg enters the membrane current
+ * after I_ext (I = I + I_ext, then I = I + I_bg) at the old value, every step, also while
+ * refractory. The current is set to mu (0 where tau <= 0, which turns it off). It adds to the
+ * Poisson background (set bg_rate_hz = 0 for OU alone). Arrays of n_pops over all populations
+ * (members one after another). Synchronises.
+ */
+int dbsim_set_ou_background(struct dbsim* h, const float* mu, const float* sigma, const float* tau_ms,
+                            uint32_t n_pops);
+
 /* Overwrites the state (checkpoint restore). Only at a bin boundary (ESTATE
    otherwise). ref values must lie in [0, 255]. */
 int dbsim_write_state(struct dbsim* h, const float* V, const float* J, const int32_t* ref);

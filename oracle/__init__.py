@@ -44,6 +44,11 @@ def lib():
     L.orc_destroy.argtypes = [c_void_p]
     L.orc_step.argtypes = [c_void_p, c_uint64]
     L.orc_set_injection.argtypes = [c_void_p, POINTER(c_float), c_uint32, c_uint64]
+    L.orc_set_ou.argtypes = [c_void_p, POINTER(c_float), POINTER(c_float), POINTER(c_float), c_uint32]
+    L.orc_set_ou.restype = c_int
+    L.orc_get_ou.argtypes = [c_void_p, POINTER(c_double)]
+    L.orc_ou_normal.argtypes = [c_uint64, c_uint32, c_uint64, c_uint32]
+    L.orc_ou_normal.restype = c_float
     L.orc_step.restype = c_int
     for nm, rt in [("orc_num_neurons", c_uint32), ("orc_num_receptors", c_uint32), ("orc_steps_per_bin", c_uint32),
                    ("orc_steps_done", c_uint64), ("orc_num_edges", c_uint64), ("orc_edge_events", c_uint64),
@@ -109,6 +114,21 @@ class Oracle:
         pr = np.broadcast_to(np.asarray(prob, np.float32), (n,)).copy()
         if lib().orc_set_injection(self._h, pr.ctypes.data_as(POINTER(c_float)), n, int(until_bin)) != 0:
             raise ValueError("bad injection arguments")
+
+    def set_ou(self, mu, sigma, tau_ms) -> None:
+        """Ornstein-Uhlenbeck background current per population (eq. 1 / eq. 4): mean mu,
+        stationary standard deviation sigma, time constant tau_ms (<= 0: off); scalars
+        apply to every population. The current starts at mu."""
+        n = len(self.spec.pops)
+        a = [np.broadcast_to(np.asarray(x, np.float32), (n,)).copy() for x in (mu, sigma, tau_ms)]
+        if lib().orc_set_ou(self._h, *[_p(x, c_float) for x in a], n) != 0:
+            raise ValueError("bad OU arguments")
+
+    def ou_current(self):
+        """OU current per neuron (float64; exact for the FP32 variant)."""
+        out = np.zeros(self.N, np.float64)
+        lib().orc_get_ou(self._h, _p(out, c_double))
+        return out
 
     @property
     def steps_done(self) -> int:
@@ -200,6 +220,10 @@ def philox(ctr, key):
 
 def bg_word(seed: int, net_id: int, n: int, i: int) -> int:
     return int(lib().orc_bg_word(seed, net_id, n, i))
+
+
+def ou_normal(seed: int, net_id: int, n: int, i: int) -> float:
+    return float(lib().orc_ou_normal(seed, net_id, n, i))
 
 
 def poisson_table(lam: float):

@@ -128,6 +128,10 @@ typedef struct {
     int32_t r;
     int cmax;
     uint32_t T[ORC_MAX_TABLE];
+    /* Ornstein-Uhlenbeck background current (eq. 1, eq. 4): on, mean, dt/tau, sigma sqrt(2 dt/tau) */
+    int ou;
+    float ou_mu32, ou_c1_32, ou_c2_32;
+    double ou_mu64, ou_c1_64, ou_c2_64;
 } orc_pop;
 
 struct orc {
@@ -166,6 +170,9 @@ struct orc {
     /* initial spike injection (Methods): per-population threshold, active below inj_until */
     uint32_t* inj_T;
     uint64_t inj_until;
+    /* OU background current per neuron */
+    float* Iou32;
+    double* Iou64;
 };
 
 static void* xcalloc(size_t n, size_t s) {
@@ -176,6 +183,8 @@ static void* xcalloc(size_t n, size_t s) {
 void orc_destroy(orc* o) {
     if (!o) return;
     free(o->inj_T);
+    free(o->Iou32);
+    free(o->Iou64);
     free(o->pops); free(o->projs); free(o->xyz);
     free(o->pop_of); free(o->is_exc); free(o->region_of); free(o->region_size); free(o->P);
     free(o->in_ptr); free(o->in_src); free(o->in_w0); free(o->in_w1); free(o->in_d);
@@ -401,7 +410,8 @@ static void arrivals(orc* o, uint64_t k) {
 /* One Euler step of one neuron (FP32): all right-hand sides use the old V and
    J; A is this step's arrival (zero except at a bin start), c the background
    count. Returns 1 if the neuron spiked. */
-static int neuron_step32(const orc_pop* P, uint32_t U, uint32_t c, const float* A, float* Vp, float* J, int32_t* ref) {
+static int neuron_step32(const orc_pop* P, uint32_t U, uint32_t c, const float* A, float* Vp, float* J, int32_t* ref,
+                         float Ibg) {
     const float V = *Vp;
     float Vn;
     int spiked = 0;
@@ -415,6 +425,7 @@ static int neuron_step32(const orc_pop* P, uint32_t U, uint32_t c, const float* 
             I = I + gJ * (P->Vu32[u] - V);
         }
         I = I + P->Iext32;
+        if (P->ou) I = I + Ibg;
         Vn = V + P->k32 * I;
         if (Vn >= P->Vth32) { spiked = 1; Vn = P->Vr32; *ref = P->r; }
     }
@@ -429,7 +440,8 @@ static int neuron_step32(const orc_pop* P, uint32_t U, uint32_t c, const float* 
 }
 
 /* The same step in FP64. */
-static int neuron_step64(const orc_pop* P, uint32_t U, uint32_t c, const double* A, double* Vp, double* J, int32_t* ref) {
+static int neuron_step64(const orc_pop* P, uint32_t U, uint32_t c, const double* A, double* Vp, double* J, int32_t* ref,
+                         double Ibg) {
     const double V = *Vp;
     double Vn;
     int spiked = 0;
@@ -440,6 +452,7 @@ static int neuron_step64(const orc_pop* P, uint32_t U, uint32_t c, const double*
         double I = P->gL64 * (P->VL64 - V);
         for (uint32_t u = 0; u < U; u++) I = I + (P->g64[u] * J[u]) * (P->Vu64[u] - V);
         I = I + P->Iext64;
+        if (P->ou) I = I + Ibg;
         Vn = V + P->k64 * I;
         if (Vn >= P->Vth64) { spiked = 1; Vn = P->Vr64; *ref = P->r; }
     }
@@ -466,6 +479,52 @@ static int injected(const orc* o, uint64_t k, uint32_t i) {
     uint32_t out[4];
     orc_philox4x32_10(ctr, key, out);
     return out[0] < T;
+}
+
+/* Gaussian-like increment of the OU background: the 128 bits of Philox4x32-10 with key =
+   seed and counter (n, n >> 32, i, 3 << 24 | net_id) as twelve 10-bit uniform integers
+   (bits 0-9, 10-19, 20-29 of each word); each field has mean 511.5 and variance
+   (1024^2 - 1) / 12, so z = (2 s - 12276) / 2048 for their sum s has mean 0 and variance
+   1 - 2^-20 (Irwin-Hall with twelve terms). Computed exactly. */
+float orc_ou_normal(uint64_t seed, uint32_t net_id, uint64_t n, uint32_t i) {
+    uint32_t ctr[4] = {(uint32_t)n, (uint32_t)(n >> 32), i, (3u << 24) | (net_id & 0xFFFFFFu)};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    uint32_t sum = 0;
+    for (int q = 0; q < 4; q++)
+        for (int f = 0; f < 3; f++) sum += (w[q] >> (10 * f)) & 1023u;
+    return (float)((int)(2u * sum) - 12276) * 0x1p-11f;
+}
+
+int orc_set_ou(orc* o, const float* mu, const float* sigma, const float* tau_ms, uint32_t npops) {
+    if (!o || npops != o->d.n_pops || !mu || !sigma || !tau_ms) return -1;
+    if (!o->Iou32) o->Iou32 = (float*)xcalloc(o->N, sizeof(float));
+    if (!o->Iou64) o->Iou64 = (double*)xcalloc(o->N, sizeof(double));
+    const double dt = (double)o->d.dt_ms;
+    uint64_t first = 0;
+    for (uint32_t q = 0; q < npops; q++) {
+        if (!isfinite(mu[q]) || !isfinite(sigma[q]) || !isfinite(tau_ms[q]) || sigma[q] < 0.0f) return -1;
+        orc_pop* P = &o->P[q];
+        P->ou = tau_ms[q] > 0.0f;
+        P->ou_mu32 = mu[q];
+        P->ou_c1_32 = P->ou ? (float)(dt / (double)tau_ms[q]) : 0.0f;
+        P->ou_c2_32 = P->ou ? (float)((double)sigma[q] * sqrt(2.0 * dt / (double)tau_ms[q])) : 0.0f;
+        P->ou_mu64 = (double)mu[q];
+        P->ou_c1_64 = P->ou ? dt / (double)tau_ms[q] : 0.0;
+        P->ou_c2_64 = P->ou ? (double)sigma[q] * sqrt(2.0 * dt / (double)tau_ms[q]) : 0.0;
+        for (uint64_t i = first; i < first + o->pops[q].size; i++) {
+            o->Iou32[i] = P->ou ? mu[q] : 0.0f;
+            o->Iou64[i] = P->ou ? (double)mu[q] : 0.0;
+        }
+        first += o->pops[q].size;
+    }
+    return 0;
+}
+
+void orc_get_ou(const orc* o, double* I) {
+    for (uint32_t i = 0; i < o->N; i++)
+        I[i] = o->Iou32 ? (o->prec == 32 ? (double)o->Iou32[i] : o->Iou64[i]) : 0.0;
 }
 
 int orc_set_injection(orc* o, const float* p, uint32_t npops, uint64_t until_bin) {
@@ -502,16 +561,28 @@ int orc_step(orc* o, uint64_t nsteps) {
                     J[u] = o->J32[(size_t)u * N + i];
                     A[u] = (s == 0) ? o->A32[(size_t)u * N + i] : 0.0f;
                 }
-                spiked = neuron_step32(P, U, c, A, &o->V32[i], J, &o->ref[i]);
+                const float Ibg = P->ou ? o->Iou32[i] : 0.0f;
+                spiked = neuron_step32(P, U, c, A, &o->V32[i], J, &o->ref[i], Ibg);
                 for (uint32_t u = 0; u < U; u++) o->J32[(size_t)u * N + i] = J[u];
+                if (P->ou) { /* OU current: drift towards mu, then the scaled increment */
+                    const float z = orc_ou_normal(o->d.seed, o->d.net_id, n, i);
+                    const float drift = P->ou_c1_32 * (P->ou_mu32 - Ibg);
+                    const float Ih = Ibg + drift;
+                    o->Iou32[i] = Ih + P->ou_c2_32 * z;
+                }
             } else {
                 double J[4], A[4];
                 for (uint32_t u = 0; u < U; u++) {
                     J[u] = o->J64[(size_t)u * N + i];
                     A[u] = (s == 0) ? o->A64[(size_t)u * N + i] : 0.0;
                 }
-                spiked = neuron_step64(P, U, c, A, &o->V64[i], J, &o->ref[i]);
+                const double Ibg = P->ou ? o->Iou64[i] : 0.0;
+                spiked = neuron_step64(P, U, c, A, &o->V64[i], J, &o->ref[i], Ibg);
                 for (uint32_t u = 0; u < U; u++) o->J64[(size_t)u * N + i] = J[u];
+                if (P->ou) {
+                    const double z = (double)orc_ou_normal(o->d.seed, o->d.net_id, n, i);
+                    o->Iou64[i] = (Ibg + P->ou_c1_64 * (P->ou_mu64 - Ibg)) + P->ou_c2_64 * z;
+                }
             }
             if (spiked) {
                 o->binspk[i] = 1;
@@ -632,9 +703,10 @@ int orc_point_arrivals(orc* o, uint64_t bin, uint64_t nspk, const uint64_t* spk_
 int orc_point_step(orc* o, uint32_t i, uint64_t n, const float* A, float* V, float* J, int32_t* ref, int* spiked) {
     if (o->prec != 32 || i >= o->N) return -1;
     const orc_pop* P = &o->P[o->pop_of[i]];
+    if (P->ou) return -1; /* the OU current is state of its own; point checks run without it */
     uint32_t c = orc_poisson_count(orc_bg_word(o->d.seed, o->d.net_id, n, i), P->T, P->cmax);
     float Az[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    int s = neuron_step32(P, o->U, c, (n % o->S == 0 && A) ? A : Az, V, J, ref);
+    int s = neuron_step32(P, o->U, c, (n % o->S == 0 && A) ? A : Az, V, J, ref, 0.0f);
     if (spiked) *spiked = s;
     return 0;
 }

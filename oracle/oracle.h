@@ -59,6 +59,13 @@ void orc_get_in_edges(const orc* o, uint64_t* ptr, uint32_t* src, float* w0, flo
    equal the description's. Returns 0, or -1 on bad arguments. */
 int orc_set_injection(orc* o, const float* p, uint32_t npops, uint64_t until_bin);
 
+/* Ornstein-Uhlenbeck background current (eq. 1 / eq. 4) per population (tau_ms <= 0: off);
+   the current starts at mu. Returns 0, or -1 on bad arguments. orc_get_ou copies the
+   current per neuron; orc_ou_normal is its increment draw (see oracle.c). */
+int orc_set_ou(orc* o, const float* mu, const float* sigma, const float* tau_ms, uint32_t npops);
+void orc_get_ou(const orc* o, double* I);
+float orc_ou_normal(uint64_t seed, uint32_t net_id, uint64_t n, uint32_t i);
+
 /* Point evaluations for sampled checks of large runs (FP32 oracle):
    arrivals A[t*U+u] due at the start of `bin` for each target, from the given
    spike list (pull form of eq. 3, fixed point), and one Euler step of neuron

@@ -127,6 +127,7 @@ void fill_devnet(dbsim* h) {
     n.ref = at<uint8_t>(b, p.ref);
     n.pend = at<uint8_t>(b, p.pend);
     n.A = at<float>(b, p.A);
+    n.Iou = at<float>(b, p.Iou);
     n.pops = at<const PopParams>(b, p.pops);
     n.ptab = at<const uint32_t>(b, p.ptab);
     n.blk = at<const uint2>(b, p.blk);
@@ -423,6 +424,7 @@ static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32
         if (e == hipSuccess) e = up(p.V, ht.V0.data(), 4 * N);
         if (e == hipSuccess) e = up(p.J, zeros.data(), 4 * (size_t)p.U * N);
         if (e == hipSuccess) e = up(p.A, zeros.data(), 4 * (size_t)p.U * N);
+        if (e == hipSuccess) e = up(p.Iou, zeros.data(), 4 * N);
         if (e == hipSuccess) e = up(p.ref, z8.data(), N);
         if (e == hipSuccess) e = up(p.pend, pend.data(), N);
         if (e == hipSuccess) e = up(p.pops, ht.pops.data(), sizeof(PopParams) * ht.pops.size());
@@ -868,6 +870,44 @@ int dbsim_set_spike_injection(dbsim* h, const float* prob, uint32_t n_pops, uint
     HIPCHK(h, hipMemcpy((void*)h->net.pops, pp.data(), sizeof(PopParams) * pp.size(), hipMemcpyHostToDevice), "hipMemcpy");
     const unsigned long long until = bins ? h->step / p.S + bins : 0ull;
     HIPCHK(h, hipMemcpy(&h->net.ctl->inject_until, &until, sizeof until, hipMemcpyHostToDevice), "hipMemcpy");
+    return DBSIM_OK;
+}
+
+int dbsim_set_ou_background(dbsim* h, const float* mu, const float* sigma, const float* tau_ms, uint32_t n_pops) {
+    int rc = check_usable(h);
+    if (rc) return rc;
+    const Plan& p = h->plan;
+    if (!mu || !sigma || !tau_ms) return fail(DBSIM_EINVAL, "null argument");
+    if (n_pops != p.n_pops)
+        return fail(DBSIM_EINVAL, "n_pops must equal the handle's " + std::to_string(p.n_pops) + " populations");
+    for (uint32_t q = 0; q < n_pops; q++)
+        if (!std::isfinite(mu[q]) || !std::isfinite(sigma[q]) || !std::isfinite(tau_ms[q]) || sigma[q] < 0.0f)
+            return fail(DBSIM_EINVAL, "OU parameters must be finite with sigma >= 0");
+    DeviceGuard dg(h->device);
+    rc = sync_and_check(h);
+    if (rc) return rc;
+    std::vector<PopParams> pp(p.n_pops);
+    HIPCHK(h, hipMemcpy(pp.data(), h->net.pops, sizeof(PopParams) * pp.size(), hipMemcpyDeviceToHost), "hipMemcpy");
+    std::vector<float> I(p.N); // every neuron belongs to one population: all overwritten below
+    uint32_t q = 0;
+    for (size_t m = 0; m < h->mem.m.size(); m++) {
+        const dbnet_desc& d = h->mem.m[m];
+        const double dt = (double)d.dt_ms;
+        uint64_t first = h->mem.nbase[m];
+        for (uint32_t lq = 0; lq < d.n_pops; lq++, q++) {
+            const uint32_t sz = d.pops[lq].size;
+            PopParams& P = pp[q];
+            P.ou_on = tau_ms[q] > 0.0f ? 1u : 0u;
+            P.ou_mu = mu[q];
+            P.ou_c1 = P.ou_on ? (float)(dt / (double)tau_ms[q]) : 0.0f;
+            P.ou_c2 = P.ou_on ? (float)((double)sigma[q] * std::sqrt(2.0 * dt / (double)tau_ms[q])) : 0.0f;
+            // the current starts at its mean (or 0 when off)
+            for (uint64_t i = first; i < first + sz; i++) I[i] = P.ou_on ? mu[q] : 0.0f;
+            first += sz;
+        }
+    }
+    HIPCHK(h, hipMemcpy((void*)h->net.pops, pp.data(), sizeof(PopParams) * pp.size(), hipMemcpyHostToDevice), "hipMemcpy");
+    HIPCHK(h, hipMemcpy(h->net.Iou, I.data(), 4 * I.size(), hipMemcpyHostToDevice), "hipMemcpy");
     return DBSIM_OK;
 }
 

@@ -69,6 +69,9 @@ struct PopParams {
     uint32_t id_base;           // global id of its network's first neuron (noise counters use local ids)
     unsigned long long seed;    // its network's seed (Philox key)
     uint32_t inject_t;          // injected output spike when a Philox word < inject_t (0: none)
+    uint32_t ou_on;             // Ornstein-Uhlenbeck background current on
+    float ou_mu;                // its mean (pA)
+    float ou_c1, ou_c2;         // dt / tau and sigma * sqrt(2 dt / tau), rounded once
     uint32_t pad;
 };
 
@@ -104,6 +107,7 @@ struct DevNet {
     uint8_t* ref;
     uint8_t* pend;
     float* A;
+    float* Iou; // Ornstein-Uhlenbeck background current per neuron (populations with it on)
     // populations and neuron blocks
     const PopParams* pops;
     const uint32_t* ptab;

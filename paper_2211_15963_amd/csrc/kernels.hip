@@ -696,7 +696,7 @@ __global__ void __launch_bounds__(kNeuronBlock) k_neuron(DevNet net, int s0, int
     const uint32_t N = net.N;
     const uint32_t S = net.S;
 
-    float V = 0.0f, J[U], A[U];
+    float V = 0.0f, J[U], A[U], Iou = 0.0f;
     int ref = 0;
     uint32_t sub = 0xFFu;
 #pragma unroll
@@ -709,6 +709,7 @@ __global__ void __launch_bounds__(kNeuronBlock) k_neuron(DevNet net, int s0, int
 #pragma unroll
         for (int u = 0; u < U; u++) J[u] = net.J[(size_t)u * N + i];
         ref = net.ref[i];
+        if (P.ou_on) Iou = net.Iou[i];
         if (s0 == 0) {
 #pragma unroll
             for (int u = 0; u < U; u++) A[u] = net.A[(size_t)u * N + i];
@@ -727,6 +728,8 @@ __global__ void __launch_bounds__(kNeuronBlock) k_neuron(DevNet net, int s0, int
         dec[u] = P.dec[u];
     }
     const int rsteps = P.r;
+    const bool ou = P.ou_on != 0u; // uniform: neuron blocks never straddle populations
+    const float ou_mu = P.ou_mu, ou_c1 = P.ou_c1, ou_c2 = P.ou_c2;
     const unsigned long long seed = P.seed;
     const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
     const uint32_t tag = (1u << 24) | (P.net_id & 0xFFFFFFu);
@@ -767,6 +770,7 @@ __global__ void __launch_bounds__(kNeuronBlock) k_neuron(DevNet net, int s0, int
                 I = I + gJ * (Vu[u] - V);
             }
             I = I + Iext;
+            if (ou) I = I + Iou;
             Vn = V + k_dt * I;
             if (Vn >= Vth) {
                 Vn = Vr;
@@ -775,6 +779,18 @@ __global__ void __launch_bounds__(kNeuronBlock) k_neuron(DevNet net, int s0, int
             }
         }
         V = Vn;
+        if (ou) { // Ornstein-Uhlenbeck background current (eq. 1, discretised as eq. 4), old value above
+            uint32_t y0 = (uint32_t)n, y1 = (uint32_t)(n >> 32), y2 = local, y3 = (3u << 24) | (P.net_id & 0xFFFFFFu);
+            philox4x32_10(y0, y1, y2, y3, key0, key1);
+            // twelve 10-bit uniforms; their standardised sum is the increment (exact integers)
+            const uint32_t sum = (y0 & 1023u) + ((y0 >> 10) & 1023u) + ((y0 >> 20) & 1023u) + (y1 & 1023u) +
+                                 ((y1 >> 10) & 1023u) + ((y1 >> 20) & 1023u) + (y2 & 1023u) + ((y2 >> 10) & 1023u) +
+                                 ((y2 >> 20) & 1023u) + (y3 & 1023u) + ((y3 >> 10) & 1023u) + ((y3 >> 20) & 1023u);
+            const float z = (float)((int)(2u * sum) - 12276) * 0x1p-11f;
+            const float drift = ou_c1 * (ou_mu - Iou);
+            const float Ih = Iou + drift;
+            Iou = Ih + ou_c2 * z;
+        }
         const float B = wbg * (float)c;
 #pragma unroll
         for (int u = 0; u < U; u++) {
@@ -789,6 +805,7 @@ __global__ void __launch_bounds__(kNeuronBlock) k_neuron(DevNet net, int s0, int
 #pragma unroll
         for (int u = 0; u < U; u++) net.J[(size_t)u * N + i] = J[u];
         net.ref[i] = (uint8_t)ref;
+        if (ou) net.Iou[i] = Iou;
         if (s1 < (int)S) net.pend[i] = (uint8_t)sub;
     }
     if (s1 < (int)S) return; // block-uniform: the bin continues in a later launch

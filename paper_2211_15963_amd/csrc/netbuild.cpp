@@ -221,6 +221,7 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     slot(p.ref, N);
     slot(p.pend, N);
     slot(p.A, 4 * U * N);
+    slot(p.Iou, 4 * N);
     slot(p.pops, sizeof(PopParams) * p.n_pops);
     slot(p.ptab, 4 * (size_t)kMaxPoisson * p.n_pops);
     slot(p.blk, sizeof(uint2) * p.n_blocks);

@@ -49,7 +49,7 @@ struct Plan {
     struct Slot {
         size_t off = 0, bytes = 0;
     };
-    Slot V, J, ref, pend, A, pops, ptab, blk, hdr, edge, ev, tile_base, tile_fill, st_base, st_fill, sev, stage,
+    Slot V, J, ref, pend, A, Iou, pops, ptab, blk, hdr, edge, ev, tile_base, tile_fill, st_base, st_fill, sev, stage,
         grp_cnt, rec, bin_start, bin_cnt, blk_sig, blk_cnt, reg_blk_ptr, reg_blk, reg_size, l1_ptr, l1_region, l1_sig,
         l1_cnt, sig, sig_cnt, bold_zs, bold, bold_y, bold_ctl, ctl;
     size_t total = 0;

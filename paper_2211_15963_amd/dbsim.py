@@ -141,6 +141,7 @@ def lib():
     L.dbsim_read_bold.argtypes = [H, c_uint64, c_uint64, POINTER(c_double), c_uint64, POINTER(c_uint64)]
     L.dbsim_read_bold_state.argtypes = [H, POINTER(c_double), POINTER(c_uint64)]
     L.dbsim_set_spike_injection.argtypes = [H, POINTER(c_float), c_uint32, c_uint64]
+    L.dbsim_set_ou_background.argtypes = [H, POINTER(c_float), POINTER(c_float), POINTER(c_float), c_uint32]
     for nm in EXPORTED:
         if nm not in ("dbsim_abi_version", "dbsim_last_error"):
             getattr(L, nm).restype = c_int
@@ -357,6 +358,13 @@ class Simulator:
         n = sum(len(sp.pops) for sp in self.specs)
         pr = np.broadcast_to(np.asarray(prob, np.float32), (n,)).copy()
         _check(lib().dbsim_set_spike_injection(self._h, _p(pr, c_float), n, int(bins)))
+
+    def set_ou_background(self, mu, sigma, tau_ms) -> None:
+        """OU background current per population (scalars apply to every population);
+        tau_ms <= 0 turns it off for that population."""
+        n = sum(len(sp.pops) for sp in self.specs)
+        a = [np.broadcast_to(np.asarray(x, np.float32), (n,)).copy() for x in (mu, sigma, tau_ms)]
+        _check(lib().dbsim_set_ou_background(self._h, _p(a[0], c_float), _p(a[1], c_float), _p(a[2], c_float), n))
 
     def bold(self, sample_lo: int = 0, sample_hi: Optional[int] = None) -> np.ndarray:
         """BOLD samples [samples][regions]."""

@@ -255,6 +255,36 @@ def test_one_ms_euler_step_bit_exact(Sim):
     sim.close()
 
 
+def test_ou_background_bit_exact(Sim):
+    """OU background current (eq. 1 / eq. 4) on the GPU vs the oracle: the increments, the
+    recurrence and its effect on V, spikes and delivery, bit for bit."""
+    spec = configs.tiny(seed=14, bg_rate_hz=0.0)
+    S = spec.steps_per_bin
+    _say("tiny seed 14, no Poisson background: OU mu = (450, 400), sigma = 150, tau = 3 ms, 200 bins")
+    sim = Sim(spec)
+    sim.set_ou_background([450.0, 400.0], 150.0, 3.0)
+    sim.step(200 * S)
+    orc = Oracle(spec, 32)
+    orc.set_ou([450.0, 400.0], 150.0, 3.0)
+    orc.step(200 * S)
+    assert orc.spikes()[0].size > 1000
+    _compare(sim, orc, spec)
+    sim.close()
+    spec = configs.share(n=20000, indegree=300, seed=15)
+    for two_pass in (False, True):
+        _say(f"share 20000 / k300 seed 15: OU on the inhibitory population from bin 5, two_pass={two_pass}")
+        sim = Sim(spec, two_pass=two_pass)
+        sim.step(5 * S + 3)  # switched on mid-bin
+        sim.set_ou_background([0.0, 20.0], [0.0, 40.0], [0.0, 4.0])
+        sim.step(25 * S - 3)
+        orc = Oracle(spec, 32)
+        orc.step(5 * S + 3)
+        orc.set_ou([0.0, 20.0], [0.0, 40.0], [0.0, 4.0])
+        orc.step(25 * S - 3)
+        _compare(sim, orc, spec)
+        sim.close()
+
+
 def test_spike_injection_bit_exact(Sim):
     """Initial spike injection (Methods) on the GPU vs the oracle: injected output spikes,
     their delivery and the rest of the trajectory."""
