@@ -112,6 +112,7 @@ void fill_devnet(dbsim* h) {
     n.ts_bits = p.ts_bits;
     n.HW = p.HW;
     n.round_events = p.round_events;
+    n.bucket_events = p.bucket_events;
     n.chunks_per_wg = 4;
     n.ahead_passes = default_ahead_passes(p);
     n.T = p.T;
@@ -190,7 +191,8 @@ hipError_t enqueue_ahead(dbsim* h, hipStream_t st) {
     hipError_t e = hipSuccess;
     for (uint32_t g = 0; g < P && e == hipSuccess; g++) {
         const uint32_t lo = 2 + (D - 1) * g / P, hi = 1 + (D - 1) * (g + 1) / P;
-        e = launch_scatter(h->net, h->scatter_grid, st, lo, hi, 1);
+        if (g > 0) e = launch_pass_reset(h->net, st);
+        if (e == hipSuccess) e = launch_scatter(h->net, h->scatter_grid, st, lo, hi, 1);
     }
     return e;
 }
@@ -929,7 +931,8 @@ int dbsim_set_tuning(dbsim* h, const dbsim_tuning* t) {
     const uint32_t pmax = std::max(1u, h->plan.D - 1);
     if (t->ahead_passes > pmax) return fail(DBSIM_EINVAL, "ahead_passes must lie in 0..max delay - 1");
     const uint32_t rmax = max_round_events(h->plan, t->scatter_wgs_per_cu);
-    if (rmax == 0) return fail(DBSIM_EINVAL, "this schedule does not fit the LDS");
+    const uint32_t bmax = max_bucket_events(h->plan, t->scatter_wgs_per_cu);
+    if (rmax == 0 || bmax == 0) return fail(DBSIM_EINVAL, "this schedule does not fit the LDS");
     const uint32_t re = t->round_events ? t->round_events : rmax;
     if (re % 256 || re > rmax) return fail(DBSIM_EINVAL, "round_events must be a multiple of 256 that fits the LDS");
     DeviceGuard dg(h->device);
@@ -938,6 +941,7 @@ int dbsim_set_tuning(dbsim* h, const dbsim_tuning* t) {
     h->scatter_wgs = t->scatter_wgs_per_cu;
     h->scatter_grid = std::min((int)kMaxPartGrid, (int)h->scatter_wgs * h->num_cus);
     h->net.round_events = re;
+    h->net.bucket_events = std::min(bmax, std::max<uint32_t>(re / kScatterThreads, 1u) * kScatterThreads);
     h->net.chunks_per_wg = t->chunks_per_wg;
     h->net.ahead_passes = t->ahead_passes ? t->ahead_passes : default_ahead_passes(h->plan);
     if (h->g_multi) (void)hipGraphExecDestroy(h->g_multi);

@@ -56,6 +56,7 @@ constexpr int kMaxBatch = 8;           // partition: events per thread per round
 constexpr uint32_t kChunk = 16;        // records per write-combined tile chunk (192 B with two weights)
 constexpr uint32_t kMaxPartGrid = 2048; // most partition workgroups (bounds the chunk padding per tile)
 constexpr uint32_t kMaxLdsBytes = 160u * 1024u;
+constexpr uint32_t kStaticLds = 1024u; // room left per workgroup for the kernels' static LDS
 
 struct PopParams {
     float k;      // dt / C
@@ -82,7 +83,9 @@ struct Ctl {
     unsigned int err;               // sticky error bits
     unsigned int done;              // readout workgroups finished in the current bin
     unsigned long long ahead_events; // events of the next bin assembled ahead, not yet delivered
-    unsigned int bdone;              // k_bucket workgroups finished in the current launch
+    unsigned int pad0;
+    unsigned long long bnext;        // next k_bucket round to hand out (work queue)
+    unsigned long long pnext;        // next k_part chunk to hand out (work queue)
     unsigned long long inject_until; // output spikes are injected in bins below this one
 };
 
@@ -93,7 +96,8 @@ struct DevNet {
     uint32_t NS;           // super-tiles (buckets of k_part when wc == 0)
     uint32_t ts_bits;      // log2(tiles per super-tile)
     uint32_t HW;           // words per row header
-    uint32_t round_events; // events staged in LDS per partition round
+    uint32_t round_events; // events staged in LDS per partition round (k_part)
+    uint32_t bucket_events; // events per round of the second pass (k_bucket)
     uint32_t chunks_per_wg; // target scatter chunks per workgroup and bin
     uint32_t ahead_passes;  // partition passes of the next bin's delay >= 2 fan-in (two-pass form)
     uint64_t RCmask;
@@ -158,6 +162,7 @@ hipError_t prepare_kernels(); // one-time function attributes (LDS opt-in); call
 // fan-in of the delays d_lo..d_hi of the current bin (ahead = 0) or of the next one (ahead = 1)
 hipError_t launch_scatter(const DevNet& n, int grid, hipStream_t st, uint32_t d_lo, uint32_t d_hi, uint32_t ahead);
 hipError_t launch_gather(const DevNet& n, hipStream_t st);
+hipError_t launch_pass_reset(const DevNet& n, hipStream_t st);
 hipError_t launch_neuron(const DevNet& n, int s0, int s1, hipStream_t st);
 hipError_t launch_compact(const DevNet& n, hipStream_t st);
 hipError_t launch_readout_close(const DevNet& n, hipStream_t st);

@@ -12,8 +12,11 @@
 //              per tile) when the tiles are few, else into at most 64 super-tile
 //              streams. Launched twice per bin: delays 2..D of bin k+1 while bin k's
 //              neurons are stepped (side stream), delay 1 at the start of bin k+1.
+//              After each workgroup's first chunk the chunks come from a counter.
 //   k_bucket   second pass of the two-pass form: each super-tile stream is
-//              partitioned into its tiles the same way.
+//              partitioned into its tiles the same way, in rounds handed out by a
+//              counter; the next round's records are copied global -> LDS directly
+//              (no registers) while the current round is reserved and written.
 //   k_gather   one workgroup per tile: sums its events in LDS as int64 fixed
 //              point (exact, so any order gives the same bits), converts once
 //              to float, writes A.
@@ -38,10 +41,11 @@ namespace {
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
-// Exclusive prefix sum over a 1024-thread block; *total receives the block sum.
+// Exclusive prefix sum over a partition workgroup (kScatterThreads threads); *total receives
+// the block sum.
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_wave, uint32_t* total) {
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
-    const uint32_t nw = blockDim.x >> 6;
+    const uint32_t nw = kScatterThreads >> 6;
     uint32_t x = v;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -108,7 +112,7 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
 
 namespace {
 
-// exclusive scan of v[0..n) in place (n <= 2 * blockDim.x), returns the total
+// exclusive scan of v[0..n) in place (n <= 2 * kScatterThreads), returns the total
 __device__ uint32_t block_scan_inplace(uint32_t* v, uint32_t n, uint32_t* s_wave) {
     const uint32_t t = threadIdx.x;
     const uint32_t a = 2 * t < n ? v[2 * t] : 0u, b = 2 * t + 1 < n ? v[2 * t + 1] : 0u;
@@ -178,12 +182,15 @@ struct PartLayout {
 };
 
 struct BucketLayout {
-    size_t cpre, ccnt, total;
+    size_t stage, cpre, sbase, ccnt, fill, total;
     RoundLayout r;
     __host__ __device__ BucketLayout(uint32_t nb, uint32_t RE) {
         LdsLayout L;
+        stage = L.take(16 * (size_t)RE, 16);
         cpre = L.take(8 * (kMaxSuperTiles + 2), 8);
+        sbase = L.take(8 * (kMaxSuperTiles + 2), 8);
         ccnt = L.take(4 * (kMaxSuperTiles + 2), 4);
+        fill = L.take(4 * (kMaxSuperTiles + 2), 4);
         r.place(L, nb, RE);
         total = L.take(0, 16);
     }
@@ -230,6 +237,33 @@ struct Batch {
     uint32_t br[kMaxBatch]; // bucket << 16 | rank within the bucket
 };
 
+// Direct global -> LDS copy of records (12 bytes each; an 8-byte record brings the next
+// record's first word along, which is never used): one instruction per wavefront moves 64
+// records into 64 consecutive 16-byte LDS slots (lane l lands at byte 16 l) without passing
+// through registers. The copy is counted like a vector load of the issuing wavefront; it has
+// landed after that wavefront's next wait for all its vector memory operations (dma_wait).
+// The compiler does not see the LDS write, so every read of the slots follows dma_wait and a
+// barrier.
+__device__ __forceinline__ void dma_records64(const uint32_t* g, uint32_t lds_byte_addr) {
+    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx3 %1, off" ::"s"(lds_byte_addr), "v"(g) : "m0");
+}
+
+__device__ __forceinline__ void dma_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Wavefronts w0 .. of the block copy records src[first + e], e < ne, into stage[e] (64 per
+// instruction; the lanes past ne repeat the last record, so every access stays in the round).
+template <int KW>
+__device__ __forceinline__ void dma_round(const uint32_t* src, unsigned long long first, uint32_t ne, uint4* stage,
+                                          uint32_t w0) {
+    const uint32_t w = threadIdx.x >> 6, nw = kScatterThreads >> 6, l = threadIdx.x & 63u;
+    const uint32_t nch = (ne + 63u) >> 6;
+    for (uint32_t c = w - w0; c < nch; c += nw - w0) {
+        const uint32_t e = min(c * 64u + l, ne - 1u);
+        const uint32_t m0 = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(stage + (size_t)c * 64u));
+        dma_records64(src + (first + e) * (1u + KW), m0);
+    }
+}
+
 __device__ __forceinline__ uint32_t bucket_of(const DevNet& net, uint32_t key, uint32_t nb, uint32_t b0, uint32_t bshift) {
     const uint32_t b = ((key & 0x7FFFFFFFu) >> bshift) - b0;
     return b < nb ? b : 0u;
@@ -271,7 +305,7 @@ __device__ __forceinline__ void store_record(uint32_t* out, unsigned long long p
 // out_base[b0+b] .. out_base[b0+b+1]); sets gbase and the sorted starts.
 __device__ void reserve_runs(const DevNet& net, Round& R, uint32_t nb, uint32_t b0, const uint64_t* out_base,
                              uint32_t* out_fill) {
-    for (uint32_t t = threadIdx.x; t < nb; t += blockDim.x) {
+    for (uint32_t t = threadIdx.x; t < nb; t += kScatterThreads) {
         const uint32_t h = R.hist[t];
         unsigned long long gb = ~0ull;
         if (h) {
@@ -292,7 +326,7 @@ __device__ void reserve_runs(const DevNet& net, Round& R, uint32_t nb, uint32_t 
 template <int KW>
 __device__ void write_runs(const DevNet& net, Round& R, uint32_t ne, uint32_t nb, uint32_t b0, uint32_t bshift,
                            uint32_t* out) {
-    for (uint32_t q = threadIdx.x; q < ne; q += blockDim.x) {
+    for (uint32_t q = threadIdx.x; q < ne; q += kScatterThreads) {
         const uint32_t key = R.s_key[q];
         const uint32_t b = bucket_of(net, key, nb, b0, bshift);
         const unsigned long long gb = R.gbase[b];
@@ -307,7 +341,7 @@ __device__ void write_runs(const DevNet& net, Round& R, uint32_t ne, uint32_t nb
 // the chunk -> tile map.
 __device__ void wc_reserve(const DevNet& net, Round& R, Wc& W, uint32_t nb, bool final) {
     const uint32_t tid = threadIdx.x;
-    for (uint32_t t = tid; t < nb; t += blockDim.x) {
+    for (uint32_t t = tid; t < nb; t += kScatterThreads) {
         const uint32_t c = W.bcnt[t], h = R.hist[t], tot = c + h;
         const uint32_t f = final ? (tot + kChunk - 1) / kChunk : tot / kChunk;
         unsigned long long gb = ~0ull;
@@ -328,7 +362,7 @@ __device__ void wc_reserve(const DevNet& net, Round& R, Wc& W, uint32_t nb, bool
     const uint32_t nch = block_scan_inplace(W.cpre, nb, R.s_wave);
     if (tid == 0) W.cpre[nb] = nch;
     __syncthreads();
-    for (uint32_t t = tid; t < nb; t += blockDim.x)
+    for (uint32_t t = tid; t < nb; t += kScatterThreads)
         for (uint32_t i = W.cpre[t]; i < W.cpre[t + 1]; i++) W.cmap[i] = (uint16_t)t;
     __syncthreads();
 }
@@ -340,7 +374,7 @@ template <int KW>
 __device__ void wc_write(const DevNet& net, Round& R, Wc& W, uint32_t ne, uint32_t nb, uint32_t bshift, bool final) {
     const uint32_t tid = threadIdx.x;
     const uint32_t nch = W.cpre[nb];
-    for (uint32_t x = tid; x < nch * kChunk; x += blockDim.x) {
+    for (uint32_t x = tid; x < nch * kChunk; x += kScatterThreads) {
         const uint32_t ch = x / kChunk, slot = x % kChunk;
         const uint32_t b = W.cmap[ch];
         const uint32_t local = (ch - W.cpre[b]) * kChunk + slot, c = W.bc[b];
@@ -359,7 +393,7 @@ __device__ void wc_write(const DevNet& net, Round& R, Wc& W, uint32_t ne, uint32
     }
     __syncthreads();
     if (!final) {
-        for (uint32_t q = tid; q < ne; q += blockDim.x) {
+        for (uint32_t q = tid; q < ne; q += kScatterThreads) {
             const uint32_t key = R.s_key[q];
             const uint32_t b = bucket_of(net, key, nb, 0, bshift);
             const uint32_t local = W.bc[b] + (q - R.lstart[b]);
@@ -370,7 +404,7 @@ __device__ void wc_write(const DevNet& net, Round& R, Wc& W, uint32_t ne, uint32
             }
         }
     }
-    for (uint32_t t = tid; t < nb; t += blockDim.x)
+    for (uint32_t t = tid; t < nb; t += kScatterThreads)
         W.bcnt[t] = final ? 0u : W.bc[t] + R.hist[t] - (W.cpre[t + 1] - W.cpre[t]) * kChunk;
     __syncthreads();
 }
@@ -409,7 +443,7 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
     const uint32_t tid = threadIdx.x;
     // spike lists of bins k-d for the delays d_lo <= d <= d_hi (one thread per delay),
     // then their prefix over all D delays (the other delays contribute nothing)
-    for (uint32_t x = tid; x < D; x += blockDim.x) {
+    for (uint32_t x = tid; x < D; x += kScatterThreads) {
         const uint32_t d = x + 1;
         uint32_t cnt = 0;
         unsigned long long st = 0;
@@ -422,24 +456,29 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
         s_dcnt[x] = cnt;
     }
     __syncthreads();
-    for (uint32_t x = tid; x <= D; x += blockDim.x) {
+    for (uint32_t x = tid; x <= D; x += kScatterThreads) {
         unsigned long long tot = 0;
         for (uint32_t y = 0; y < x; y++) tot += s_dcnt[y];
         s_dpre[x] = tot;
     }
     if (wc)
-        for (uint32_t t = tid; t < nb; t += blockDim.x) W.bcnt[t] = 0u;
+        for (uint32_t t = tid; t < nb; t += kScatterThreads) W.bcnt[t] = 0u;
     __syncthreads();
     const unsigned long long total = s_dpre[D];
     if (total == 0) return;
     // segments per chunk: about chunks_per_wg chunks per workgroup, at most kScatterSegs
-    const unsigned long long cw = (unsigned long long)net.chunks_per_wg * gridDim.x;
+    const uint32_t G = gridDim.x;
+    const unsigned long long cw = (unsigned long long)net.chunks_per_wg * G;
     const uint32_t spc = (uint32_t)min((unsigned long long)kScatterSegs, max(32ull, (total + cw - 1) / cw));
     const unsigned long long nchunks = (total + spc - 1) / spc;
     const uint32_t bshift = wc ? net.tile_bits : net.tile_bits + net.ts_bits;
     unsigned long long my_events = 0;
-
-    for (unsigned long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    // the first chunk of every workgroup is fixed, the others are handed out through a
+    // counter (a workgroup that starts late, behind another kernel's workgroups, takes
+    // fewer); the next one is claimed while this one is read
+    __shared__ unsigned long long s_pc;
+    unsigned long long c = blockIdx.x;
+    while (c < nchunks) {
         const unsigned long long i0 = c * spc;
         const uint32_t nseg = (uint32_t)min((unsigned long long)spc, total - i0);
         uint32_t len = 0;
@@ -479,7 +518,7 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
         for (uint32_t r0 = 0; r0 < ec; r0 += RE) {
             const uint32_t ne = min(RE, ec - r0);
             const uint32_t nbt = (ne + kScatterThreads - 1) / kScatterThreads;
-            for (uint32_t t = tid; t < nb; t += blockDim.x) R.hist[t] = 0;
+            for (uint32_t t = tid; t < nb; t += kScatterThreads) R.hist[t] = 0;
             __syncthreads();
             Batch B;
             // all loads of the batch are issued before any is used (latency cover); the
@@ -507,17 +546,27 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
             for (int u = 0; u < kMaxBatch; u++)
                 if (u < (int)nbt && u * kScatterThreads + tid < ne) B.br[u] = rank_event(net, R, B.key[u], nb, 0, bshift);
             __syncthreads();
+            // the next chunk is claimed in the first round, alongside wavefront 0's
+            // reservations (one wait for both)
+            unsigned long long claim = ~0ull;
+            if (tid == 0 && r0 == 0) claim = G + atomicAdd(&net.ctl->pnext, 1ull);
             if (wc) wc_reserve(net, R, W, nb, false);
             else reserve_runs(net, R, nb, 0, net.st_base, net.st_fill);
             place_batch(R, B, ne, nbt);
+            if (tid == 0 && r0 == 0) s_pc = claim; // read by every thread at the end of the chunk
             __syncthreads();
             if (wc) wc_write<KW>(net, R, W, ne, nb, bshift, false);
             else write_runs<KW>(net, R, ne, nb, 0, bshift, net.sev);
         }
+        if (ec == 0) { // no round: claim here
+            if (tid == 0) s_pc = G + atomicAdd(&net.ctl->pnext, 1ull);
+            __syncthreads();
+        }
         my_events += ec;
+        c = s_pc;
     }
     if (wc) { // the carried events of every tile, as padded chunks
-        for (uint32_t t = tid; t < nb; t += blockDim.x) R.hist[t] = 0;
+        for (uint32_t t = tid; t < nb; t += kScatterThreads) R.hist[t] = 0;
         __syncthreads();
         wc_reserve(net, R, W, nb, true);
         wc_write<KW>(net, R, W, 0, nb, bshift, true);
@@ -525,6 +574,8 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
     // events count as delivered when their bin's arrivals are consumed (the gather moves
     // the ahead count over)
     if (tid == 0 && my_events) atomicAdd(ahead ? &net.ctl->ahead_events : &net.ctl->edge_events, my_events);
+    // the chunk counter is reset by the next kernel of the stream (k_bucket, k_gather or the
+    // bin close): no grid-wide completion count, whose same-address atomics cost tens of us
 }
 
 // Records in super-tile stream st. A stream never holds more than its slice (each edge
@@ -539,78 +590,105 @@ __device__ __forceinline__ uint32_t stream_fill(const DevNet& net, uint32_t st) 
 template <int KW>
 __global__ void __launch_bounds__(kScatterThreads) k_bucket(DevNet net) {
     extern __shared__ __align__(16) unsigned char dyn[];
-    const uint32_t RE = net.round_events, NS = net.NS, TS = 1u << net.ts_bits;
+    const uint32_t RE = net.bucket_events, NS = net.NS, TS = 1u << net.ts_bits, G = gridDim.x;
     const BucketLayout L(TS, RE);
+    uint4* stage = reinterpret_cast<uint4*>(dyn + L.stage);
     unsigned long long* s_cpre = reinterpret_cast<unsigned long long*>(dyn + L.cpre);
+    unsigned long long* s_sbase = reinterpret_cast<unsigned long long*>(dyn + L.sbase);
     Round R;
     R.at(dyn, L.r);
     uint32_t* s_ccnt = reinterpret_cast<uint32_t*>(dyn + L.ccnt);
+    uint32_t* s_fill = reinterpret_cast<uint32_t*>(dyn + L.fill);
     const uint32_t tid = threadIdx.x;
-    // rounds per stream (one thread per stream), then their prefix
-    for (uint32_t st = tid; st < NS; st += blockDim.x) s_ccnt[st] = (stream_fill(net, st) + RE - 1) / RE;
+    if (blockIdx.x == 0 && tid == 0) net.ctl->pnext = 0; // the partition pass has finished
+    // records and rounds per stream (one thread per stream), then the rounds' prefix
+    for (uint32_t st = tid; st < NS; st += kScatterThreads) {
+        const uint32_t f = stream_fill(net, st);
+        s_fill[st] = f;
+        s_sbase[st] = net.st_base[st];
+        s_ccnt[st] = (f + RE - 1) / RE;
+    }
     __syncthreads();
-    for (uint32_t st = tid; st <= NS; st += blockDim.x) {
+    for (uint32_t st = tid; st <= NS; st += kScatterThreads) {
         unsigned long long tot = 0;
         for (uint32_t y = 0; y < st; y++) tot += s_ccnt[y];
         s_cpre[st] = tot;
     }
     __syncthreads();
     const unsigned long long nchunks = s_cpre[NS];
-    for (unsigned long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    // round c: stream, first record and size
+    auto locate = [&](unsigned long long c, uint32_t& st, unsigned long long& r0, uint32_t& ne) {
         uint32_t lo = 0, hi = NS;
         while (hi - lo > 1u) {
             const uint32_t mid = (lo + hi) >> 1;
             if (s_cpre[mid] <= c) lo = mid;
             else hi = mid;
         }
-        const uint32_t st = lo;
-        const unsigned long long r0 = (c - s_cpre[st]) * RE;
-        const uint32_t fill = stream_fill(net, st);
-        const uint32_t ne = (uint32_t)min((unsigned long long)RE, fill - r0);
+        st = lo;
+        r0 = (c - s_cpre[st]) * RE;
+        ne = (uint32_t)min((unsigned long long)RE, s_fill[st] - r0);
+    };
+    // Rounds: the first two of every workgroup are fixed, the others are handed out through
+    // a counter (a workgroup that starts late, behind another kernel's workgroups, takes
+    // fewer), two ahead: while round c is processed, the records of the next round cn are
+    // copied into the staging slots (free once c is ranked) and the round after it is claimed.
+    __shared__ unsigned long long s_claim;
+    unsigned long long c = blockIdx.x, cn = blockIdx.x + G;
+    if (c < nchunks) {
+        uint32_t st, ne;
+        unsigned long long r0;
+        locate(c, st, r0, ne);
+        dma_round<KW>(net.sev, s_sbase[st] + r0, ne, stage, 0);
+    }
+    while (c < nchunks) {
+        uint32_t st, ne;
+        unsigned long long r0;
+        locate(c, st, r0, ne);
         const uint32_t nbt = (ne + kScatterThreads - 1) / kScatterThreads;
         const uint32_t t0 = st * TS;
         const uint32_t nt = min(TS, net.T - t0);
-        for (uint32_t t = tid; t < nt; t += blockDim.x) R.hist[t] = 0;
+        for (uint32_t t = tid; t < nt; t += kScatterThreads) R.hist[t] = 0;
+        dma_wait();
         __syncthreads();
-        const unsigned long long src0 = net.st_base[st] + r0;
         Batch B;
 #pragma unroll
         for (int u = 0; u < kMaxBatch; u++) {
-            if (u < (int)nbt) {
-                const uint32_t e = min(u * kScatterThreads + tid, ne - 1); // unconditional loads
-                if (KW == 2) {
-                    const uint3 q = reinterpret_cast<const uint3*>(net.sev)[src0 + e];
-                    B.key[u] = q.x;
-                    B.w[u] = make_float2(__uint_as_float(q.y), __uint_as_float(q.z));
-                } else {
-                    const uint2 q = reinterpret_cast<const uint2*>(net.sev)[src0 + e];
-                    B.key[u] = q.x;
-                    B.w[u] = make_float2(__uint_as_float(q.y), 0.0f);
-                }
+            const uint32_t e = u * kScatterThreads + tid;
+            if (u < (int)nbt && e < ne) {
+                const uint4 q = stage[e];
+                B.key[u] = q.x;
+                B.w[u] = make_float2(__uint_as_float(q.y), KW == 2 ? __uint_as_float(q.z) : 0.0f);
+                B.br[u] = rank_event(net, R, B.key[u], nt, t0, net.tile_bits);
             }
         }
-#pragma unroll
-        for (int u = 0; u < kMaxBatch; u++)
-            if (u < (int)nbt && u * kScatterThreads + tid < ne)
-                B.br[u] = rank_event(net, R, B.key[u], nt, t0, net.tile_bits);
         __syncthreads();
+        if (cn < nchunks && tid >= 64u) { // wavefront 0 makes the reservations meanwhile
+            uint32_t st2, ne2;
+            unsigned long long r2;
+            locate(cn, st2, r2, ne2);
+            dma_round<KW>(net.sev, s_sbase[st2] + r2, ne2, stage, 1);
+        }
+        // the claim travels with wavefront 0's reservations (one wait for both)
+        unsigned long long claim = ~0ull;
+        if (tid == 0 && cn < nchunks) claim = 2ull * G + atomicAdd(&net.ctl->bnext, 1ull);
         reserve_runs(net, R, nt, t0, net.tile_base, net.tile_fill);
         place_batch(R, B, ne, nbt);
+        if (tid == 0) s_claim = claim;
         __syncthreads();
         write_runs<KW>(net, R, ne, nt, t0, net.tile_bits, net.ev);
+        c = cn;
+        cn = s_claim;
     }
-    // the last workgroup to finish empties the streams for the next partition pass (every
-    // workgroup read the fill counts in its prologue, before it got here)
-    __shared__ bool last;
-    __syncthreads();
-    if (tid == 0) {
-        __threadfence();
-        last = atomicAdd(&net.ctl->bdone, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (last) {
-        for (uint32_t st = tid; st < NS; st += blockDim.x) net.st_fill[st] = 0;
-        if (tid == 0) net.ctl->bdone = 0;
+    // the round counter and the stream fills are reset by the next kernel of the stream
+    // (k_gather, the bin close, or the reset between two ahead passes)
+}
+
+// between two partition passes of one bin: empty streams and work-queue counters
+__global__ void __launch_bounds__(256) k_pass_reset(DevNet net) {
+    for (uint32_t x = threadIdx.x; x < net.NS; x += blockDim.x) net.st_fill[x] = 0;
+    if (threadIdx.x == 0) {
+        net.ctl->pnext = 0;
+        net.ctl->bnext = 0;
     }
 }
 
@@ -670,6 +748,8 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(DevNet net) {
     if (t == 0 && threadIdx.x == 0) {
         net.ctl->edge_events += net.ctl->ahead_events;
         net.ctl->ahead_events = 0;
+        net.ctl->pnext = 0; // work-queue counters of the partition kernels
+        net.ctl->bnext = 0;
     }
     const float qinv = net.qinv;
     for (uint32_t x = threadIdx.x; x < nt; x += blockDim.x) {
@@ -1006,6 +1086,8 @@ __global__ void __launch_bounds__(256) k_readout_close(DevNet net) {
         net.bin_cnt[(k + 1) & m] = 0;
         net.ctl->spikes += c;
         net.ctl->done = 0;
+        net.ctl->pnext = 0;
+        net.ctl->bnext = 0;
         net.ctl->bin = k + 1;
     }
 }
@@ -1020,7 +1102,7 @@ hipError_t prepare_kernels() {
                          (const void*)k_bucket<2>};
     hipError_t e = hipSuccess;
     for (const void* f : big) { // leave room for the kernels' few static LDS bytes
-        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytes - 256);
+        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kMaxLdsBytes - kStaticLds));
         if (e != hipSuccess) return e;
     }
     e = hipFuncSetAttribute((const void*)k_gather<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1032,7 +1114,7 @@ hipError_t prepare_kernels() {
 
 hipError_t launch_scatter(const DevNet& n, int grid, hipStream_t st, uint32_t d_lo, uint32_t d_hi, uint32_t ahead) {
     const size_t la = part_lds_bytes(n.wc ? n.T : n.NS, n.round_events, n.wc != 0, n.D);
-    const size_t lb = bucket_lds_bytes(1u << n.ts_bits, n.round_events);
+    const size_t lb = bucket_lds_bytes(1u << n.ts_bits, n.bucket_events);
     if (n.KW == 2)
         hipLaunchKernelGGL(k_part<2>, dim3(grid), dim3(kScatterThreads), la, st, n, d_lo, d_hi, ahead);
     else
@@ -1043,6 +1125,11 @@ hipError_t launch_scatter(const DevNet& n, int grid, hipStream_t st, uint32_t d_
         hipLaunchKernelGGL(k_bucket<2>, dim3(grid), dim3(kScatterThreads), lb, st, n);
     else
         hipLaunchKernelGGL(k_bucket<1>, dim3(grid), dim3(kScatterThreads), lb, st, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_pass_reset(const DevNet& n, hipStream_t st) {
+    hipLaunchKernelGGL(k_pass_reset, dim3(1), dim3(256), 0, st, n);
     return hipGetLastError();
 }
 

@@ -89,14 +89,21 @@ static double bucket_build_bytes() {
 }
 
 uint32_t max_round_events(const Plan& p, uint32_t wgs_per_cu) {
-    const size_t budget = kMaxLdsBytes / wgs_per_cu - 256;
+    const size_t budget = kMaxLdsBytes / wgs_per_cu - kStaticLds;
     uint32_t best = 0;
     for (uint32_t re = kScatterThreads; re <= (uint32_t)(kScatterThreads * kMaxBatch); re += kScatterThreads) {
-        const bool fits = p.wc ? part_lds_bytes(p.T, re, true, p.D) <= budget
-                               : part_lds_bytes(p.NS, re, false, p.D) <= budget &&
-                                     bucket_lds_bytes(1u << p.ts_bits, re) <= budget;
+        const bool fits = p.wc ? part_lds_bytes(p.T, re, true, p.D) <= budget : part_lds_bytes(p.NS, re, false, p.D) <= budget;
         if (fits) best = re;
     }
+    return best;
+}
+
+uint32_t max_bucket_events(const Plan& p, uint32_t wgs_per_cu) {
+    if (p.wc) return kScatterThreads; // no second pass
+    const size_t budget = kMaxLdsBytes / wgs_per_cu - kStaticLds;
+    uint32_t best = 0;
+    for (uint32_t re = kScatterThreads; re <= (uint32_t)(kScatterThreads * kMaxBatch); re += kScatterThreads)
+        if (bucket_lds_bytes(1u << p.ts_bits, re) <= budget) best = re;
     return best;
 }
 
@@ -165,7 +172,7 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     // round of 1024 events fit twice in a CU's LDS, else two passes through at most
     // kMaxSuperTiles super-tile streams of a power-of-two number of tiles each
     p.wc = !(opts.flags & DBSIM_F_TWO_PASS) && p.T <= 2u * kScatterThreads &&
-           part_lds_bytes(p.T, 1024, true, p.D) <= kMaxLdsBytes / 2 - 256;
+           part_lds_bytes(p.T, 1024, true, p.D) <= kMaxLdsBytes / 2 - kStaticLds;
     p.ts_bits = 0;
     if (!p.wc)
         while (((p.T + (1u << p.ts_bits) - 1) >> p.ts_bits) > kMaxSuperTiles) p.ts_bits++;
@@ -175,7 +182,8 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     // workgroups per CU, the largest LDS round that fits
     p.scatter_wgs_per_cu = 2;
     p.round_events = max_round_events(p, p.scatter_wgs_per_cu);
-    if (p.round_events == 0) return "too many tiles per super-tile for the LDS budget";
+    p.bucket_events = max_bucket_events(p, p.scatter_wgs_per_cu);
+    if (p.round_events == 0 || p.bucket_events == 0) return "too many tiles per super-tile for the LDS budget";
     const double dt = (double)m0.dt_ms;
     p.E = 0;
     p.n_blocks = 0;
@@ -234,7 +242,8 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     slot(p.tile_fill, 4 * (size_t)p.T);
     slot(p.st_base, 8 * ((size_t)p.NS + 1));
     slot(p.st_fill, 4 * (size_t)p.NS);
-    slot(p.sev, p.wc ? 16 : 4 * (size_t)(1 + p.KW) * E);
+    // 64 spare bytes: the partition kernels copy 8-byte records with 12-byte reads
+    slot(p.sev, p.wc ? 16 : 4 * (size_t)(1 + p.KW) * E + 64);
     p.n_grp = (p.n_blocks + 255) / 256;
     slot(p.stage, 4 * (size_t)p.n_blocks * kNeuronBlock);
     slot(p.grp_cnt, 4 * 2 * (size_t)p.n_grp);

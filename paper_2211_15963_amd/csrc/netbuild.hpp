@@ -41,7 +41,7 @@ struct Plan {
     bool wc = false;              // k_part writes tile chunks directly (else two passes)
     uint32_t NS = 0, ts_bits = 0; // super-tiles, log2(tiles per super-tile) of the two-pass form
     uint32_t HW = 0;              // words per row header
-    uint32_t round_events = 0, scatter_wgs_per_cu = 0;
+    uint32_t round_events = 0, bucket_events = 0, scatter_wgs_per_cu = 0;
     uint64_t RC = 0; // spike-history ring entries (power of two)
     uint64_t E = 0;  // edges
     bool regions_on = false;
@@ -58,6 +58,7 @@ struct Plan {
 // Largest multiple of 1024 events (at most 8192) a partition round can stage in LDS for
 // the plan's form (0 if none fits).
 uint32_t max_round_events(const Plan& p, uint32_t wgs_per_cu);
+uint32_t max_bucket_events(const Plan& p, uint32_t wgs_per_cu);
 
 // Validates the runtime options and the members for this simulator and fills the plan.
 // Returns an empty string on success, else the reason.
