@@ -18,6 +18,7 @@ ARCH = os.environ.get("DBSIM_OFFLOAD_ARCH", "gfx950")
 
 HIPFLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
             "-fno-gpu-flush-denormals-to-zero", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
             "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 SOURCES = ["kernels.hip", "netbuild.cpp", "abi.cpp"]
 

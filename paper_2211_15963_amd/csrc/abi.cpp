@@ -728,7 +728,7 @@ int dbsim_export_csr(dbsim* h, uint64_t* row_ptr, uint32_t* seg, uint32_t* tgt, 
         std::vector<uint32_t> rec((size_t)p.E * RW);
         HIPCHK(h, hipMemcpy(rec.data(), h->net.edge, 4 * rec.size(), hipMemcpyDeviceToHost), "hipMemcpy");
         for (uint64_t e = 0; e < p.E; e++) {
-            if (tgt) tgt[e] = rec[e * RW];
+            if (tgt) tgt[e] = rec[e * RW] & 0x7FFFFFFFu; // bit 31: the source is inhibitory
             if (w0) std::memcpy(&w0[e], &rec[e * RW + 1], 4);
             if (w1) {
                 if (p.KW == 2) std::memcpy(&w1[e], &rec[e * RW + 2], 4);

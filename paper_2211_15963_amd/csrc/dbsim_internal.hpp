@@ -10,7 +10,8 @@
 //     uniform (scalar registers);
 //   connection table by presynaptic neuron (Suppl. Table 5's table is stored
 //     by target; the push-based fan-out of Suppl. Algorithm 2 wants it by
-//     source): one record of 1 + KW words per edge (target, then the weights),
+//     source): one record of 1 + KW words per edge (target | source class << 31,
+//     then the weights: the record is already the fan-in's event key),
 //     so that a (spike, delay) segment is one contiguous run; rows sorted by
 //     delay, then target; one row header per neuron, hdr u32[N][HW]
 //     (HW = D + 3 rounded up to 4 words: the row start as u64 with the source
@@ -118,7 +119,7 @@ struct DevNet {
     const uint2* blk; // (first neuron, population)
     // connection table
     const uint32_t* hdr;  // [N][HW] row headers
-    const uint32_t* edge; // [E][1 + KW] records: target, then the weights
+    const uint32_t* edge; // [E][1 + KW] records: target | inhibitory source << 31, then the weights
     // event arena: records of (1 + KW) words: target within tile | source class << 31, weights
     uint32_t* ev;
     const uint64_t* tile_base;

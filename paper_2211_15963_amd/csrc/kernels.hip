@@ -162,7 +162,7 @@ struct WcLayout {
 };
 
 struct PartLayout {
-    size_t dpre, dstart, sstart, spre, dcnt, smap, scls, total;
+    size_t dpre, dstart, sstart, spre, dcnt, smap, total;
     RoundLayout r;
     WcLayout w;
     __host__ __device__ PartLayout(uint32_t nb, uint32_t RE, bool wc, uint32_t D) {
@@ -176,7 +176,6 @@ struct PartLayout {
         spre = L.take(4 * (kScatterSegs + 4), 4);
         dcnt = L.take(4 * ((size_t)D + 1), 4);
         smap = L.take(2 * (kScatterSegs + 2), 2);
-        scls = L.take(kScatterSegs, 1);
         total = L.take(0, 16);
     }
 };
@@ -429,7 +428,6 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
     unsigned long long* s_dstart = reinterpret_cast<unsigned long long*>(dyn + L.dstart);
     unsigned long long* s_sstart = reinterpret_cast<unsigned long long*>(dyn + L.sstart);
     uint32_t* s_spre = reinterpret_cast<uint32_t*>(dyn + L.spre);
-    uint8_t* s_scls = reinterpret_cast<uint8_t*>(dyn + L.scls);
     Round R;
     R.at(dyn, L.r);
     Wc W{};
@@ -492,12 +490,12 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
             }
             const uint32_t d = lo + 1;
             const uint32_t j = net.rec[(s_dstart[lo] + (it - s_dpre[lo])) & net.RCmask] >> 4;
-            // row header of j: row start (bit 63: inhibitory source), then the delay segment offsets
+            // row header of j: row start (bit 63: inhibitory source), then the delay segment
+            // offsets (the records carry the source class themselves)
             const uint32_t* hp = net.hdr + (size_t)j * net.HW;
             const uint2 rs = *reinterpret_cast<const uint2*>(hp);
             const uint32_t so = hp[1 + d], eo = hp[2 + d];
             s_sstart[tid] = (((unsigned long long)(rs.y & 0x7FFFFFFFu) << 32) | rs.x) + so;
-            s_scls[tid] = (uint8_t)(rs.y >> 31);
             len = eo - so;
         }
         uint32_t ec;
@@ -529,15 +527,15 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
                     const uint32_t ge = r0 + min(u * kScatterThreads + tid, ne - 1);
                     const uint32_t m = ge >> mb_bits;
                     const uint32_t lo = s_map[m], hi = m + 1 < nmap ? s_map[m + 1] : nseg - 1;
-                    const uint32_t s = lo + seg_search(s_spre + lo, hi - lo + 1, ge);
-                    const unsigned long long edge = s_sstart[s] + (ge - s_spre[s]);
+                    const uint32_t sg = lo + seg_search(s_spre + lo, hi - lo + 1, ge);
+                    const unsigned long long edge = s_sstart[sg] + (ge - s_spre[sg]);
                     if (KW == 2) {
                         const uint3 r = reinterpret_cast<const uint3*>(net.edge)[edge];
-                        B.key[u] = r.x | ((uint32_t)s_scls[s] << 31);
+                        B.key[u] = r.x; // target | source class << 31
                         B.w[u] = make_float2(__uint_as_float(r.y), __uint_as_float(r.z));
                     } else {
                         const uint2 r = reinterpret_cast<const uint2*>(net.edge)[edge];
-                        B.key[u] = r.x | ((uint32_t)s_scls[s] << 31);
+                        B.key[u] = r.x;
                         B.w[u] = make_float2(__uint_as_float(r.y), 0.0f);
                     }
                 }
@@ -548,12 +546,12 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
             __syncthreads();
             // the next chunk is claimed in the first round, alongside wavefront 0's
             // reservations (one wait for both)
-            unsigned long long claim = ~0ull;
-            if (tid == 0 && r0 == 0) claim = G + atomicAdd(&net.ctl->pnext, 1ull);
+            unsigned long long claim = 0;
+            if (tid == 0 && r0 == 0) claim = atomicAdd(&net.ctl->pnext, 1ull);
             if (wc) wc_reserve(net, R, W, nb, false);
             else reserve_runs(net, R, nb, 0, net.st_base, net.st_fill);
             place_batch(R, B, ne, nbt);
-            if (tid == 0 && r0 == 0) s_pc = claim; // read by every thread at the end of the chunk
+            if (tid == 0 && r0 == 0) s_pc = G + claim; // read by every thread at the end of the chunk
             __syncthreads();
             if (wc) wc_write<KW>(net, R, W, ne, nb, bshift, false);
             else write_runs<KW>(net, R, ne, nb, 0, bshift, net.sev);
@@ -669,11 +667,11 @@ __global__ void __launch_bounds__(kScatterThreads) k_bucket(DevNet net) {
             dma_round<KW>(net.sev, s_sbase[st2] + r2, ne2, stage, 1);
         }
         // the claim travels with wavefront 0's reservations (one wait for both)
-        unsigned long long claim = ~0ull;
-        if (tid == 0 && cn < nchunks) claim = 2ull * G + atomicAdd(&net.ctl->bnext, 1ull);
+        unsigned long long claim = 0;
+        if (tid == 0 && cn < nchunks) claim = atomicAdd(&net.ctl->bnext, 1ull);
         reserve_runs(net, R, nt, t0, net.tile_base, net.tile_fill);
         place_batch(R, B, ne, nbt);
-        if (tid == 0) s_claim = claim;
+        if (tid == 0) s_claim = cn < nchunks ? 2ull * G + claim : ~0ull;
         __syncthreads();
         write_runs<KW>(net, R, ne, nt, t0, net.tile_bits, net.ev);
         c = cn;
@@ -808,6 +806,11 @@ __global__ void __launch_bounds__(kNeuronBlock) k_neuron(DevNet net, int s0, int
         dec[u] = P.dec[u];
     }
     const int rsteps = P.r;
+    // the first Poisson thresholds in registers (uniform: the block's population)
+    constexpr int kTr = 8;
+    uint32_t Tr[kTr];
+#pragma unroll
+    for (int m = 0; m < kTr; m++) Tr[m] = m < cmax ? s_T[m] : 0u;
     const bool ou = P.ou_on != 0u; // uniform: neuron blocks never straddle populations
     const float ou_mu = P.ou_mu, ou_c1 = P.ou_c1, ou_c2 = P.ou_c2;
     const unsigned long long seed = P.seed;
@@ -830,13 +833,26 @@ __global__ void __launch_bounds__(kNeuronBlock) k_neuron(DevNet net, int s0, int
         }
         const uint32_t sel = (uint32_t)(n & 3ull);
         const uint32_t x = sel == 0 ? w0 : sel == 1 ? w1 : sel == 2 ? w2 : w3;
-        // c = #{m < cmax : T_m <= x}; T is nondecreasing, so a binary search counts it
+        // c = #{m < cmax : T_m <= x}. T is nondecreasing, so every lane's condition holds
+        // for m below its count and fails above: a linear scan over m that stops at the first
+        // threshold above the x of every lane of the wavefront counts exactly (the counts are
+        // small, so it stops after a few thresholds)
         uint32_t c = 0;
+        bool more = true;
 #pragma unroll
-        for (uint32_t step = kMaxPoisson / 2; step > 0; step >>= 1) {
-            const uint32_t probe = c + step;
-            if (probe <= (uint32_t)cmax && s_T[probe - 1] <= x) c = probe;
+        for (int m = 0; m < kTr; m++) {
+            if (more && m < cmax) { // wavefront-uniform
+                const bool ge = Tr[m] <= x;
+                c += ge ? 1u : 0u;
+                more = __any(ge);
+            }
         }
+        if (more)
+            for (int m = kTr; m < cmax; m++) {
+                const bool ge = s_T[m] <= x;
+                if (!__any(ge)) break;
+                c += ge ? 1u : 0u;
+            }
 
         float Vn;
         if (ref > 0) {

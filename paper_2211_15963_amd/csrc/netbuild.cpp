@@ -234,7 +234,7 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     slot(p.ptab, 4 * (size_t)kMaxPoisson * p.n_pops);
     slot(p.blk, sizeof(uint2) * p.n_blocks);
     slot(p.hdr, 4 * N * (size_t)p.HW);
-    slot(p.edge, 4 * (size_t)(1 + p.KW) * E);
+    slot(p.edge, 4 * (size_t)(1 + p.KW) * E + 64); // spare: 8-byte records are copied with 12-byte reads
     // event arena: write-combined tile slices are padded (see build_tables)
     const size_t arena = p.wc ? E + (size_t)p.T * (kChunk - 1 + 2 * (size_t)kChunk * kMaxPartGrid) : E;
     slot(p.ev, 4 * (size_t)(1 + p.KW) * arena);
@@ -475,7 +475,7 @@ std::string build_tables(const Members& mem, const Plan& p, unsigned threads, Ho
                     for (const BucketEdge& be : bucket[(size_t)t * SB + b]) {
                         const uint64_t e = cur[(size_t)(be.src_dl >> 8) * D + (be.src_dl & 0xFF) - 1]++;
                         uint32_t* rec = &h.edge[e * RW];
-                        rec[0] = be.tgt;
+                        rec[0] = be.tgt | ((uint32_t)h.src_inh[j0 + (be.src_dl >> 8)] << 31);
                         rec[1] = be.w0;
                         if (KW == 2) rec[2] = be.w1;
                     }
@@ -547,7 +547,7 @@ std::string build_tables(const Members& mem, const Plan& p, unsigned threads, Ho
                 for (int64_t e = 0; e < k; e++) {
                     const uint64_t pos = cur[(size_t)(src[e] + base) * D + dl[e] - 1].fetch_add(1, std::memory_order_relaxed);
                     uint32_t* rec = &h.edge[pos * RW];
-                    rec[0] = (uint32_t)i;
+                    rec[0] = (uint32_t)i | ((uint32_t)h.src_inh[src[e] + base] << 31);
                     std::memcpy(&rec[1], &w0[e], 4);
                     if (KW == 2) std::memcpy(&rec[2], &w1[e], 4);
                     if (!(std::fabs((double)w0[e]) < wlim) || !(std::fabs((double)w1[e]) < wlim)) wbad.store(1);
