@@ -297,7 +297,8 @@ typedef struct dbsim_tuning {
     uint32_t scatter_wgs_per_cu; /* 1..8 partition workgroups per CU (they split the LDS) */
     uint32_t round_events;       /* events staged in LDS per round, multiple of 256, at most 4096;
                                     0 = the most that fit */
-    uint32_t chunks_per_wg;      /* target (spike, delay) chunks per partition workgroup per bin, 1..64 */
+    uint32_t chunks_per_wg;      /* target (spike, delay) chunks per partition workgroup in the pass of
+                                    delays >= 2, 1..64 (the delay-1 pass uses one) */
     uint32_t ahead_passes;       /* two-pass form: the next bin's delay >= 2 fan-in runs as this many
                                     partition passes over consecutive delay groups (smaller passes keep
                                     their streams cache-resident), 1..max delay - 1; 0 = default */

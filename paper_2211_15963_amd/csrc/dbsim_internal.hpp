@@ -82,7 +82,7 @@ struct Ctl {
     unsigned long long edge_events; // delivered synaptic events
     unsigned long long spikes;      // spikes emitted in closed bins
     unsigned int err;               // sticky error bits
-    unsigned int done;              // readout workgroups finished in the current bin
+    unsigned int pad1;
     unsigned long long ahead_events; // events of the next bin assembled ahead, not yet delivered
     unsigned int pad0;
     unsigned long long bnext;        // next k_bucket round to hand out (work queue)

@@ -26,9 +26,10 @@
 //              end, wavefront-ballot compaction of the spike list and the
 //              per-block region partial sums.
 //   k_compact  places every block's staged spikes in the bin's dense spike list.
-//   k_readout_close  per-region mean synaptic current and spike count (fixed-order
-//              tree over the region's block partials), the region BOLD step
-//              (Extended Data Table 4), and the bin close (bin counter, spike ring).
+//   k_region_partials, k_readout_close  per-region mean synaptic current and spike
+//              count (fixed-order tree over groups of 256 block partials, then the
+//              groups in order), the region BOLD step (Extended Data Table 4), and the
+//              bin close (bin counter, spike ring).
 //
 // All float arithmetic is single IEEE operations in a fixed order (the file
 // is built with -ffp-contract=off and f32 denormals preserved) so the result
@@ -464,9 +465,10 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
     __syncthreads();
     const unsigned long long total = s_dpre[D];
     if (total == 0) return;
-    // segments per chunk: about chunks_per_wg chunks per workgroup, at most kScatterSegs
+    // segments per chunk: about chunks_per_wg chunks per workgroup (one for the small
+    // delay-1 pass, where a chunk's fixed cost weighs most), at most kScatterSegs
     const uint32_t G = gridDim.x;
-    const unsigned long long cw = (unsigned long long)net.chunks_per_wg * G;
+    const unsigned long long cw = (unsigned long long)(ahead ? net.chunks_per_wg : 1u) * G;
     const uint32_t spc = (uint32_t)min((unsigned long long)kScatterSegs, max(32ull, (total + cw - 1) / cw));
     const unsigned long long nchunks = (total + spc - 1) / spc;
     const uint32_t bshift = wc ? net.tile_bits : net.tile_bits + net.ts_bits;
@@ -1043,42 +1045,60 @@ __device__ void bold_step(const DevNet& net, uint32_t r, uint32_t c) {
     }
 }
 
-__global__ void __launch_bounds__(256) k_readout_close(DevNet net) {
+// Level 1 of the region readout: workgroup g sums up to 256 neuron blocks of one region
+// (fixed tree).
+__global__ void __launch_bounds__(256) k_region_partials(DevNet net) {
     __shared__ double s[256];
     __shared__ uint32_t sc[256];
-    __shared__ bool last;
+    const uint32_t gid = blockIdx.x;
+    const uint32_t r = net.l1_region[gid];
+    const uint32_t b0 = net.reg_blk_ptr[r] + (gid - net.l1_ptr[r]) * 256u;
+    const uint32_t b1 = min(b0 + 256u, net.reg_blk_ptr[r + 1]);
+    const uint32_t b = b0 + threadIdx.x;
+    s[threadIdx.x] = b < b1 ? net.blk_sig[net.reg_blk[b]] : 0.0;
+    sc[threadIdx.x] = b < b1 ? net.blk_cnt[net.reg_blk[b]] : 0u;
+    __syncthreads();
+    for (uint32_t st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            s[threadIdx.x] += s[threadIdx.x + st];
+            sc[threadIdx.x] += sc[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        net.l1_sig[gid] = s[0];
+        net.l1_cnt[gid] = sc[0];
+    }
+}
+
+// Region sums over their level-1 partials in order, the BOLD step, and the bin close
+// (one workgroup).
+__global__ void __launch_bounds__(256) k_readout_close(DevNet net) {
     const unsigned long long k = net.ctl->bin;
     if (net.regions_on) {
-        const uint32_t gid = blockIdx.x;
-        const uint32_t r = net.l1_region[gid];
-        const uint32_t b0 = net.reg_blk_ptr[r] + (gid - net.l1_ptr[r]) * 256u;
-        const uint32_t b1 = min(b0 + 256u, net.reg_blk_ptr[r + 1]);
-        const uint32_t b = b0 + threadIdx.x;
-        s[threadIdx.x] = b < b1 ? net.blk_sig[net.reg_blk[b]] : 0.0;
-        sc[threadIdx.x] = b < b1 ? net.blk_cnt[net.reg_blk[b]] : 0u;
-        __syncthreads();
-        for (uint32_t st = 128; st > 0; st >>= 1) {
-            if (threadIdx.x < st) {
-                s[threadIdx.x] += s[threadIdx.x + st];
-                sc[threadIdx.x] += sc[threadIdx.x + st];
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            net.l1_sig[gid] = s[0];
-            net.l1_cnt[gid] = sc[0];
-            __threadfence();
-            last = atomicAdd(&net.ctl->done, 1u) == gridDim.x - 1;
-        }
-        __syncthreads();
-        if (!last) return;
-        __threadfence();
         for (uint32_t rr = threadIdx.x; rr < net.n_regions; rr += blockDim.x) {
+            // in group order; eight loads in flight at a time
             double a = 0.0;
             uint32_t c = 0;
-            for (uint32_t g = net.l1_ptr[rr]; g < net.l1_ptr[rr + 1]; g++) {
-                a += __hip_atomic_load(&net.l1_sig[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                c += __hip_atomic_load(&net.l1_cnt[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t g0 = net.l1_ptr[rr], g1 = net.l1_ptr[rr + 1];
+            uint32_t g = g0;
+            for (; g + 8u <= g1; g += 8u) {
+                double v[8];
+                uint32_t w[8];
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    v[q] = net.l1_sig[g + q];
+                    w[q] = net.l1_cnt[g + q];
+                }
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    a += v[q];
+                    c += w[q];
+                }
+            }
+            for (; g < g1; g++) {
+                a += net.l1_sig[g];
+                c += net.l1_cnt[g];
             }
             const size_t o = (size_t)(k & net.MBmask) * net.n_regions + rr;
             net.sig[o] = net.reg_size[rr] ? a / (double)net.reg_size[rr] : 0.0;
@@ -1101,7 +1121,6 @@ __global__ void __launch_bounds__(256) k_readout_close(DevNet net) {
         net.bin_start[(k + 1) & m] = net.bin_start[k & m] + c;
         net.bin_cnt[(k + 1) & m] = 0;
         net.ctl->spikes += c;
-        net.ctl->done = 0;
         net.ctl->pnext = 0;
         net.ctl->bnext = 0;
         net.ctl->bin = k + 1;
@@ -1171,7 +1190,12 @@ hipError_t launch_compact(const DevNet& n, hipStream_t st) {
 }
 
 hipError_t launch_readout_close(const DevNet& n, hipStream_t st) {
-    hipLaunchKernelGGL(k_readout_close, dim3(n.regions_on ? n.n_l1 : 1u), dim3(256), 0, st, n);
+    if (n.regions_on) {
+        hipLaunchKernelGGL(k_region_partials, dim3(n.n_l1), dim3(256), 0, st, n);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_readout_close, dim3(1), dim3(256), 0, st, n);
     return hipGetLastError();
 }
 
