@@ -418,11 +418,11 @@ __device__ void wc_write(const DevNet& net, Round& R, Wc& W, uint32_t ne, uint32
 // with LDS counters, the round is placed in LDS sorted by bucket and written out.
 // wc != 0: the buckets are the tiles, written as whole chunks through the carry buffers.
 // wc == 0: the buckets are the super-tile streams (runs), re-bucketed by k_bucket.
-template <int KW>
+template <int KW, bool WC>
 __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d_lo, uint32_t d_hi, uint32_t ahead) {
     extern __shared__ __align__(16) unsigned char dyn[];
     const uint32_t D = net.D, RE = net.round_events;
-    const bool wc = net.wc != 0;
+    constexpr bool wc = WC; // the form is fixed per network; one instantiation each
     const uint32_t nb = wc ? net.T : net.NS;
     const PartLayout L(nb, RE, wc, D);
     unsigned long long* s_dpre = reinterpret_cast<unsigned long long*>(dyn + L.dpre);
@@ -432,7 +432,7 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
     Round R;
     R.at(dyn, L.r);
     Wc W{};
-    if (wc) W.at(dyn, L.w);
+    if constexpr (wc) W.at(dyn, L.w);
 
     uint32_t* s_dcnt = reinterpret_cast<uint32_t*>(dyn + L.dcnt);
     uint16_t* s_map = reinterpret_cast<uint16_t*>(dyn + L.smap);
@@ -550,12 +550,12 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
             // reservations (one wait for both)
             unsigned long long claim = 0;
             if (tid == 0 && r0 == 0) claim = atomicAdd(&net.ctl->pnext, 1ull);
-            if (wc) wc_reserve(net, R, W, nb, false);
+            if constexpr (wc) wc_reserve(net, R, W, nb, false);
             else reserve_runs(net, R, nb, 0, net.st_base, net.st_fill);
             place_batch(R, B, ne, nbt);
             if (tid == 0 && r0 == 0) s_pc = G + claim; // read by every thread at the end of the chunk
             __syncthreads();
-            if (wc) wc_write<KW>(net, R, W, ne, nb, bshift, false);
+            if constexpr (wc) wc_write<KW>(net, R, W, ne, nb, bshift, false);
             else write_runs<KW>(net, R, ne, nb, 0, bshift, net.sev);
         }
         if (ec == 0) { // no round: claim here
@@ -565,7 +565,7 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
         my_events += ec;
         c = s_pc;
     }
-    if (wc) { // the carried events of every tile, as padded chunks
+    if constexpr (wc) { // the carried events of every tile, as padded chunks
         for (uint32_t t = tid; t < nb; t += kScatterThreads) R.hist[t] = 0;
         __syncthreads();
         wc_reserve(net, R, W, nb, true);
@@ -1133,8 +1133,8 @@ size_t gather_lds_bytes(const DevNet& n) { return ((size_t)1 << n.tile_bits) * n
 
 
 hipError_t prepare_kernels() {
-    const void* big[] = {(const void*)k_part<1>, (const void*)k_part<2>, (const void*)k_bucket<1>,
-                         (const void*)k_bucket<2>};
+    const void* big[] = {(const void*)k_part<1, false>, (const void*)k_part<2, false>, (const void*)k_part<1, true>,
+                         (const void*)k_part<2, true>, (const void*)k_bucket<1>, (const void*)k_bucket<2>};
     hipError_t e = hipSuccess;
     for (const void* f : big) { // leave room for the kernels' few static LDS bytes
         e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kMaxLdsBytes - kStaticLds));
@@ -1150,10 +1150,14 @@ hipError_t prepare_kernels() {
 hipError_t launch_scatter(const DevNet& n, int grid, hipStream_t st, uint32_t d_lo, uint32_t d_hi, uint32_t ahead) {
     const size_t la = part_lds_bytes(n.wc ? n.T : n.NS, n.round_events, n.wc != 0, n.D);
     const size_t lb = bucket_lds_bytes(1u << n.ts_bits, n.bucket_events);
-    if (n.KW == 2)
-        hipLaunchKernelGGL(k_part<2>, dim3(grid), dim3(kScatterThreads), la, st, n, d_lo, d_hi, ahead);
+    if (n.KW == 2 && n.wc)
+        hipLaunchKernelGGL((k_part<2, true>), dim3(grid), dim3(kScatterThreads), la, st, n, d_lo, d_hi, ahead);
+    else if (n.KW == 2)
+        hipLaunchKernelGGL((k_part<2, false>), dim3(grid), dim3(kScatterThreads), la, st, n, d_lo, d_hi, ahead);
+    else if (n.wc)
+        hipLaunchKernelGGL((k_part<1, true>), dim3(grid), dim3(kScatterThreads), la, st, n, d_lo, d_hi, ahead);
     else
-        hipLaunchKernelGGL(k_part<1>, dim3(grid), dim3(kScatterThreads), la, st, n, d_lo, d_hi, ahead);
+        hipLaunchKernelGGL((k_part<1, false>), dim3(grid), dim3(kScatterThreads), la, st, n, d_lo, d_hi, ahead);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || n.wc) return e;
     if (n.KW == 2)

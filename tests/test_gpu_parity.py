@@ -192,6 +192,17 @@ def test_two_pass_fanin_bit_exact(Sim):
     orc.step(400)
     _compare(sim, orc, spec)
     sim.close()
+    # one weight per edge (8-byte records, copied into LDS with 12-byte reads) over 3 tiles
+    spec = configs.tiny(seed=8, n_exc=16000, n_inh=4000, indegree=100)
+    _say("tiny-recipe 20000 / k100 seed 8 (one weight per edge), two-pass fan-in, 300 steps")
+    sim = Sim(spec, two_pass=True)
+    assert sim.info.fanin_passes == 2
+    sim.step(300)
+    orc = Oracle(spec, 32)
+    orc.step(300)
+    assert orc.spikes()[0].size > 1000
+    _compare(sim, orc, spec)
+    sim.close()
     spec = configs.multi_region(n_regions=20, per_region=1000, seed=6)
     _say("multi-region 20 x 1000 seed 6, two-pass fan-in, 300 steps")
     sim = Sim(spec, two_pass=True)
