@@ -4,7 +4,7 @@ One benchmark step is one 1 ms spike bin of the whole hot path: the radix-partit
 fan-in of the bin's arrivals (k_part, k_bucket when two passes are needed, k_gather),
 ten fused 0.1 ms Euler substeps of every neuron with Poisson background (k_neuron),
 the spike-list compaction (k_compact), and the region readout and bin close
-(k_readout_close).
+(k_region_partials, k_readout_close).
 
 Workload (default): one GPU's share of the whole-brain model, 6.1 M LIF neurons,
 in-degree 556 (3.39e9 synapses, two weights each), 4 receptors, delays uniform in
@@ -302,7 +302,8 @@ def _rocpd(db):
 
 
 def _short(name):
-    for k in ("k_part", "k_bucket", "k_gather", "k_neuron", "k_compact", "k_readout_close", "copyBuffer"):
+    for k in ("k_part", "k_bucket", "k_gather", "k_neuron", "k_compact", "k_region_partials", "k_readout_close",
+              "copyBuffer"):
         if k in name:
             return k
     return name
