@@ -262,6 +262,27 @@ def run_ensemble(args):
             "speedup": wall_seq / wall_ens}
 
 
+def copy_bandwidth() -> float:
+    """Achievable HBM bandwidth: a plain 2 GiB device-to-device copy (read + write bytes
+    per second), timed with HIP events; the best of five."""
+    import torch
+    n = 1 << 29
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = 0.0
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = max(best, 8.0 * n / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del a, b
+    torch.cuda.empty_cache()
+    return best
+
+
 def calibrate_copy(args):
     """A plain device copy of known size, so that profiler byte counters can be scaled."""
     import torch
@@ -456,11 +477,15 @@ def main():
     if g["timed_bins"]:
         achieved = BYTES_PER_EVENT * g["phase_events"] / (fan_ms * 1e-3) / 1e9
         traffic = measured_traffic(g["phase_events"] / nb)
+        copy_gbs = copy_bandwidth()
         roof = {"bound": "hbm", "kernel": "fan-out phase (k_part + k_bucket + k_gather), per bin",
                 "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": None if traffic is None else round(traffic),
                 "traffic_unit": "bytes per bin (FETCH_SIZE x copy factor + WRITE_SIZE x copy factor)",
+                "traffic_bytes_per_event": None if traffic is None else round(traffic * nb / g["phase_events"], 2),
+                "measured_gbs": None if traffic is None else round(traffic / (fan_ms / nb * 1e-3) / 1e9, 1),
+                "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
                 "bytes_per_event": BYTES_PER_EVENT, "events_per_launch": g["phase_events"] / nb,
                 "phase_window_bins": nb,
                 "avg_launch_ms": {"k_part+k_bucket": g["ms_scatter"] / nb, "k_gather": g["ms_gather"] / nb,

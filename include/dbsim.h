@@ -295,8 +295,10 @@ int dbsim_export_csr(struct dbsim* h, uint64_t* row_ptr, uint32_t* seg, uint32_t
  */
 typedef struct dbsim_tuning {
     uint32_t scatter_wgs_per_cu; /* 1..8 partition workgroups per CU (they split the LDS) */
-    uint32_t round_events;       /* events staged in LDS per round, multiple of 256, at most 4096;
-                                    0 = the most that fit */
+    uint32_t round_events;       /* events staged in LDS per round of the first partition pass,
+                                    multiple of 256, at most 4096; 0 = the most that fit (the second
+                                    pass takes the most that fit beside its staging copy, at most
+                                    this, rounded down to whole 512-event batches) */
     uint32_t chunks_per_wg;      /* target (spike, delay) chunks per partition workgroup in the pass of
                                     delays >= 2, 1..64 (the delay-1 pass uses one) */
     uint32_t ahead_passes;       /* two-pass form: the next bin's delay >= 2 fan-in runs as this many
