@@ -118,6 +118,29 @@ def test_launch_modes_agree(Sim):
         s.close()
 
 
+def test_mixed_launch_sequence_bit_exact(Sim):
+    """One handle driven through replayed graphs, direct and timed launches, partial bins
+    and a schedule change (the partition kernels' work-queue counters and stream fills are
+    reset by whichever kernel follows them), in both fan-in forms, against the oracle."""
+    spec = configs.share(n=20000, indegree=300, seed=16)
+    S = spec.steps_per_bin
+    for two_pass in (False, True):
+        _say(f"share 20000 / k300 seed 16: mixed launch sequence, two_pass={two_pass}")
+        sim = Sim(spec, two_pass=two_pass)
+        orc = Oracle(spec, 32)
+        plan = [("graph", 20 * S), ("step", 3), ("step", S - 3), ("timed", 7 * S + 4), ("graph", 9 * S - 4),
+                ("tune", 0), ("graph", 12 * S), ("timed", 5), ("step", 2 * S - 5)]
+        for what, n in plan:
+            if what == "tune":
+                sim.set_tuning(scatter_wgs_per_cu=3, round_events=0, chunks_per_wg=2, ahead_passes=0)
+                continue
+            sim.set_timing(what == "timed")
+            sim.step(n)
+            orc.step(n)
+        _compare(sim, orc, spec)
+        sim.close()
+
+
 def test_exported_table_is_the_generated_network(Sim):
     from netgen.desc import generate
     spec = configs.share(n=3000, indegree=50, seed=5)
