@@ -134,6 +134,38 @@ def run_gpu(args):
     return out
 
 
+def run_regimes(args, regimes):
+    """Real-time factor of the same share workload in the other firing regimes (the
+    background rate set for a 7 or 30 Hz population rate), graph launches, after a warm-up."""
+    import torch
+    from netgen import configs
+    from paper_2211_15963_amd import Simulator
+
+    out = {}
+    for r in regimes:
+        spec = configs.share(n=args.n, indegree=args.indegree, regime_hz=r, seed=args.seed)
+        sim = Simulator(spec, record_regions=True, device=0)
+        sim.set_tuning(scatter_wgs_per_cu=2, round_events=0, chunks_per_wg=4)
+        S = sim.S
+        sim.step(100 * S)
+        sim.sync()
+        s0 = sim.stats()
+        bins = 300
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(bins * S)
+        sim.sync()
+        wall = time.perf_counter() - t0
+        s1 = sim.stats()
+        sim.close()
+        bio = bins * spec.bin_ms * 1e-3
+        out[str(r)] = {"rtf": wall / bio, "events_per_s": (s1["edge_events"] - s0["edge_events"]) / wall,
+                       "mean_rate_hz": round((s1["spikes"] - s0["spikes"]) / (spec.num_neurons * bio), 3),
+                       "bins": bins}
+        log(f"regime {r} Hz: real-time factor {wall / bio:.3f}, {out[str(r)]['events_per_s']:.3e} events/s")
+    return out
+
+
 def run_served(args):
     """Served stream: seeded Poisson arrivals of requests of log-uniform size, admitted by
     footprint, built on host threads and advanced together on the device. First at the
@@ -432,6 +464,7 @@ def main():
     ap.add_argument("--n", type=int, default=6_100_000)
     ap.add_argument("--indegree", type=int, default=556)
     ap.add_argument("--regime", type=int, default=15, choices=[7, 15, 30])
+    ap.add_argument("--regimes", type=int, default=1, help="also time the other firing regimes (1) or not (0)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--mode", default="graph", choices=["graph", "timed", "direct"],
                     help="graph: replayed HIP graphs with the next bin's fan-in overlapped (headline), then a "
@@ -485,11 +518,17 @@ def main():
                 "traffic_unit": "bytes per bin (FETCH_SIZE x copy factor + WRITE_SIZE x copy factor)",
                 "traffic_bytes_per_event": None if traffic is None else round(traffic * nb / g["phase_events"], 2),
                 "measured_gbs": None if traffic is None else round(traffic / (fan_ms / nb * 1e-3) / 1e9, 1),
+                "measured_frac": None if traffic is None else round(traffic / (fan_ms / nb * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                 "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
                 "bytes_per_event": BYTES_PER_EVENT, "events_per_launch": g["phase_events"] / nb,
                 "phase_window_bins": nb,
                 "avg_launch_ms": {"k_part+k_bucket": g["ms_scatter"] / nb, "k_gather": g["ms_gather"] / nb,
                                   "k_neuron": g["ms_neuron"] / nb, "readout_close": g["ms_readout"] / nb}}
+    regimes = None
+    if args.regimes:
+        regimes = {str(args.regime): {"rtf": g["wall"] / g["bio_s"], "events_per_s": value,
+                                      "mean_rate_hz": round(g["rate_hz"], 3), "bins": args.steps}}
+        regimes.update(run_regimes(args, [r for r in (7, 15, 30) if r != args.regime]))
     ens = run_ensemble(args) if args.ensemble else None
     served = run_served(args) if args.serve else None
     cpu = None
@@ -508,6 +547,7 @@ def main():
                    "device_gb": round(g["hbm_bytes"] / 1e9, 2), "fanin_schedule": g["tuning"],
                    "run_totals": g["run_totals"]},
         "rtf_15hz": g["wall"] / g["bio_s"] if args.regime == 15 else None,
+        "regimes": regimes,
         "ensemble": ens,
         "served": served,
         "roofline": roof, "cpu_baseline": cpu,
