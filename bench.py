@@ -335,8 +335,21 @@ def _rocpd(db):
     q = ("select k.kernel_name, d.start, d.end from rocpd_kernel_dispatch d "
          "join rocpd_info_kernel_symbol k on d.kernel_id = k.id")
     dur = collections.defaultdict(list)
-    for name, t0, t1 in c.execute(q):
+    rows = sorted(c.execute(q), key=lambda r: r[1])
+    for name, t0, t1 in rows:
         dur[name].append((t1 - t0) / 1e3)
+    # the one-stream timed window at the end of the run: every dispatch after the last two
+    # that overlapped by more than 2 us (back-to-back dispatches touch within the clocks' jitter)
+    lib_rows = [r for r in rows if "dbs" in r[0]]
+    last = 0
+    end_so_far = 0
+    for x, (name, t0, t1) in enumerate(lib_rows):
+        if x and t0 + 2000 < end_so_far:
+            last = x + 1
+        end_so_far = max(end_so_far, t1)
+    alone = collections.defaultdict(list)
+    for name, t0, t1 in lib_rows[last:]:
+        alone[name].append((t1 - t0) / 1e3)
     pmc = collections.defaultdict(lambda: collections.defaultdict(float))
     try:
         q = ("select k.kernel_name, d.event_id, p.name, e.value from rocpd_pmc_event e "
@@ -348,7 +361,9 @@ def _rocpd(db):
         pass
     out = {}
     for name, v in dur.items():
-        out[name] = {"calls": len(v), "avg_us": sum(v) / len(v)}
+        a = alone.get(name, [])
+        out[name] = {"calls": len(v), "avg_us": sum(v) / len(v), "alone_calls": len(a),
+                     "alone_avg_us": sum(a) / len(a) if a else None}
     for (name, pn), per_disp in pmc.items():
         out.setdefault(name, {})[pn] = sum(per_disp.values()) / len(per_disp)
     return out
@@ -410,6 +425,21 @@ def summarize_profiles(args):
     for name, v in sorted(trace.items(), key=lambda kv: -kv[1]["calls"] * kv[1]["avg_us"]):
         lines.append(f"  {name[:46]:46s} {v['calls']:6d} {v['avg_us']:10.2f}  "
                      f"({v['calls'] * v['avg_us'] / tot['bins']:8.2f} us per bin)")
+    # the one-stream timed window: what bench.py's phase timers measure (roofline.avg_launch_ms)
+    alone_bins = max((v["alone_calls"] for k, v in trace.items() if "k_neuron" in k), default=0)
+    if alone_bins:
+        lines += ["", f"Same kernels in the one-stream timed window at the end of the run (every dispatch "
+                      f"after the last overlap; {alone_bins} bins):"]
+        fan_us = 0.0
+        for name, v in sorted(trace.items(), key=lambda kv: -(kv[1]["alone_calls"] * (kv[1]["alone_avg_us"] or 0))):
+            if not v["alone_calls"] or "dbs" not in name:
+                continue
+            per_bin_us = v["alone_calls"] * v["alone_avg_us"] / alone_bins
+            if _short(name) in FANIN_KERNELS:
+                fan_us += per_bin_us
+            lines.append(f"  {name[:46]:46s} {v['alone_calls']:6d} {v['alone_avg_us']:10.2f}  "
+                         f"({per_bin_us:8.2f} us per bin)")
+        lines.append(f"  fan-out phase (k_part + k_bucket + k_gather): {fan_us:.1f} us per bin")
     lines += ["", f"Counter calibration: a 2 GiB device copy reads FETCH_SIZE {cal_f:.4g} KiB and WRITE_SIZE "
                   f"{cal_w:.4g} KiB per launch -> scale factors FETCH x{f_fac:.3f}, WRITE x{w_fac:.3f}.", "",
               "HBM-side bytes per bin (calibrated) and per edge event:"]
