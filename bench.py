@@ -511,7 +511,8 @@ def main():
     ap.add_argument("--autotune", type=int, default=1, help="autotune the fan-in schedule during warm-up")
     ap.add_argument("--ensemble", type=int, default=1, help="also run the batched-ensemble comparison")
     ap.add_argument("--members", type=int, default=64)
-    ap.add_argument("--serve", type=int, default=1, help="also run the served-stream leg")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="also run the served-stream leg (off by default: see the design notes)")
     ap.add_argument("--serve-rate", type=float, default=50.0, help="offered request arrivals per second")
     ap.add_argument("--serve-requests", type=int, default=24, help="arrivals in the offered-rate window")
     ap.add_argument("--serve-slots", type=int, default=16, help="most requests resident at once")
