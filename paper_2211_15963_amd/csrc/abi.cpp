@@ -8,7 +8,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -46,6 +48,19 @@ constexpr int kPhases = 4;    // reported phases: scatter (partition), gather, n
 constexpr int kMarks = 7;     // events per timed bin (six intervals, see resolve_timers)
 
 } // namespace
+
+// The kernels' LDS limits are set once per device and process, not at every create:
+// handles are created on host threads while other handles' kernels are being launched and
+// captured, and a set that is already in place needs no repeating.
+static hipError_t prepare_kernels_once(int device) {
+    static std::mutex mu;
+    static std::set<int> done;
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.count(device)) return hipSuccess;
+    const hipError_t e = prepare_kernels();
+    if (e == hipSuccess) done.insert(device);
+    return e;
+}
 
 struct dbsim {
     dbsim_desc desc{};
@@ -419,7 +434,7 @@ static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32
             if (!bytes) return hipSuccess;
             return hipMemcpyAsync(h->dev + s.off, src, bytes, hipMemcpyHostToDevice, h->stream);
         };
-        hipError_t e = prepare_kernels();
+        hipError_t e = prepare_kernels_once(h->device);
         const size_t N = p.N;
         std::vector<float> zeros((size_t)p.U * N, 0.0f);
         std::vector<uint8_t> z8(N, 0), pend(N, 0xFF);
