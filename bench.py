@@ -84,6 +84,9 @@ def run_gpu(args):
     if args.autotune:
         sim.step((args.warmup // 2) * S)
         from paper_2211_15963_amd.tune import autotune
+        # fan-in kernels on one stream (phase events): stable over short trials; whole
+        # replayed bins (mode="wall") measure the overlapped form but need long trials to
+        # rank these close schedules
         tuned = autotune(sim, bins_per_trial=max(2, args.warmup // 40))
         log(f"autotuned fan-in schedule: {tuned['chosen']}")
         sim.step((args.warmup - args.warmup // 2) * S)

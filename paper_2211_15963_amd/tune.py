@@ -1,13 +1,16 @@
 """Autotuner of the fan-in schedule.
 
 Tries scatter schedules (workgroups per CU, LDS round size, chunks per workgroup) on a
-live simulator for a few bins each, timing the fan-in kernels with the library's
-phase events, and keeps the fastest per delivered event. Every schedule gives
-bit-identical results (the arrival sums are exact integers), so tuning changes speed
-only; the bins it runs are ordinary simulation steps.
+live simulator for a few bins each and keeps the fastest per delivered event, timed
+either as the fan-in kernels alone (the library's phase events, one stream) or as the
+wall time of whole bins replayed from graphs (the partition then shares the CUs with the
+neuron step, and its registers and workgroup count matter beyond its own speed). Every
+schedule gives bit-identical results (the arrival sums are exact integers), so tuning
+changes speed only; the bins it runs are ordinary simulation steps.
 """
 from __future__ import annotations
 
+import time
 from typing import Dict, List, Optional, Tuple
 
 from .dbsim import DbsimError, Simulator
@@ -22,10 +25,13 @@ def candidates(sim: Simulator) -> List[Tuple[int, int, int]]:
     return out
 
 
-def autotune(sim: Simulator, bins_per_trial: int = 10, verbose: bool = False) -> Dict:
-    """Returns the chosen schedule and the per-candidate timings (ms per million events)."""
+def autotune(sim: Simulator, bins_per_trial: int = 10, verbose: bool = False, mode: str = "phases") -> Dict:
+    """Returns the chosen schedule and the per-candidate timings (ms per million events).
+    mode: "phases" (fan-in kernels, phase events) or "wall" (whole replayed bins)."""
+    if mode not in ("phases", "wall"):
+        raise ValueError("mode must be 'phases' or 'wall'")
     was = sim.tuning()
-    sim.set_timing(True)
+    sim.set_timing(mode == "phases")
     results = []
     best: Optional[Tuple[float, Dict]] = None
     for wgs, re_div, cpw in candidates(sim):
@@ -37,11 +43,21 @@ def autotune(sim: Simulator, bins_per_trial: int = 10, verbose: bool = False) ->
                 sim.set_tuning(scatter_wgs_per_cu=wgs, round_events=re, chunks_per_wg=cpw)
         except DbsimError:
             continue
+        if mode == "wall":
+            sim.step(2 * sim.S)  # the new schedule's graphs are captured here
+            sim.sync()
         s0 = sim.stats()
+        t0 = time.perf_counter()
         sim.step(bins_per_trial * sim.S)
+        if mode == "wall":
+            sim.sync()
+        wall_ms = (time.perf_counter() - t0) * 1e3
         s1 = sim.stats()
         ev = s1["edge_events"] - s0["edge_events"]
-        ms = (s1["ms_scatter"] - s0["ms_scatter"]) + (s1["ms_gather"] - s0["ms_gather"])
+        if mode == "wall":
+            ms = wall_ms
+        else:
+            ms = (s1["ms_scatter"] - s0["ms_scatter"]) + (s1["ms_gather"] - s0["ms_gather"])
         score = ms / max(ev, 1) * 1e6
         t = sim.tuning()
         results.append({**t, "ms_per_mevent": score})
