@@ -15,7 +15,8 @@ a seeded network description plus a biological duration. The server:
   of slice_bins bins, keeping up to two slices queued per stream, so the kernels of
   different requests overlap on the device;
 * retires a request when its last slice has completed: reads its results, frees its
-  memory and admits the next waiting requests.
+  memory and admits the next waiting requests. A request whose build, step or read
+  fails retires with the error and frees its memory; the others go on.
 
 Each request's result depends only on its own description (every handle is
 independent and bit-deterministic), so a request gives the same bits alone and in
@@ -31,7 +32,7 @@ from typing import Dict, List, Optional
 
 import numpy as np
 
-from .dbsim import Simulator, footprint
+from .dbsim import DbsimError, Simulator, footprint
 
 
 @dataclass
@@ -168,21 +169,29 @@ class Server:
                 for a in active:
                     while a.inflight and a.inflight[0].query():
                         a.inflight.pop(0)
-                    while len(a.inflight) < 2 and a.enqueued < a.req.n_steps:
+                    while a.req.error is None and len(a.inflight) < 2 and a.enqueued < a.req.n_steps:
                         n = min(self.slice_bins * a.sim.S, a.req.n_steps - a.enqueued)
-                        with torch.cuda.stream(a.stream):
-                            a.sim.step(n)
-                            ev = torch.cuda.Event()
-                            ev.record(a.stream)
+                        try:
+                            with torch.cuda.stream(a.stream):
+                                a.sim.step(n)
+                                ev = torch.cuda.Event()
+                                ev.record(a.stream)
+                        except DbsimError as ex:
+                            a.req.error = str(ex)
+                            break
                         a.inflight.append(ev)
                         a.enqueued += n
                         progressed = True
-                # retire finished requests
+                # retire finished and failed requests (destroy waits for the handle's stream)
                 still = []
                 for a in active:
-                    if a.enqueued >= a.req.n_steps and not a.inflight:
-                        a.sim.sync()
-                        a.req.result = summarize(a.sim, self.state_digest)
+                    if a.req.error is not None or (a.enqueued >= a.req.n_steps and not a.inflight):
+                        if a.req.error is None:
+                            try:
+                                a.sim.sync()
+                                a.req.result = summarize(a.sim, self.state_digest)
+                            except DbsimError as ex:
+                                a.req.error = str(ex)
                         a.sim.close()
                         a.req.t_done = time.perf_counter() - t0
                         in_use -= a.req.footprint
@@ -195,6 +204,12 @@ class Server:
                     time.sleep(poll_s)
         finally:
             pool.shutdown(wait=True)
+            # on an exception, free what is still resident or built
+            for a in active:
+                a.sim.close()
+            for fut in building:
+                if fut.done() and fut.exception() is None:
+                    fut.result()[0].close()
         wall = time.perf_counter() - t0
         ok = [r for r in done if r.error is None]
         lat = np.array([r.latency_s for r in ok]) if ok else np.zeros(1)

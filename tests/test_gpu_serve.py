@@ -80,3 +80,35 @@ def test_admission_by_footprint():
     too_big = _requests(1, seed=13, n_hi=2e4, d_hi_s=0.06, gap_s=0.0)
     out = Server(hbm_budget=1 << 20, max_active=2).run(too_big)
     assert out["completed"] == 0 and out["failed"] == 1 and "exceeds" in out["requests"][0].error
+
+
+def test_a_failing_request_retires_alone(monkeypatch):
+    """A request whose stepping fails (the failure is forced from the host, before any
+    device work of that slice is queued) retires with its error and frees its memory; the
+    other requests complete with the same bits as alone."""
+    import torch
+    from paper_2211_15963_amd import dbsim as D
+    from paper_2211_15963_amd.serve import Server
+    reqs = _requests(4, seed=14, n_hi=5e4, d_hi_s=0.1, gap_s=0.0)
+    bad = reqs[1].spec
+    real_step = D.Simulator.step
+
+    def step(self, n):
+        if self.spec is bad and self.steps_done > 0:
+            raise D.DbsimError(D.EDEVICE, "stepping failure forced from the host")
+        real_step(self, n)
+
+    monkeypatch.setattr(D.Simulator, "step", step)
+    _say(f"serve 4 requests, request 1 fails on its second slice; sizes {[r.spec.num_neurons for r in reqs]}")
+    torch.cuda.synchronize()
+    m0 = torch.cuda.memory_allocated()
+    out = Server(max_active=4, slice_bins=5, build_workers=2).run(reqs)
+    assert out["completed"] == 3 and out["failed"] == 1
+    failed = [r for r in out["requests"] if r.error is not None]
+    assert failed[0].rid == 1 and "forced" in failed[0].error and failed[0].result is None
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == m0
+    for r in sorted(out["requests"], key=lambda r: r.rid):
+        if r.error is None:
+            _say(f"  request {r.rid}: alone run")
+            _same(r.result, _alone(r))
