@@ -232,7 +232,9 @@ def cpu_baseline(args, budget_s: float):
             "sample": f"share recipe at N={n} (1/64 of the GPU share), in-degree {args.indegree}, delays 1..10 ms, "
                       f"{bins} bins ({bins} ms bio) after 20 ms warm-up, FP32 oracle on one host core; "
                       f"real-time factor {wall / (bins * 1e-3):.1f}",
-            "rtf": wall / (bins * 1e-3)}
+            "rtf": wall / (bins * 1e-3),
+            # the oracle's work per bin grows linearly with N at a fixed rate and in-degree
+            "rtf_full_share_extrapolated": wall / (bins * 1e-3) * args.n / n}
 
 
 def run_ensemble(args):
@@ -554,6 +556,7 @@ def main():
                 "measured_gbs": None if traffic is None else round(traffic / (fan_ms / nb * 1e-3) / 1e9, 1),
                 "measured_frac": None if traffic is None else round(traffic / (fan_ms / nb * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                 "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
+                "measured_frac_of_copy": None if traffic is None else round(traffic / (fan_ms / nb * 1e-3) / 1e9 / copy_gbs, 4),
                 "bytes_per_event": BYTES_PER_EVENT, "events_per_launch": g["phase_events"] / nb,
                 "phase_window_bins": nb,
                 "avg_launch_ms": {"k_part+k_bucket": g["ms_scatter"] / nb, "k_gather": g["ms_gather"] / nb,
