@@ -512,7 +512,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true", help="run only a 2 GiB device copy (counter scaling)")
     ap.add_argument("--summarize-profiles", default=None, help="directory of rocprofv3 runs to summarise (CPU only)")
     ap.add_argument("--profile-command", default="python3 bench.py --steps 100 --warmup 200 --autotune 0 "
-                    "--no-cpu-baseline --ensemble 0", help="the profiled command, quoted in the summary")
+                    "--no-cpu-baseline --ensemble 0 --serve 0 --regimes 0",
+                    help="the profiled command, quoted in the summary")
     ap.add_argument("--autotune", type=int, default=1, help="autotune the fan-in schedule during warm-up")
     ap.add_argument("--ensemble", type=int, default=1, help="also run the batched-ensemble comparison")
     ap.add_argument("--members", type=int, default=64)

@@ -241,11 +241,12 @@ struct Batch {
 // record's first word along, which is never used): one instruction per wavefront moves 64
 // records into 64 consecutive 16-byte LDS slots (lane l lands at byte 16 l) without passing
 // through registers. The copy is counted like a vector load of the issuing wavefront; it has
-// landed after that wavefront's next wait for all its vector memory operations (dma_wait).
-// The compiler does not see the LDS write, so every read of the slots follows dma_wait and a
-// barrier.
-__device__ __forceinline__ void dma_records64(const uint32_t* g, uint32_t lds_byte_addr) {
-    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx3 %1, off" ::"s"(lds_byte_addr), "v"(g) : "m0");
+// landed after that wavefront's next wait for all its vector memory operations (dma_wait),
+// so every read of the slots follows dma_wait and a barrier. The compiler builtin sets the
+// wave-uniform LDS base itself (the slots of one instruction start at a wave-uniform address).
+__device__ __forceinline__ void dma_records64(const uint32_t* g, uint4* lds) {
+    __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)g,
+                                     (__attribute__((address_space(3))) void*)lds, 12, 0, 0);
 }
 
 __device__ __forceinline__ void dma_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
@@ -259,8 +260,7 @@ __device__ __forceinline__ void dma_round(const uint32_t* src, unsigned long lon
     const uint32_t nch = (ne + 63u) >> 6;
     for (uint32_t c = w - w0; c < nch; c += nw - w0) {
         const uint32_t e = min(c * 64u + l, ne - 1u);
-        const uint32_t m0 = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(stage + (size_t)c * 64u));
-        dma_records64(src + (first + e) * (1u + KW), m0);
+        dma_records64(src + (first + e) * (1u + KW), stage + (size_t)c * 64u);
     }
 }
 
