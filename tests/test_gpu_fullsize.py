@@ -58,9 +58,19 @@ def _run_and_check(spec, K, n_sample=1500, seed=0):
         sel = bins + d <= K
         want += int(seglen[ids[sel], d - 1].sum())
     assert stats["edge_events"] == want
-    # sampled point evaluations
+    _check_points(spec, K, S, st, ids, (V0, J0, r0), (V1, J1, r1), n_sample, seed)
+    _say(f"{spec.name}: {n_sample} sampled neurons bit-identical after the bin-start step")
+
+
+def _check_points(spec, K, S, st, ids, before, after, n_sample, seed):
+    """oracle point evaluations: for sampled neurons, the arrivals due at bin K (from the
+    recorded spikes and the generator's in-edges) and one Euler step from the recorded
+    state reproduce the recorded state after that step bit for bit"""
+    V0, J0, r0 = before
+    V1, J1, r1 = after
+    N = spec.num_neurons
     rng = np.random.default_rng(seed)
-    sample = np.sort(rng.choice(N, size=n_sample, replace=False)).astype(np.uint32)
+    sample = np.sort(rng.choice(N, size=min(n_sample, N), replace=False)).astype(np.uint32)
     o = Oracle(spec, 32, params_only=True)
     A, ev = o.point_arrivals(K, st, ids, sample)
     assert ev > 0
@@ -70,7 +80,6 @@ def _run_and_check(spec, K, n_sample=1500, seed=0):
         assert np.float32(v) == V1[i], (i, v, V1[i])
         assert np.array_equal(j, J1[:, i]), (i, j, J1[:, i])
         assert r == r1[i]
-    _say(f"{spec.name}: {n_sample} sampled neurons bit-identical after the bin-start step")
 
 
 def test_one_gpu_share_full_size_sampled():
@@ -79,3 +88,49 @@ def test_one_gpu_share_full_size_sampled():
 
 def test_multi_region_full_size_sampled():
     _run_and_check(configs.multi_region(), K=40)
+
+
+def test_ensemble_full_size_sampled():
+    """The 64-member ensemble as the benchmark runs it (10.3 M neurons, 3.96e9 synapses,
+    one handle, replayed graphs, one chunk per partition workgroup): per member, the
+    properties that hold at any size and sampled oracle point evaluations on eight
+    members (the smallest, the largest and six others)."""
+    from paper_2211_15963_amd import Simulator
+    members = [configs.ensemble_member(m, seed=0) for m in range(64)]
+    _say(f"ensemble: building 64 members, {sum(s.num_neurons for s in members)} neurons")
+    ens = Simulator(members, record_regions=True, spike_record_capacity=1 << 27)
+    ens.set_tuning(scatter_wgs_per_cu=2, round_events=0, chunks_per_wg=1)
+    S = ens.S
+    K = 30
+    _say(f"ensemble: built; running {K} bins")
+    ens.step(K * S)
+    st, ids = ens.spikes()
+    V0, J0, r0 = ens.state()
+    ens.step(1)
+    V1, J1, r1 = ens.state()
+    stats = ens.stats()
+    row_ptr, seg, _, _, _ = ens.export_csr(edges=False)
+    spans = [ens.member(m) for m in range(len(members))]
+    ens.close()
+    N = V0.size
+    assert len(st) > 0 and ids.max() < N
+    bins = st // S
+    key = bins.astype(np.int64) * N + ids.astype(np.int64)
+    assert len(np.unique(key)) == len(key), "a neuron spiked twice in one bin"
+    D = seg.shape[1] - 1
+    seglen = np.diff(seg.astype(np.int64), axis=1)
+    want = 0
+    for d in range(1, D + 1):
+        sel = bins + d <= K
+        want += int(seglen[ids[sel], d - 1].sum())
+    assert stats["edge_events"] == want
+    sizes = [s.num_neurons for s in members]
+    chosen = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 5, 17, 29, 41, 50, 63})
+    for m in chosen:
+        a, n, _, _ = spans[m]
+        sel = (ids >= a) & (ids < a + n)
+        local = (st[sel], (ids[sel] - a).astype(np.uint32))
+        cut = lambda x: x[..., a:a + n]
+        _check_points(members[m], K, S, local[0], local[1], (cut(V0), cut(J0), cut(r0)), (cut(V1), cut(J1), cut(r1)),
+                      250, m)
+        _say(f"ensemble member {m} ({n} neurons): 250 sampled neurons bit-identical after the bin-start step")
