@@ -289,6 +289,63 @@ int dbsim_export_csr(struct dbsim* h, uint64_t* row_ptr, uint32_t* seg, uint32_t
                      float* w1);
 
 /*
+ * Derived constants of one population, as the kernels use them (the discrete step
+ * of the Methods' CV equation and eq. 2, SI Section 3, with the readings stated in
+ * the header comment): every value is computed in double from the description and
+ * rounded once to float, so a CPU implementation of the same step can check them
+ * bit for bit (the paper validates its GPU code against a CPU run of a debug graph).
+ */
+#define DBSIM_MAX_POISSON 64u
+typedef struct dbsim_pop_constants {
+    uint32_t first_neuron;  /* global id of the population's first neuron */
+    uint32_t end_neuron;    /* one past its last neuron */
+    uint32_t member;        /* network of the handle (ensemble member) it belongs to */
+    uint32_t region;        /* global region index */
+    float k;                /* dt / C */
+    float g_L, V_L, V_th, V_reset, I_ext, w_bg; /* copied from the description */
+    float g[4], V_rev[4];   /* compact receptor order: AMPA, [NMDA], GABA_A, [GABA_B] */
+    float decay[4];         /* exp(-dt / tau_u); 1 for tau = +inf */
+    int32_t ref_steps;      /* round(T_ref / dt): steps held after a spike */
+    uint32_t poisson_len;   /* c_max: entries of poisson_T in use */
+    uint32_t poisson_T[DBSIM_MAX_POISSON]; /* T_c = floor(2^32 P(Poisson(lambda) <= c)), lambda =
+                                              bg_rate dt, pmf by p_0 = exp(-lambda), p_c = p_{c-1}
+                                              lambda / c summed in ascending c; the table ends at
+                                              the first c whose upper tail is below 2^-32; the
+                                              background count of a step is #{c : T_c <= x} for
+                                              the step's 32-bit Philox word x */
+} dbsim_pop_constants;
+
+/*
+ * Host only (no device is touched, nothing is generated): validates the description(s)
+ * as dbsim_create / dbsim_create_ensemble would and writes the derived constants of
+ * every population (members one after another) to out[0 .. cap). *n_out receives the
+ * population count; ETRUNC if cap is smaller; EINVAL for an invalid description.
+ * n_members = 1 with members = &common->net for a single network.
+ */
+int dbsim_derive_constants(const dbsim_desc* common, const dbnet_desc* members, uint32_t n_members,
+                           dbsim_pop_constants* out, uint32_t cap, uint32_t* n_out);
+
+/*
+ * Everything the handle built from its description, for a CPU check of the same
+ * network (the paper's GPU-vs-CPU comparison of a debug graph): each pointer may be
+ * NULL; arrays are caller-owned and sized as stated.
+ */
+typedef struct dbsim_network_view {
+    uint64_t* row_ptr;          /* [N + 1] edge offset of each presynaptic row */
+    uint32_t* seg;              /* [N * (D + 1)] delay segment offsets inside each row (as dbsim_export_csr) */
+    uint32_t* tgt;              /* [E] target of each edge (rows sorted by delay, then target) */
+    float* w0;                  /* [E] first weight */
+    float* w1;                  /* [E] second weight (zero with one weight per edge) */
+    float* V0;                  /* [N] initial membrane potentials (the values set at creation) */
+    dbsim_pop_constants* pops;  /* [pops_cap] read back from the device copy the kernels use */
+    uint32_t pops_cap;          /* entries available in pops */
+    uint32_t n_pops;            /* out: populations of the handle */
+} dbsim_network_view;
+
+/* Fills the view (ETRUNC, with n_pops set, if pops_cap is too small). Synchronises. */
+int dbsim_export_network(struct dbsim* h, dbsim_network_view* v);
+
+/*
  * Launch schedule of the fan-in partition kernels. Any valid schedule gives
  * bit-identical results (the arrival sums are exact integers); it only changes
  * speed, so an autotuner may try schedules on a live handle.

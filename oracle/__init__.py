@@ -71,6 +71,9 @@ def lib():
     L.orc_poisson_count.restype = c_uint32
     L.orc_quantize.argtypes = [c_float, c_uint32]
     L.orc_quantize.restype = c_int64
+    L.orc_pop_constants.argtypes = [c_void_p, c_uint32, POINTER(c_float), POINTER(c_float), POINTER(c_int32),
+                                    POINTER(c_int), POINTER(c_uint32), c_int]
+    L.orc_pop_constants.restype = c_int
     L.orc_i64_to_f32.argtypes = [c_int64]
     L.orc_i64_to_f32.restype = c_float
     _LIB = L
@@ -198,6 +201,18 @@ class Oracle:
                                 _p(r, c_int32), ctypes.byref(sp)) != 0:
             raise RuntimeError("point step failed")
         return float(v[0]), j, int(r[0]), bool(sp.value)
+
+    def pop_constants(self, p: int) -> dict:
+        """Derived constants of population p as the FP32 step uses them (float32 / int)."""
+        k = c_float(0)
+        dec = (c_float * 4)()
+        r = c_int32(0)
+        n = c_int(0)
+        T = (c_uint32 * 256)()
+        if lib().orc_pop_constants(self._h, int(p), ctypes.byref(k), dec, ctypes.byref(r), ctypes.byref(n), T, 256) != 0:
+            raise ValueError("bad population index")
+        return {"k": np.float32(k.value), "decay": np.array(dec[:self.U], np.float32), "ref_steps": int(r.value),
+                "poisson_T": np.array(T[:n.value], np.uint32)}
 
     def in_edges(self):
         E = self.num_edges

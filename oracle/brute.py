@@ -52,8 +52,12 @@ def poisson_thresholds(lam: float):
     return np.array(T, dtype=np.uint64)
 
 
-def simulate(spec: NetSpec, n_steps: int):
-    """Returns (raster list of (step, id), V float32 [N], J float32 [U, N], ref int32 [N], edge_events)."""
+def simulate(spec: NetSpec, n_steps: int, regions: bool = False):
+    """Returns (raster list of (step, id), V float32 [N], J float32 [U, N], ref int32 [N], edge_events);
+    with regions=True also (sig float64 [bins, regions], counts int64 [bins, regions]): at every bin
+    end, the mean over each region's neurons of the FP32 current sum_u (g_u J_u)(V_u - V) (each
+    neuron's current in float32, receptor order, one operation at a time; the region sum in double in
+    ascending neuron id) and the region's spike count in the bin."""
     net = generate(spec)
     N = spec.num_neurons
     S = spec.steps_per_bin
@@ -98,6 +102,9 @@ def simulate(spec: NetSpec, n_steps: int):
     spk_hist = np.zeros((n_steps // S + 2, N), bool)  # spikes per bin
     raster = []
     events = 0
+    reg = np.array([P[p].region for p in pop], np.int64)
+    R = spec.n_regions
+    sigs, cnts = [], []
     seed = int(spec.seed)
     ids = np.arange(N, dtype=np.uint64)
     for n in range(n_steps):
@@ -138,4 +145,21 @@ def simulate(spec: NetSpec, n_steps: int):
         for i in np.nonzero(fire)[0]:
             raster.append((n, int(i)))
         spk_hist[kb] |= fire
+        if regions and s == S - 1:
+            cur = np.zeros(N, f32)
+            for u in range(U):
+                cur = cur + (g[u] * J[u]) * (Vu[u] - V)
+            sig = np.zeros(R)
+            cnt = np.zeros(R, np.int64)
+            for rr in range(R):
+                idx = np.nonzero(reg == rr)[0]
+                acc = 0.0
+                for i in idx:  # ascending neuron id, double accumulator
+                    acc = acc + float(cur[i])
+                sig[rr] = acc / len(idx) if len(idx) else 0.0
+                cnt[rr] = int(spk_hist[kb][idx].sum())
+            sigs.append(sig)
+            cnts.append(cnt)
+    if regions:
+        return raster, V, J, ref, events, np.array(sigs).reshape(-1, R), np.array(cnts).reshape(-1, R)
     return raster, V, J, ref, events

@@ -710,3 +710,17 @@ int orc_point_step(orc* o, uint32_t i, uint64_t n, const float* A, float* V, flo
     if (spiked) *spiked = s;
     return 0;
 }
+
+int orc_pop_constants(const orc* o, uint32_t p, float* k, float* decay4, int32_t* ref_steps, int* table_len,
+                      uint32_t* T, int cap) {
+    if (!o || p >= o->d.n_pops) return -1;
+    const orc_pop* P = &o->P[p];
+    if (k) *k = P->k32;
+    if (decay4)
+        for (uint32_t u = 0; u < 4; u++) decay4[u] = u < o->U ? P->d32[u] : 0.0f;
+    if (ref_steps) *ref_steps = P->r;
+    if (table_len) *table_len = P->cmax;
+    if (T)
+        for (int c = 0; c < P->cmax && c < cap; c++) T[c] = P->T[c];
+    return 0;
+}

@@ -74,6 +74,13 @@ int orc_point_arrivals(orc* o, uint64_t bin, uint64_t nspk, const uint64_t* spk_
                        uint32_t ntargets, const uint32_t* targets, float* A, uint64_t* events);
 int orc_point_step(orc* o, uint32_t i, uint64_t n, const float* A, float* V, float* J, int32_t* ref, int* spiked);
 
+/* Derived constants of population p as the FP32 oracle uses them (each computed in
+   double from the description and rounded once to float): dt/C, the receptor decays
+   in compact receptor order, the refractory steps, and the Poisson inversion table
+   (its length, then up to cap thresholds). Returns 0, or -1 for a bad p. */
+int orc_pop_constants(const orc* o, uint32_t p, float* k, float* decay4, int32_t* ref_steps, int* table_len,
+                      uint32_t* T, int cap);
+
 /* Building blocks, exported so that the tests can pin them. */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 uint32_t orc_bg_word(uint64_t seed, uint32_t net_id, uint64_t n, uint32_t i);

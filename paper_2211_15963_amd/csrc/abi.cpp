@@ -498,6 +498,58 @@ static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32
     }
 }
 
+static void to_constants(const Members& mem, const Plan& p, const std::vector<PopParams>& pops,
+                         const std::vector<uint32_t>& ptab, dbsim_pop_constants* out) {
+    for (uint32_t gq = 0; gq < p.n_pops; gq++) {
+        const PopParams& P = pops[gq];
+        dbsim_pop_constants& c = out[gq];
+        std::memset(&c, 0, sizeof c);
+        c.first_neuron = gq ? pops[gq - 1].end : 0u;
+        c.end_neuron = P.end;
+        c.member = (uint32_t)(std::upper_bound(mem.pbase.begin(), mem.pbase.end(), gq) - mem.pbase.begin()) - 1;
+        c.region = P.region;
+        c.k = P.k;
+        c.g_L = P.gL;
+        c.V_L = P.VL;
+        c.V_th = P.Vth;
+        c.V_reset = P.Vr;
+        c.I_ext = P.Iext;
+        c.w_bg = P.wbg;
+        for (uint32_t u = 0; u < p.U; u++) {
+            c.g[u] = P.g[u];
+            c.V_rev[u] = P.Vu[u];
+            c.decay[u] = P.dec[u];
+        }
+        c.ref_steps = P.r;
+        c.poisson_len = (uint32_t)P.cmax;
+        for (int x = 0; x < P.cmax && x < (int)kMaxPoisson; x++) c.poisson_T[x] = ptab[(size_t)gq * kMaxPoisson + x];
+    }
+}
+
+int dbsim_derive_constants(const dbsim_desc* common, const dbnet_desc* members, uint32_t n_members,
+                           dbsim_pop_constants* out, uint32_t cap, uint32_t* n_out) {
+    if (!common || !members || n_members == 0 || !n_out) return fail(DBSIM_EINVAL, "null argument or no network");
+    try {
+        Members mem;
+        mem.assign(members, n_members);
+        Plan p;
+        std::string m = make_plan(*common, mem, p);
+        if (!m.empty()) return fail(DBSIM_EINVAL, m);
+        *n_out = p.n_pops;
+        if (cap < p.n_pops) return fail(DBSIM_ETRUNC, "buffer too small; *n_out holds the count needed");
+        if (!out) return fail(DBSIM_EINVAL, "out is NULL");
+        std::vector<PopParams> pops;
+        std::vector<uint32_t> ptab;
+        fill_populations(mem, p, pops, ptab, nullptr, nullptr);
+        to_constants(mem, p, pops, ptab, out);
+        return DBSIM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(DBSIM_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(DBSIM_EINVAL, "unexpected exception");
+    }
+}
+
 int dbsim_create(const dbsim_desc* desc, dbsim** out) {
     if (!desc) return fail(DBSIM_EINVAL, "null argument");
     return create_impl(desc, &desc->net, 1, out);
@@ -750,6 +802,35 @@ int dbsim_export_csr(dbsim* h, uint64_t* row_ptr, uint32_t* seg, uint32_t* tgt, 
                 else w1[e] = 0.0f;
             }
         }
+    }
+    return DBSIM_OK;
+}
+
+int dbsim_export_network(dbsim* h, dbsim_network_view* v) {
+    int rc = check_usable(h);
+    if (rc) return rc;
+    if (!v) return fail(DBSIM_EINVAL, "null argument");
+    const Plan& p = h->plan;
+    v->n_pops = p.n_pops;
+    if (v->pops && v->pops_cap < p.n_pops) return fail(DBSIM_ETRUNC, "pops_cap too small; n_pops holds the count needed");
+    rc = dbsim_export_csr(h, v->row_ptr, v->seg, v->tgt, v->w0, v->w1);
+    if (rc) return rc;
+    DeviceGuard dg(h->device);
+    try {
+        if (v->pops) { // what the kernels read: the device copies of the tables
+            std::vector<PopParams> pops(p.n_pops);
+            std::vector<uint32_t> ptab((size_t)p.n_pops * kMaxPoisson);
+            HIPCHK(h, hipMemcpy(pops.data(), h->net.pops, sizeof(PopParams) * pops.size(), hipMemcpyDeviceToHost),
+                   "hipMemcpy");
+            HIPCHK(h, hipMemcpy(ptab.data(), h->net.ptab, 4 * ptab.size(), hipMemcpyDeviceToHost), "hipMemcpy");
+            to_constants(h->mem, p, pops, ptab, v->pops);
+        }
+        if (v->V0) // the generator's initial potentials, as uploaded at creation
+            for (uint32_t m = 0; m < p.n_members; m++)
+                for (uint64_t i = h->mem.nbase[m]; i < h->mem.nbase[m + 1]; i++)
+                    v->V0[i] = dbnet_v0(&h->mem.m[m], (uint32_t)(i - h->mem.nbase[m]));
+    } catch (const std::bad_alloc&) {
+        return fail(DBSIM_ENOMEM, "host allocation failed");
     }
     return DBSIM_OK;
 }

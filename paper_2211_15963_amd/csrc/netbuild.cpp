@@ -271,27 +271,26 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     return "";
 }
 
-std::string build_tables(const Members& mem, const Plan& p, unsigned threads, HostTables& h) {
-    const unsigned nt = threads ? threads : std::max(1u, std::thread::hardware_concurrency());
-    const uint32_t N = p.N, D = p.D, KW = p.KW;
+void fill_populations(const Members& mem, const Plan& p, std::vector<PopParams>& pops, std::vector<uint32_t>& ptab,
+                      std::vector<uint64_t>* first, std::vector<uint32_t>* indeg) {
+    const uint32_t KW = p.KW;
     const uint32_t M = (uint32_t)mem.m.size();
     const double dt = (double)mem.m[0].dt_ms;
-
-    // populations: derived constants, computed in double and rounded once to float
-    h.pops.assign(p.n_pops, PopParams{});
-    h.ptab.assign((size_t)p.n_pops * kMaxPoisson, 0u);
+    // derived constants, computed in double and rounded once to float
+    pops.assign(p.n_pops, PopParams{});
+    ptab.assign((size_t)p.n_pops * kMaxPoisson, 0u);
     static const uint32_t umap2[2] = {DBNET_AMPA, DBNET_GABA_A};
     static const uint32_t umap4[4] = {DBNET_AMPA, DBNET_NMDA, DBNET_GABA_A, DBNET_GABA_B};
     const uint32_t* umap = KW == 1 ? umap2 : umap4;
-    std::vector<uint32_t> pop_indeg(p.n_pops);
-    std::vector<uint64_t> pop_first(p.n_pops + 1, 0);
+    if (indeg) indeg->assign(p.n_pops, 0u);
+    if (first) first->assign((size_t)p.n_pops + 1, 0ull);
     uint64_t off = 0;
     for (uint32_t m = 0; m < M; m++) {
         const dbnet_desc& d = mem.m[m];
         for (uint32_t q = 0; q < d.n_pops; q++) {
             const uint32_t gq = mem.pbase[m] + q;
             const dbnet_pop& Q = d.pops[q];
-            PopParams& P = h.pops[gq];
+            PopParams& P = pops[gq];
             P.k = (float)(dt / (double)Q.C);
             P.gL = Q.g_L;
             P.VL = Q.V_L;
@@ -306,19 +305,28 @@ std::string build_tables(const Members& mem, const Plan& p, unsigned threads, Ho
                 P.dec[c] = (float)std::exp(-dt / (double)Q.tau[u]);
             }
             P.r = (int32_t)std::lround((double)Q.T_ref / dt);
-            P.cmax = poisson_thresholds((double)Q.bg_rate_hz * dt * 1e-3, &h.ptab[(size_t)gq * kMaxPoisson],
-                                        kMaxPoisson);
-            pop_first[gq] = off;
+            P.cmax = poisson_thresholds((double)Q.bg_rate_hz * dt * 1e-3, &ptab[(size_t)gq * kMaxPoisson], kMaxPoisson);
+            if (first) (*first)[gq] = off;
             off += Q.size;
             P.end = (uint32_t)off;
             P.region = mem.rbase[m] + Q.region;
             P.net_id = d.net_id;
             P.id_base = (uint32_t)mem.nbase[m];
             P.seed = d.seed;
-            pop_indeg[gq] = indeg_of_pop(d, q);
+            if (indeg) (*indeg)[gq] = indeg_of_pop(d, q);
         }
     }
-    pop_first[p.n_pops] = off;
+    if (first) (*first)[p.n_pops] = off;
+}
+
+std::string build_tables(const Members& mem, const Plan& p, unsigned threads, HostTables& h) {
+    const unsigned nt = threads ? threads : std::max(1u, std::thread::hardware_concurrency());
+    const uint32_t N = p.N, D = p.D, KW = p.KW;
+    const uint32_t M = (uint32_t)mem.m.size();
+
+    std::vector<uint32_t> pop_indeg;
+    std::vector<uint64_t> pop_first;
+    fill_populations(mem, p, h.pops, h.ptab, &pop_first, &pop_indeg);
     // neuron blocks never straddle populations; regions list their blocks
     h.blk.clear();
     h.reg_size.assign(p.n_regions, 0u);

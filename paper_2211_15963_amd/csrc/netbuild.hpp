@@ -82,6 +82,12 @@ struct HostTables {
     std::vector<uint32_t> reg_blk_ptr, reg_blk, reg_size, l1_ptr, l1_region;
 };
 
+// Per-population parameters and derived constants of the plan's populations (members one
+// after another): PopParams and the Poisson thresholds [n_pops][kMaxPoisson]; optionally the
+// first global neuron of every population [n_pops + 1] and its in-degree. Host only.
+void fill_populations(const Members& mem, const Plan& p, std::vector<PopParams>& pops, std::vector<uint32_t>& ptab,
+                      std::vector<uint64_t>* first, std::vector<uint32_t>* indeg);
+
 // Generates the networks (threads: 0 = all cores) and builds every host table.
 // Returns an empty string on success, else the reason.
 std::string build_tables(const Members& mem, const Plan& p, unsigned threads, HostTables& h);

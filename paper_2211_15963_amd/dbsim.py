@@ -65,6 +65,32 @@ class SimTuning(Structure):
                 ("ahead_passes", c_uint32)]
 
 
+MAX_POISSON = 64
+
+
+class PopConstants(Structure):
+    _fields_ = [("first_neuron", c_uint32), ("end_neuron", c_uint32), ("member", c_uint32), ("region", c_uint32),
+                ("k", c_float), ("g_L", c_float), ("V_L", c_float), ("V_th", c_float), ("V_reset", c_float),
+                ("I_ext", c_float), ("w_bg", c_float), ("g", c_float * 4), ("V_rev", c_float * 4),
+                ("decay", c_float * 4), ("ref_steps", c_int32), ("poisson_len", c_uint32),
+                ("poisson_T", c_uint32 * MAX_POISSON)]
+
+    def as_dict(self, U: int) -> dict:
+        f32 = np.float32
+        return {"first_neuron": int(self.first_neuron), "end_neuron": int(self.end_neuron), "member": int(self.member),
+                "region": int(self.region), "k": f32(self.k), "g_L": f32(self.g_L), "V_L": f32(self.V_L),
+                "V_th": f32(self.V_th), "V_reset": f32(self.V_reset), "I_ext": f32(self.I_ext), "w_bg": f32(self.w_bg),
+                "g": np.array(self.g[:U], f32), "V_rev": np.array(self.V_rev[:U], f32),
+                "decay": np.array(self.decay[:U], f32), "ref_steps": int(self.ref_steps),
+                "poisson_T": np.array(self.poisson_T[:self.poisson_len], np.uint32)}
+
+
+class NetworkView(Structure):
+    _fields_ = [("row_ptr", POINTER(c_uint64)), ("seg", POINTER(c_uint32)), ("tgt", POINTER(c_uint32)),
+                ("w0", POINTER(c_float)), ("w1", POINTER(c_float)), ("V0", POINTER(c_float)),
+                ("pops", POINTER(PopConstants)), ("pops_cap", c_uint32), ("n_pops", c_uint32)]
+
+
 class BoldParams(Structure):
     _fields_ = [("kappa", c_double), ("gamma", c_double), ("tau", c_double), ("alpha", c_double),
                 ("rho", c_double), ("V0", c_double), ("k1", c_double), ("k2", c_double), ("k3", c_double),
@@ -94,7 +120,8 @@ EXPORTED = ["dbsim_abi_version", "dbsim_last_error", "dbsim_create", "dbsim_foot
             "dbsim_create_ensemble", "dbsim_footprint_ensemble", "dbsim_member_info", "dbsim_get_tuning",
             "dbsim_set_tuning",
             "dbsim_step", "dbsim_sync", "dbsim_read_spikes", "dbsim_read_region_signal", "dbsim_read_state",
-            "dbsim_write_state", "dbsim_export_csr", "dbsim_set_timing", "dbsim_get_stats", "dbsim_destroy"]
+            "dbsim_write_state", "dbsim_export_csr", "dbsim_set_timing", "dbsim_get_stats", "dbsim_destroy",
+            "dbsim_derive_constants", "dbsim_export_network"]
 
 
 def lib():
@@ -132,6 +159,9 @@ def lib():
     L.dbsim_write_state.argtypes = [H, POINTER(c_float), POINTER(c_float), POINTER(c_int32)]
     L.dbsim_export_csr.argtypes = [H, POINTER(c_uint64), POINTER(c_uint32), POINTER(c_uint32), POINTER(c_float),
                                    POINTER(c_float)]
+    L.dbsim_derive_constants.argtypes = [POINTER(SimDesc), POINTER(Desc), c_uint32, POINTER(PopConstants), c_uint32,
+                                         POINTER(c_uint32)]
+    L.dbsim_export_network.argtypes = [H, POINTER(NetworkView)]
     L.dbsim_set_timing.argtypes = [H, c_int]
     L.dbsim_get_stats.argtypes = [H, POINTER(SimStats)]
     L.dbsim_destroy.argtypes = [H]
@@ -223,6 +253,23 @@ def footprint(spec, record_regions: bool = True, **kw) -> int:
         d, holder = make_desc(spec, record_regions=record_regions, **kw)
         _check(lib().dbsim_footprint(byref(d), byref(out)))
     return int(out.value)
+
+
+def derive_constants(spec, **kw) -> list:
+    """Derived per-population constants (dicts, members one after another) of one network
+    (NetSpec) or an ensemble (list of NetSpec), computed by the library on the host
+    without a device."""
+    specs = list(spec) if isinstance(spec, (list, tuple)) else [spec]
+    d, holder = make_desc(specs[0], **kw)
+    arr, holders = _member_array(specs)
+    n = c_uint32(0)
+    rc = lib().dbsim_derive_constants(byref(d), arr, len(specs), None, 0, byref(n))
+    if rc not in (OK, ETRUNC):
+        _check(rc)
+    out = (PopConstants * max(1, n.value))()
+    _check(lib().dbsim_derive_constants(byref(d), arr, len(specs), out, n.value, byref(n)))
+    U = 2 * specs[0].weights_per_edge
+    return [out[q].as_dict(U) for q in range(n.value)]
 
 
 class Simulator:
@@ -425,6 +472,25 @@ class Simulator:
         _check(lib().dbsim_export_csr(self._h, _p(row_ptr, c_uint64), _p(seg, c_uint32), _p(tgt, c_uint32),
                                       _p(w0, c_float), _p(w1, c_float)))
         return row_ptr, seg.reshape(self.N, D + 1), tgt[:E], w0[:E], w1[:E]
+
+    def export_network(self) -> dict:
+        """The network the handle built: CSR (row_ptr, seg [N, D+1], tgt, w0, w1), the initial
+        potentials V0 and the per-population constants read back from the device."""
+        E = int(self.info.num_edges)
+        D = int(self.info.max_delay)
+        n_pops = sum(len(sp.pops) for sp in self.specs)
+        row_ptr = np.zeros(self.N + 1, np.uint64)
+        seg = np.zeros(self.N * (D + 1), np.uint32)
+        tgt = np.zeros(max(E, 1), np.uint32)
+        w0 = np.zeros(max(E, 1), np.float32)
+        w1 = np.zeros(max(E, 1), np.float32)
+        V0 = np.zeros(max(self.N, 1), np.float32)
+        pops = (PopConstants * max(1, n_pops))()
+        v = NetworkView(_p(row_ptr, c_uint64), _p(seg, c_uint32), _p(tgt, c_uint32), _p(w0, c_float), _p(w1, c_float),
+                        _p(V0, c_float), pops, n_pops, 0)
+        _check(lib().dbsim_export_network(self._h, byref(v)))
+        return {"row_ptr": row_ptr, "seg": seg.reshape(self.N, D + 1), "tgt": tgt[:E], "w0": w0[:E], "w1": w1[:E],
+                "V0": V0[:self.N], "pops": [pops[q].as_dict(self.U) for q in range(v.n_pops)]}
 
     def stats(self) -> dict:
         s = SimStats()

@@ -404,6 +404,23 @@ def test_oracle_matches_dense_brute_force(idx):
     assert o.edge_events == events
 
 
+@pytest.mark.parametrize("idx", range(4))
+def test_oracle_region_signal_fp32_matches_brute_force(idx):
+    """The FP32 oracle's per-bin region signal and spike counts equal the dense brute force's bit for
+    bit (a wrong receptor order, a current taken from the pre-step V or a count from the wrong bin
+    fails); spec 2 has four regions, the others one."""
+    spec = _small_specs()[idx]
+    n = 300
+    *_, sig, cnt = brute.simulate(spec, n, regions=True)
+    o = Oracle(spec, 32)
+    o.step(n)
+    osig, ocnt = o.region_signal()
+    assert osig.shape == sig.shape == (n // spec.steps_per_bin, spec.n_regions)
+    assert np.array_equal(ocnt.astype(np.int64), cnt)
+    assert cnt.sum() > 0
+    assert np.array_equal(osig.view(np.uint64), sig.view(np.uint64))
+
+
 def test_edge_events_equal_delivered_out_edges():
     spec = configs.share(n=300, indegree=40, d_max=5, bg_rate_hz=8000.0, seed=9)
     o = Oracle(spec, 32)
