@@ -71,6 +71,8 @@ def lib():
     L.orc_poisson_count.restype = c_uint32
     L.orc_quantize.argtypes = [c_float, c_uint32]
     L.orc_quantize.restype = c_int64
+    L.orc_set_threads.argtypes = [c_void_p, c_uint32]
+    L.orc_set_threads.restype = c_int
     L.orc_pop_constants.argtypes = [c_void_p, c_uint32, POINTER(c_float), POINTER(c_float), POINTER(c_int32),
                                     POINTER(c_int), POINTER(c_uint32), c_int]
     L.orc_pop_constants.restype = c_int
@@ -105,6 +107,11 @@ class Oracle:
         if getattr(self, "_h", None):
             lib().orc_destroy(self._h)
             self._h = None
+
+    def set_threads(self, threads: int) -> None:
+        """Host threads for step() (the neurons split into ranges; same results on any count)."""
+        if lib().orc_set_threads(self._h, int(threads)) != 0:
+            raise ValueError("threads must lie in 1..256")
 
     def step(self, n: int) -> None:
         if lib().orc_step(self._h, int(n)) != 0:

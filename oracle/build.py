@@ -14,7 +14,7 @@ CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC", "-W
 def build(verbose: bool = False) -> str:
     out = os.path.join(HERE, "liboracle.so")
     cmd = ["gcc", *CFLAGS, "-shared", "-I", os.path.join(ROOT, "include"), "-I", HERE,
-           os.path.join(HERE, "oracle.c"), os.path.join(ROOT, "netgen", "dbnet.c"), "-o", out + ".tmp", "-lm"]
+           os.path.join(HERE, "oracle.c"), os.path.join(ROOT, "netgen", "dbnet.c"), "-o", out + ".tmp", "-lm", "-lpthread"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

@@ -52,6 +52,7 @@
 #include "oracle.h"
 
 #include <math.h>
+#include <pthread.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -120,6 +121,7 @@ float orc_i64_to_f32(int64_t v) { return (float)v; }
 /* ---------------- the simulator state ---------------- */
 
 #define ORC_MAX_TABLE 160
+#define ORC_MAX_THREADS 256
 
 typedef struct {
     /* membrane and receptor parameters, per population */
@@ -159,6 +161,8 @@ struct orc {
     int32_t* ref;
     uint8_t* hist;    /* [R][N] spike flags of recent bins */
     uint8_t* binspk;  /* spike flag of the current bin */
+    uint8_t* stepspk; /* spike flag of the current step */
+    uint32_t threads; /* host threads of orc_step (1 unless set) */
     float* A32; double* A64;
     uint64_t step, edge_events;
     /* recordings */
@@ -189,7 +193,7 @@ void orc_destroy(orc* o) {
     free(o->pop_of); free(o->is_exc); free(o->region_of); free(o->region_size); free(o->P);
     free(o->in_ptr); free(o->in_src); free(o->in_w0); free(o->in_w1); free(o->in_d);
     free(o->V32); free(o->J32); free(o->V64); free(o->J64); free(o->ref);
-    free(o->hist); free(o->binspk); free(o->A32); free(o->A64);
+    free(o->hist); free(o->binspk); free(o->stepspk); free(o->A32); free(o->A64);
     free(o->spk_step); free(o->spk_id); free(o->sig); free(o->cnt);
     free(o);
 }
@@ -318,6 +322,8 @@ orc* orc_create_ex(const dbnet_desc* d, int precision, uint32_t flags, char* err
     }
     o->hist = (uint8_t*)xcalloc((size_t)o->R * N, 1);
     o->binspk = (uint8_t*)xcalloc(N, 1);
+    o->stepspk = (uint8_t*)xcalloc(N, 1);
+    o->threads = 1;
     return o;
 }
 
@@ -380,9 +386,10 @@ static int record_bin(orc* o) {
 
 /* Arrival sums for the bin starting at step kS: eq. 3's sum_j w_ij^u A_j
    with A_j taken at bin k - d_ij (pull form of the definition). */
-static void arrivals(orc* o, uint64_t k) {
+static uint64_t arrivals(orc* o, uint64_t k, uint32_t i0, uint32_t i1) {
     const uint32_t N = o->N, KW = o->KW;
-    for (uint32_t i = 0; i < N; i++) {
+    uint64_t events = 0;
+    for (uint32_t i = i0; i < i1; i++) {
         int64_t q[4] = {0, 0, 0, 0};
         double s[4] = {0.0, 0.0, 0.0, 0.0};
         for (uint64_t e = o->in_ptr[i]; e < o->in_ptr[i + 1]; e++) {
@@ -391,7 +398,7 @@ static void arrivals(orc* o, uint64_t k) {
             uint32_t j = o->in_src[e];
             if (!o->hist[(size_t)((k - dl) % o->R) * N + j]) continue;
             uint32_t base = o->is_exc[j] ? 0u : KW;
-            o->edge_events++;
+            events++;
             if (o->prec == 32) {
                 q[base] += orc_quantize(o->in_w0[e], o->F);
                 if (KW == 2) q[base + 1] += orc_quantize(o->in_w1[e], o->F);
@@ -405,6 +412,7 @@ static void arrivals(orc* o, uint64_t k) {
             else o->A64[(size_t)u * N + i] = s[u];
         }
     }
+    return events;
 }
 
 /* One Euler step of one neuron (FP32): all right-hand sides use the old V and
@@ -538,8 +546,98 @@ int orc_set_injection(orc* o, const float* p, uint32_t npops, uint64_t until_bin
     return 0;
 }
 
-int orc_step(orc* o, uint64_t nsteps) {
+/* One Euler step n of the neurons i0 <= i < i1 (each independent of the others within the
+   step): background draw, membrane and synapse update; the spike flag of each neuron (own
+   spike or injected output spike) goes to spk[i]. */
+static void neurons(orc* o, uint64_t n, uint32_t i0, uint32_t i1, uint8_t* spk) {
     const uint32_t N = o->N, U = o->U, S = o->S;
+    const uint64_t k = n / S;
+    const uint32_t s = (uint32_t)(n % S);
+    for (uint32_t i = i0; i < i1; i++) {
+        const orc_pop* P = &o->P[o->pop_of[i]];
+        /* background Poisson count */
+        uint32_t x = orc_bg_word(o->d.seed, o->d.net_id, n, i);
+        uint32_t c = orc_poisson_count(x, P->T, P->cmax);
+        int spiked;
+        if (o->prec == 32) {
+            float J[4], A[4];
+            for (uint32_t u = 0; u < U; u++) {
+                J[u] = o->J32[(size_t)u * N + i];
+                A[u] = (s == 0) ? o->A32[(size_t)u * N + i] : 0.0f;
+            }
+            const float Ibg = P->ou ? o->Iou32[i] : 0.0f;
+            spiked = neuron_step32(P, U, c, A, &o->V32[i], J, &o->ref[i], Ibg);
+            for (uint32_t u = 0; u < U; u++) o->J32[(size_t)u * N + i] = J[u];
+            if (P->ou) { /* OU current: drift towards mu, then the scaled increment */
+                const float z = orc_ou_normal(o->d.seed, o->d.net_id, n, i);
+                const float drift = P->ou_c1_32 * (P->ou_mu32 - Ibg);
+                const float Ih = Ibg + drift;
+                o->Iou32[i] = Ih + P->ou_c2_32 * z;
+            }
+        } else {
+            double J[4], A[4];
+            for (uint32_t u = 0; u < U; u++) {
+                J[u] = o->J64[(size_t)u * N + i];
+                A[u] = (s == 0) ? o->A64[(size_t)u * N + i] : 0.0;
+            }
+            const double Ibg = P->ou ? o->Iou64[i] : 0.0;
+            spiked = neuron_step64(P, U, c, A, &o->V64[i], J, &o->ref[i], Ibg);
+            for (uint32_t u = 0; u < U; u++) o->J64[(size_t)u * N + i] = J[u];
+            if (P->ou) {
+                const double z = (double)orc_ou_normal(o->d.seed, o->d.net_id, n, i);
+                o->Iou64[i] = (Ibg + P->ou_c1_64 * (P->ou_mu64 - Ibg)) + P->ou_c2_64 * z;
+            }
+        }
+        /* an injected output spike is delivered and recorded, the neuron is not reset */
+        spk[i] = (uint8_t)(spiked || (s == S - 1 && !o->binspk[i] && injected(o, k, i)));
+    }
+}
+
+/* Host threads: the neurons (and the targets of the arrival sums) are split into
+   contiguous ranges, one per thread; every neuron's arithmetic is the same as on one
+   thread, and spikes are recorded afterwards in ascending id. */
+typedef struct {
+    orc* o;
+    uint64_t n, k;
+    uint32_t i0, i1;
+    int phase; /* 0: arrivals of bin k, 1: neurons of step n */
+    uint64_t events;
+} orc_job;
+
+static void* run_job(void* arg) {
+    orc_job* j = (orc_job*)arg;
+    if (j->phase == 0) j->events = arrivals(j->o, j->k, j->i0, j->i1);
+    else neurons(j->o, j->n, j->i0, j->i1, j->o->stepspk);
+    return NULL;
+}
+
+static uint64_t run_split(orc* o, int phase, uint64_t n, uint64_t k) {
+    const uint32_t T = o->threads > 1 ? o->threads : 1, N = o->N;
+    orc_job jobs[ORC_MAX_THREADS];
+    pthread_t th[ORC_MAX_THREADS];
+    int started[ORC_MAX_THREADS];
+    for (uint32_t t = 0; t < T; t++) {
+        jobs[t] = (orc_job){o, n, k, (uint32_t)((uint64_t)N * t / T), (uint32_t)((uint64_t)N * (t + 1) / T), phase, 0};
+        started[t] = t > 0 && pthread_create(&th[t], NULL, run_job, &jobs[t]) == 0;
+        if (t > 0 && !started[t]) run_job(&jobs[t]); /* no thread: run the range here */
+    }
+    run_job(&jobs[0]);
+    uint64_t ev = 0;
+    for (uint32_t t = 0; t < T; t++) {
+        if (started[t]) pthread_join(th[t], NULL);
+        ev += jobs[t].events;
+    }
+    return ev;
+}
+
+int orc_set_threads(orc* o, uint32_t threads) {
+    if (!o || threads < 1 || threads > ORC_MAX_THREADS) return -1;
+    o->threads = threads;
+    return 0;
+}
+
+int orc_step(orc* o, uint64_t nsteps) {
+    const uint32_t N = o->N, S = o->S;
     if (o->params_only) return -2;
     for (uint64_t t = 0; t < nsteps; t++) {
         const uint64_t n = o->step;
@@ -547,51 +645,13 @@ int orc_step(orc* o, uint64_t nsteps) {
         const uint32_t s = (uint32_t)(n % S);
         if (s == 0) {
             memset(o->binspk, 0, N);
-            arrivals(o, k);
+            o->edge_events += run_split(o, 0, n, k);
         }
+        run_split(o, 1, n, k);
         for (uint32_t i = 0; i < N; i++) {
-            const orc_pop* P = &o->P[o->pop_of[i]];
-            /* background Poisson count */
-            uint32_t x = orc_bg_word(o->d.seed, o->d.net_id, n, i);
-            uint32_t c = orc_poisson_count(x, P->T, P->cmax);
-            int spiked;
-            if (o->prec == 32) {
-                float J[4], A[4];
-                for (uint32_t u = 0; u < U; u++) {
-                    J[u] = o->J32[(size_t)u * N + i];
-                    A[u] = (s == 0) ? o->A32[(size_t)u * N + i] : 0.0f;
-                }
-                const float Ibg = P->ou ? o->Iou32[i] : 0.0f;
-                spiked = neuron_step32(P, U, c, A, &o->V32[i], J, &o->ref[i], Ibg);
-                for (uint32_t u = 0; u < U; u++) o->J32[(size_t)u * N + i] = J[u];
-                if (P->ou) { /* OU current: drift towards mu, then the scaled increment */
-                    const float z = orc_ou_normal(o->d.seed, o->d.net_id, n, i);
-                    const float drift = P->ou_c1_32 * (P->ou_mu32 - Ibg);
-                    const float Ih = Ibg + drift;
-                    o->Iou32[i] = Ih + P->ou_c2_32 * z;
-                }
-            } else {
-                double J[4], A[4];
-                for (uint32_t u = 0; u < U; u++) {
-                    J[u] = o->J64[(size_t)u * N + i];
-                    A[u] = (s == 0) ? o->A64[(size_t)u * N + i] : 0.0;
-                }
-                const double Ibg = P->ou ? o->Iou64[i] : 0.0;
-                spiked = neuron_step64(P, U, c, A, &o->V64[i], J, &o->ref[i], Ibg);
-                for (uint32_t u = 0; u < U; u++) o->J64[(size_t)u * N + i] = J[u];
-                if (P->ou) {
-                    const double z = (double)orc_ou_normal(o->d.seed, o->d.net_id, n, i);
-                    o->Iou64[i] = (Ibg + P->ou_c1_64 * (P->ou_mu64 - Ibg)) + P->ou_c2_64 * z;
-                }
-            }
-            if (spiked) {
-                o->binspk[i] = 1;
-                if (record_spike(o, n, i)) return -1;
-            } else if (s == S - 1 && !o->binspk[i] && injected(o, k, i)) {
-                /* an injected output spike: delivered and recorded, the neuron is not reset */
-                o->binspk[i] = 1;
-                if (record_spike(o, n, i)) return -1;
-            }
+            if (!o->stepspk[i]) continue;
+            o->binspk[i] = 1;
+            if (record_spike(o, n, i)) return -1;
         }
         if (s == S - 1) {
             memcpy(o->hist + (size_t)(k % o->R) * N, o->binspk, N);

@@ -30,6 +30,10 @@ orc* orc_create(const dbnet_desc* d, int precision, char* err, size_t errlen);
 orc* orc_create_ex(const dbnet_desc* d, int precision, uint32_t flags, char* err, size_t errlen);
 void orc_destroy(orc* o);
 
+/* Host threads used by orc_step (default 1, at most 256): the neurons are split into
+   contiguous ranges; results do not depend on the count. Returns 0, or -1. */
+int orc_set_threads(orc* o, uint32_t threads);
+
 /* Advances n Euler steps. Returns 0, or -1 if host memory ran out. */
 int orc_step(orc* o, uint64_t n);
 

@@ -562,3 +562,18 @@ def test_euler_step_convergence():
             errs[dt] = float(np.linalg.norm(V - ref) / np.linalg.norm(ref))
     print("relative V error at 50 ms vs dt = 0.0625 ms:", {k: round(v, 4) for k, v in errs.items()})
     assert errs[0.125] < errs[1.0]
+
+
+def test_threaded_oracle_equals_one_thread():
+    """The oracle split over host threads (the all-core CPU baseline) gives the same raster,
+    state, delivered-event count and region signal as on one thread, for a count that does
+    not divide N."""
+    spec = configs.share(n=3000, indegree=80, d_max=5, bg_rate_hz=9000.0, seed=4)
+    a = Oracle(spec, 32)
+    b = Oracle(spec, 32)
+    b.set_threads(7)
+    a.step(400)
+    b.step(400)
+    for x, y in zip(a.spikes() + a.state() + a.region_signal(), b.spikes() + b.state() + b.region_signal()):
+        assert np.array_equal(x, y)
+    assert a.edge_events == b.edge_events > 0
