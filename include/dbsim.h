@@ -137,6 +137,23 @@ const char* dbsim_last_error(void);
  */
 int dbsim_create(const dbsim_desc* desc, struct dbsim** out);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): dbsim_create with every device array of
+ * the handle placed in a static region of DBSIM_STATIC_BYTES per GPU that the library holds
+ * from its load to the end of the process. No hipMalloc, hipFree, stream, event or graph
+ * is created: dev_alloc must be NULL, and the handle's bins run on desc->hip_stream (NULL:
+ * the default stream) as direct launches, one kernel after another, with the same results
+ * as dbsim_create (no phase timers: dbsim_set_timing(h, 1) gives ESTATE). Everything the
+ * kernels read is initialised here, whatever the region held before. The region is shared:
+ * one such handle per device at a time (ESTATE while another is alive; dbsim_destroy frees
+ * the region for the next). Errors: EINVAL when the footprint (dbsim_footprint) exceeds
+ * DBSIM_STATIC_BYTES (checked before any device work) or dev_alloc is set; otherwise as
+ * dbsim_create.
+ */
+#define DBSIM_STATIC_BYTES (64u << 20)
+int dbsim_create_static(const dbsim_desc* desc, struct dbsim** out);
+
 /* Exact device bytes dbsim_create would allocate for desc, without building. */
 int dbsim_footprint(const dbsim_desc* desc, uint64_t* hbm_bytes);
 

@@ -49,6 +49,35 @@ constexpr int kMarks = 7;     // events per timed bin (six intervals, see resolv
 
 } // namespace
 
+// Device memory of the handles made by dbsim_create_static: one region per GPU, held from the
+// library's load to the end of the process. In host code the array's name is only a host-side
+// stand-in, so its device address is looked up once per device (static_region_of) and only
+// that address is used afterwards (kernel arguments, copies, fills).
+static __device__ __align__(256) unsigned char scratch[DBSIM_STATIC_BYTES];
+
+namespace {
+constexpr int kStaticDevices = 64;
+std::mutex g_static_mu;
+unsigned char* g_static_ptr[kStaticDevices] = {};
+bool g_static_busy[kStaticDevices] = {};
+} // namespace
+
+// The region's device address on `device` (current device set by the caller); nullptr with
+// *err set when the lookup fails.
+static unsigned char* static_region_of(int device, hipError_t* err) {
+    *err = hipSuccess;
+    if (!g_static_ptr[device]) {
+        void* ptr = nullptr;
+        *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (*err != hipSuccess || !ptr) {
+            if (*err == hipSuccess) *err = hipErrorInvalidSymbol;
+            return nullptr;
+        }
+        g_static_ptr[device] = static_cast<unsigned char*>(ptr);
+    }
+    return g_static_ptr[device];
+}
+
 // The kernels' LDS limits are set once per device and process, not at every create:
 // handles are created on host threads while other handles' kernels are being launched and
 // captured, and a set that is already in place needs no repeating.
@@ -73,6 +102,7 @@ struct dbsim {
     hipStream_t side_stream = nullptr; // the next bin's delay >= 2 fan-in, beside the neuron step
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     unsigned char* dev = nullptr;
+    bool static_mem = false; // dev is the device's static region (dbsim_create_static)
     DevNet net{};
     int scatter_grid = 256;
     int num_cus = 256;
@@ -236,6 +266,15 @@ hipError_t enqueue_full_bin(dbsim* h, hipStream_t st, hipStream_t side) {
     return launch_readout_close(h->net, st);
 }
 
+// One whole bin on one stream, kernel after kernel (the order of the timed bins, without
+// their events): the same results as the two-stream form.
+hipError_t enqueue_serial_bin(dbsim* h, hipStream_t st) {
+    hipError_t e = enqueue_bin_start(h, st);
+    if (e == hipSuccess) e = launch_neuron(h->net, 0, (int)h->plan.S, st);
+    if (e == hipSuccess) e = enqueue_bin_end(h, st);
+    return e;
+}
+
 hipError_t capture_graph(dbsim* h, int bins, hipGraphExec_t* out) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
@@ -310,8 +349,14 @@ void release_device(dbsim* h) {
     h->ev_pending.clear();
     h->ev_pool.clear();
     if (h->dev) {
-        if (h->desc.dev_alloc) h->desc.dev_free(h->desc.alloc_ctx, h->dev, h->plan.total);
-        else (void)hipFree(h->dev);
+        if (h->static_mem) {
+            std::lock_guard<std::mutex> lock(g_static_mu);
+            g_static_busy[h->device] = false;
+        } else if (h->desc.dev_alloc) {
+            h->desc.dev_free(h->desc.alloc_ctx, h->dev, h->plan.total);
+        } else {
+            (void)hipFree(h->dev);
+        }
         h->dev = nullptr;
     }
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
@@ -358,10 +403,13 @@ int dbsim_footprint_ensemble(const dbsim_desc* common, const dbnet_desc* members
     return footprint_impl(common, members, n_members, hbm_bytes);
 }
 
-static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32_t n_members, dbsim** out) {
+static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32_t n_members, dbsim** out,
+                       bool in_static = false) {
     if (!desc || !out || !members || n_members == 0) return fail(DBSIM_EINVAL, "null argument or no network");
     *out = nullptr;
     if (desc->dev_alloc && !desc->dev_free) return fail(DBSIM_EINVAL, "dev_alloc given without dev_free");
+    if (in_static && desc->dev_alloc)
+        return fail(DBSIM_EINVAL, "dbsim_create_static allocates nothing: dev_alloc must be NULL");
     dbsim* h = nullptr;
     try {
         h = new dbsim();
@@ -373,6 +421,12 @@ static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32
             delete h;
             return fail(DBSIM_EINVAL, m);
         }
+        if (in_static && h->plan.total > (size_t)DBSIM_STATIC_BYTES) {
+            const std::string need = std::to_string(h->plan.total);
+            delete h;
+            return fail(DBSIM_EINVAL, "the network needs " + need + " bytes of device memory; the static region of "
+                                      "dbsim_create_static holds " + std::to_string((size_t)DBSIM_STATIC_BYTES));
+        }
         h->device = desc->device;
         if (h->device < 0 && hipGetDevice(&h->device) != hipSuccess) {
             delete h;
@@ -381,7 +435,27 @@ static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32
         DeviceGuard dg(h->device);
         const Plan& p = h->plan;
         // device memory first, so an allocation failure costs no build time
-        if (desc->dev_alloc) {
+        if (in_static) {
+            if (h->device >= kStaticDevices) {
+                delete h;
+                return fail(DBSIM_EINVAL, "device ordinal too large for the static regions");
+            }
+            std::lock_guard<std::mutex> lock(g_static_mu);
+            hipError_t se;
+            unsigned char* region = static_region_of(h->device, &se);
+            if (!region) {
+                delete h;
+                return fail(DBSIM_EDEVICE, std::string("hipGetSymbolAddress(static region): ") + hipGetErrorString(se));
+            }
+            if (g_static_busy[h->device]) {
+                delete h;
+                return fail(DBSIM_ESTATE, "the static region of this device is held by another handle of "
+                                          "dbsim_create_static; destroy that one first");
+            }
+            g_static_busy[h->device] = true;
+            h->dev = region;
+            h->static_mem = true;
+        } else if (desc->dev_alloc) {
             h->dev = (unsigned char*)desc->dev_alloc(desc->alloc_ctx, p.total);
             if (!h->dev) {
                 delete h;
@@ -406,8 +480,11 @@ static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32
             return fail(DBSIM_EINVAL, m);
         }
         h->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        // streams
-        if (desc->hip_stream) {
+        // streams (a handle in the static region creates none: its bins run on the caller's
+        // stream, or the default stream, one kernel after another)
+        if (in_static) {
+            h->stream = (hipStream_t)desc->hip_stream;
+        } else if (desc->hip_stream) {
             h->stream = (hipStream_t)desc->hip_stream;
         } else {
             hipError_t se = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
@@ -418,7 +495,7 @@ static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32
             }
             h->own_stream = true;
         }
-        {
+        if (!in_static) {
             hipError_t se = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
             if (se == hipSuccess) se = hipStreamCreateWithFlags(&h->side_stream, hipStreamNonBlocking);
             if (se == hipSuccess) se = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
@@ -555,6 +632,11 @@ int dbsim_create(const dbsim_desc* desc, dbsim** out) {
     return create_impl(desc, &desc->net, 1, out);
 }
 
+int dbsim_create_static(const dbsim_desc* desc, dbsim** out) {
+    if (!desc) return fail(DBSIM_EINVAL, "null argument");
+    return create_impl(desc, &desc->net, 1, out, true);
+}
+
 int dbsim_create_ensemble(const dbsim_desc* common, const dbnet_desc* members, uint32_t n_members, dbsim** out) {
     return create_impl(common, members, n_members, out);
 }
@@ -592,7 +674,7 @@ int dbsim_step(dbsim* h, uint64_t n_steps) {
     if (rc) return rc;
     DeviceGuard dg(h->device);
     const uint32_t S = h->plan.S;
-    const bool direct = h->timing || (h->desc.flags & DBSIM_F_NO_GRAPH);
+    const bool direct = h->timing || h->static_mem || (h->desc.flags & DBSIM_F_NO_GRAPH);
     while (n_steps > 0) {
         const uint32_t s0 = (uint32_t)(h->step % S);
         if (s0 == 0 && n_steps >= S) {
@@ -620,6 +702,8 @@ int dbsim_step(dbsim* h, uint64_t n_steps) {
                         HIPCHK(h, launch_readout_close(h->net, st), "readout launch");
                         HIPCHK(h, hipEventRecord(ev[6], st), "hipEventRecord");
                         h->ev_pending.push_back(ev);
+                    } else if (h->static_mem) {
+                        HIPCHK(h, enqueue_serial_bin(h, h->stream), "bin launch");
                     } else {
                         HIPCHK(h, enqueue_full_bin(h, h->stream, h->side_stream), "bin launch");
                     }
@@ -1049,6 +1133,8 @@ int dbsim_set_tuning(dbsim* h, const dbsim_tuning* t) {
 int dbsim_set_timing(dbsim* h, int on) {
     int rc = check_usable(h);
     if (rc) return rc;
+    if (on && h->static_mem) return fail(DBSIM_ESTATE, "phase timers create HIP events; a handle of "
+                                                       "dbsim_create_static has none");
     h->timing = on != 0;
     return DBSIM_OK;
 }
@@ -1083,7 +1169,7 @@ int dbsim_destroy(dbsim* h) {
     if (!h) return DBSIM_OK;
     {
         DeviceGuard dg(h->device);
-        if (h->stream) (void)hipStreamSynchronize(h->stream);
+        if (h->stream || h->static_mem) (void)hipStreamSynchronize(h->stream);
         release_device(h);
     }
     delete h;

@@ -25,6 +25,7 @@ ABI_VERSION = 1
 REC_REGIONS = 1
 F_NO_GRAPH = 1
 F_TWO_PASS = 2
+STATIC_BYTES = 64 << 20  # DBSIM_STATIC_BYTES: the static region of dbsim_create_static
 
 OK, EINVAL, ENOMEM, EHBM, EDEVICE, ETRUNC, EOVERFLOW, ESTATE, ERANGE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHBM: "EHBM", EDEVICE: "EDEVICE", ETRUNC: "ETRUNC",
@@ -121,7 +122,7 @@ EXPORTED = ["dbsim_abi_version", "dbsim_last_error", "dbsim_create", "dbsim_foot
             "dbsim_set_tuning",
             "dbsim_step", "dbsim_sync", "dbsim_read_spikes", "dbsim_read_region_signal", "dbsim_read_state",
             "dbsim_write_state", "dbsim_export_csr", "dbsim_set_timing", "dbsim_get_stats", "dbsim_destroy",
-            "dbsim_derive_constants", "dbsim_export_network"]
+            "dbsim_derive_constants", "dbsim_export_network", "dbsim_create_static"]
 
 
 def lib():
@@ -142,6 +143,7 @@ def lib():
     L.dbsim_abi_version.restype = c_uint32
     L.dbsim_last_error.restype = c_char_p
     L.dbsim_create.argtypes = [POINTER(SimDesc), POINTER(c_void_p)]
+    L.dbsim_create_static.argtypes = [POINTER(SimDesc), POINTER(c_void_p)]
     L.dbsim_footprint.argtypes = [POINTER(SimDesc), POINTER(c_uint64)]
     L.dbsim_get_info.argtypes = [H, POINTER(SimInfo)]
     L.dbsim_create_ensemble.argtypes = [POINTER(SimDesc), POINTER(Desc), c_uint32, POINTER(c_void_p)]
@@ -280,11 +282,13 @@ class Simulator:
     torch's current HIP stream (otherwise the library uses hipMalloc and its own stream).
     For an ensemble, reads return global neuron ids; member(m) gives each member's
     id range and member_spikes / member_state its own view.
+    static_region: create with dbsim_create_static (no device allocation; the device's
+    static region of STATIC_BYTES, one such handle per device at a time).
     """
 
     def __init__(self, spec: NetSpec, record_regions: bool = True, use_torch: bool = True, device: int = 0,
                  spike_record_capacity: int = 0, record_bins: int = 0, host_threads: Optional[int] = None,
-                 no_graph: bool = False, stream=None, two_pass: bool = False):
+                 no_graph: bool = False, stream=None, two_pass: bool = False, static_region: bool = False):
         L = lib()
         if host_threads is None:
             # the process's CPU share (OMP_NUM_THREADS) rather than every core of the machine
@@ -299,7 +303,8 @@ class Simulator:
             torch.cuda.set_device(device)
             st = stream if stream is not None else torch.cuda.current_stream(device)
             stream_handle = int(st.cuda_stream) or None
-            self._alloc = _TorchAllocator(device, int(st.cuda_stream))
+            if not static_region:  # dbsim_create_static takes no allocator
+                self._alloc = _TorchAllocator(device, int(st.cuda_stream))
         self.specs = list(spec) if isinstance(spec, (list, tuple)) else [spec]
         first = self.specs[0]
         self._desc, self._holder = make_desc(first, record_regions, spike_record_capacity, record_bins, device,
@@ -308,6 +313,8 @@ class Simulator:
         if isinstance(spec, (list, tuple)):
             self._members, self._member_holders = _member_array(self.specs)
             _check(L.dbsim_create_ensemble(byref(self._desc), self._members, len(self.specs), byref(h)))
+        elif static_region:
+            _check(L.dbsim_create_static(byref(self._desc), byref(h)))
         else:
             _check(L.dbsim_create(byref(self._desc), byref(h)))
         self._h = h
