@@ -138,7 +138,7 @@ def run_gpu(args):
     return out
 
 
-def run_regimes(args, regimes):
+def run_regimes(args, regimes, tuning=None):
     """Real-time factor of the same share workload in the other firing regimes (the
     background rate set for a 7 or 30 Hz population rate), graph launches, after a warm-up."""
     import torch
@@ -149,7 +149,8 @@ def run_regimes(args, regimes):
     for r in regimes:
         spec = configs.share(n=args.n, indegree=args.indegree, regime_hz=r, seed=args.seed)
         sim = Simulator(spec, record_regions=True, device=0)
-        sim.set_tuning(scatter_wgs_per_cu=2, round_events=0, chunks_per_wg=4)
+        if tuning:  # the schedule the autotuner chose for the headline regime
+            sim.set_tuning(**tuning)
         S = sim.S
         sim.step(args.settle * S)
         sim.sync()
@@ -603,6 +604,8 @@ def tune(args):
 
 
 def main():
+    import faulthandler
+    faulthandler.enable()  # a fatal signal prints every thread's Python stack to stderr
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000, help="timed 1 ms bins")
@@ -684,7 +687,7 @@ def main():
     if args.regimes:
         regimes = {str(args.regime): {"rtf": g["wall"] / g["bio_s"], "events_per_s": value,
                                       "mean_rate_hz": round(g["rate_hz"], 3), "bins": args.steps}}
-        regimes.update(run_regimes(args, [r for r in (7, 15, 30) if r != args.regime]))
+        regimes.update(run_regimes(args, [r for r in (7, 15, 30) if r != args.regime], g["tuning"]))
     small = run_small_configs(args) if args.small_configs else None
     ens = run_ensemble(args) if args.ensemble else None
     served = run_served(args) if args.serve else None

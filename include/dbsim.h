@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define DBSIM_ABI_VERSION 1u
+#define DBSIM_ABI_VERSION 2u
 
 typedef enum dbsim_status {
     DBSIM_OK = 0,
@@ -66,7 +66,9 @@ typedef struct dbsim_desc {
     uint32_t record_flags;          /* DBSIM_REC_* */
     dbnet_desc net;                 /* the seeded network description (dbnet.h) */
     uint64_t spike_record_capacity; /* spike entries kept on the device (rounded up to
-                                       a power of two >= (max delay + 1) * N); 0 = 2^22 */
+                                       a power of two >= (max delay + 1) * N); 0 = that
+                                       minimum while spikes are recorded to host memory
+                                       (host_spike_capacity), else 2^22 */
     uint32_t record_bins;           /* bins of spike/region history kept (power of two,
                                        >= max delay + 1); 0 = 4096 */
     int32_t device;                 /* HIP device ordinal, -1 = the current device */
@@ -76,12 +78,18 @@ typedef struct dbsim_desc {
     void* alloc_ctx;
     uint32_t host_threads;          /* threads for network construction, 0 = all cores */
     uint32_t flags;                 /* DBSIM_F_* */
+    uint64_t host_spike_capacity;   /* spike entries recorded in pinned host memory (rounded
+                                       up to a power of two); 0 = 2^24; unused with
+                                       DBSIM_F_NO_HOST_RECORD. The last 2^20 bins' offsets are
+                                       kept beside them. */
 } dbsim_desc;
 
 /* flags */
 #define DBSIM_F_NO_GRAPH 1u /* launch kernels directly instead of replaying HIP graphs */
-#define DBSIM_F_TWO_PASS 2u /* fan-in through super-tile streams even where the tiles fit the
-                               single-pass write-combining buffers (same results; for tests
+#define DBSIM_F_NO_HOST_RECORD 4u /* keep the raster only in the device ring (no pinned host
+                                     memory; reads copy from the device) */
+#define DBSIM_F_TWO_PASS 2u /* fan-in through super-tile streams even where the tiles' carry
+                               buffers fit the single-pass kernel's LDS (same results; for tests
                                and comparisons) */
 
 typedef struct dbsim_stats {
@@ -111,7 +119,7 @@ typedef struct dbsim_info {
     uint32_t n_tiles;
     uint32_t frac_bits;        /* F of the fixed-point arrival sums */
     uint32_t n_members;        /* networks in the handle (1 unless an ensemble) */
-    uint32_t fanin_passes;     /* 1: single-pass write-combined fan-in, 2: through super-tile streams */
+    uint32_t fanin_passes;     /* 1: single-pass fan-in into tile blocks, 2: through super-tile streams */
 } dbsim_info;
 
 typedef struct dbsim_member {
@@ -144,7 +152,8 @@ int dbsim_create(const dbsim_desc* desc, struct dbsim** out);
  * from its load to the end of the process. No hipMalloc, hipFree, stream, event or graph
  * is created: dev_alloc must be NULL, and the handle's bins run on desc->hip_stream (NULL:
  * the default stream) as direct launches, one kernel after another, with the same results
- * as dbsim_create (no phase timers: dbsim_set_timing(h, 1) gives ESTATE). Everything the
+ * as dbsim_create (no phase timers: dbsim_set_timing(h, 1) gives ESTATE; spikes are read
+ * from the device ring, as with DBSIM_F_NO_HOST_RECORD). Everything the
  * kernels read is initialised here, whatever the region held before. The region is shared:
  * one such handle per device at a time (ESTATE while another is alive; dbsim_destroy frees
  * the region for the next). Errors: EINVAL when the footprint (dbsim_footprint) exceeds
@@ -153,6 +162,22 @@ int dbsim_create(const dbsim_desc* desc, struct dbsim** out);
  */
 #define DBSIM_STATIC_BYTES (64u << 20)
 int dbsim_create_static(const dbsim_desc* desc, struct dbsim** out);
+
+/*
+ * The two steps of dbsim_create apart, following the paper's workflow (Methods: generate the
+ * neuron attribute and connection tables, then load and deploy them). dbsim_build validates
+ * the description and builds every host table; it makes no HIP call and touches no device, so
+ * it may run on worker threads while another thread drives the GPU (a server builds requests
+ * that way). dbsim_create_built allocates, uploads and initialises the handle; it consumes b
+ * (freed whether it succeeds or not). device_opts (may be NULL: those given to dbsim_build)
+ * supplies device, hip_stream, dev_alloc, dev_free and alloc_ctx; its other fields are
+ * ignored. dbsim_built_free releases a built network that is not deployed (NULL: no-op).
+ * Errors: as dbsim_create.
+ */
+typedef struct dbsim_built dbsim_built;
+int dbsim_build(const dbsim_desc* desc, dbsim_built** out);
+int dbsim_create_built(dbsim_built* b, const dbsim_desc* device_opts, struct dbsim** out);
+void dbsim_built_free(dbsim_built* b);
 
 /* Exact device bytes dbsim_create would allocate for desc, without building. */
 int dbsim_footprint(const dbsim_desc* desc, uint64_t* hbm_bytes);
@@ -196,7 +221,15 @@ int dbsim_sync(struct dbsim* h);
  * Spikes with step_lo <= step < step_hi, sorted by (step, id), copied to
  * steps[] / ids[] (cap entries each). Only completed bins are visible. If
  * cap is too small returns ETRUNC with *n_out = the count needed. ERANGE if
- * part of the range has left the device history. Synchronises.
+ * part of the range is no longer recorded. Synchronises.
+ *
+ * Recording (SI Section 3: a second stream copies every iteration's spikes to CPU
+ * memory): at the end of every bin, once its spike list is compacted, a kernel on a
+ * second stream copies the list into a ring of host_spike_capacity entries in pinned
+ * host memory, concurrently with the rest of the bin; reads are served from that ring,
+ * so the device ring only needs the last max delay + 1 bins the fan-in reads. With
+ * DBSIM_F_NO_HOST_RECORD (and for handles of dbsim_create_static) reads copy from the
+ * device ring instead.
  */
 int dbsim_read_spikes(struct dbsim* h, uint64_t step_lo, uint64_t step_hi, uint64_t* steps,
                       uint32_t* ids, uint64_t cap, uint64_t* n_out);
@@ -291,6 +324,17 @@ int dbsim_set_spike_injection(struct dbsim* h, const float* prob, uint32_t n_pop
 int dbsim_set_ou_background(struct dbsim* h, const float* mu, const float* sigma, const float* tau_ms,
                             uint32_t n_pops);
 
+/*
+ * The measurement step of the conductance initialisation (Suppl. Algorithm 1: run the
+ * off-line model, obtain the mean current of each receptor type) at the current state:
+ * mean[q * 4 + u] = the mean over population q's neurons of g_u J_u (V_u - V), u in the
+ * paper's order AMPA, NMDA, GABA_A, GABA_B (0 for receptors the network lacks). Each
+ * neuron's term is evaluated in float as in the region signal; sums are in double, in a
+ * fixed order on the device. n_pops must be the handle's population count (members of an
+ * ensemble one after another; EINVAL otherwise). Synchronises.
+ */
+int dbsim_receptor_currents(struct dbsim* h, double* mean, uint32_t n_pops);
+
 /* Overwrites the state (checkpoint restore). Only at a bin boundary (ESTATE
    otherwise). ref values must lie in [0, 255]. */
 int dbsim_write_state(struct dbsim* h, const float* V, const float* J, const int32_t* ref);
@@ -368,16 +412,20 @@ int dbsim_export_network(struct dbsim* h, dbsim_network_view* v);
  * speed, so an autotuner may try schedules on a live handle.
  */
 typedef struct dbsim_tuning {
-    uint32_t scatter_wgs_per_cu; /* 1..8 partition workgroups per CU (they split the LDS) */
-    uint32_t round_events;       /* events staged in LDS per round of the first partition pass,
-                                    multiple of 256, at most 4096; 0 = the most that fit (the second
-                                    pass takes the most that fit beside its staging copy, at most
-                                    this, rounded down to whole 512-event batches) */
+    uint32_t scatter_wgs_per_cu; /* partition workgroups per CU (they split the LDS): 1..8 of 512
+                                    threads in the two-pass form, 1..2 of 1,024 in the single-pass
+                                    form (whose per-tile carry buffers shrink with the LDS share) */
+    uint32_t round_events;       /* events per round of the first partition pass, multiple of 256:
+                                    two-pass form, staged in LDS, at most 4096 (0 = the most that
+                                    fit; the second pass takes the most that fit beside its staging
+                                    copy, at most this, rounded down to whole 512-event batches);
+                                    single-pass form, held in registers, at most 8192 (0 = 8192) */
     uint32_t chunks_per_wg;      /* target (spike, delay) chunks per partition workgroup in the pass of
                                     delays >= 2, 1..64 (the delay-1 pass uses one) */
     uint32_t ahead_passes;       /* two-pass form: the next bin's delay >= 2 fan-in runs as this many
                                     partition passes over consecutive delay groups (smaller passes keep
-                                    their streams cache-resident), 1..max delay - 1; 0 = default */
+                                    their streams cache-resident), 1..max delay - 1; 0 = default; the
+                                    single-pass form always runs one */
 } dbsim_tuning;
 
 /* Reads / sets the schedule (EINVAL if it does not fit the LDS). Takes effect

@@ -60,6 +60,8 @@ def lib():
     L.orc_get_region_signal.argtypes = [c_void_p, POINTER(c_double), POINTER(c_uint32)]
     L.orc_get_state.argtypes = [c_void_p, POINTER(c_double), POINTER(c_double), POINTER(c_int32)]
     L.orc_set_state.argtypes = [c_void_p, POINTER(c_double), POINTER(c_double), POINTER(c_int32)]
+    L.orc_receptor_currents.argtypes = [c_void_p, POINTER(c_double)]
+    L.orc_receptor_currents.restype = None
     L.orc_set_state.restype = c_int
     L.orc_get_in_edges.argtypes = [c_void_p, POINTER(c_uint64), POINTER(c_uint32), POINTER(c_float), POINTER(c_float), POINTER(c_uint8)]
     L.orc_philox4x32_10.argtypes = [POINTER(c_uint32), POINTER(c_uint32), POINTER(c_uint32)]
@@ -176,6 +178,13 @@ class Oracle:
         ref = np.zeros(self.N, np.int32)
         lib().orc_get_state(self._h, _p(V, c_double), _p(J, c_double), _p(ref, c_int32))
         return V, J.reshape(self.U, self.N), ref
+
+    def receptor_currents(self):
+        """[n_pops, 4] mean current per receptor (AMPA, NMDA, GABA_A, GABA_B) of every
+        population at the current state (Suppl. Algorithm 1's measurement)."""
+        out = np.zeros(4 * len(self.spec.pops), np.float64)
+        lib().orc_receptor_currents(self._h, _p(out, c_double))
+        return out.reshape(len(self.spec.pops), 4)
 
     def set_state(self, V, J, ref=None) -> None:
         V = np.ascontiguousarray(V, np.float64)

@@ -384,6 +384,32 @@ static int record_bin(orc* o) {
     return 0;
 }
 
+/* Suppl. Algorithm 1 measures the mean current of each receptor type: per population,
+   the mean over its neurons of g_u J_u (V_u - V) (the same per-receptor term as the region
+   signal), summed in ascending neuron id. */
+void orc_receptor_currents(const orc* o, double* out) {
+    const uint32_t N = o->N, U = o->U, Q = o->d.n_pops;
+    for (uint32_t q = 0; q < 4 * Q; q++) out[q] = 0.0;
+    uint64_t i0 = 0;
+    for (uint32_t q = 0; q < Q; q++) {
+        const orc_pop* P = &o->P[q];
+        const uint64_t i1 = i0 + o->pops[q].size;
+        for (uint32_t u = 0; u < U; u++) {
+            double s = 0.0;
+            for (uint64_t i = i0; i < i1; i++) {
+                if (o->prec == 32) {
+                    const float t = (P->g32[u] * o->J32[(size_t)u * N + i]) * (P->Vu32[u] - o->V32[i]);
+                    s += (double)t;
+                } else {
+                    s += (P->g64[u] * o->J64[(size_t)u * N + i]) * (P->Vu64[u] - o->V64[i]);
+                }
+            }
+            out[(size_t)q * 4 + o->umap[u]] = i1 > i0 ? s / (double)(i1 - i0) : 0.0;
+        }
+        i0 = i1;
+    }
+}
+
 /* Arrival sums for the bin starting at step kS: eq. 3's sum_j w_ij^u A_j
    with A_j taken at bin k - d_ij (pull form of the definition). */
 static uint64_t arrivals(orc* o, uint64_t k, uint32_t i0, uint32_t i1) {

@@ -70,6 +70,13 @@ int orc_set_ou(orc* o, const float* mu, const float* sigma, const float* tau_ms,
 void orc_get_ou(const orc* o, double* I);
 float orc_ou_normal(uint64_t seed, uint32_t net_id, uint64_t n, uint32_t i);
 
+/* Mean synaptic current per receptor of every population at the current state (the
+   measurement step of Suppl. Algorithm 1): out[q*4 + u] = the mean over population q's
+   neurons, in ascending id, of g_u J_u (V_u - V), u in the paper's receptor order (AMPA,
+   NMDA, GABA_A, GABA_B; absent receptors 0). The FP32 oracle evaluates each neuron's term in
+   float (the region signal's expression), the FP64 one in double; sums are in double. */
+void orc_receptor_currents(const orc* o, double* out);
+
 /* Point evaluations for sampled checks of large runs (FP32 oracle):
    arrivals A[t*U+u] due at the start of `bin` for each target, from the given
    spike list (pull form of eq. 3, fixed point), and one Euler step of neuron

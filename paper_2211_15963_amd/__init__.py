@@ -4,6 +4,6 @@ The compute path is the HIP library ``libdbsim.so`` (C ABI in ``include/dbsim.h`
 ``paper_2211_15963_amd.dbsim`` is its ctypes binding. Network descriptions come from
 the seeded generator package ``netgen``.
 """
-from .dbsim import Simulator, DbsimError, footprint, lib  # noqa: F401
+from .dbsim import Built, Simulator, DbsimError, footprint, lib  # noqa: F401
 
-__all__ = ["Simulator", "DbsimError", "footprint", "lib"]
+__all__ = ["Built", "Simulator", "DbsimError", "footprint", "lib"]

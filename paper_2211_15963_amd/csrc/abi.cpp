@@ -101,6 +101,10 @@ struct dbsim {
     hipStream_t cap_stream = nullptr;
     hipStream_t side_stream = nullptr; // the next bin's delay >= 2 fan-in, beside the neuron step
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipStream_t drain_stream = nullptr; // copies each bin's spikes to the pinned host ring
+    hipEvent_t ev_dfork = nullptr, ev_djoin = nullptr;
+    uint32_t* hrec = nullptr;             // pinned host ring of spike entries (host recording)
+    unsigned long long* hbend = nullptr;  // pinned: end offset of bin k at (k + 1) & (HMB - 1)
     unsigned char* dev = nullptr;
     bool static_mem = false; // dev is the device's static region (dbsim_create_static)
     DevNet net{};
@@ -117,6 +121,16 @@ struct dbsim {
     double ms[kPhases] = {0, 0, 0, 0};
     uint64_t timed_bins = 0;
     double build_seconds = 0.0;
+};
+
+// A network built on the host and not yet deployed (dbsim_build -> dbsim_create_built).
+struct dbsim_built {
+    dbsim_desc desc{};
+    Members mem;
+    Plan plan;
+    HostTables ht;
+    double build_seconds = 0.0;
+    bool in_static = false;
 };
 
 namespace {
@@ -152,13 +166,15 @@ void fill_devnet(dbsim* h) {
     n.D = p.D;
     n.F = p.F;
     n.tile_bits = p.tile_bits;
-    n.wc = p.wc ? 1u : 0u;
+    n.blocked = p.blocked ? 1u : 0u;
     n.NS = p.NS;
     n.ts_bits = p.ts_bits;
     n.HW = p.HW;
     n.round_events = p.round_events;
     n.bucket_events = p.bucket_events;
     n.chunks_per_wg = 4;
+    n.fan_K = kFanBlock;
+    n.fan_C = p.blocked ? fan_chunk_records(p, p.scatter_wgs_per_cu) : 0u;
     n.ahead_passes = default_ahead_passes(p);
     n.T = p.T;
     n.n_blocks = p.n_blocks;
@@ -180,6 +196,8 @@ void fill_devnet(dbsim* h) {
     n.hdr = at<const uint32_t>(b, p.hdr);
     n.edge = at<const uint32_t>(b, p.edge);
     n.ev = at<uint32_t>(b, p.ev);
+    n.evk = at<uint16_t>(b, p.evk);
+    n.bcnt = at<uint32_t>(b, p.bcnt);
     n.tile_base = at<const uint64_t>(b, p.tile_base);
     n.tile_fill = at<uint32_t>(b, p.tile_fill);
     n.st_base = at<const uint64_t>(b, p.st_base);
@@ -191,6 +209,10 @@ void fill_devnet(dbsim* h) {
     n.rec = at<uint32_t>(b, p.rec);
     n.bin_start = at<unsigned long long>(b, p.bin_start);
     n.bin_cnt = at<uint32_t>(b, p.bin_cnt);
+    n.hrec = nullptr; // set once the pinned host ring exists
+    n.hbend = nullptr;
+    n.HCmask = p.HC ? p.HC - 1 : 0;
+    n.HMBmask = p.HMB ? p.HMB - 1 : 0;
     n.blk_sig = at<double>(b, p.blk_sig);
     n.blk_cnt = at<uint32_t>(b, p.blk_cnt);
     n.reg_blk_ptr = at<const uint32_t>(b, p.reg_blk_ptr);
@@ -232,7 +254,7 @@ hipError_t enqueue_ahead(dbsim* h, hipStream_t st) {
     // two-pass form: consecutive delay groups, one partition pass (k_part + k_bucket) each,
     // so that one pass's super-tile streams are small enough to stay in the memory-side
     // cache between the partition and its bucketing
-    const uint32_t P = h->plan.wc ? 1u : std::min(h->net.ahead_passes, D - 1);
+    const uint32_t P = h->plan.blocked ? 1u : std::min(h->net.ahead_passes, D - 1);
     hipError_t e = hipSuccess;
     for (uint32_t g = 0; g < P && e == hipSuccess; g++) {
         const uint32_t lo = 2 + (D - 1) * g / P, hi = 1 + (D - 1) * (g + 1) / P;
@@ -244,6 +266,7 @@ hipError_t enqueue_ahead(dbsim* h, hipStream_t st) {
 
 hipError_t enqueue_bin_end(dbsim* h, hipStream_t st) {
     hipError_t e = launch_compact(h->net, st);
+    if (e == hipSuccess && h->plan.host_record) e = launch_drain(h->net, st);
     if (e == hipSuccess) e = enqueue_ahead(h, st);
     if (e != hipSuccess) return e;
     return launch_readout_close(h->net, st);
@@ -261,7 +284,13 @@ hipError_t enqueue_full_bin(dbsim* h, hipStream_t st, hipStream_t side) {
     if (e == hipSuccess && fork) e = hipEventRecord(h->ev_join, side);
     if (e == hipSuccess) e = launch_neuron(h->net, 0, (int)h->plan.S, st);
     if (e == hipSuccess) e = launch_compact(h->net, st);
+    const bool drain = h->plan.host_record;
+    if (e == hipSuccess && drain) e = hipEventRecord(h->ev_dfork, st);
+    if (e == hipSuccess && drain) e = hipStreamWaitEvent(h->drain_stream, h->ev_dfork, 0);
+    if (e == hipSuccess && drain) e = launch_drain(h->net, h->drain_stream);
+    if (e == hipSuccess && drain) e = hipEventRecord(h->ev_djoin, h->drain_stream);
     if (e == hipSuccess && fork) e = hipStreamWaitEvent(st, h->ev_join, 0);
+    if (e == hipSuccess && drain) e = hipStreamWaitEvent(st, h->ev_djoin, 0);
     if (e != hipSuccess) return e;
     return launch_readout_close(h->net, st);
 }
@@ -359,6 +388,15 @@ void release_device(dbsim* h) {
         }
         h->dev = nullptr;
     }
+    if (h->hrec) (void)hipHostFree(h->hrec);
+    if (h->hbend) (void)hipHostFree(h->hbend);
+    h->hrec = nullptr;
+    h->hbend = nullptr;
+    if (h->drain_stream) (void)hipStreamDestroy(h->drain_stream);
+    if (h->ev_dfork) (void)hipEventDestroy(h->ev_dfork);
+    if (h->ev_djoin) (void)hipEventDestroy(h->ev_djoin);
+    h->drain_stream = nullptr;
+    h->ev_dfork = h->ev_djoin = nullptr;
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->side_stream) (void)hipStreamDestroy(h->side_stream);
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
@@ -403,30 +441,80 @@ int dbsim_footprint_ensemble(const dbsim_desc* common, const dbnet_desc* members
     return footprint_impl(common, members, n_members, hbm_bytes);
 }
 
-static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32_t n_members, dbsim** out,
-                       bool in_static = false) {
+// Host phase of the creation: validation, memory plan and every host table (no HIP call, so
+// it may run on any thread while other threads drive the device).
+static int build_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32_t n_members, bool in_static,
+                      dbsim_built** out) {
     if (!desc || !out || !members || n_members == 0) return fail(DBSIM_EINVAL, "null argument or no network");
     *out = nullptr;
     if (desc->dev_alloc && !desc->dev_free) return fail(DBSIM_EINVAL, "dev_alloc given without dev_free");
     if (in_static && desc->dev_alloc)
         return fail(DBSIM_EINVAL, "dbsim_create_static allocates nothing: dev_alloc must be NULL");
-    dbsim* h = nullptr;
+    dbsim_built* b = nullptr;
     try {
-        h = new dbsim();
-        h->desc = *desc;
-        h->mem.assign(members, n_members);
-        h->desc.net = h->mem.m[0];
-        std::string m = make_plan(h->desc, h->mem, h->plan);
+        b = new dbsim_built();
+        b->in_static = in_static;
+        b->desc = *desc;
+        b->mem.assign(members, n_members);
+        b->desc.net = b->mem.m[0];
+        if (in_static) b->desc.flags |= DBSIM_F_NO_HOST_RECORD; // pinned host memory is an allocation
+        std::string m = make_plan(b->desc, b->mem, b->plan);
         if (!m.empty()) {
-            delete h;
+            delete b;
             return fail(DBSIM_EINVAL, m);
         }
-        if (in_static && h->plan.total > (size_t)DBSIM_STATIC_BYTES) {
-            const std::string need = std::to_string(h->plan.total);
-            delete h;
+        if (in_static && b->plan.total > (size_t)DBSIM_STATIC_BYTES) {
+            const std::string need = std::to_string(b->plan.total);
+            delete b;
             return fail(DBSIM_EINVAL, "the network needs " + need + " bytes of device memory; the static region of "
                                       "dbsim_create_static holds " + std::to_string((size_t)DBSIM_STATIC_BYTES));
         }
+        auto t0 = std::chrono::steady_clock::now();
+        m = build_tables(b->mem, b->plan, desc->host_threads, b->ht);
+        if (!m.empty()) {
+            delete b;
+            return fail(DBSIM_EINVAL, m);
+        }
+        b->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        *out = b;
+        return DBSIM_OK;
+    } catch (const std::bad_alloc&) {
+        delete b;
+        return fail(DBSIM_ENOMEM, "host allocation failed while building the network");
+    } catch (...) {
+        delete b;
+        return fail(DBSIM_EINVAL, "unexpected exception while building the network");
+    }
+}
+
+// Device phase: allocation, streams, upload and initial state from a built network, which
+// it consumes. dev_opts (may be NULL) replaces the device, stream and allocator options.
+static int deploy_impl(dbsim_built* bt, const dbsim_desc* dev_opts, dbsim** out) {
+    std::unique_ptr<dbsim_built> own(bt);
+    if (!bt || !out) return fail(DBSIM_EINVAL, "null argument");
+    *out = nullptr;
+    const bool in_static = bt->in_static;
+    dbsim_desc dsc = bt->desc;
+    if (dev_opts) {
+        if (dev_opts->dev_alloc && !dev_opts->dev_free) return fail(DBSIM_EINVAL, "dev_alloc given without dev_free");
+        if (in_static && dev_opts->dev_alloc)
+            return fail(DBSIM_EINVAL, "dbsim_create_static allocates nothing: dev_alloc must be NULL");
+        dsc.device = dev_opts->device;
+        dsc.hip_stream = dev_opts->hip_stream;
+        dsc.dev_alloc = dev_opts->dev_alloc;
+        dsc.dev_free = dev_opts->dev_free;
+        dsc.alloc_ctx = dev_opts->alloc_ctx;
+    }
+    const dbsim_desc* desc = &dsc;
+    dbsim* h = nullptr;
+    try {
+        h = new dbsim();
+        h->desc = dsc;
+        h->mem = std::move(bt->mem);
+        h->plan = std::move(bt->plan);
+        h->desc.net = h->mem.m[0];
+        h->build_seconds = bt->build_seconds;
+        HostTables& ht = bt->ht;
         h->device = desc->device;
         if (h->device < 0 && hipGetDevice(&h->device) != hipSuccess) {
             delete h;
@@ -434,7 +522,6 @@ static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32
         }
         DeviceGuard dg(h->device);
         const Plan& p = h->plan;
-        // device memory first, so an allocation failure costs no build time
         if (in_static) {
             if (h->device >= kStaticDevices) {
                 delete h;
@@ -471,15 +558,6 @@ static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32
             h->dev = (unsigned char*)ptr;
         }
         fill_devnet(h);
-        auto t0 = std::chrono::steady_clock::now();
-        HostTables ht;
-        m = build_tables(h->mem, p, desc->host_threads, ht);
-        if (!m.empty()) {
-            release_device(h);
-            delete h;
-            return fail(DBSIM_EINVAL, m);
-        }
-        h->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         // streams (a handle in the static region creates none: its bins run on the caller's
         // stream, or the default stream, one kernel after another)
         if (in_static) {
@@ -500,10 +578,29 @@ static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32
             if (se == hipSuccess) se = hipStreamCreateWithFlags(&h->side_stream, hipStreamNonBlocking);
             if (se == hipSuccess) se = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
             if (se == hipSuccess) se = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming);
+            if (se == hipSuccess && p.host_record) {
+                // the recording ring: pinned, coherent host memory the drain kernel writes
+                void *a = nullptr, *b = nullptr, *da = nullptr, *db = nullptr;
+                se = hipHostMalloc(&a, 4 * (size_t)p.HC, hipHostMallocCoherent);
+                if (se == hipSuccess) h->hrec = static_cast<uint32_t*>(a);
+                if (se == hipSuccess) se = hipHostMalloc(&b, 8 * (size_t)p.HMB, hipHostMallocCoherent);
+                if (se == hipSuccess) h->hbend = static_cast<unsigned long long*>(b);
+                if (se == hipSuccess) std::memset(h->hbend, 0, 8 * (size_t)p.HMB);
+                if (se == hipSuccess) se = hipHostGetDevicePointer(&da, a, 0);
+                if (se == hipSuccess) se = hipHostGetDevicePointer(&db, b, 0);
+                if (se == hipSuccess) {
+                    h->net.hrec = static_cast<uint32_t*>(da);
+                    h->net.hbend = static_cast<unsigned long long*>(db);
+                }
+                if (se == hipSuccess) se = hipStreamCreateWithFlags(&h->drain_stream, hipStreamNonBlocking);
+                if (se == hipSuccess) se = hipEventCreateWithFlags(&h->ev_dfork, hipEventDisableTiming);
+                if (se == hipSuccess) se = hipEventCreateWithFlags(&h->ev_djoin, hipEventDisableTiming);
+            }
             if (se != hipSuccess) {
                 release_device(h);
                 delete h;
-                return fail(DBSIM_EDEVICE, std::string("stream/event creation: ") + hipGetErrorString(se));
+                return fail(DBSIM_EDEVICE, std::string("stream/event creation or pinned host ring: ") +
+                                                hipGetErrorString(se));
             }
         }
         // upload
@@ -557,7 +654,7 @@ static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) h->num_cus = prop.multiProcessorCount;
         h->scatter_wgs = p.scatter_wgs_per_cu;
-        h->scatter_grid = std::min((int)kMaxPartGrid, (int)h->scatter_wgs * h->num_cus);
+        h->scatter_grid = std::min((int)(p.blocked ? kFanMaxGrid : kMaxPartGrid), (int)h->scatter_wgs * h->num_cus);
         *out = h;
         return DBSIM_OK;
     } catch (const std::bad_alloc&) {
@@ -571,8 +668,19 @@ static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32
             release_device(h);
             delete h;
         }
-        return fail(DBSIM_EINVAL, "unexpected exception in dbsim_create");
+        return fail(DBSIM_EINVAL, "unexpected exception while deploying the network");
     }
+}
+
+
+static int create_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32_t n_members, dbsim** out,
+                       bool in_static = false) {
+    if (!out) return fail(DBSIM_EINVAL, "null argument");
+    *out = nullptr;
+    dbsim_built* b = nullptr;
+    const int rc = build_impl(desc, members, n_members, in_static, &b);
+    if (rc) return rc;
+    return deploy_impl(b, nullptr, out);
 }
 
 static void to_constants(const Members& mem, const Plan& p, const std::vector<PopParams>& pops,
@@ -637,6 +745,17 @@ int dbsim_create_static(const dbsim_desc* desc, dbsim** out) {
     return create_impl(desc, &desc->net, 1, out, true);
 }
 
+int dbsim_build(const dbsim_desc* desc, dbsim_built** out) {
+    if (!desc) return fail(DBSIM_EINVAL, "null argument");
+    return build_impl(desc, &desc->net, 1, false, out);
+}
+
+int dbsim_create_built(dbsim_built* b, const dbsim_desc* device_opts, dbsim** out) {
+    return deploy_impl(b, device_opts, out);
+}
+
+void dbsim_built_free(dbsim_built* b) { delete b; }
+
 int dbsim_create_ensemble(const dbsim_desc* common, const dbnet_desc* members, uint32_t n_members, dbsim** out) {
     return create_impl(common, members, n_members, out);
 }
@@ -665,7 +784,7 @@ int dbsim_get_info(dbsim* h, dbsim_info* info) {
     info->n_tiles = p.T;
     info->frac_bits = p.F;
     info->n_members = p.n_members;
-    info->fanin_passes = p.wc ? 1u : 2u;
+    info->fanin_passes = p.blocked ? 1u : 2u;
     return DBSIM_OK;
 }
 
@@ -696,6 +815,7 @@ int dbsim_step(dbsim* h, uint64_t n_steps) {
                         HIPCHK(h, launch_neuron(h->net, 0, (int)S, st), "neuron launch");
                         HIPCHK(h, hipEventRecord(ev[3], st), "hipEventRecord");
                         HIPCHK(h, launch_compact(h->net, st), "compact launch");
+                        if (h->plan.host_record) HIPCHK(h, launch_drain(h->net, st), "recording launch");
                         HIPCHK(h, hipEventRecord(ev[4], st), "hipEventRecord");
                         HIPCHK(h, enqueue_ahead(h, st), "partition launch");
                         HIPCHK(h, hipEventRecord(ev[5], st), "hipEventRecord");
@@ -751,31 +871,46 @@ int dbsim_read_spikes(dbsim* h, uint64_t step_lo, uint64_t step_hi, uint64_t* st
     *n_out = 0;
     if (step_lo >= step_hi) return DBSIM_OK;
     const uint64_t b_lo = step_lo / S, b_hi = (step_hi + S - 1) / S;
-    if (done_bins - b_lo > p.MB - 1) return fail(DBSIM_ERANGE, "requested bins have left the device history");
-    std::vector<unsigned long long> bstart(p.MB);
-    std::vector<uint32_t> bcnt(p.MB);
-    HIPCHK(h, hipMemcpy(bstart.data(), h->net.bin_start, 8 * (size_t)p.MB, hipMemcpyDeviceToHost), "hipMemcpy");
-    HIPCHK(h, hipMemcpy(bcnt.data(), h->net.bin_cnt, 4 * (size_t)p.MB, hipMemcpyDeviceToHost), "hipMemcpy");
-    const uint64_t head = bstart[done_bins & (p.MB - 1)];
-    const uint64_t first = bstart[b_lo & (p.MB - 1)];
-    if (head - first > p.RC) return fail(DBSIM_ERANGE, "requested spikes have been overwritten in the device ring");
-    std::vector<uint32_t> raw(head - first);
-    uint64_t a = first & (p.RC - 1), left = head - first, o = 0;
-    while (left) {
-        const uint64_t n = std::min(left, p.RC - a);
-        HIPCHK(h, hipMemcpy(raw.data() + o, h->net.rec + a, 4 * n, hipMemcpyDeviceToHost), "hipMemcpy");
-        o += n;
-        left -= n;
-        a = 0;
-    }
     std::vector<std::pair<uint64_t, uint32_t>> out;
-    for (uint64_t b = b_lo; b < b_hi; b++) {
-        const uint64_t s = bstart[b & (p.MB - 1)] - first;
-        const uint32_t c = bcnt[b & (p.MB - 1)];
-        for (uint32_t x = 0; x < c; x++) {
-            const uint32_t v = raw[s + x];
-            const uint64_t st = b * S + (v & 15u);
-            if (st >= step_lo && st < step_hi) out.emplace_back(st, v >> 4);
+    if (p.host_record) { // the pinned host ring, complete up to the last synchronised bin
+        if (done_bins - b_lo > p.HMB - 1) return fail(DBSIM_ERANGE, "requested bins have left the host record");
+        const uint64_t hm = p.HMB - 1, cm = p.HC - 1;
+        const uint64_t head = h->hbend[done_bins & hm], first = h->hbend[b_lo & hm];
+        if (head - first > p.HC) return fail(DBSIM_ERANGE, "requested spikes have been overwritten in the host record");
+        for (uint64_t b = b_lo; b < b_hi; b++) {
+            const uint64_t s0 = h->hbend[b & hm], s1 = h->hbend[(b + 1) & hm];
+            for (uint64_t o = s0; o < s1; o++) {
+                const uint32_t v = h->hrec[o & cm];
+                const uint64_t st = b * S + (v & 15u);
+                if (st >= step_lo && st < step_hi) out.emplace_back(st, v >> 4);
+            }
+        }
+    } else {
+        if (done_bins - b_lo > p.MB - 1) return fail(DBSIM_ERANGE, "requested bins have left the device history");
+        std::vector<unsigned long long> bstart(p.MB);
+        std::vector<uint32_t> bcnt(p.MB);
+        HIPCHK(h, hipMemcpy(bstart.data(), h->net.bin_start, 8 * (size_t)p.MB, hipMemcpyDeviceToHost), "hipMemcpy");
+        HIPCHK(h, hipMemcpy(bcnt.data(), h->net.bin_cnt, 4 * (size_t)p.MB, hipMemcpyDeviceToHost), "hipMemcpy");
+        const uint64_t head = bstart[done_bins & (p.MB - 1)];
+        const uint64_t first = bstart[b_lo & (p.MB - 1)];
+        if (head - first > p.RC) return fail(DBSIM_ERANGE, "requested spikes have been overwritten in the device ring");
+        std::vector<uint32_t> raw(head - first);
+        uint64_t a = first & (p.RC - 1), left = head - first, o = 0;
+        while (left) {
+            const uint64_t n = std::min(left, p.RC - a);
+            HIPCHK(h, hipMemcpy(raw.data() + o, h->net.rec + a, 4 * n, hipMemcpyDeviceToHost), "hipMemcpy");
+            o += n;
+            left -= n;
+            a = 0;
+        }
+        for (uint64_t b = b_lo; b < b_hi; b++) {
+            const uint64_t s = bstart[b & (p.MB - 1)] - first;
+            const uint32_t c = bcnt[b & (p.MB - 1)];
+            for (uint32_t x = 0; x < c; x++) {
+                const uint32_t v = raw[s + x];
+                const uint64_t st = b * S + (v & 15u);
+                if (st >= step_lo && st < step_hi) out.emplace_back(st, v >> 4);
+            }
         }
     }
     std::sort(out.begin(), out.end());
@@ -835,6 +970,23 @@ int dbsim_read_state(dbsim* h, float* V, float* J, int32_t* ref) {
     return DBSIM_OK;
 }
 
+int dbsim_receptor_currents(dbsim* h, double* mean, uint32_t n_pops) {
+    int rc = check_usable(h);
+    if (rc) return rc;
+    if (!mean) return fail(DBSIM_EINVAL, "mean is NULL");
+    const Plan& p = h->plan;
+    if (n_pops != p.n_pops) return fail(DBSIM_EINVAL, "n_pops does not match the handle's population count");
+    DeviceGuard dg(h->device);
+    rc = sync_and_check(h);
+    if (rc) return rc;
+    double* rblk = at<double>(h->dev, p.rblk);
+    double* rpop = at<double>(h->dev, p.rpop);
+    HIPCHK(h, launch_receptor_currents(h->net, p.n_pops, rblk, rpop, h->stream), "receptor current launch");
+    HIPCHK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    HIPCHK(h, hipMemcpy(mean, rpop, 8 * 4 * (size_t)p.n_pops, hipMemcpyDeviceToHost), "hipMemcpy");
+    return DBSIM_OK;
+}
+
 int dbsim_write_state(dbsim* h, const float* V, const float* J, const int32_t* ref) {
     int rc = check_usable(h);
     if (rc) return rc;
@@ -878,11 +1030,11 @@ int dbsim_export_csr(dbsim* h, uint64_t* row_ptr, uint32_t* seg, uint32_t* tgt, 
         const size_t RW = 1 + p.KW;
         std::vector<uint32_t> rec((size_t)p.E * RW);
         HIPCHK(h, hipMemcpy(rec.data(), h->net.edge, 4 * rec.size(), hipMemcpyDeviceToHost), "hipMemcpy");
-        for (uint64_t e = 0; e < p.E; e++) {
-            if (tgt) tgt[e] = rec[e * RW] & 0x7FFFFFFFu; // bit 31: the source is inhibitory
-            if (w0) std::memcpy(&w0[e], &rec[e * RW + 1], 4);
+        for (uint64_t e = 0; e < p.E; e++) { // weights first, then the target
+            if (tgt) tgt[e] = rec[e * RW + p.KW] & 0x7FFFFFFFu; // bit 31: the source is inhibitory
+            if (w0) std::memcpy(&w0[e], &rec[e * RW], 4);
             if (w1) {
-                if (p.KW == 2) std::memcpy(&w1[e], &rec[e * RW + 2], 4);
+                if (p.KW == 2) std::memcpy(&w1[e], &rec[e * RW + 1], 4);
                 else w1[e] = 0.0f;
             }
         }
@@ -1098,7 +1250,7 @@ int dbsim_get_tuning(dbsim* h, dbsim_tuning* t) {
     t->scatter_wgs_per_cu = h->scatter_wgs;
     t->round_events = h->net.round_events;
     t->chunks_per_wg = h->net.chunks_per_wg;
-    t->ahead_passes = h->net.ahead_passes;
+    t->ahead_passes = h->plan.blocked ? 1u : h->net.ahead_passes;
     return DBSIM_OK;
 }
 
@@ -1107,6 +1259,11 @@ int dbsim_set_tuning(dbsim* h, const dbsim_tuning* t) {
     if (rc) return rc;
     if (!t) return fail(DBSIM_EINVAL, "null argument");
     if (t->scatter_wgs_per_cu < 1 || t->scatter_wgs_per_cu > 8) return fail(DBSIM_EINVAL, "scatter_wgs_per_cu must lie in 1..8");
+    const bool blocked = h->plan.blocked;
+    // single pass: workgroups of kFanThreads threads, at most two per CU, whose carry buffers fit
+    const uint32_t fan_c = blocked ? fan_chunk_records(h->plan, t->scatter_wgs_per_cu) : 0u;
+    if (blocked && (t->scatter_wgs_per_cu > 2 || fan_c == 0))
+        return fail(DBSIM_EINVAL, "this schedule does not fit the LDS (single pass: 1 or 2 workgroups per CU)");
     if (t->chunks_per_wg < 1 || t->chunks_per_wg > 64) return fail(DBSIM_EINVAL, "chunks_per_wg must lie in 1..64");
     const uint32_t pmax = std::max(1u, h->plan.D - 1);
     if (t->ahead_passes > pmax) return fail(DBSIM_EINVAL, "ahead_passes must lie in 0..max delay - 1");
@@ -1119,7 +1276,8 @@ int dbsim_set_tuning(dbsim* h, const dbsim_tuning* t) {
     rc = sync_and_check(h);
     if (rc) return rc;
     h->scatter_wgs = t->scatter_wgs_per_cu;
-    h->scatter_grid = std::min((int)kMaxPartGrid, (int)h->scatter_wgs * h->num_cus);
+    h->scatter_grid = std::min((int)(blocked ? kFanMaxGrid : kMaxPartGrid), (int)h->scatter_wgs * h->num_cus);
+    h->net.fan_C = fan_c;
     h->net.round_events = re;
     h->net.bucket_events = std::min(bmax, std::max<uint32_t>(re / kScatterThreads, 1u) * kScatterThreads);
     h->net.chunks_per_wg = t->chunks_per_wg;

@@ -10,20 +10,24 @@
 //     uniform (scalar registers);
 //   connection table by presynaptic neuron (Suppl. Table 5's table is stored
 //     by target; the push-based fan-out of Suppl. Algorithm 2 wants it by
-//     source): one record of 1 + KW words per edge (target | source class << 31,
-//     then the weights: the record is already the fan-in's event key),
+//     source): one record of 1 + KW words per edge (the weights, then target |
+//     source class << 31, the fan-in's event key; weights first, so a whole-record
+//     load puts them in an aligned register pair),
 //     so that a (spike, delay) segment is one contiguous run; rows sorted by
 //     delay, then target; one row header per neuron, hdr u32[N][HW]
 //     (HW = D + 3 rounded up to 4 words: the row start as u64 with the source
 //     class in bit 63, then the D + 1 delay segment offsets inside the row), so
 //     that one 64-byte read gives everything a (spike, delay) segment needs;
-//   the event arena of the fan-in: records of 1 + KW words (target | source
-//     class << 31, then the weights); tile t owns the slice tile_base[t] ..
-//     tile_base[t+1]: the tile's total in-degree (the most events a tile can
-//     receive in one bin: an edge delivers at most once per bin), plus, when
-//     k_part writes whole chunks, kChunk records of padding per partition
-//     workgroup and partition launch (two per bin); the super-tile streams of
-//     the two-pass form use the same record format;
+//   the event arena of the fan-in, sized by each tile's total in-degree (the most
+//     events a tile can receive in one bin: an edge delivers at most once per bin).
+//     Single-pass form (the tiles' carry buffers fit a workgroup's LDS): blocks of
+//     kFanBlock records, a 16-bit key array (target within the tile | inhibitory
+//     source << 15) beside the weights; tile t owns blocks tile_base[t] ..
+//     tile_base[t+1]: its in-degree in whole blocks plus two part-filled blocks per
+//     workgroup and bin (each workgroup and pass leaves at most one). Two-pass
+//     form: records of 1 + KW words (target | source class << 31, then the
+//     weights) in slice tile_base[t] .. tile_base[t+1]; the super-tile streams
+//     use the same record format;
 //   spike history: rec u32[RC] ring of (id << 4 | substep), per-bin start u64[MB]
 //     and count u32[MB] (rings indexed by bin & (MB-1));
 //   region readout: per-block partial sums f64/u32, per-region block lists,
@@ -53,9 +57,12 @@ constexpr uint32_t kErrLayout = 2u;   // a table entry outside its tile group (c
 constexpr uint32_t kMaxSuperTiles = 64; // buckets of the first partition pass
 constexpr uint32_t kBoldRing = 1024;     // BOLD samples kept per region (power of two)
 constexpr int kLoadBatch = 8;          // gather: records loaded per thread before they are consumed
-constexpr int kMaxBatch = 8;           // partition: events per thread per round (round_events <= 4096)
-constexpr uint32_t kChunk = 16;        // records per write-combined tile chunk (192 B with two weights)
-constexpr uint32_t kMaxPartGrid = 2048; // most partition workgroups (bounds the chunk padding per tile)
+constexpr int kMaxBatch = 8;           // partition: events per thread per round
+constexpr uint32_t kMaxPartGrid = 2048; // most partition workgroups
+constexpr int kFanThreads = 1024;       // threads per workgroup of the single-pass fan-in
+constexpr uint32_t kFanBlock = 256;     // records per block of the single-pass event arena
+constexpr uint32_t kFanMaxGrid = 512;   // most single-pass workgroups (bounds the part-filled blocks)
+constexpr uint32_t kFanMinChunk = 4, kFanMaxChunk = 64; // records per carry buffer (power of two)
 constexpr uint32_t kMaxLdsBytes = 160u * 1024u;
 constexpr uint32_t kStaticLds = 1024u; // room left per workgroup for the kernels' static LDS
 
@@ -93,14 +100,16 @@ struct Ctl {
 struct DevNet {
     uint32_t N, U, KW, S, D, F;
     uint32_t tile_bits, T, n_blocks, n_regions;
-    uint32_t wc;           // 1: k_part writes the tiles directly (write-combined chunks)
-    uint32_t NS;           // super-tiles (buckets of k_part when wc == 0)
+    uint32_t blocked;      // 1: single-pass fan-in (k_fan into tile blocks), 0: two passes
+    uint32_t NS;           // super-tiles (buckets of k_part in the two-pass form; 0 otherwise)
     uint32_t ts_bits;      // log2(tiles per super-tile)
     uint32_t HW;           // words per row header
     uint32_t round_events; // events staged in LDS per partition round (k_part)
     uint32_t bucket_events; // events per round of the second pass (k_bucket)
     uint32_t chunks_per_wg; // target scatter chunks per workgroup and bin
     uint32_t ahead_passes;  // partition passes of the next bin's delay >= 2 fan-in (two-pass form)
+    uint32_t fan_C;         // single-pass form: records per carry buffer
+    uint32_t fan_K;         // single-pass form: records per block
     uint64_t RCmask;
     uint32_t MBmask;
     double qscale;   // 2^F
@@ -119,9 +128,15 @@ struct DevNet {
     const uint2* blk; // (first neuron, population)
     // connection table
     const uint32_t* hdr;  // [N][HW] row headers
-    const uint32_t* edge; // [E][1 + KW] records: target | inhibitory source << 31, then the weights
-    // event arena: records of (1 + KW) words: target within tile | source class << 31, weights
+    const uint32_t* edge; // [E][1 + KW] records: the weights, then target | inhibitory source << 31
+    // event arena. Two-pass form: records of (1 + KW) words (target | source class << 31,
+    // weights), tile t's slice tile_base[t] .. tile_base[t+1], tile_fill[t] records this bin.
+    // Single-pass form: blocks of fan_K records, keys evk (target within tile | inhibitory
+    // source << 15) beside the weights ev (KW floats per record); tile t owns blocks
+    // tile_base[t] .. tile_base[t+1], tile_fill[t] of them taken this bin, bcnt[b] records in b.
     uint32_t* ev;
+    uint16_t* evk;
+    uint32_t* bcnt;
     const uint64_t* tile_base;
     uint32_t* tile_fill;
     const uint64_t* st_base; // super-tile stream slices [NS + 1]
@@ -135,6 +150,12 @@ struct DevNet {
     uint32_t* rec;
     unsigned long long* bin_start;
     uint32_t* bin_cnt;
+    // host recording (pinned host memory, written by k_drain): ring of spike entries at the
+    // same offsets as rec (mod HCmask + 1), and the end offset of every bin k at (k + 1) & HMBmask
+    uint32_t* hrec;
+    unsigned long long* hbend;
+    uint64_t HCmask;
+    uint32_t HMBmask;
     // regions
     double* blk_sig;
     uint32_t* blk_cnt;
@@ -166,8 +187,13 @@ hipError_t launch_gather(const DevNet& n, hipStream_t st);
 hipError_t launch_pass_reset(const DevNet& n, hipStream_t st);
 hipError_t launch_neuron(const DevNet& n, int s0, int s1, hipStream_t st);
 hipError_t launch_compact(const DevNet& n, hipStream_t st);
+hipError_t launch_drain(const DevNet& n, hipStream_t st);
+// per-population mean current per receptor at the current state: rblk [n_blocks][4] scratch,
+// rpop [n_pops][4] result (paper receptor order)
+hipError_t launch_receptor_currents(const DevNet& n, uint32_t n_pops, double* rblk, double* rpop, hipStream_t st);
 hipError_t launch_readout_close(const DevNet& n, hipStream_t st);
-size_t part_lds_bytes(uint32_t nb, uint32_t RE, bool wc, uint32_t D);
+size_t part_lds_bytes(uint32_t nb, uint32_t RE, uint32_t D);
+size_t fan_lds_bytes(uint32_t T, uint32_t C, uint32_t KW, uint32_t D);
 size_t bucket_lds_bytes(uint32_t TS, uint32_t RE);
 size_t gather_lds_bytes(const DevNet& n);
 

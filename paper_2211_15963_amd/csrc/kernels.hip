@@ -42,11 +42,12 @@ namespace {
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
-// Exclusive prefix sum over a partition workgroup (kScatterThreads threads); *total receives
-// the block sum.
+// Exclusive prefix sum over a workgroup of NT threads (NT <= 1024); *total receives the block
+// sum. s_wave holds NT / 64 words.
+template <int NT = kScatterThreads>
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_wave, uint32_t* total) {
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
-    const uint32_t nw = kScatterThreads >> 6;
+    constexpr uint32_t nw = NT >> 6;
     uint32_t x = v;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -149,31 +150,15 @@ struct RoundLayout {
     }
 };
 
-// write-combining buffers: per bucket up to kChunk - 1 events carried between rounds
-struct WcLayout {
-    size_t bufw, bufk, bcnt, bc, cpre, cmap;
-    __host__ __device__ void place(LdsLayout& L, uint32_t nb, uint32_t RE) {
-        bufw = L.take(8 * (size_t)kChunk * nb, 8);
-        bufk = L.take(4 * (size_t)kChunk * nb, 4);
-        bcnt = L.take(4 * (size_t)nb, 4);
-        bc = L.take(4 * (size_t)nb, 4);
-        cpre = L.take(4 * ((size_t)nb + 1), 4);
-        cmap = L.take(2 * (2 * (size_t)nb + RE / kChunk + 1), 2);
-    }
-};
-
 struct PartLayout {
     size_t dpre, dstart, sstart, spre, dcnt, smap, total;
     RoundLayout r;
-    WcLayout w;
-    __host__ __device__ PartLayout(uint32_t nb, uint32_t RE, bool wc, uint32_t D) {
+    __host__ __device__ PartLayout(uint32_t nb, uint32_t RE, uint32_t D) {
         LdsLayout L;
         dpre = L.take(8 * ((size_t)D + 1), 8);
         dstart = L.take(8 * (size_t)D, 8);
         sstart = L.take(8 * kScatterSegs, 8);
         r.place(L, nb, RE);
-        w = WcLayout{};
-        if (wc) w.place(L, nb, RE);
         spre = L.take(4 * (kScatterSegs + 4), 4);
         dcnt = L.take(4 * ((size_t)D + 1), 4);
         smap = L.take(2 * (kScatterSegs + 2), 2);
@@ -210,23 +195,6 @@ struct Round {
         hist = reinterpret_cast<uint32_t*>(base + l.hist);
         lstart = reinterpret_cast<uint32_t*>(base + l.lstart);
         s_wave = reinterpret_cast<uint32_t*>(base + l.s_wave);
-    }
-};
-
-struct Wc {
-    float2* bufw;    // [nb][kChunk] carried weights
-    uint32_t* bufk;  // [nb][kChunk] carried keys
-    uint32_t* bcnt;  // carried events per bucket
-    uint32_t* bc;    // carried events at the start of the round
-    uint32_t* cpre;  // chunks emitted per bucket this round, exclusive prefix [nb + 1]
-    uint16_t* cmap;  // bucket of every chunk emitted this round
-    __device__ void at(unsigned char* base, const WcLayout& l) {
-        bufw = reinterpret_cast<float2*>(base + l.bufw);
-        bufk = reinterpret_cast<uint32_t*>(base + l.bufk);
-        bcnt = reinterpret_cast<uint32_t*>(base + l.bcnt);
-        bc = reinterpret_cast<uint32_t*>(base + l.bc);
-        cpre = reinterpret_cast<uint32_t*>(base + l.cpre);
-        cmap = reinterpret_cast<uint16_t*>(base + l.cmap);
     }
 };
 
@@ -335,80 +303,6 @@ __device__ void write_runs(const DevNet& net, Round& R, uint32_t ne, uint32_t nb
     __syncthreads();
 }
 
-// Write-combined tile output, first half: per tile, the carried events plus this round's
-// form whole chunks of kChunk records (on the final call the last partial chunk is
-// padded); one reservation of all of a tile's chunks in tile_fill, the sorted starts and
-// the chunk -> tile map.
-__device__ void wc_reserve(const DevNet& net, Round& R, Wc& W, uint32_t nb, bool final) {
-    const uint32_t tid = threadIdx.x;
-    for (uint32_t t = tid; t < nb; t += kScatterThreads) {
-        const uint32_t c = W.bcnt[t], h = R.hist[t], tot = c + h;
-        const uint32_t f = final ? (tot + kChunk - 1) / kChunk : tot / kChunk;
-        unsigned long long gb = ~0ull;
-        if (f) {
-            const uint32_t base = atomicAdd(&net.tile_fill[t], f * kChunk);
-            const unsigned long long s0 = net.tile_base[t];
-            if ((unsigned long long)base + f * kChunk <= net.tile_base[t + 1] - s0) gb = s0 + base;
-            else atomicOr(&net.ctl->err, kErrArena);
-        }
-        R.gbase[t] = gb;
-        R.lstart[t] = h;
-        W.bc[t] = c;
-        W.cpre[t] = f;
-    }
-    __syncthreads();
-    block_scan_inplace(R.lstart, nb, R.s_wave);
-    __syncthreads();
-    const uint32_t nch = block_scan_inplace(W.cpre, nb, R.s_wave);
-    if (tid == 0) W.cpre[nb] = nch;
-    __syncthreads();
-    for (uint32_t t = tid; t < nb; t += kScatterThreads)
-        for (uint32_t i = W.cpre[t]; i < W.cpre[t + 1]; i++) W.cmap[i] = (uint16_t)t;
-    __syncthreads();
-}
-
-// Second half, after the round's events are placed: every chunk is written by kChunk
-// consecutive threads (carried records first, then the tile's sorted events, then zero
-// padding, which adds nothing to any sum); the events left over go to the carry buffers.
-template <int KW>
-__device__ void wc_write(const DevNet& net, Round& R, Wc& W, uint32_t ne, uint32_t nb, uint32_t bshift, bool final) {
-    const uint32_t tid = threadIdx.x;
-    const uint32_t nch = W.cpre[nb];
-    for (uint32_t x = tid; x < nch * kChunk; x += kScatterThreads) {
-        const uint32_t ch = x / kChunk, slot = x % kChunk;
-        const uint32_t b = W.cmap[ch];
-        const uint32_t local = (ch - W.cpre[b]) * kChunk + slot, c = W.bc[b];
-        uint32_t key = 0u;
-        float2 w = make_float2(0.0f, 0.0f);
-        if (local < c) {
-            key = W.bufk[b * kChunk + local];
-            w = W.bufw[b * kChunk + local];
-        } else if (local - c < R.hist[b]) {
-            const uint32_t q = R.lstart[b] + (local - c);
-            key = R.s_key[q];
-            w = R.s_w[q];
-        }
-        const unsigned long long gb = R.gbase[b];
-        if (gb != ~0ull) store_record<KW>(net.ev, gb + local, key, w);
-    }
-    __syncthreads();
-    if (!final) {
-        for (uint32_t q = tid; q < ne; q += kScatterThreads) {
-            const uint32_t key = R.s_key[q];
-            const uint32_t b = bucket_of(net, key, nb, 0, bshift);
-            const uint32_t local = W.bc[b] + (q - R.lstart[b]);
-            const uint32_t full = (W.cpre[b + 1] - W.cpre[b]) * kChunk;
-            if (local >= full) {
-                W.bufk[b * kChunk + (local - full)] = key;
-                W.bufw[b * kChunk + (local - full)] = R.s_w[q];
-            }
-        }
-    }
-    for (uint32_t t = tid; t < nb; t += kScatterThreads)
-        W.bcnt[t] = final ? 0u : W.bc[t] + R.hist[t] - (W.cpre[t + 1] - W.cpre[t]) * kChunk;
-    __syncthreads();
-}
-
 } // namespace
 
 // The fan-in of the arrivals due at the start of bin k: the delay-d segments of the rows of
@@ -416,23 +310,19 @@ __device__ void wc_write(const DevNet& net, Round& R, Wc& W, uint32_t ne, uint32
 // (read whole, so the table reads are contiguous) and process them in rounds of up to
 // round_events events: each thread loads its events into registers, ranks them by bucket
 // with LDS counters, the round is placed in LDS sorted by bucket and written out.
-// wc != 0: the buckets are the tiles, written as whole chunks through the carry buffers.
-// wc == 0: the buckets are the super-tile streams (runs), re-bucketed by k_bucket.
-template <int KW, bool WC>
+// The buckets are the super-tile streams (runs), re-bucketed by k_bucket.
+template <int KW>
 __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d_lo, uint32_t d_hi, uint32_t ahead) {
     extern __shared__ __align__(16) unsigned char dyn[];
     const uint32_t D = net.D, RE = net.round_events;
-    constexpr bool wc = WC; // the form is fixed per network; one instantiation each
-    const uint32_t nb = wc ? net.T : net.NS;
-    const PartLayout L(nb, RE, wc, D);
+    const uint32_t nb = net.NS;
+    const PartLayout L(nb, RE, D);
     unsigned long long* s_dpre = reinterpret_cast<unsigned long long*>(dyn + L.dpre);
     unsigned long long* s_dstart = reinterpret_cast<unsigned long long*>(dyn + L.dstart);
     unsigned long long* s_sstart = reinterpret_cast<unsigned long long*>(dyn + L.sstart);
     uint32_t* s_spre = reinterpret_cast<uint32_t*>(dyn + L.spre);
     Round R;
     R.at(dyn, L.r);
-    Wc W{};
-    if constexpr (wc) W.at(dyn, L.w);
 
     uint32_t* s_dcnt = reinterpret_cast<uint32_t*>(dyn + L.dcnt);
     uint16_t* s_map = reinterpret_cast<uint16_t*>(dyn + L.smap);
@@ -460,8 +350,6 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
         for (uint32_t y = 0; y < x; y++) tot += s_dcnt[y];
         s_dpre[x] = tot;
     }
-    if (wc)
-        for (uint32_t t = tid; t < nb; t += kScatterThreads) W.bcnt[t] = 0u;
     __syncthreads();
     const unsigned long long total = s_dpre[D];
     if (total == 0) return;
@@ -471,7 +359,7 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
     const unsigned long long cw = (unsigned long long)(ahead ? net.chunks_per_wg : 1u) * G;
     const uint32_t spc = (uint32_t)min((unsigned long long)kScatterSegs, max(32ull, (total + cw - 1) / cw));
     const unsigned long long nchunks = (total + spc - 1) / spc;
-    const uint32_t bshift = wc ? net.tile_bits : net.tile_bits + net.ts_bits;
+    const uint32_t bshift = net.tile_bits + net.ts_bits;
     unsigned long long my_events = 0;
     // the first chunk of every workgroup is fixed, the others are handed out through a
     // counter (a workgroup that starts late, behind another kernel's workgroups, takes
@@ -531,14 +419,14 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
                     const uint32_t lo = s_map[m], hi = m + 1 < nmap ? s_map[m + 1] : nseg - 1;
                     const uint32_t sg = lo + seg_search(s_spre + lo, hi - lo + 1, ge);
                     const unsigned long long edge = s_sstart[sg] + (ge - s_spre[sg]);
-                    if (KW == 2) {
+                    if (KW == 2) { // weights, then target | source class << 31
                         const uint3 r = reinterpret_cast<const uint3*>(net.edge)[edge];
-                        B.key[u] = r.x; // target | source class << 31
-                        B.w[u] = make_float2(__uint_as_float(r.y), __uint_as_float(r.z));
+                        B.key[u] = r.z;
+                        B.w[u] = make_float2(__uint_as_float(r.x), __uint_as_float(r.y));
                     } else {
                         const uint2 r = reinterpret_cast<const uint2*>(net.edge)[edge];
-                        B.key[u] = r.x;
-                        B.w[u] = make_float2(__uint_as_float(r.y), 0.0f);
+                        B.key[u] = r.y;
+                        B.w[u] = make_float2(__uint_as_float(r.x), 0.0f);
                     }
                 }
             }
@@ -550,13 +438,11 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
             // reservations (one wait for both)
             unsigned long long claim = 0;
             if (tid == 0 && r0 == 0) claim = atomicAdd(&net.ctl->pnext, 1ull);
-            if constexpr (wc) wc_reserve(net, R, W, nb, false);
-            else reserve_runs(net, R, nb, 0, net.st_base, net.st_fill);
+            reserve_runs(net, R, nb, 0, net.st_base, net.st_fill);
             place_batch(R, B, ne, nbt);
             if (tid == 0 && r0 == 0) s_pc = G + claim; // read by every thread at the end of the chunk
             __syncthreads();
-            if constexpr (wc) wc_write<KW>(net, R, W, ne, nb, bshift, false);
-            else write_runs<KW>(net, R, ne, nb, 0, bshift, net.sev);
+            write_runs<KW>(net, R, ne, nb, 0, bshift, net.sev);
         }
         if (ec == 0) { // no round: claim here
             if (tid == 0) s_pc = G + atomicAdd(&net.ctl->pnext, 1ull);
@@ -564,12 +450,6 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
         }
         my_events += ec;
         c = s_pc;
-    }
-    if constexpr (wc) { // the carried events of every tile, as padded chunks
-        for (uint32_t t = tid; t < nb; t += kScatterThreads) R.hist[t] = 0;
-        __syncthreads();
-        wc_reserve(net, R, W, nb, true);
-        wc_write<KW>(net, R, W, 0, nb, bshift, true);
     }
     // events count as delivered when their bin's arrivals are consumed (the gather moves
     // the ahead count over)
@@ -692,7 +572,327 @@ __global__ void __launch_bounds__(256) k_pass_reset(DevNet net) {
     }
 }
 
-size_t part_lds_bytes(uint32_t nb, uint32_t RE, bool wc, uint32_t D) { return PartLayout(nb, RE, wc, D).total; }
+// ------------------------------------------------------------------ single-pass blocked fan-in
+
+namespace {
+
+template <int KW> struct WeightOf;
+template <> struct WeightOf<1> { using type = float; };
+template <> struct WeightOf<2> { using type = float2; };
+
+// an edge record as loaded: the weights, then the key (target | inhibitory source << 31)
+template <int KW> struct RecOf;
+template <> struct RecOf<1> {
+    using type = uint2;
+    __device__ static uint32_t key(const uint2& r) { return r.y; }
+    __device__ static float weights(const uint2& r) { return __uint_as_float(r.x); }
+};
+template <> struct RecOf<2> {
+    using type = uint3;
+    __device__ static uint32_t key(const uint3& r) { return r.z; }
+    __device__ static float2 weights(const uint3& r) { return make_float2(__uint_as_float(r.x), __uint_as_float(r.y)); }
+};
+
+constexpr uint32_t kNoBlock = 0xFFFFFFFFu; // the workgroup holds no block of the tile
+constexpr uint32_t kNoSpace = 0xFFFFFFFEu; // the tile's blocks ran out (kErrArena raised)
+
+// LDS of k_fan: the delay lists and one chunk's segments (as k_part), and per tile a carry
+// buffer of C records (16-bit key: target within the tile | inhibitory source << 15, and the
+// weights), its claimed slots, the workgroup's current block of the tile and the records
+// already in that block, and the list of tiles to move out.
+struct FanLayout {
+    size_t dpre, dstart, sstart, bufw, cnt, blk, spre, dcnt, wave, bufk, fill, flist, smap, total;
+    __host__ __device__ FanLayout(uint32_t T, uint32_t C, uint32_t KW, uint32_t D) {
+        LdsLayout L;
+        dpre = L.take(8 * ((size_t)D + 1), 8);
+        dstart = L.take(8 * (size_t)D, 8);
+        sstart = L.take(8 * (size_t)kFanThreads, 8);
+        bufw = L.take(4 * (size_t)KW * C * T, 8);
+        cnt = L.take(4 * (size_t)T, 4);
+        blk = L.take(4 * (size_t)T, 4);
+        spre = L.take(4 * ((size_t)kFanThreads + 4), 4);
+        dcnt = L.take(4 * ((size_t)D + 1), 4);
+        wave = L.take(4 * 32, 4);
+        bufk = L.take(2 * (size_t)C * T, 2);
+        fill = L.take(2 * (size_t)T, 2);
+        flist = L.take(2 * (size_t)T, 2);
+        smap = L.take(2 * ((size_t)kFanThreads + 2), 2);
+        total = L.take(0, 16);
+    }
+};
+
+template <int KW>
+struct Fan {
+    using W = typename WeightOf<KW>::type;
+    W* bufw;
+    uint16_t* bufk;
+    uint32_t* cnt;   // slots claimed in the carry buffer (claims beyond C wait for the next move)
+    uint32_t* blk;   // current block (kNoBlock / kNoSpace)
+    uint16_t* fill;  // records in the current block
+    uint16_t* flist; // tiles to move out
+    uint32_t* nfl;   // their number
+    __device__ void at(unsigned char* base, const FanLayout& l) {
+        bufw = reinterpret_cast<W*>(base + l.bufw);
+        bufk = reinterpret_cast<uint16_t*>(base + l.bufk);
+        cnt = reinterpret_cast<uint32_t*>(base + l.cnt);
+        blk = reinterpret_cast<uint32_t*>(base + l.blk);
+        fill = reinterpret_cast<uint16_t*>(base + l.fill);
+        flist = reinterpret_cast<uint16_t*>(base + l.flist);
+        nfl = reinterpret_cast<uint32_t*>(base + l.wave) + 20;
+    }
+};
+
+// Moves the carry buffers of the listed tiles into the workgroup's blocks: C records each
+// (full buffers), or cnt[t] (the rest, at the end of a pass). One thread per tile takes a
+// new block of the tile when the current one cannot hold them (the block left behind is
+// full: its count is K), then C consecutive threads per tile copy the records, so a tile's
+// records land contiguously. Ends with the moved buffers empty and the list cleared. The
+// first barrier also orders the reset of the list counter after every thread has read it.
+template <int KW>
+__device__ void fan_move(const DevNet& net, Fan<KW>& F, uint32_t nfl, bool full) {
+    using W = typename WeightOf<KW>::type;
+    const uint32_t tid = threadIdx.x, C = net.fan_C, K = net.fan_K;
+    for (uint32_t x = tid; x < nfl; x += kFanThreads) {
+        const uint32_t t = F.flist[x];
+        const uint32_t n = full ? C : F.cnt[t];
+        uint32_t b = F.blk[t], f = F.fill[t];
+        if (b == kNoBlock || (b != kNoSpace && f + n > K)) {
+            if (b != kNoBlock) net.bcnt[b] = f;
+            const uint32_t got = atomicAdd(&net.tile_fill[t], 1u);
+            const unsigned long long b0 = net.tile_base[t];
+            if (b0 + got < net.tile_base[t + 1]) {
+                b = (uint32_t)(b0 + got);
+            } else { // cannot happen: a tile's blocks cover its in-degree plus two part-filled
+                     // blocks per workgroup and bin
+                b = kNoSpace;
+                atomicOr(&net.ctl->err, kErrArena);
+            }
+            f = 0;
+        }
+        F.blk[t] = b;
+        F.fill[t] = (uint16_t)(f + n);
+    }
+    __syncthreads();
+    if (tid == 0) *F.nfl = 0;
+    const uint32_t cs = 31u - __clz(C); // C is a power of two
+    for (uint32_t x = tid; x < (nfl << cs); x += kFanThreads) {
+        const uint32_t t = F.flist[x >> cs], s = x & (C - 1u);
+        const uint32_t b = F.blk[t];
+        const uint32_t n = full ? C : F.cnt[t];
+        if (s < n && b < kNoSpace) {
+            const size_t pos = (size_t)b * K + (F.fill[t] - n) + s;
+            net.evk[pos] = F.bufk[t * C + s];
+            reinterpret_cast<W*>(net.ev)[pos] = F.bufw[t * C + s];
+        }
+        // a full buffer's claim count restarts (claims past C belong to events still held
+        // in registers, which claim again); read only by the next insertion, after the barrier
+        if (full && s == 0) F.cnt[t] = 0u;
+    }
+    __syncthreads();
+    if (!full) {
+        for (uint32_t x = tid; x < nfl; x += kFanThreads) F.cnt[F.flist[x]] = 0u;
+        __syncthreads();
+    }
+}
+
+} // namespace
+
+// Single-pass fan-in (the tiles fit the LDS carry buffers): the same chunks of (spike, delay)
+// segments and the same loads as k_part, but every event goes straight into the carry buffer of
+// its target tile (one LDS counter claim). A full buffer is moved out as C contiguous records
+// into a block of K records that the workgroup took from the tile's block range (one global
+// claim per block, not per event). Each thread holds up to kMaxBatch events in register slots
+// and walks its own stride of the current chunk's events: an event that finds its buffer full
+// stays in its slot and claims again in the next iteration, and freed slots are refilled right
+// after the claims, so their loads are in flight while the full buffers are moved. At the end
+// every part-filled buffer is moved and every block the workgroup holds gets its record count,
+// so k_gather_blk reads each tile's blocks in full.
+template <int KW>
+__global__ void __launch_bounds__(kFanThreads) k_fan(DevNet net, uint32_t d_lo, uint32_t d_hi, uint32_t ahead) {
+    using W = typename WeightOf<KW>::type;
+    extern __shared__ __align__(16) unsigned char dyn[];
+    const uint32_t D = net.D, T = net.T, C = net.fan_C;
+    const FanLayout L(T, C, KW, D);
+    unsigned long long* s_dpre = reinterpret_cast<unsigned long long*>(dyn + L.dpre);
+    unsigned long long* s_dstart = reinterpret_cast<unsigned long long*>(dyn + L.dstart);
+    unsigned long long* s_sstart = reinterpret_cast<unsigned long long*>(dyn + L.sstart);
+    uint32_t* s_spre = reinterpret_cast<uint32_t*>(dyn + L.spre);
+    uint32_t* s_dcnt = reinterpret_cast<uint32_t*>(dyn + L.dcnt);
+    uint32_t* s_wave = reinterpret_cast<uint32_t*>(dyn + L.wave);
+    uint32_t* s_flag = s_wave + 24; // three vote words, used in turn
+    uint16_t* s_map = reinterpret_cast<uint16_t*>(dyn + L.smap);
+    Fan<KW> F;
+    F.at(dyn, L);
+    const unsigned long long k = net.ctl->bin + ahead;
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t x = tid; x < D; x += kFanThreads) {
+        const uint32_t d = x + 1;
+        uint32_t cnt = 0;
+        unsigned long long st = 0;
+        if (k >= d && d >= d_lo && d <= d_hi) {
+            const uint32_t b = (uint32_t)((k - d) & net.MBmask);
+            st = net.bin_start[b];
+            cnt = net.bin_cnt[b];
+        }
+        s_dstart[x] = st;
+        s_dcnt[x] = cnt;
+    }
+    __syncthreads();
+    for (uint32_t x = tid; x <= D; x += kFanThreads) {
+        unsigned long long tot = 0;
+        for (uint32_t y = 0; y < x; y++) tot += s_dcnt[y];
+        s_dpre[x] = tot;
+    }
+    __syncthreads();
+    const unsigned long long total = s_dpre[D];
+    if (total == 0) return;
+    for (uint32_t t = tid; t < T; t += kFanThreads) {
+        F.cnt[t] = 0u;
+        F.blk[t] = kNoBlock;
+        F.fill[t] = 0;
+    }
+    if (tid == 0) {
+        *F.nfl = 0u;
+        s_flag[0] = s_flag[1] = s_flag[2] = 0u;
+    }
+    const uint32_t G = gridDim.x;
+    const unsigned long long cw = (unsigned long long)(ahead ? net.chunks_per_wg : 1u) * G;
+    const uint32_t spc = (uint32_t)min((unsigned long long)kFanThreads, max(32ull, (total + cw - 1) / cw));
+    const unsigned long long nchunks = (total + spc - 1) / spc;
+    const uint32_t tb = net.tile_bits, lmask = (1u << tb) - 1u;
+    const uint32_t nslots = max(1u, min((uint32_t)kMaxBatch, net.round_events / kFanThreads));
+    unsigned long long my_events = 0;
+    __shared__ unsigned long long s_pc;
+    // the current chunk (uniform) and this thread's next event in it (events tid + j NT)
+    unsigned long long c = blockIdx.x;
+    uint32_t ec = 0, nseg = 0, mb_bits = 0, nmap = 0, jn = 0;
+    bool have = false;
+    // Reads the headers of chunk c, lays out its events (prefix and coarse map) and claims the
+    // next chunk; every thread's loads of the previous chunk have been issued before this.
+    auto setup_chunk = [&]() {
+        __syncthreads();
+        have = c < nchunks;
+        if (!have) return;
+        const unsigned long long i0 = c * spc;
+        nseg = (uint32_t)min((unsigned long long)spc, total - i0);
+        uint32_t len = 0;
+        if (tid < nseg) {
+            const unsigned long long it = i0 + tid;
+            uint32_t lo = 0, hi = D;
+            while (hi - lo > 1u) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (s_dpre[mid] <= it) lo = mid;
+                else hi = mid;
+            }
+            const uint32_t d = lo + 1;
+            const uint32_t j = net.rec[(s_dstart[lo] + (it - s_dpre[lo])) & net.RCmask] >> 4;
+            const uint32_t* hp = net.hdr + (size_t)j * net.HW;
+            const uint2 rs = *reinterpret_cast<const uint2*>(hp);
+            const uint32_t so = hp[1 + d], eo = hp[2 + d];
+            s_sstart[tid] = (((unsigned long long)(rs.y & 0x7FFFFFFFu) << 32) | rs.x) + so;
+            len = eo - so;
+        }
+        const uint32_t ex = block_exclusive_scan<kFanThreads>(len, s_wave, &ec);
+        s_spre[tid] = ex;
+        if (tid == 0) s_spre[kFanThreads] = ec;
+        mb_bits = 0;
+        while (((ec + (1u << mb_bits) - 1) >> mb_bits) > (uint32_t)kFanThreads) mb_bits++;
+        if (len) {
+            const uint32_t m0 = (ex + (1u << mb_bits) - 1) >> mb_bits;
+            const uint32_t m1 = (ex + len + (1u << mb_bits) - 1) >> mb_bits;
+            for (uint32_t m = m0; m < m1; m++) s_map[m] = (uint16_t)tid;
+        }
+        nmap = (ec + (1u << mb_bits) - 1) >> mb_bits;
+        if (tid == 0) s_pc = G + atomicAdd(&net.ctl->pnext, 1ull);
+        __syncthreads();
+        c = s_pc;
+        jn = 0;
+        my_events += ec;
+    };
+    // the held events: their edge index and the record as loaded (weights, then target |
+    // class << 31). Every slot is reloaded in every iteration, unconditionally (a held event
+    // reads its own record again, an empty slot any valid one), so the loads land straight in
+    // the slots' registers and are first waited for by the next iteration's claims.
+    using Rec = typename RecOf<KW>::type;
+    Rec rec[kMaxBatch];
+    unsigned long long eidx[kMaxBatch];
+    uint32_t pend = 0u;
+#pragma unroll
+    for (int u = 0; u < kMaxBatch; u++) {
+        rec[u] = Rec{};
+        eidx[u] = 0ull;
+    }
+    setup_chunk();
+    for (uint32_t it = 0;; it++) {
+        // claims of the events held (loaded in the previous iteration, or waiting for a buffer)
+#pragma unroll
+        for (int u = 0; u < kMaxBatch; u++) {
+            if (pend & (1u << u)) {
+                const uint32_t key = RecOf<KW>::key(rec[u]), tgt = key & 0x7FFFFFFFu;
+                const uint32_t t = tgt >> tb;
+                if (t >= T) { // cannot happen for a consistent table
+                    atomicOr(&net.ctl->err, kErrLayout);
+                    pend &= ~(1u << u);
+                    continue;
+                }
+                const uint32_t slot = atomicAdd(&F.cnt[t], 1u);
+                if (slot < C) {
+                    F.bufk[t * C + slot] = (uint16_t)((tgt & lmask) | ((key >> 31) << 15));
+                    F.bufw[t * C + slot] = RecOf<KW>::weights(rec[u]);
+                    if (slot == C - 1u) F.flist[atomicAdd(F.nfl, 1u)] = (uint16_t)t;
+                    pend &= ~(1u << u);
+                }
+            }
+        }
+        // refill the free slots from this thread's stride of the chunk, then load every slot:
+        // the loads stay in flight through the vote and the buffer moves
+        if (have) {
+#pragma unroll
+            for (int u = 0; u < kMaxBatch; u++) {
+                const uint32_t e = jn * kFanThreads + tid;
+                if (u < (int)nslots && !(pend & (1u << u)) && e < ec) {
+                    const uint32_t m = e >> mb_bits;
+                    const uint32_t lo = s_map[m], hi = m + 1 < nmap ? s_map[m + 1] : nseg - 1;
+                    const uint32_t sg = lo + seg_search(s_spre + lo, hi - lo + 1, e);
+                    eidx[u] = s_sstart[sg] + (e - s_spre[sg]);
+                    pend |= 1u << u;
+                    jn++;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kMaxBatch; u++) rec[u] = reinterpret_cast<const Rec*>(net.edge)[eidx[u]];
+        // vote: 1 = events of the chunk still to load, 2 = events held; three words in turn,
+        // the one for two iterations ahead cleared after this barrier
+        const uint32_t vote = (have && jn * kFanThreads + tid < ec ? 1u : 0u) | (pend ? 2u : 0u);
+        if (vote) atomicOr(&s_flag[it % 3u], vote);
+        __syncthreads();
+        const uint32_t fl = s_flag[it % 3u], nfl = *F.nfl;
+        if (tid == 0) s_flag[(it + 2u) % 3u] = 0u;
+        if (nfl) fan_move<KW>(net, F, nfl, true);
+        if (!(fl & 1u)) {
+            if (have) setup_chunk(); // every event of this chunk is loaded: the next chunk
+            if (!have && !(fl & 2u)) break;
+        }
+    }
+    // the part-filled buffers, then the record count of every block held
+    __syncthreads();
+    for (uint32_t t = tid; t < T; t += kFanThreads)
+        if (F.cnt[t]) F.flist[atomicAdd(F.nfl, 1u)] = (uint16_t)t;
+    __syncthreads();
+    const uint32_t nfl = *F.nfl;
+    if (nfl) fan_move<KW>(net, F, nfl, false);
+    for (uint32_t t = tid; t < T; t += kFanThreads) {
+        const uint32_t b = F.blk[t];
+        if (b < kNoSpace) net.bcnt[b] = F.fill[t];
+    }
+    if (tid == 0 && my_events) atomicAdd(ahead ? &net.ctl->ahead_events : &net.ctl->edge_events, my_events);
+    // the chunk counter is reset by the next kernel of the stream (the gather or the bin close)
+}
+
+size_t fan_lds_bytes(uint32_t T, uint32_t C, uint32_t KW, uint32_t D) { return FanLayout(T, C, KW, D).total; }
+
+size_t part_lds_bytes(uint32_t nb, uint32_t RE, uint32_t D) { return PartLayout(nb, RE, D).total; }
 
 size_t bucket_lds_bytes(uint32_t TS, uint32_t RE) { return BucketLayout(TS, RE).total; }
 
@@ -753,6 +953,89 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(DevNet net) {
     }
     const float qinv = net.qinv;
     for (uint32_t x = threadIdx.x; x < nt; x += blockDim.x) {
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++)
+            net.A[(size_t)u * net.N + i0 + x] = (float)(long long)acc[x * U + u] * qinv;
+    }
+}
+
+// Gather of the single-pass form: one workgroup per tile reads the tile's blocks (record
+// counts first, in batches of up to kGatherThreads blocks whose prefix, with a coarse map of
+// every 2^m-th record, locates every record in one or two LDS probes), sums them in LDS as
+// int64 fixed point, converts once, writes A.
+template <int KW>
+__global__ void __launch_bounds__(kGatherThreads) k_gather_blk(DevNet net) {
+    using W = typename WeightOf<KW>::type;
+    extern __shared__ __align__(16) unsigned long long acc[];
+    __shared__ uint32_t s_pre[kGatherThreads];
+    __shared__ uint16_t s_map[kGatherThreads + 2];
+    __shared__ uint32_t s_wave[kGatherThreads / 64];
+    constexpr uint32_t U = 2 * KW;
+    const uint32_t t = blockIdx.x, tid = threadIdx.x;
+    const uint32_t i0 = t << net.tile_bits;
+    const uint32_t nt = min(1u << net.tile_bits, net.N - i0);
+    const uint32_t lmask = (1u << net.tile_bits) - 1u;
+    for (uint32_t x = tid; x < nt * U; x += kGatherThreads) acc[x] = 0ull;
+    const unsigned long long b0 = net.tile_base[t];
+    const uint32_t nb = (uint32_t)min((unsigned long long)net.tile_fill[t], net.tile_base[t + 1] - b0);
+    const uint32_t K = net.fan_K;
+    const double qs = net.qscale;
+    const uint16_t* evk = net.evk;
+    const W* evw = reinterpret_cast<const W*>(net.ev);
+    for (uint32_t bb = 0; bb < nb; bb += kGatherThreads) {
+        const uint32_t nbb = min(kGatherThreads, nb - bb);
+        const uint32_t cnt = tid < nbb ? min(net.bcnt[b0 + bb + tid], K) : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan<kGatherThreads>(cnt, s_wave, &tot);
+        s_pre[tid] = ex;
+        uint32_t mb = 0;
+        while (((tot + (1u << mb) - 1) >> mb) > (uint32_t)kGatherThreads) mb++;
+        if (cnt) {
+            const uint32_t m0 = (ex + (1u << mb) - 1) >> mb, m1 = (ex + cnt + (1u << mb) - 1) >> mb;
+            for (uint32_t m = m0; m < m1; m++) s_map[m] = (uint16_t)tid;
+        }
+        const uint32_t nmap = (tot + (1u << mb) - 1) >> mb;
+        __syncthreads();
+        const size_t base = (size_t)(b0 + bb) * K;
+        for (uint32_t e0 = 0; e0 < tot; e0 += kLoadBatch * kGatherThreads) {
+            uint32_t kk[kLoadBatch];
+            W ww[kLoadBatch];
+#pragma unroll
+            for (int u = 0; u < kLoadBatch; u++) { // clamped: every load is issued, none branches
+                const uint32_t e = min(e0 + u * kGatherThreads + tid, tot - 1);
+                const uint32_t m = e >> mb;
+                const uint32_t lo = s_map[m], hi = m + 1 < nmap ? s_map[m + 1] : nbb - 1;
+                const uint32_t j = lo + seg_search(s_pre + lo, hi - lo + 1, e);
+                const size_t pos = base + (size_t)j * K + (e - s_pre[j]);
+                kk[u] = evk[pos];
+                ww[u] = evw[pos];
+            }
+#pragma unroll
+            for (int u = 0; u < kLoadBatch; u++) {
+                if (e0 + u * kGatherThreads + tid < tot) {
+                    const uint32_t lt = kk[u] & lmask;
+                    const uint32_t u0 = (kk[u] >> 15) ? (uint32_t)KW : 0u;
+                    if constexpr (KW == 2) {
+                        atomicAdd(&acc[lt * U + u0], quant(ww[u].x, qs));
+                        atomicAdd(&acc[lt * U + u0 + 1], quant(ww[u].y, qs));
+                    } else {
+                        atomicAdd(&acc[lt * U + u0], quant(ww[u], qs));
+                    }
+                }
+            }
+        }
+        __syncthreads(); // s_pre is rewritten by the next batch
+    }
+    __syncthreads();
+    if (tid == 0) net.tile_fill[t] = 0;
+    if (t == 0 && tid == 0) {
+        net.ctl->edge_events += net.ctl->ahead_events;
+        net.ctl->ahead_events = 0;
+        net.ctl->pnext = 0;
+        net.ctl->bnext = 0;
+    }
+    const float qinv = net.qinv;
+    for (uint32_t x = tid; x < nt; x += kGatherThreads) {
 #pragma unroll
         for (uint32_t u = 0; u < U; u++)
             net.A[(size_t)u * net.N + i0 + x] = (float)(long long)acc[x * U + u] * qinv;
@@ -1012,6 +1295,75 @@ __global__ void __launch_bounds__(256) k_compact(DevNet net) {
 }
 
 
+// ------------------------------------------------------------------ receptor currents
+
+// The measurement step of Suppl. Algorithm 1 at the current state: per neuron block, the sum
+// of each receptor's term g_u J_u (V_u - V) (float, the region signal's expression) in a fixed
+// tree (double); then per population the sum of its blocks in ascending order, divided by its
+// size. rblk [n_blocks][4] and rpop [n_pops][4] (paper receptor order) are device arrays.
+template <int U>
+__global__ void __launch_bounds__(kNeuronBlock) k_receptor_blocks(DevNet net, double* rblk) {
+    __shared__ double s_red[U][kNeuronBlock];
+    const uint2 bi = net.blk[blockIdx.x];
+    const PopParams& P = net.pops[bi.y];
+    const uint32_t i = bi.x + threadIdx.x;
+    const bool active = i < P.end;
+    const float V = active ? net.V[i] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        const float t = active ? (P.g[u] * net.J[(size_t)u * net.N + i]) * (P.Vu[u] - V) : 0.0f;
+        s_red[u][threadIdx.x] = active ? (double)t : 0.0;
+    }
+    __syncthreads();
+    for (uint32_t st = kNeuronBlock / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st)
+#pragma unroll
+            for (int u = 0; u < U; u++) s_red[u][threadIdx.x] += s_red[u][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) {
+        // paper order: AMPA, NMDA, GABA_A, GABA_B; with two receptors, AMPA and GABA_A
+        const int u = U == 4 ? (int)threadIdx.x : (threadIdx.x == 0 ? 0 : threadIdx.x == 2 ? 1 : -1);
+        rblk[(size_t)blockIdx.x * 4 + threadIdx.x] = u >= 0 ? s_red[u][0] : 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_receptor_pops(DevNet net, uint32_t n_pops, const double* rblk, double* rpop) {
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_pops) return;
+    // blocks are laid out population by population: the first block of q and of q + 1
+    auto first = [&](uint32_t pq) {
+        uint32_t lo = 0, hi = net.n_blocks;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (net.blk[mid].y < pq) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
+    const uint32_t b0 = first(q), b1 = first(q + 1);
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (uint32_t b = b0; b < b1; b++)
+        for (int u = 0; u < 4; u++) s[u] += rblk[(size_t)b * 4 + u];
+    const uint32_t n = b1 > b0 ? net.pops[q].end - net.blk[b0].x : 0u;
+    for (int u = 0; u < 4; u++) rpop[(size_t)q * 4 + u] = n ? s[u] / (double)n : 0.0;
+}
+
+// ------------------------------------------------------------------ recording to host memory
+
+// Copies the spike list of the bin being closed (compacted, not yet closed) into the pinned
+// host ring at the same offsets (mod its size) and stores the bin's end offset. Runs on a
+// second stream beside the rest of the bin; the host reads the ring after a synchronisation.
+__global__ void __launch_bounds__(256) k_drain(DevNet net) {
+    const unsigned long long k = net.ctl->bin;
+    const uint32_t m = net.MBmask;
+    const unsigned long long st = net.bin_start[k & m];
+    const uint32_t c = net.bin_cnt[k & m];
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < c; x += gridDim.x * blockDim.x)
+        net.hrec[(st + x) & net.HCmask] = net.rec[(st + x) & net.RCmask];
+    if (blockIdx.x == 0 && threadIdx.x == 0) net.hbend[(k + 1) & net.HMBmask] = st + c;
+}
+
 // ------------------------------------------------------------------ readout + close
 
 // Level 1: workgroup (region r, group g) sums the block partials g*256 .. g*256+255 of
@@ -1133,33 +1485,39 @@ size_t gather_lds_bytes(const DevNet& n) { return ((size_t)1 << n.tile_bits) * n
 
 
 hipError_t prepare_kernels() {
-    const void* big[] = {(const void*)k_part<1, false>, (const void*)k_part<2, false>, (const void*)k_part<1, true>,
-                         (const void*)k_part<2, true>, (const void*)k_bucket<1>, (const void*)k_bucket<2>};
+    const void* big[] = {(const void*)k_part<1>, (const void*)k_part<2>, (const void*)k_bucket<1>,
+                         (const void*)k_bucket<2>, (const void*)k_fan<1>, (const void*)k_fan<2>};
     hipError_t e = hipSuccess;
     for (const void* f : big) { // leave room for the kernels' few static LDS bytes
         e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kMaxLdsBytes - kStaticLds));
         if (e != hipSuccess) return e;
     }
-    e = hipFuncSetAttribute((const void*)k_gather<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)kTileLdsBytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_gather<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)kTileLdsBytes);
+    const void* gat[] = {(const void*)k_gather<1>, (const void*)k_gather<2>, (const void*)k_gather_blk<1>,
+                         (const void*)k_gather_blk<2>};
+    for (const void* f : gat) {
+        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileLdsBytes);
+        if (e != hipSuccess) return e;
+    }
+    return e;
 }
 
 hipError_t launch_scatter(const DevNet& n, int grid, hipStream_t st, uint32_t d_lo, uint32_t d_hi, uint32_t ahead) {
-    const size_t la = part_lds_bytes(n.wc ? n.T : n.NS, n.round_events, n.wc != 0, n.D);
+    if (n.blocked) {
+        const size_t lf = fan_lds_bytes(n.T, n.fan_C, n.KW, n.D);
+        if (n.KW == 2)
+            hipLaunchKernelGGL(k_fan<2>, dim3(grid), dim3(kFanThreads), lf, st, n, d_lo, d_hi, ahead);
+        else
+            hipLaunchKernelGGL(k_fan<1>, dim3(grid), dim3(kFanThreads), lf, st, n, d_lo, d_hi, ahead);
+        return hipGetLastError();
+    }
+    const size_t la = part_lds_bytes(n.NS, n.round_events, n.D);
     const size_t lb = bucket_lds_bytes(1u << n.ts_bits, n.bucket_events);
-    if (n.KW == 2 && n.wc)
-        hipLaunchKernelGGL((k_part<2, true>), dim3(grid), dim3(kScatterThreads), la, st, n, d_lo, d_hi, ahead);
-    else if (n.KW == 2)
-        hipLaunchKernelGGL((k_part<2, false>), dim3(grid), dim3(kScatterThreads), la, st, n, d_lo, d_hi, ahead);
-    else if (n.wc)
-        hipLaunchKernelGGL((k_part<1, true>), dim3(grid), dim3(kScatterThreads), la, st, n, d_lo, d_hi, ahead);
+    if (n.KW == 2)
+        hipLaunchKernelGGL(k_part<2>, dim3(grid), dim3(kScatterThreads), la, st, n, d_lo, d_hi, ahead);
     else
-        hipLaunchKernelGGL((k_part<1, false>), dim3(grid), dim3(kScatterThreads), la, st, n, d_lo, d_hi, ahead);
+        hipLaunchKernelGGL(k_part<1>, dim3(grid), dim3(kScatterThreads), la, st, n, d_lo, d_hi, ahead);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || n.wc) return e;
+    if (e != hipSuccess) return e;
     if (n.KW == 2)
         hipLaunchKernelGGL(k_bucket<2>, dim3(grid), dim3(kScatterThreads), lb, st, n);
     else
@@ -1173,6 +1531,13 @@ hipError_t launch_pass_reset(const DevNet& n, hipStream_t st) {
 }
 
 hipError_t launch_gather(const DevNet& n, hipStream_t st) {
+    if (n.blocked) {
+        if (n.KW == 2)
+            hipLaunchKernelGGL(k_gather_blk<2>, dim3(n.T), dim3(kGatherThreads), gather_lds_bytes(n), st, n);
+        else
+            hipLaunchKernelGGL(k_gather_blk<1>, dim3(n.T), dim3(kGatherThreads), gather_lds_bytes(n), st, n);
+        return hipGetLastError();
+    }
     if (n.KW == 2)
         hipLaunchKernelGGL(k_gather<2>, dim3(n.T), dim3(kGatherThreads), gather_lds_bytes(n), st, n);
     else
@@ -1190,6 +1555,22 @@ hipError_t launch_neuron(const DevNet& n, int s0, int s1, hipStream_t st) {
 
 hipError_t launch_compact(const DevNet& n, hipStream_t st) {
     hipLaunchKernelGGL(k_compact, dim3(n.n_grp), dim3(256), 0, st, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_receptor_currents(const DevNet& n, uint32_t n_pops, double* rblk, double* rpop, hipStream_t st) {
+    if (n.U == 4)
+        hipLaunchKernelGGL(k_receptor_blocks<4>, dim3(n.n_blocks), dim3(kNeuronBlock), 0, st, n, rblk);
+    else
+        hipLaunchKernelGGL(k_receptor_blocks<2>, dim3(n.n_blocks), dim3(kNeuronBlock), 0, st, n, rblk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_receptor_pops, dim3((n_pops + 255) / 256), dim3(256), 0, st, n, n_pops, rblk, rpop);
+    return hipGetLastError();
+}
+
+hipError_t launch_drain(const DevNet& n, hipStream_t st) {
+    hipLaunchKernelGGL(k_drain, dim3(64), dim3(256), 0, st, n);
     return hipGetLastError();
 }
 

@@ -89,21 +89,29 @@ static double bucket_build_bytes() {
 }
 
 uint32_t max_round_events(const Plan& p, uint32_t wgs_per_cu) {
+    if (p.blocked) return (uint32_t)(kFanThreads * kMaxBatch); // events stay in registers
     const size_t budget = kMaxLdsBytes / wgs_per_cu - kStaticLds;
     uint32_t best = 0;
-    for (uint32_t re = kScatterThreads; re <= (uint32_t)(kScatterThreads * kMaxBatch); re += kScatterThreads) {
-        const bool fits = p.wc ? part_lds_bytes(p.T, re, true, p.D) <= budget : part_lds_bytes(p.NS, re, false, p.D) <= budget;
-        if (fits) best = re;
-    }
+    for (uint32_t re = kScatterThreads; re <= (uint32_t)(kScatterThreads * kMaxBatch); re += kScatterThreads)
+        if (part_lds_bytes(p.NS, re, p.D) <= budget) best = re;
     return best;
 }
 
 uint32_t max_bucket_events(const Plan& p, uint32_t wgs_per_cu) {
-    if (p.wc) return kScatterThreads; // no second pass
+    if (p.blocked) return kScatterThreads; // no second pass
     const size_t budget = kMaxLdsBytes / wgs_per_cu - kStaticLds;
     uint32_t best = 0;
     for (uint32_t re = kScatterThreads; re <= (uint32_t)(kScatterThreads * kMaxBatch); re += kScatterThreads)
         if (bucket_lds_bytes(1u << p.ts_bits, re) <= budget) best = re;
+    return best;
+}
+
+uint32_t fan_chunk_records(const Plan& p, uint32_t wgs_per_cu) {
+    if (wgs_per_cu == 0) return 0;
+    const size_t budget = kMaxLdsBytes / wgs_per_cu - kStaticLds;
+    uint32_t best = 0;
+    for (uint32_t c = kFanMinChunk; c <= kFanMaxChunk; c *= 2)
+        if (fan_lds_bytes(p.T, c, p.KW, p.D) <= budget) best = c;
     return best;
 }
 
@@ -168,19 +176,19 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     while ((1u << (p.tile_bits + 1)) <= tile_neurons) p.tile_bits++;
     p.T = (p.N + (1u << p.tile_bits) - 1) >> p.tile_bits;
     if (p.T > (uint32_t)kMaxTilesLds) return "network too large for the tile histogram (too many neurons)";
-    // fan-in form: k_part writes the tiles directly when a carry buffer per tile and a
-    // round of 1024 events fit twice in a CU's LDS, else two passes through at most
-    // kMaxSuperTiles super-tile streams of a power-of-two number of tiles each
-    p.wc = !(opts.flags & DBSIM_F_TWO_PASS) && p.T <= 2u * kScatterThreads &&
-           part_lds_bytes(p.T, 1024, true, p.D) <= kMaxLdsBytes / 2 - kStaticLds;
+    // fan-in form: one pass straight into the tiles when a carry buffer of at least
+    // kFanMinChunk records per tile fits one workgroup's LDS (T up to about 2,900 tiles with
+    // two weights per edge), else two passes through at most kMaxSuperTiles super-tile
+    // streams of a power-of-two number of tiles each
+    p.blocked = !(opts.flags & DBSIM_F_TWO_PASS) && p.T <= 65535u && fan_chunk_records(p, 1) != 0;
     p.ts_bits = 0;
-    if (!p.wc)
+    if (!p.blocked)
         while (((p.T + (1u << p.ts_bits) - 1) >> p.ts_bits) > kMaxSuperTiles) p.ts_bits++;
-    p.NS = (p.T + (1u << p.ts_bits) - 1) >> p.ts_bits;
+    p.NS = p.blocked ? 0u : (p.T + (1u << p.ts_bits) - 1) >> p.ts_bits;
     p.HW = (p.D + 3 + 3) & ~3u;
-    // default schedule (what the autotuner settles on for the 6.1 M share): two partition
-    // workgroups per CU, the largest LDS round that fits
-    p.scatter_wgs_per_cu = 2;
+    // default schedule: single pass, one workgroup per CU with the largest carry buffers;
+    // two passes, two partition workgroups per CU and the largest LDS round that fits
+    p.scatter_wgs_per_cu = p.blocked ? 1 : 2;
     p.round_events = max_round_events(p, p.scatter_wgs_per_cu);
     p.bucket_events = max_bucket_events(p, p.scatter_wgs_per_cu);
     if (p.round_events == 0 || p.bucket_events == 0) return "too many tiles per super-tile for the LDS budget";
@@ -201,7 +209,7 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
                 return "background rate too high for the Poisson table (rate * dt above about 20)";
             const uint32_t kin = indeg_of_pop(n, q);
             // super-tile streams and tile slices are indexed with 32-bit fill counters
-            if (((uint64_t)kin << (p.tile_bits + p.ts_bits)) + (uint64_t)kChunk * (2 * kMaxPartGrid + 1) >= (1ull << 32))
+            if (((uint64_t)kin << (p.tile_bits + p.ts_bits)) >= (1ull << 32))
                 return "in-degree too large for a super-tile stream";
             p.E += (uint64_t)P.size * kin;
             const uint32_t nb = (P.size + kNeuronBlock - 1) / kNeuronBlock;
@@ -213,9 +221,14 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     for (uint32_t r = 0; r < p.n_regions; r++) p.n_l1 += (uint32_t)std::max<uint64_t>(1, (rblocks[r] + 255) / 256);
     const uint32_t rb = opts.record_bins ? opts.record_bins : 4096u;
     p.MB = pow2_at_least32(std::max<uint64_t>(rb, (uint64_t)p.D + 1));
-    // spike history: at least the last D bins for the fan-in, plus a default reading window
-    const uint64_t want = opts.spike_record_capacity ? opts.spike_record_capacity : (1ull << 22);
+    // spike history: at least the last D + 1 bins for the fan-in, plus (when the raster is
+    // read from the device) a default reading window; the host ring takes the raster otherwise
+    p.host_record = !(opts.flags & DBSIM_F_NO_HOST_RECORD);
+    const uint64_t want = opts.spike_record_capacity ? opts.spike_record_capacity : (p.host_record ? 0 : (1ull << 22));
     p.RC = pow2_at_least64(std::max<uint64_t>(want, ((uint64_t)p.D + 1) * p.N));
+    p.HC = p.host_record ? pow2_at_least64(std::max<uint64_t>(opts.host_spike_capacity ? opts.host_spike_capacity
+                                                                                      : (1ull << 24), 64)) : 0;
+    p.HMB = p.host_record ? (1u << 20) : 0;
     // memory plan (one allocation, 256-byte aligned slots)
     size_t off = 0;
     auto slot = [&](Plan::Slot& s, size_t bytes) {
@@ -223,6 +236,27 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
         s.bytes = bytes;
         off += (bytes + 255) & ~(size_t)255;
     };
+    // single-pass form: tile t's blocks hold its total in-degree in whole blocks plus two
+    // part-filled blocks per workgroup and bin (one per workgroup and pass)
+    p.tile_blk.clear();
+    if (p.blocked) {
+        std::vector<uint64_t> tin(p.T, 0);
+        uint64_t i0 = 0;
+        for (size_t k = 0; k < mem.m.size(); k++)
+            for (uint32_t q = 0; q < mem.m[k].n_pops; q++) {
+                const uint64_t kin = indeg_of_pop(mem.m[k], q), i1 = i0 + mem.m[k].pops[q].size;
+                for (uint64_t a = i0; a < i1;) {
+                    const uint64_t t = a >> p.tile_bits, b = std::min(i1, (t + 1) << p.tile_bits);
+                    tin[t] += kin * (b - a);
+                    a = b;
+                }
+                i0 = i1;
+            }
+        p.tile_blk.assign((size_t)p.T + 1, 0);
+        for (uint32_t t = 0; t < p.T; t++)
+            p.tile_blk[t + 1] = p.tile_blk[t] + tin[t] / kFanBlock + 2ull * kFanMaxGrid;
+        if (p.tile_blk[p.T] >= 0xFFFFFFF0ull) return "network too large for the single-pass event arena";
+    }
     const size_t N = p.N, U = p.U, E = p.E;
     slot(p.V, 4 * N);
     slot(p.J, 4 * U * N);
@@ -235,15 +269,23 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     slot(p.blk, sizeof(uint2) * p.n_blocks);
     slot(p.hdr, 4 * N * (size_t)p.HW);
     slot(p.edge, 4 * (size_t)(1 + p.KW) * E + 64); // spare: 8-byte records are copied with 12-byte reads
-    // event arena: write-combined tile slices are padded (see build_tables)
-    const size_t arena = p.wc ? E + (size_t)p.T * (kChunk - 1 + 2 * (size_t)kChunk * kMaxPartGrid) : E;
-    slot(p.ev, 4 * (size_t)(1 + p.KW) * arena);
+    // event arena
+    if (p.blocked) {
+        const size_t recs = (size_t)p.tile_blk[p.T] * kFanBlock;
+        slot(p.ev, 4 * (size_t)p.KW * recs);
+        slot(p.evk, 2 * recs);
+        slot(p.bcnt, 4 * (size_t)p.tile_blk[p.T]);
+    } else {
+        slot(p.ev, 4 * (size_t)(1 + p.KW) * E);
+        slot(p.evk, 16);
+        slot(p.bcnt, 16);
+    }
     slot(p.tile_base, 8 * ((size_t)p.T + 1));
     slot(p.tile_fill, 4 * (size_t)p.T);
     slot(p.st_base, 8 * ((size_t)p.NS + 1));
-    slot(p.st_fill, 4 * (size_t)p.NS);
+    slot(p.st_fill, 4 * (size_t)p.NS + 4);
     // 64 spare bytes: the partition kernels copy 8-byte records with 12-byte reads
-    slot(p.sev, p.wc ? 16 : 4 * (size_t)(1 + p.KW) * E + 64);
+    slot(p.sev, p.blocked ? 16 : 4 * (size_t)(1 + p.KW) * E + 64);
     p.n_grp = (p.n_blocks + 255) / 256;
     slot(p.stage, 4 * (size_t)p.n_blocks * kNeuronBlock);
     slot(p.grp_cnt, 4 * 2 * (size_t)p.n_grp);
@@ -266,6 +308,8 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     slot(p.bold, 8 * 4 * RB);
     slot(p.bold_y, 8 * (size_t)kBoldRing * RB);
     slot(p.bold_ctl, 16);
+    slot(p.rblk, 8 * 4 * (size_t)p.n_blocks); // receptor-current measurement (block sums)
+    slot(p.rpop, 8 * 4 * (size_t)p.n_pops);
     slot(p.ctl, sizeof(Ctl));
     p.total = off;
     return "";
@@ -368,13 +412,11 @@ std::string build_tables(const Members& mem, const Plan& p, unsigned threads, Ho
         for (uint32_t t = 0; t < p.T; t++) sum += h.tile_base[t + 1];
         if (sum != p.E) return "internal error: edge count mismatch";
     }
-    // write-combined form: every slice starts on a whole chunk and holds, besides the
-    // tile's in-degree, one padded chunk per partition workgroup and partition launch
-    // (two launches per bin: delay 1, and delays 2..D)
-    for (uint32_t t = 0; t < p.T; t++) {
-        uint64_t len = h.tile_base[t + 1];
-        if (p.wc) len = (len + kChunk - 1) / kChunk * kChunk + 2ull * kChunk * kMaxPartGrid;
-        h.tile_base[t + 1] = h.tile_base[t] + len;
+    // record slices of the two-pass form; block ranges of the single-pass form (the plan's)
+    if (p.blocked) {
+        h.tile_base = p.tile_blk;
+    } else {
+        for (uint32_t t = 0; t < p.T; t++) h.tile_base[t + 1] += h.tile_base[t];
     }
 
     // initial membrane potentials
@@ -392,7 +434,7 @@ std::string build_tables(const Members& mem, const Plan& p, unsigned threads, Ho
         scratch_bytes = std::max(scratch_bytes, dbnet_scratch_bytes(&d));
         kmax = std::max(kmax, dbnet_max_indegree(&d));
     }
-    const size_t RW = 1 + KW; // words per edge record: target, then the weights
+    const size_t RW = 1 + KW; // words per edge record: the weights, then the target (key)
     const double wlim = std::ldexp(1.0, 52 - (int)p.F);
     std::atomic<int> gen_fail{0}, wbad{0};
     if ((double)p.E * sizeof(BucketEdge) <= bucket_build_bytes()) {
@@ -483,9 +525,9 @@ std::string build_tables(const Members& mem, const Plan& p, unsigned threads, Ho
                     for (const BucketEdge& be : bucket[(size_t)t * SB + b]) {
                         const uint64_t e = cur[(size_t)(be.src_dl >> 8) * D + (be.src_dl & 0xFF) - 1]++;
                         uint32_t* rec = &h.edge[e * RW];
-                        rec[0] = be.tgt | ((uint32_t)h.src_inh[j0 + (be.src_dl >> 8)] << 31);
-                        rec[1] = be.w0;
-                        if (KW == 2) rec[2] = be.w1;
+                        rec[KW] = be.tgt | ((uint32_t)h.src_inh[j0 + (be.src_dl >> 8)] << 31);
+                        rec[0] = be.w0;
+                        if (KW == 2) rec[1] = be.w1;
                     }
                 for (unsigned t = 0; t < T; t++) std::vector<BucketEdge>().swap(bucket[(size_t)t * SB + b]);
             }
@@ -555,9 +597,9 @@ std::string build_tables(const Members& mem, const Plan& p, unsigned threads, Ho
                 for (int64_t e = 0; e < k; e++) {
                     const uint64_t pos = cur[(size_t)(src[e] + base) * D + dl[e] - 1].fetch_add(1, std::memory_order_relaxed);
                     uint32_t* rec = &h.edge[pos * RW];
-                    rec[0] = (uint32_t)i | ((uint32_t)h.src_inh[src[e] + base] << 31);
-                    std::memcpy(&rec[1], &w0[e], 4);
-                    if (KW == 2) std::memcpy(&rec[2], &w1[e], 4);
+                    rec[KW] = (uint32_t)i | ((uint32_t)h.src_inh[src[e] + base] << 31);
+                    std::memcpy(&rec[0], &w0[e], 4);
+                    if (KW == 2) std::memcpy(&rec[1], &w1[e], 4);
                     if (!(std::fabs((double)w0[e]) < wlim) || !(std::fabs((double)w1[e]) < wlim)) wbad.store(1);
                 }
             }
@@ -579,12 +621,12 @@ std::string build_tables(const Members& mem, const Plan& p, unsigned threads, Ho
                     if (s1 - s0 < 2) continue;
                     tmp.resize(s1 - s0);
                     for (uint64_t e = s0; e < s1; e++)
-                        tmp[e - s0] = Ed{h.edge[e * RW], h.edge[e * RW + 1], KW == 2 ? h.edge[e * RW + 2] : 0u};
+                        tmp[e - s0] = Ed{h.edge[e * RW + KW], h.edge[e * RW], KW == 2 ? h.edge[e * RW + 1] : 0u};
                     std::sort(tmp.begin(), tmp.end(), [](const Ed& A, const Ed& B) { return A.t < B.t; });
                     for (uint64_t e = s0; e < s1; e++) {
-                        h.edge[e * RW] = tmp[e - s0].t;
-                        h.edge[e * RW + 1] = tmp[e - s0].w0;
-                        if (KW == 2) h.edge[e * RW + 2] = tmp[e - s0].w1;
+                        h.edge[e * RW + KW] = tmp[e - s0].t;
+                        h.edge[e * RW] = tmp[e - s0].w0;
+                        if (KW == 2) h.edge[e * RW + 1] = tmp[e - s0].w1;
                     }
                 }
             }

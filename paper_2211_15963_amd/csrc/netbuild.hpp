@@ -38,27 +38,36 @@ struct Plan {
     uint32_t MB = 0;    // bins kept in the per-bin rings (power of two)
     uint32_t n_l1 = 0;  // level-1 readout groups (256 neuron blocks each, per region)
     uint32_t n_grp = 0; // compaction groups (256 consecutive neuron blocks each)
-    bool wc = false;              // k_part writes tile chunks directly (else two passes)
+    bool blocked = false;         // single-pass fan-in into tile blocks (else two passes)
     uint32_t NS = 0, ts_bits = 0; // super-tiles, log2(tiles per super-tile) of the two-pass form
+    std::vector<uint64_t> tile_blk; // single-pass form: first block of every tile [T + 1]
     uint32_t HW = 0;              // words per row header
     uint32_t round_events = 0, bucket_events = 0, scatter_wgs_per_cu = 0;
     uint64_t RC = 0; // spike-history ring entries (power of two)
+    bool host_record = false; // every bin's spikes are copied to a pinned host ring
+    uint64_t HC = 0;          // host ring entries (power of two)
+    uint32_t HMB = 0;         // bins of offsets kept beside it (power of two)
     uint64_t E = 0;  // edges
     bool regions_on = false;
     // byte offsets of every device array inside one allocation
     struct Slot {
         size_t off = 0, bytes = 0;
     };
-    Slot V, J, ref, pend, A, Iou, pops, ptab, blk, hdr, edge, ev, tile_base, tile_fill, st_base, st_fill, sev, stage,
+    Slot V, J, ref, pend, A, Iou, pops, ptab, blk, hdr, edge, ev, evk, bcnt, tile_base, tile_fill, st_base, st_fill,
+        sev, stage,
         grp_cnt, rec, bin_start, bin_cnt, blk_sig, blk_cnt, reg_blk_ptr, reg_blk, reg_size, l1_ptr, l1_region, l1_sig,
-        l1_cnt, sig, sig_cnt, bold_zs, bold, bold_y, bold_ctl, ctl;
+        l1_cnt, sig, sig_cnt, bold_zs, bold, bold_y, bold_ctl, rblk, rpop, ctl;
     size_t total = 0;
 };
 
-// Largest multiple of 1024 events (at most 8192) a partition round can stage in LDS for
-// the plan's form (0 if none fits).
+// Largest multiple of kScatterThreads events (at most 4096) a round of the two-pass form can
+// stage in LDS (0 if none fits); the single-pass form keeps its rounds in registers (at most
+// kMaxBatch * kFanThreads events).
 uint32_t max_round_events(const Plan& p, uint32_t wgs_per_cu);
 uint32_t max_bucket_events(const Plan& p, uint32_t wgs_per_cu);
+// Single-pass form: the largest carry buffer (records per tile, a power of two in
+// kFanMinChunk .. kFanMaxChunk) whose LDS fits wgs_per_cu workgroups per CU (0 if none).
+uint32_t fan_chunk_records(const Plan& p, uint32_t wgs_per_cu);
 
 // Validates the runtime options and the members for this simulator and fills the plan.
 // Returns an empty string on success, else the reason.

@@ -21,10 +21,11 @@ from netgen.desc import Desc, NetSpec
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdbsim.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 REC_REGIONS = 1
 F_NO_GRAPH = 1
 F_TWO_PASS = 2
+F_NO_HOST_RECORD = 4
 STATIC_BYTES = 64 << 20  # DBSIM_STATIC_BYTES: the static region of dbsim_create_static
 
 OK, EINVAL, ENOMEM, EHBM, EDEVICE, ETRUNC, EOVERFLOW, ESTATE, ERANGE = 0, -1, -2, -3, -4, -5, -6, -7, -8
@@ -39,7 +40,7 @@ class SimDesc(Structure):
     _fields_ = [("abi_version", c_uint32), ("record_flags", c_uint32), ("net", Desc),
                 ("spike_record_capacity", c_uint64), ("record_bins", c_uint32), ("device", c_int32),
                 ("hip_stream", c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_ctx", c_void_p),
-                ("host_threads", c_uint32), ("flags", c_uint32)]
+                ("host_threads", c_uint32), ("flags", c_uint32), ("host_spike_capacity", c_uint64)]
 
 
 class SimStats(Structure):
@@ -122,7 +123,8 @@ EXPORTED = ["dbsim_abi_version", "dbsim_last_error", "dbsim_create", "dbsim_foot
             "dbsim_set_tuning",
             "dbsim_step", "dbsim_sync", "dbsim_read_spikes", "dbsim_read_region_signal", "dbsim_read_state",
             "dbsim_write_state", "dbsim_export_csr", "dbsim_set_timing", "dbsim_get_stats", "dbsim_destroy",
-            "dbsim_derive_constants", "dbsim_export_network", "dbsim_create_static"]
+            "dbsim_derive_constants", "dbsim_export_network", "dbsim_create_static", "dbsim_receptor_currents",
+            "dbsim_build", "dbsim_create_built", "dbsim_built_free"]
 
 
 def lib():
@@ -144,6 +146,9 @@ def lib():
     L.dbsim_last_error.restype = c_char_p
     L.dbsim_create.argtypes = [POINTER(SimDesc), POINTER(c_void_p)]
     L.dbsim_create_static.argtypes = [POINTER(SimDesc), POINTER(c_void_p)]
+    L.dbsim_build.argtypes = [POINTER(SimDesc), POINTER(c_void_p)]
+    L.dbsim_create_built.argtypes = [c_void_p, POINTER(SimDesc), POINTER(c_void_p)]
+    L.dbsim_built_free.argtypes = [c_void_p]
     L.dbsim_footprint.argtypes = [POINTER(SimDesc), POINTER(c_uint64)]
     L.dbsim_get_info.argtypes = [H, POINTER(SimInfo)]
     L.dbsim_create_ensemble.argtypes = [POINTER(SimDesc), POINTER(Desc), c_uint32, POINTER(c_void_p)]
@@ -165,6 +170,7 @@ def lib():
                                          POINTER(c_uint32)]
     L.dbsim_export_network.argtypes = [H, POINTER(NetworkView)]
     L.dbsim_set_timing.argtypes = [H, c_int]
+    L.dbsim_receptor_currents.argtypes = [H, POINTER(c_double), c_uint32]
     L.dbsim_get_stats.argtypes = [H, POINTER(SimStats)]
     L.dbsim_destroy.argtypes = [H]
     L.dbsim_bold_defaults.argtypes = [POINTER(BoldParams)]
@@ -175,8 +181,9 @@ def lib():
     L.dbsim_set_spike_injection.argtypes = [H, POINTER(c_float), c_uint32, c_uint64]
     L.dbsim_set_ou_background.argtypes = [H, POINTER(c_float), POINTER(c_float), POINTER(c_float), c_uint32]
     for nm in EXPORTED:
-        if nm not in ("dbsim_abi_version", "dbsim_last_error"):
+        if nm not in ("dbsim_abi_version", "dbsim_last_error", "dbsim_built_free"):
             getattr(L, nm).restype = c_int
+    L.dbsim_built_free.restype = None
     if L.dbsim_abi_version() != ABI_VERSION:
         raise RuntimeError("libdbsim ABI version mismatch")
     _LIB = L
@@ -218,7 +225,8 @@ class _TorchAllocator:
 
 def make_desc(spec: NetSpec, record_regions: bool = True, spike_record_capacity: int = 0, record_bins: int = 0,
               device: int = -1, stream_handle: Optional[int] = None, allocator: Optional[_TorchAllocator] = None,
-              host_threads: int = 0, no_graph: bool = False, two_pass: bool = False):
+              host_threads: int = 0, no_graph: bool = False, two_pass: bool = False, host_record: bool = True,
+              host_spike_capacity: int = 0):
     holder = spec.to_c()
     d = SimDesc()
     d.abi_version = ABI_VERSION
@@ -232,7 +240,8 @@ def make_desc(spec: NetSpec, record_regions: bool = True, spike_record_capacity:
         d.dev_alloc = allocator.alloc
         d.dev_free = allocator.free
     d.host_threads = int(host_threads)
-    d.flags = (F_NO_GRAPH if no_graph else 0) | (F_TWO_PASS if two_pass else 0)
+    d.flags = (F_NO_GRAPH if no_graph else 0) | (F_TWO_PASS if two_pass else 0) | (0 if host_record else F_NO_HOST_RECORD)
+    d.host_spike_capacity = int(host_spike_capacity)
     return d, holder
 
 
@@ -274,6 +283,41 @@ def derive_constants(spec, **kw) -> list:
     return [out[q].as_dict(U) for q in range(n.value)]
 
 
+class Built:
+    """A network built on the host (dbsim_build: validation, plan and every table; no HIP
+    call, so worker threads may build while another thread drives the GPU). Simulator(...,
+    built=b) deploys it (dbsim_create_built), which consumes it."""
+
+    def __init__(self, spec: NetSpec, record_regions: bool = True, spike_record_capacity: int = 0,
+                 record_bins: int = 0, host_threads: Optional[int] = None, no_graph: bool = False,
+                 two_pass: bool = False, host_record: bool = True, host_spike_capacity: int = 0):
+        if host_threads is None:
+            host_threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+        self.spec = spec
+        self._desc, self._holder = make_desc(spec, record_regions, spike_record_capacity, record_bins, -1, None, None,
+                                             host_threads, no_graph, two_pass, host_record, host_spike_capacity)
+        h = c_void_p()
+        _check(lib().dbsim_build(byref(self._desc), byref(h)))
+        self._b = h
+
+    def take(self):
+        b, self._b = self._b, None
+        if not b:
+            raise ValueError("this built network was already deployed or freed")
+        return b
+
+    def free(self) -> None:
+        if getattr(self, "_b", None):
+            lib().dbsim_built_free(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
 class Simulator:
     """One network (a NetSpec) or an ensemble (a list of NetSpec) on one GPU, driven
     through the C ABI.
@@ -284,11 +328,17 @@ class Simulator:
     id range and member_spikes / member_state its own view.
     static_region: create with dbsim_create_static (no device allocation; the device's
     static region of STATIC_BYTES, one such handle per device at a time).
+    host_record: record every bin's spikes into a pinned host ring of host_spike_capacity
+    entries (0: the library default), from which spikes() reads; off, spikes() copies from
+    the device ring.
+    built: deploy a network built on the host (Built, made from this same spec); the build's
+    recording and form options apply, this call's device, stream and allocator.
     """
 
     def __init__(self, spec: NetSpec, record_regions: bool = True, use_torch: bool = True, device: int = 0,
                  spike_record_capacity: int = 0, record_bins: int = 0, host_threads: Optional[int] = None,
-                 no_graph: bool = False, stream=None, two_pass: bool = False, static_region: bool = False):
+                 no_graph: bool = False, stream=None, two_pass: bool = False, static_region: bool = False,
+                 host_record: bool = True, host_spike_capacity: int = 0, built: Optional["Built"] = None):
         L = lib()
         if host_threads is None:
             # the process's CPU share (OMP_NUM_THREADS) rather than every core of the machine
@@ -308,11 +358,16 @@ class Simulator:
         self.specs = list(spec) if isinstance(spec, (list, tuple)) else [spec]
         first = self.specs[0]
         self._desc, self._holder = make_desc(first, record_regions, spike_record_capacity, record_bins, device,
-                                             stream_handle, self._alloc, host_threads, no_graph, two_pass)
+                                             stream_handle, self._alloc, host_threads, no_graph, two_pass,
+                                             host_record, host_spike_capacity)
         h = c_void_p()
         if isinstance(spec, (list, tuple)):
             self._members, self._member_holders = _member_array(self.specs)
             _check(L.dbsim_create_ensemble(byref(self._desc), self._members, len(self.specs), byref(h)))
+        elif built is not None:  # the device phase of a network built on the host
+            if built.spec is not spec:
+                raise ValueError("built was made from another description")
+            _check(L.dbsim_create_built(built.take(), byref(self._desc), byref(h)))
         elif static_region:
             _check(L.dbsim_create_static(byref(self._desc), byref(h)))
         else:
@@ -457,6 +512,14 @@ class Simulator:
         ref = np.zeros(self.N, np.int32)
         _check(lib().dbsim_read_state(self._h, _p(V, c_float), _p(J, c_float), _p(ref, c_int32)))
         return V, J.reshape(self.U, self.N), ref
+
+    def receptor_currents(self) -> np.ndarray:
+        """[n_pops, 4] mean current per receptor (AMPA, NMDA, GABA_A, GABA_B) of every
+        population at the current state, reduced on the device (Suppl. Algorithm 1)."""
+        n = sum(len(sp.pops) for sp in self.specs)
+        out = np.zeros(4 * n, np.float64)
+        _check(lib().dbsim_receptor_currents(self._h, _p(out, c_double), n))
+        return out.reshape(n, 4)
 
     def write_state(self, V, J, ref) -> None:
         V = np.ascontiguousarray(V, np.float32)

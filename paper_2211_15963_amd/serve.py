@@ -9,8 +9,10 @@ a seeded network description plus a biological duration. The server:
   device footprints (dbsim_footprint) stays within an HBM budget and fewer than
   max_active are resident; a request that does not fit waits (no skipping ahead, so
   no request starves);
-* builds admitted networks on a pool of host threads (network construction is the
-  host's job and overlaps with device work), each onto its own HIP stream;
+* builds admitted networks' host tables on a pool of host threads (dbsim_build: no HIP
+  call, so construction overlaps with device work), then deploys each from the serving
+  thread onto its own HIP stream (dbsim_create_built): every HIP call of the server - and
+  torch's - is made by that one thread;
 * keeps every admitted network's state resident and advances all of them in slices
   of slice_bins bins, keeping up to two slices queued per stream, so the kernels of
   different requests overlap on the device;
@@ -32,7 +34,7 @@ from typing import Dict, List, Optional
 
 import numpy as np
 
-from .dbsim import DbsimError, Simulator, footprint
+from .dbsim import Built, DbsimError, Simulator, footprint
 
 
 @dataclass
@@ -54,18 +56,23 @@ class Request:
         return self.t_done - self.arrival_s
 
 
-def summarize(sim: Simulator, with_state_digest: bool = True) -> Dict:
+def summarize(sim: Simulator, with_state_digest: bool = True, full: bool = False) -> Dict:
     """Result of a finished request: counters, per-bin spike counts (all regions) and a
-    digest of the final state (V, J, refractory counters)."""
+    digest of the final state (V, J, refractory counters); with full=True also the raster
+    (steps, ids) and the final state arrays."""
     st = sim.stats()
     _, cnt = sim.region_signal()
     out = {"steps": st["steps"], "bins": st["bins"], "spikes": st["spikes"], "edge_events": st["edge_events"],
            "bin_spikes": cnt.sum(axis=1).astype(np.int64)}
+    state = sim.state() if (with_state_digest or full) else None
     if with_state_digest:
         h = hashlib.sha256()
-        for a in sim.state():
+        for a in state:
             h.update(np.ascontiguousarray(a).tobytes())
         out["state_sha256"] = h.hexdigest()
+    if full:
+        out["raster"] = sim.spikes()
+        out["state"] = state
     return out
 
 
@@ -81,7 +88,7 @@ class _Active:
 class Server:
     def __init__(self, hbm_budget: Optional[int] = None, max_active: int = 16, slice_bins: int = 25,
                  build_workers: int = 2, build_threads: Optional[int] = None, device: int = 0,
-                 state_digest: bool = True):
+                 state_digest: bool = True, full_results: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible to torch")
@@ -101,14 +108,17 @@ class Server:
             build_threads = max(1, total // max(1, self.build_workers))
         self.build_threads = int(build_threads)
         self.state_digest = state_digest
+        self.full_results = full_results
 
-    def _build(self, req: Request):
-        torch = self.torch
-        torch.cuda.set_device(self.device)
-        stream = torch.cuda.Stream(device=self.device)  # default priority
+    def _build(self, req: Request) -> Built:
+        """Host phase, on a pool thread: validation, plan and tables; no HIP or torch call."""
         bins = -(-req.n_steps // req.spec.steps_per_bin)
-        sim = Simulator(req.spec, record_regions=True, device=self.device, stream=stream,
-                        host_threads=self.build_threads, record_bins=max(4096, bins))
+        return Built(req.spec, record_regions=True, host_threads=self.build_threads, record_bins=max(4096, bins))
+
+    def _deploy(self, req: Request, built: Built):
+        """Device phase, on the serving thread: its own stream, memory from torch, upload."""
+        stream = self.torch.cuda.Stream(device=self.device)  # default priority
+        sim = Simulator(req.spec, record_regions=True, device=self.device, stream=stream, built=built)
         return sim, stream
 
     def run(self, requests: List[Request], poll_s: float = 2e-4) -> Dict:
@@ -150,12 +160,12 @@ class Server:
                     r.t_admit = now
                     building[pool.submit(self._build, r)] = r
                     progressed = True
-                # finished builds join the active set
+                # finished builds are deployed (here, on the serving thread) and join the active set
                 for fut in [f for f in building if f.done()]:
                     r = building.pop(fut)
                     try:
-                        sim, stream = fut.result()
-                    except Exception as ex:  # a failed build retires the request with its error
+                        sim, stream = self._deploy(r, fut.result())
+                    except Exception as ex:  # a failed build or deploy retires the request with its error
                         r.error = str(ex)
                         r.t_done = time.perf_counter() - t0
                         in_use -= r.footprint
@@ -189,7 +199,7 @@ class Server:
                         if a.req.error is None:
                             try:
                                 a.sim.sync()
-                                a.req.result = summarize(a.sim, self.state_digest)
+                                a.req.result = summarize(a.sim, self.state_digest, self.full_results)
                             except DbsimError as ex:
                                 a.req.error = str(ex)
                         a.sim.close()
@@ -209,7 +219,7 @@ class Server:
                 a.sim.close()
             for fut in building:
                 if fut.done() and fut.exception() is None:
-                    fut.result()[0].close()
+                    fut.result().free()
         wall = time.perf_counter() - t0
         ok = [r for r in done if r.error is None]
         lat = np.array([r.latency_s for r in ok]) if ok else np.zeros(1)

@@ -17,8 +17,11 @@ from .dbsim import DbsimError, Simulator
 
 
 def candidates(sim: Simulator) -> List[Tuple[int, int, int]]:
+    """(workgroups per CU, round-size divisor, chunks per workgroup). The single-pass form
+    runs one or two workgroups of 1,024 threads per CU; the two-pass form two to eight of 512."""
     out = []
-    for wgs in (2, 4, 6, 8):
+    wgs_set = (1, 2) if sim.info.fanin_passes == 1 else (2, 4, 6, 8)
+    for wgs in wgs_set:
         for cpw in (1, 4):
             for re_div in (1, 2):
                 out.append((wgs, re_div, cpw))

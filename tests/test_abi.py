@@ -53,6 +53,7 @@ int main(void) {
   P(dbnet_pop); P(dbnet_proj); P(dbnet_desc); P(dbsim_desc); P(dbsim_stats); P(dbsim_info);
   O(dbnet_desc, seed); O(dbnet_desc, pops); O(dbnet_desc, region_xyz_mm);
   O(dbsim_desc, net); O(dbsim_desc, spike_record_capacity); O(dbsim_desc, hip_stream); O(dbsim_desc, flags);
+  O(dbsim_desc, host_spike_capacity);
   O(dbsim_stats, ms_scatter); O(dbsim_stats, build_seconds); O(dbsim_info, frac_bits); O(dbsim_info, n_members);
   O(dbsim_info, fanin_passes);
   P(dbsim_member); O(dbsim_member, first_region);
@@ -80,6 +81,7 @@ def test_struct_layouts_match_ctypes(L):
     assert int(out["dbsim_desc.net"]) == D.SimDesc.net.offset
     assert int(out["dbsim_desc.hip_stream"]) == D.SimDesc.hip_stream.offset
     assert int(out["dbsim_desc.flags"]) == D.SimDesc.flags.offset
+    assert int(out["dbsim_desc.host_spike_capacity"]) == D.SimDesc.host_spike_capacity.offset
     assert int(out["dbsim_stats.ms_scatter"]) == D.SimStats.ms_scatter.offset
     assert int(out["dbsim_info.frac_bits"]) == D.SimInfo.frac_bits.offset
     assert int(out["dbsim_info.n_members"]) == D.SimInfo.n_members.offset
@@ -132,19 +134,26 @@ def test_footprint_matches_layout(L):
     fp = D.footprint(s)
     E = s.num_edges()
     assert E == 100000 * 556
-    # dominant terms: targets (4 B), two weights (8 B) and the tile arena record (12 B) per
-    # edge; 25 tiles of 4096 neurons are written directly in 16-record chunks, with room
-    # for one padded chunk per partition workgroup (at most 2048) and launch (two per bin)
-    # in every tile slice
-    pad = 25 * (15 + 2 * 16 * 2048) * 12
-    assert 24 * E + pad < fp < 24 * E + pad + 60 * 100000 + (64 << 20)
-    # 1490 tiles are too many for the write-combining buffers: two passes, with a 12 B
-    # super-tile stream record per edge as well
+    # single pass: 12 B per edge (target and two weights), and the event arena of 256-record
+    # blocks (2 B key + 8 B weights + a 4 B count per block): every one of the 25 tiles of 4096
+    # neurons gets its in-degree in whole blocks plus two part-filled blocks per workgroup (at
+    # most 512) and bin
+    def arena(n, k, T, K=256, G=512):
+        tin = [k * (min(n, (t + 1) * 4096) - t * 4096) for t in range(T)]
+        blocks = sum(x // K + 2 * G for x in tin)
+        return blocks * K * 10 + blocks * 4
+    lo = 12 * E + arena(100000, 556, 25)
+    assert lo < fp < lo + 60 * 100000 + (64 << 20)
+    # 1490 tiles still fit the carry buffers (8 records each)
     s = configs.share(n=6100000, indegree=20)
     fp, E = D.footprint(s), s.num_edges()
+    lo = 12 * E + arena(6100000, 20, 1490)
     # per neuron: a 64 B row header, the state, and the spike-history ring of at least
     # (D + 1) N entries rounded up to a power of two
-    assert 36 * E < fp < 36 * E + 220 * 6100000 + (64 << 20)
+    assert lo < fp < lo + 220 * 6100000 + (64 << 20)
+    # forced through two passes: 12 B super-tile stream and 12 B arena records per edge
+    fp2 = D.footprint(s, two_pass=True)
+    assert 36 * E < fp2 < 36 * E + 220 * 6100000 + (64 << 20)
 
 
 def test_ensemble_footprint_and_validation(L):
@@ -156,3 +165,27 @@ def test_ensemble_footprint_and_validation(L):
     c = configs.tiny()   # two receptors: cannot share kernels with four-receptor members
     with pytest.raises(D.DbsimError, match="share dt_ms"):
         D.footprint([a, c])
+
+
+def test_host_build_phase_runs_on_threads_without_a_device(L):
+    """dbsim_build makes no HIP call: several networks build at once on worker threads (as the
+    server does) on a machine without a GPU; deploying one here fails cleanly (no device) and
+    consumes it; an unused build is freed."""
+    import concurrent.futures as cf
+    from paper_2211_15963_amd import dbsim as D
+    specs = [configs.share(n=3000 + 500 * k, indegree=80, seed=40 + k) for k in range(4)] + [configs.tiny(seed=44)]
+    with cf.ThreadPoolExecutor(max_workers=3) as ex:
+        built = list(ex.map(lambda s: D.Built(s, host_threads=2), specs))
+    assert all(b._b for b in built)
+    b = built[0]
+    h = ctypes.c_void_p()
+    d, holder = D.make_desc(specs[0])
+    rc = L.dbsim_create_built(b.take(), ctypes.byref(d), ctypes.byref(h))
+    assert rc == D.EDEVICE and not h.value
+    for b in built[1:]:
+        b.free()
+    bad = configs.tiny()
+    bad.pops[0].T_ref = 0.5
+    with pytest.raises(D.DbsimError) as e:
+        D.Built(bad)
+    assert e.value.code == D.EINVAL and "T_ref" in str(e.value)

@@ -1,5 +1,5 @@
 """Region BOLD on the GPU vs the FP64 Balloon-Windkessel oracle, fed with the same
-per-bin region spike counts.
+per-bin region spike counts (the GPU's, and the FP32 oracle's own).
 
 Tolerance: both sides evaluate the same FP64 expressions in the same order (no FMA);
 only pow() may differ by an ulp between the device and host math libraries. The
@@ -53,6 +53,36 @@ def test_bold_matches_oracle():
     sim.step(100 * sim.S)
     assert sim.bold_state()[1] == 0
     sim.close()
+
+
+def test_bold_from_the_oracles_own_counts():
+    """The whole chain against the oracles alone: the FP32 oracle simulates the network, its
+    per-bin region spike counts drive the FP64 Balloon-Windkessel oracle, and the GPU's BOLD
+    samples (computed on the device from the GPU's own counts) must match."""
+    from oracle import Oracle
+    from paper_2211_15963_amd import Simulator
+    from paper_2211_15963_amd.dbsim import bold_defaults
+    spec = configs.multi_region(n_regions=6, per_region=600, seed=9)
+    bins = 1200
+    _say(f"multi-region 6 x 600: BOLD with TR = 40 bins over {bins} bins, counts from the FP32 oracle")
+    sim = Simulator(spec, record_regions=True)
+    p = bold_defaults(tr_bins=40, activity_scale=0.02)
+    sim.set_bold(p)
+    sim.step(bins * sim.S)
+    y_gpu = sim.bold()
+    st_gpu, n = sim.bold_state()
+    sim.close()
+    orc = Oracle(spec, 32)
+    orc.step(bins * spec.steps_per_bin)
+    _, counts = orc.region_signal()
+    assert counts.shape == (bins, 6) and counts.sum() > 0
+    sizes = np.bincount(spec.region_of_neuron(), minlength=spec.n_regions)
+    y_orc, st_orc = obold.run(counts, sizes, p.as_dict(), spec.bin_ms)
+    assert n == bins // 40 and y_gpu.shape == y_orc.shape
+    scale = np.max(np.abs(y_orc))
+    assert scale > 0
+    assert np.max(np.abs(y_gpu - y_orc)) <= 1e-10 * scale
+    assert np.allclose(st_gpu, st_orc, rtol=1e-10, atol=1e-14)
 
 
 def test_bold_requires_regions_and_valid_params():

@@ -12,7 +12,12 @@ sample of neurons, that
 
 and, over the whole network, properties that hold at any size: at most one spike per
 neuron per bin, ids in range, delivered events equal the summed delay-segment lengths
-of the recorded spikes.
+of the recorded spikes; the record is complete (the neurons whose refractory counter at
+the start of each of the last three bins says they fired in the bin before, and at which
+step, are exactly that bin's recorded spikes); and every region's signal for the last
+bin equals its definition evaluated on the recorded state (the mean over the region of
+each neuron's FP32 current sum_u (g_u J_u)(V_u - V), summed in double), within the
+rounding bound of two summation orders.
 """
 import sys
 
@@ -32,12 +37,17 @@ def _say(msg):
 def _run_and_check(spec, K, n_sample=1500, seed=0):
     from paper_2211_15963_amd import Simulator
     _say(f"{spec.name}: building {spec.num_neurons} neurons / {spec.num_edges()} synapses")
-    sim = Simulator(spec, record_regions=True, spike_record_capacity=1 << 26)
+    sim = Simulator(spec, record_regions=True, host_spike_capacity=1 << 26)
     S = sim.S
     _say(f"{spec.name}: built; running {K} bins")
-    sim.step(K * S)
+    sim.step((K - 3) * S)
+    refs = {}
+    for b in range(K - 3, K):
+        sim.step(S)
+        V0, J0, r0 = sim.state()
+        refs[b] = r0  # state at the start of bin b + 1
     st, ids = sim.spikes()
-    V0, J0, r0 = sim.state()
+    sig, _ = sim.region_signal(K - 1, K)
     sim.step(1)
     V1, J1, r1 = sim.state()
     stats = sim.stats()
@@ -58,8 +68,45 @@ def _run_and_check(spec, K, n_sample=1500, seed=0):
         sel = bins + d <= K
         want += int(seglen[ids[sel], d - 1].sum())
     assert stats["edge_events"] == want
+    _check_record_complete(spec, S, st, ids, refs)
+    _check_region_signal(spec, V0, J0, sig[0])
+    _say(f"{spec.name}: spike record complete over the last 3 bins; region signals equal their definition")
     _check_points(spec, K, S, st, ids, (V0, J0, r0), (V1, J1, r1), n_sample, seed)
     _say(f"{spec.name}: {n_sample} sampled neurons bit-identical after the bin-start step")
+
+
+def _check_record_complete(spec, S, st, ids, refs):
+    """A neuron that fired at step n of bin b (n in bS .. bS + S - 1) holds r - ((b + 1) S - 1 - n)
+    refractory steps at the start of bin b + 1 (r = round(T_ref / dt) >= S), one that fired
+    earlier holds at most r - S: the counters name every spike of bin b and its step."""
+    from paper_2211_15963_amd.dbsim import derive_constants
+    N = spec.num_neurons
+    r = np.zeros(N, np.int64)
+    for p in derive_constants(spec):
+        r[p["first_neuron"]:p["end_neuron"]] = p["ref_steps"]
+    assert r.min() >= S
+    for b, ref in refs.items():
+        ref = ref.astype(np.int64)
+        fired = np.nonzero(ref >= r - S + 1)[0]
+        steps = (b + 1) * S - 1 - (r[fired] - ref[fired])
+        sel = (st // S) == b
+        got = sorted(zip(st[sel].tolist(), ids[sel].tolist()))
+        want = sorted(zip(steps.tolist(), fired.tolist()))
+        assert got == want, f"bin {b}: recorded spikes differ from those the refractory counters imply"
+
+
+def _check_region_signal(spec, V, J, sig):
+    from paper_2211_15963_amd.dbsim import derive_constants
+    cur = np.zeros(spec.num_neurons, np.float32)
+    for p in derive_constants(spec):
+        a, b = p["first_neuron"], p["end_neuron"]
+        for u in range(len(p["g"])):
+            cur[a:b] = cur[a:b] + (p["g"][u] * J[u, a:b]) * (p["V_rev"][u] - V[a:b])
+    reg = spec.region_of_neuron()
+    n_reg = np.bincount(reg, minlength=spec.n_regions)
+    want = np.bincount(reg, weights=cur.astype(np.float64), minlength=spec.n_regions) / n_reg
+    bound = n_reg * np.finfo(np.float64).eps * 1e5
+    assert np.all(np.abs(sig - want) <= bound), np.max(np.abs(sig - want) / bound)
 
 
 def _check_points(spec, K, S, st, ids, before, after, n_sample, seed):
@@ -98,8 +145,8 @@ def test_ensemble_full_size_sampled():
     from paper_2211_15963_amd import Simulator
     members = [configs.ensemble_member(m, seed=0) for m in range(64)]
     _say(f"ensemble: building 64 members, {sum(s.num_neurons for s in members)} neurons")
-    ens = Simulator(members, record_regions=True, spike_record_capacity=1 << 27)
-    ens.set_tuning(scatter_wgs_per_cu=2, round_events=0, chunks_per_wg=1)
+    ens = Simulator(members, record_regions=True, host_spike_capacity=1 << 27)
+    ens.set_tuning(scatter_wgs_per_cu=ens.tuning()["scatter_wgs_per_cu"], round_events=0, chunks_per_wg=1)
     S = ens.S
     K = 30
     _say(f"ensemble: built; running {K} bins")

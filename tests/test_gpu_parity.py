@@ -132,7 +132,7 @@ def test_mixed_launch_sequence_bit_exact(Sim):
                 ("tune", 0), ("graph", 12 * S), ("timed", 5), ("step", 2 * S - 5)]
         for what, n in plan:
             if what == "tune":
-                sim.set_tuning(scatter_wgs_per_cu=3, round_events=0, chunks_per_wg=2, ahead_passes=0)
+                sim.set_tuning(scatter_wgs_per_cu=2, round_events=0, chunks_per_wg=2, ahead_passes=0)
                 continue
             sim.set_timing(what == "timed")
             sim.step(n)
@@ -346,3 +346,38 @@ def test_spike_injection_bit_exact(Sim):
         orc.step(30 * S)
         _compare(sim, orc, spec)
         sim.close()
+
+
+def test_host_record_with_minimal_device_ring(Sim):
+    """Every bin's spikes are copied to the pinned host ring while the device keeps only the
+    last max delay + 1 bins the fan-in reads: over 1 s the device ring (2,048 entries) wraps
+    several times and the raster read back still equals the oracle's; a host ring smaller
+    than the raster keeps its most recent part and refuses older reads."""
+    from paper_2211_15963_amd import dbsim as D
+    spec = configs.tiny(seed=17)
+    _say("tiny seed 17, 1 s, device ring at its minimum, raster from the host ring")
+    sim = Sim(spec)
+    sim.step(10000)
+    orc = Oracle(spec, 32)
+    orc.step(10000)
+    assert orc.spikes()[0].size > 4 * 2048  # the device ring wrapped at least four times
+    _compare(sim, orc, spec)
+    sim.close()
+    spec = configs.share(n=20000, indegree=300, seed=18)
+    S = spec.steps_per_bin
+    _say("share 20000 / k300 seed 18: host ring of 4096 entries, 60 bins, graph and partial launches")
+    sim = Sim(spec, host_spike_capacity=4096)
+    sim.step(30 * S)
+    sim.step(7)
+    sim.step(30 * S - 7)
+    orc = Oracle(spec, 32)
+    orc.step(60 * S)
+    so, io = orc.spikes()
+    keep = so >= 55 * S
+    assert 0 < keep.sum() <= 4096 and len(so) > 4096
+    st, ids = sim.spikes(55 * S, 60 * S)
+    assert np.array_equal(st, so[keep]) and np.array_equal(ids, io[keep])
+    with pytest.raises(D.DbsimError) as ex:
+        sim.spikes(0, 10 * S)
+    assert ex.value.code == D.ERANGE
+    sim.close()

@@ -1,6 +1,7 @@
 """Served stream: requests admitted by footprint and overlapped on the device give
 the same bits as each request run alone (every handle is independent and
-deterministic), and admission respects the HBM budget and the slot limit."""
+deterministic) and, for small requests, as the FP32 oracle; admission respects the
+HBM budget and the slot limit."""
 import sys
 
 import numpy as np
@@ -58,6 +59,34 @@ def test_served_results_equal_alone():
     for r in sorted(out["requests"], key=lambda r: r.rid):
         _say(f"  request {r.rid}: {r.spec.num_neurons} neurons, latency {r.latency_s:.3f} s; alone run")
         _same(r.result, _alone(r))
+
+
+def test_served_results_equal_the_oracle():
+    """Two small requests served among larger ones (overlapping on the device with them)
+    against the FP32 oracle: raster, final V, J, refractory counters and delivered events
+    bit for bit."""
+    from oracle import Oracle
+    from paper_2211_15963_amd.serve import Request, Server
+    reqs = _requests(4, seed=15, n_hi=6e4, d_hi_s=0.1, gap_s=0.01)
+    for k, rid in enumerate((4, 5)):
+        spec, _ = configs.served_request(rid, seed=15, n_lo=2000, n_hi=4000)
+        reqs.insert(1 + 2 * k, Request(rid, spec, 40 * spec.steps_per_bin, arrival_s=0.005 + 0.01 * k))
+    _say(f"serve 6 requests, sizes {[r.spec.num_neurons for r in reqs]}; requests 4 and 5 against the oracle")
+    out = Server(max_active=4, slice_bins=10, build_workers=2, full_results=True).run(reqs)
+    assert out["completed"] == 6
+    for r in out["requests"]:
+        if r.rid not in (4, 5):
+            continue
+        orc = Oracle(r.spec, 32)
+        orc.step(r.n_steps)
+        so, io = orc.spikes()
+        sg, ig = r.result["raster"]
+        assert len(so) > 0 and np.array_equal(sg, so) and np.array_equal(ig, io), f"request {r.rid}: raster"
+        Vo, Jo, ro = orc.state()
+        Vg, Jg, rg = r.result["state"]
+        assert np.array_equal(Vg.astype(np.float64), Vo) and np.array_equal(Jg.astype(np.float64), Jo)
+        assert np.array_equal(rg, ro) and r.result["edge_events"] == orc.edge_events
+        _say(f"  request {r.rid} ({r.spec.num_neurons} neurons, {len(so)} spikes): bit-identical to the oracle")
 
 
 def test_admission_by_footprint():

@@ -577,3 +577,44 @@ def test_threaded_oracle_equals_one_thread():
     for x, y in zip(a.spikes() + a.state() + a.region_signal(), b.spikes() + b.state() + b.region_signal()):
         assert np.array_equal(x, y)
     assert a.edge_events == b.edge_events > 0
+
+
+def test_receptor_currents_exact_case_and_structure():
+    """Suppl. Algorithm 1's measurement, pinned by an exactly representable case: conductances
+    and reversal potentials chosen so that every term g_u J_u (V_u - V) is a small integer
+    times a power of two (exact in float and double), so each population's mean is an exact
+    rational; plus the structure (only the receptor and population given a conductance report
+    a current; doubling J doubles every mean exactly)."""
+    from fractions import Fraction
+    from netgen.desc import NetSpec, PopSpec, RECEPTORS_4
+    g = (0.5, 0.25, 1.0, 2.0)
+    Vr = (0.0, 0.0, -64.0, -96.0)
+    pops = [PopSpec(37, True, g=g, V_rev=Vr), PopSpec(23, False, g=g, V_rev=Vr), PopSpec(11, True, g=g, V_rev=Vr)]
+    spec = NetSpec(pops, [], seed=3, receptor_mask=RECEPTORS_4, name="receptor-pin")
+    N = spec.num_neurons
+    rng = np.random.default_rng(7)
+    V = -32.0 + rng.integers(-4, 5, N) * 8.0          # multiples of 8 mV around -32
+    J = rng.integers(0, 9, (4, N)).astype(np.float64)  # small integers
+    for prec in (32, 64):
+        o = Oracle(spec, prec)
+        o.set_state(V, J)
+        got = o.receptor_currents()
+        off = spec.pop_offsets()
+        for q in range(len(pops)):
+            a, b = off[q], off[q + 1]
+            for u in range(4):
+                want = sum(Fraction(g[u]) * Fraction(J[u, i]) * (Fraction(Vr[u]) - Fraction(V[i])) for i in range(a, b))
+                assert got[q, u] == float(want / (b - a)), (prec, q, u)
+        o.set_state(V, 2 * J)
+        assert np.array_equal(o.receptor_currents(), 2 * got)
+        J1 = np.zeros_like(J)
+        J1[2, off[1]:off[2]] = J[2, off[1]:off[2]]
+        o.set_state(V, J1)
+        only = o.receptor_currents()
+        assert only[1, 2] == got[1, 2] and np.count_nonzero(only) == (1 if got[1, 2] else 0)
+    # two receptors (one weight per edge): AMPA and GABA_A slots, NMDA and GABA_B zero
+    spec2 = configs.tiny(seed=4)
+    o = Oracle(spec2, 32)
+    o.step(200)
+    c = o.receptor_currents()
+    assert np.all(c[:, [1, 3]] == 0.0) and np.all(c[:, 0] > 0) and np.all(c[:, 2] < 0)
