@@ -638,8 +638,7 @@ def main():
     ap.add_argument("--small-configs", type=int, default=1,
                     help="also time the tiny and the 200-region networks (real-time factor)")
     ap.add_argument("--members", type=int, default=64)
-    ap.add_argument("--serve", type=int, default=0,
-                    help="also run the served-stream leg (off by default: see the design notes)")
+    ap.add_argument("--serve", type=int, default=1, help="also run the served-stream leg")
     ap.add_argument("--serve-rate", type=float, default=50.0, help="offered request arrivals per second")
     ap.add_argument("--serve-requests", type=int, default=24, help="arrivals in the offered-rate window")
     ap.add_argument("--serve-slots", type=int, default=16, help="most requests resident at once")

@@ -88,9 +88,11 @@ typedef struct dbsim_desc {
 #define DBSIM_F_NO_GRAPH 1u /* launch kernels directly instead of replaying HIP graphs */
 #define DBSIM_F_NO_HOST_RECORD 4u /* keep the raster only in the device ring (no pinned host
                                      memory; reads copy from the device) */
-#define DBSIM_F_TWO_PASS 2u /* fan-in through super-tile streams even where the tiles' carry
-                               buffers fit the single-pass kernel's LDS (same results; for tests
-                               and comparisons) */
+#define DBSIM_F_SINGLE_PASS 2u /* fan-in in one pass into per-workgroup blocks of each tile
+                                  (no super-tile streams: about a third less device memory,
+                                  slower on every measured network); taken where the tiles'
+                                  carry buffers fit one workgroup's LDS (up to about 2,900
+                                  tiles), else the default two passes. Same results. */
 
 typedef struct dbsim_stats {
     uint64_t steps;        /* Euler steps completed (queued) */
@@ -335,9 +337,33 @@ int dbsim_set_ou_background(struct dbsim* h, const float* mu, const float* sigma
  */
 int dbsim_receptor_currents(struct dbsim* h, double* mean, uint32_t n_pops);
 
-/* Overwrites the state (checkpoint restore). Only at a bin boundary (ESTATE
-   otherwise). ref values must lie in [0, 255]. */
+/* Overwrites V, J and the refractory counters of this handle. Only at a bin boundary
+   (ESTATE otherwise). ref values must lie in [0, 255]. */
 int dbsim_write_state(struct dbsim* h, const float* V, const float* J, const int32_t* ref);
+
+/*
+ * Checkpoint and resume of a run (a long simulation continued in another process or
+ * after a failure; the clock-driven step of SI Section 3 depends only on this state).
+ * A checkpoint is an opaque byte image of everything the coming bins depend on, taken
+ * at a bin boundary (ESTATE otherwise): V, J, refractory counters, OU currents, the
+ * per-population settings (spike injection, OU background), the spike lists of the last
+ * max-delay bins (the fan-in of the coming bins reads them), the counters (steps, bins,
+ * spikes, delivered events) and, when the BOLD model is on, its parameters, state and
+ * sample ring.
+ *
+ * dbsim_checkpoint_size: the image's size now (synchronises).
+ * dbsim_checkpoint_save: writes it to buf (host memory, caller-owned, cap bytes);
+ *   *n_out = the size; ETRUNC if cap is smaller.
+ * dbsim_checkpoint_restore: loads an image into a handle created from the same network
+ *   description that has not been stepped (ESTATE otherwise); EINVAL for an image of
+ *   another network (sizes, descriptions and a sample of the connection table are
+ *   compared) or a damaged one. The handle then continues bit-identically to the saved
+ *   one. Its spike and region-signal history starts at the checkpoint's bin (earlier bins:
+ *   ERANGE); its tuning, timing and launch mode stay its own.
+ */
+int dbsim_checkpoint_size(struct dbsim* h, uint64_t* bytes);
+int dbsim_checkpoint_save(struct dbsim* h, void* buf, uint64_t cap, uint64_t* n_out);
+int dbsim_checkpoint_restore(struct dbsim* h, const void* buf, uint64_t len);
 
 /*
  * Host copy of the device connection table: row_ptr[N+1] (edge offsets of

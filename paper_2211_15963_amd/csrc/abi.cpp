@@ -6,6 +6,7 @@
 #include <array>
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -114,6 +115,7 @@ struct dbsim {
     hipGraphExec_t g_multi = nullptr;
     hipGraphExec_t g_one = nullptr;
     uint64_t step = 0;
+    uint64_t first_bin = 0; // first bin whose spikes and region signal can be read (restores)
     int dead = 0; // sticky error code
     bool timing = false;
     std::vector<std::array<hipEvent_t, kMarks>> ev_pending;
@@ -248,13 +250,14 @@ hipError_t enqueue_bin_start(dbsim* h, hipStream_t st) {
     return launch_gather(h->net, st);
 }
 
+// The next bin's delay >= 2 fan-in on `st`, after this bin's gather (which empties the
+// super-tile streams). Two-pass form: consecutive delay groups, one partition pass
+// (k_part + k_bucket) each, with a reset between two passes.
 hipError_t enqueue_ahead(dbsim* h, hipStream_t st) {
     const uint32_t D = h->plan.D;
     if (D < 2) return hipSuccess;
-    // two-pass form: consecutive delay groups, one partition pass (k_part + k_bucket) each,
-    // so that one pass's super-tile streams are small enough to stay in the memory-side
-    // cache between the partition and its bucketing
-    const uint32_t P = h->plan.blocked ? 1u : std::min(h->net.ahead_passes, D - 1);
+    if (h->plan.blocked) return launch_scatter(h->net, h->scatter_grid, st, 2, D, 1);
+    const uint32_t P = std::min(h->net.ahead_passes, D - 1);
     hipError_t e = hipSuccess;
     for (uint32_t g = 0; g < P && e == hipSuccess; g++) {
         const uint32_t lo = 2 + (D - 1) * g / P, hi = 1 + (D - 1) * (g + 1) / P;
@@ -274,10 +277,13 @@ hipError_t enqueue_bin_end(dbsim* h, hipStream_t st) {
 
 // One whole bin with the next bin's delay >= 2 fan-in forked onto the side stream right
 // after the gather (it touches neither the neuron state nor this bin's spike list) and
-// joined before the bin close.
+// joined before the bin close; the spike recording of the bin runs on the drain stream
+// beside the close. (Forking earlier, after the delay-1 bucketing, so that the side
+// partition overlaps the gather, was measured 13 % slower: the partition's workgroups take
+// the CUs' LDS before the gather's, which is on the critical path.)
 hipError_t enqueue_full_bin(dbsim* h, hipStream_t st, hipStream_t side) {
-    hipError_t e = enqueue_bin_start(h, st);
     const bool fork = h->plan.D >= 2;
+    hipError_t e = enqueue_bin_start(h, st);
     if (e == hipSuccess && fork) e = hipEventRecord(h->ev_fork, st);
     if (e == hipSuccess && fork) e = hipStreamWaitEvent(side, h->ev_fork, 0);
     if (e == hipSuccess && fork) e = enqueue_ahead(h, side);
@@ -871,6 +877,8 @@ int dbsim_read_spikes(dbsim* h, uint64_t step_lo, uint64_t step_hi, uint64_t* st
     *n_out = 0;
     if (step_lo >= step_hi) return DBSIM_OK;
     const uint64_t b_lo = step_lo / S, b_hi = (step_hi + S - 1) / S;
+    if (b_lo < h->first_bin)
+        return fail(DBSIM_ERANGE, "requested bins precede the checkpoint this handle was restored from");
     std::vector<std::pair<uint64_t, uint32_t>> out;
     if (p.host_record) { // the pinned host ring, complete up to the last synchronised bin
         if (done_bins - b_lo > p.HMB - 1) return fail(DBSIM_ERANGE, "requested bins have left the host record");
@@ -939,6 +947,8 @@ int dbsim_read_region_signal(dbsim* h, uint64_t bin_lo, uint64_t bin_hi, double*
     *n_out = 0;
     if (bin_lo >= bin_hi) return DBSIM_OK;
     if (done_bins - bin_lo > p.MB) return fail(DBSIM_ERANGE, "requested bins have left the device history");
+    if (bin_lo < h->first_bin)
+        return fail(DBSIM_ERANGE, "requested bins precede the checkpoint this handle was restored from");
     const uint64_t R = p.n_regions, need = (bin_hi - bin_lo) * R;
     *n_out = need;
     if (need > cap) return fail(DBSIM_ETRUNC, "buffer too small; *n_out holds the count needed");
@@ -1007,6 +1017,324 @@ int dbsim_write_state(dbsim* h, const float* V, const float* J, const int32_t* r
     }
     return DBSIM_OK;
 }
+
+// ------------------------------------------------------------------ checkpoint and resume
+
+namespace {
+
+struct CkHeader {
+    char magic[8];
+    uint64_t fingerprint;
+    uint64_t N, U, n_pops, n_regions, D, S;
+    uint64_t bin, edge_events, spikes, inject_until;
+    uint64_t b0;    // first bin of the saved spike history
+    uint64_t off0;  // spike-stream offset of bin b0's first entry
+    uint64_t n_spk; // saved spike entries, bins b0 .. bin - 1
+    uint64_t bold_on, tr_bins;
+    double bw[10];  // h, h/tau, kappa, gamma, 1/alpha, rho, V0, k1, k2, k3
+    uint64_t bold_ctl[2];
+};
+constexpr char kCkMagic[8] = {'D', 'B', 'S', 'I', 'M', 'C', 'K', '1'};
+
+inline size_t up8(size_t x) { return (x + 7) & ~(size_t)7; }
+
+void fnv(uint64_t& h, const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; i++) {
+        h ^= b[i];
+        h *= 0x100000001b3ull;
+    }
+}
+
+// Identity of the network a checkpoint belongs to: sizes, the members' descriptions (their
+// reserved words excluded) and the first and last 4 KiB of the device edge table.
+int ck_fingerprint(dbsim* h, uint64_t* out) {
+    const Plan& p = h->plan;
+    uint64_t f = 0xcbf29ce484222325ull;
+    const uint64_t sc[] = {p.N, p.E, p.U, p.KW, p.S, p.D, p.F, p.n_pops, p.n_regions, p.n_members};
+    fnv(f, sc, sizeof sc);
+    for (const dbnet_desc& d : h->mem.m) {
+        const uint64_t ds[] = {d.seed, d.n_pops, d.n_projs, d.n_regions, d.receptor_mask, d.frac_bits, d.net_id};
+        fnv(f, ds, sizeof ds);
+        const float df[] = {d.dt_ms, d.bin_ms, d.velocity_mm_per_ms};
+        fnv(f, df, sizeof df);
+        for (uint32_t q = 0; q < d.n_pops; q++) {
+            fnv(f, &d.pops[q], offsetof(dbnet_pop, reserved));
+            fnv(f, &d.pops[q].C, sizeof(dbnet_pop) - offsetof(dbnet_pop, C));
+        }
+        for (uint32_t q = 0; q < d.n_projs; q++) fnv(f, &d.projs[q], offsetof(dbnet_proj, reserved));
+        if (d.region_xyz_mm) fnv(f, d.region_xyz_mm, 12 * (size_t)d.n_regions);
+    }
+    const size_t eb = 4 * (size_t)(1 + p.KW) * p.E, n = std::min<size_t>(eb, 4096);
+    if (n) {
+        std::vector<unsigned char> a(2 * n);
+        const unsigned char* e = reinterpret_cast<const unsigned char*>(h->net.edge);
+        HIPCHK(h, hipMemcpy(a.data(), e, n, hipMemcpyDeviceToHost), "hipMemcpy");
+        HIPCHK(h, hipMemcpy(a.data() + n, e + eb - n, n, hipMemcpyDeviceToHost), "hipMemcpy");
+        fnv(f, a.data(), a.size());
+    }
+    *out = f;
+    return DBSIM_OK;
+}
+
+// Saved spike history of the bins b0 .. bin-1 (the fan-in of the coming bins reads them).
+int ck_history(dbsim* h, uint64_t bin, uint64_t* b0, std::vector<unsigned long long>& st,
+               std::vector<uint32_t>& cnt) {
+    const Plan& p = h->plan;
+    *b0 = bin > p.D ? bin - p.D : 0;
+    st.assign(p.MB, 0);
+    cnt.assign(p.MB, 0);
+    HIPCHK(h, hipMemcpy(st.data(), h->net.bin_start, 8 * (size_t)p.MB, hipMemcpyDeviceToHost), "hipMemcpy");
+    HIPCHK(h, hipMemcpy(cnt.data(), h->net.bin_cnt, 4 * (size_t)p.MB, hipMemcpyDeviceToHost), "hipMemcpy");
+    return DBSIM_OK;
+}
+
+size_t ck_bytes(const Plan& p, uint64_t nb, uint64_t n_spk, bool bold) {
+    size_t b = up8(sizeof(CkHeader));
+    b += up8(4 * (size_t)p.N) * (2 + p.U); // V, Iou, J
+    b += up8((size_t)p.N);                 // ref
+    b += up8(sizeof(PopParams) * p.n_pops);
+    b += up8(4 * nb);                      // per-bin counts
+    b += up8(4 * n_spk);
+    if (bold) b += 8 * (size_t)p.n_regions * (5 + kBoldRing);
+    return b;
+}
+
+int ck_check_boundary(dbsim* h) {
+    if (h->step % h->plan.S) return fail(DBSIM_ESTATE, "checkpoints are taken at bin boundaries");
+    return DBSIM_OK;
+}
+
+} // namespace
+
+int dbsim_checkpoint_size(dbsim* h, uint64_t* bytes) {
+    int rc = check_usable(h);
+    if (rc) return rc;
+    if (!bytes) return fail(DBSIM_EINVAL, "bytes is NULL");
+    if ((rc = ck_check_boundary(h))) return rc;
+    DeviceGuard dg(h->device);
+    if ((rc = sync_and_check(h))) return rc;
+    const Plan& p = h->plan;
+    const uint64_t bin = h->step / p.S;
+    uint64_t b0;
+    std::vector<unsigned long long> st;
+    std::vector<uint32_t> cnt;
+    if ((rc = ck_history(h, bin, &b0, st, cnt))) return rc;
+    uint64_t n_spk = 0;
+    for (uint64_t b = b0; b < bin; b++) n_spk += cnt[b & (p.MB - 1)];
+    *bytes = ck_bytes(p, bin - b0, n_spk, h->net.bold_on != 0);
+    return DBSIM_OK;
+}
+
+int dbsim_checkpoint_save(dbsim* h, void* buf, uint64_t cap, uint64_t* n_out) {
+    int rc = check_usable(h);
+    if (rc) return rc;
+    if (!n_out) return fail(DBSIM_EINVAL, "n_out is NULL");
+    if ((rc = ck_check_boundary(h))) return rc;
+    DeviceGuard dg(h->device);
+    if ((rc = sync_and_check(h))) return rc;
+    const Plan& p = h->plan;
+    const DevNet& n = h->net;
+    const uint64_t bin = h->step / p.S;
+    uint64_t b0;
+    std::vector<unsigned long long> st;
+    std::vector<uint32_t> cnt;
+    if ((rc = ck_history(h, bin, &b0, st, cnt))) return rc;
+    const uint64_t m = p.MB - 1;
+    uint64_t n_spk = 0;
+    for (uint64_t b = b0; b < bin; b++) n_spk += cnt[b & m];
+    const bool bold = n.bold_on != 0;
+    const size_t need = ck_bytes(p, bin - b0, n_spk, bold);
+    *n_out = need;
+    if (cap < need) return fail(DBSIM_ETRUNC, "buffer too small; *n_out holds the size needed");
+    if (!buf) return fail(DBSIM_EINVAL, "buf is NULL");
+    Ctl c{};
+    HIPCHK(h, hipMemcpy(&c, n.ctl, sizeof c, hipMemcpyDeviceToHost), "hipMemcpy(ctl)");
+    CkHeader hd{};
+    std::memcpy(hd.magic, kCkMagic, 8);
+    if ((rc = ck_fingerprint(h, &hd.fingerprint))) return rc;
+    hd.N = p.N;
+    hd.U = p.U;
+    hd.n_pops = p.n_pops;
+    hd.n_regions = p.n_regions;
+    hd.D = p.D;
+    hd.S = p.S;
+    hd.bin = bin;
+    hd.edge_events = c.edge_events;
+    hd.spikes = c.spikes;
+    hd.inject_until = c.inject_until;
+    hd.b0 = b0;
+    hd.off0 = st[b0 & m];
+    hd.n_spk = n_spk;
+    hd.bold_on = bold;
+    hd.tr_bins = n.tr_bins;
+    const double bw[10] = {n.bw_h, n.bw_htau, n.bw_kappa, n.bw_gamma, n.bw_inv_alpha,
+                           n.bw_rho, n.bw_V0, n.bw_k1, n.bw_k2, n.bw_k3};
+    std::memcpy(hd.bw, bw, sizeof bw);
+    if (bold) HIPCHK(h, hipMemcpy(hd.bold_ctl, n.bold_ctl, 16, hipMemcpyDeviceToHost), "hipMemcpy");
+    unsigned char* o = static_cast<unsigned char*>(buf);
+    std::memset(o, 0, need);
+    std::memcpy(o, &hd, sizeof hd);
+    size_t at_ = up8(sizeof hd);
+    const size_t N = p.N;
+    HIPCHK(h, hipMemcpy(o + at_, n.V, 4 * N, hipMemcpyDeviceToHost), "hipMemcpy");
+    at_ += up8(4 * N);
+    HIPCHK(h, hipMemcpy(o + at_, n.Iou, 4 * N, hipMemcpyDeviceToHost), "hipMemcpy");
+    at_ += up8(4 * N);
+    HIPCHK(h, hipMemcpy(o + at_, n.J, 4 * N * p.U, hipMemcpyDeviceToHost), "hipMemcpy");
+    at_ += up8(4 * N) * p.U;
+    HIPCHK(h, hipMemcpy(o + at_, n.ref, N, hipMemcpyDeviceToHost), "hipMemcpy");
+    at_ += up8(N);
+    HIPCHK(h, hipMemcpy(o + at_, n.pops, sizeof(PopParams) * p.n_pops, hipMemcpyDeviceToHost), "hipMemcpy");
+    at_ += up8(sizeof(PopParams) * p.n_pops);
+    uint32_t* bc = reinterpret_cast<uint32_t*>(o + at_);
+    for (uint64_t b = b0; b < bin; b++) bc[b - b0] = cnt[b & m];
+    at_ += up8(4 * (bin - b0));
+    // the entries of bins b0 .. bin-1 are contiguous in the ring (mod its size)
+    {
+        uint64_t a = hd.off0 & (p.RC - 1), left = n_spk, w = 0;
+        while (left) {
+            const uint64_t k = std::min<uint64_t>(left, p.RC - a);
+            HIPCHK(h, hipMemcpy(o + at_ + 4 * w, n.rec + a, 4 * k, hipMemcpyDeviceToHost), "hipMemcpy");
+            w += k;
+            left -= k;
+            a = 0;
+        }
+    }
+    at_ += up8(4 * n_spk);
+    if (bold) {
+        const size_t R = p.n_regions;
+        HIPCHK(h, hipMemcpy(o + at_, n.bold_zs, 8 * R, hipMemcpyDeviceToHost), "hipMemcpy");
+        at_ += 8 * R;
+        HIPCHK(h, hipMemcpy(o + at_, n.bold, 8 * 4 * R, hipMemcpyDeviceToHost), "hipMemcpy");
+        at_ += 8 * 4 * R;
+        HIPCHK(h, hipMemcpy(o + at_, n.bold_y, 8 * (size_t)kBoldRing * R, hipMemcpyDeviceToHost), "hipMemcpy");
+        at_ += 8 * (size_t)kBoldRing * R;
+    }
+    return DBSIM_OK;
+}
+
+int dbsim_checkpoint_restore(dbsim* h, const void* buf, uint64_t len) {
+    int rc = check_usable(h);
+    if (rc) return rc;
+    if (!buf) return fail(DBSIM_EINVAL, "buf is NULL");
+    if (h->step != 0) return fail(DBSIM_ESTATE, "a checkpoint is restored into a handle that has not been stepped");
+    const Plan& p = h->plan;
+    CkHeader hd;
+    if (len < sizeof hd) return fail(DBSIM_EINVAL, "checkpoint too short");
+    std::memcpy(&hd, buf, sizeof hd);
+    if (std::memcmp(hd.magic, kCkMagic, 8) != 0) return fail(DBSIM_EINVAL, "not a checkpoint of this library");
+    if (hd.N != p.N || hd.U != p.U || hd.n_pops != p.n_pops || hd.n_regions != p.n_regions || hd.D != p.D ||
+        hd.S != p.S)
+        return fail(DBSIM_EINVAL, "the checkpoint belongs to a network of other sizes");
+    if (hd.b0 > hd.bin || hd.bin - hd.b0 > p.D || hd.n_spk > (uint64_t)p.D * p.N || hd.tr_bins == 0)
+        return fail(DBSIM_EINVAL, "corrupt checkpoint header");
+    const bool bold = hd.bold_on != 0;
+    if (bold && !p.regions_on) return fail(DBSIM_EINVAL, "the checkpoint has BOLD state; the handle records no regions");
+    const size_t need = ck_bytes(p, hd.bin - hd.b0, hd.n_spk, bold);
+    if (len < need) return fail(DBSIM_EINVAL, "checkpoint shorter than its header says");
+    DeviceGuard dg(h->device);
+    if ((rc = sync_and_check(h))) return rc;
+    uint64_t fp;
+    if ((rc = ck_fingerprint(h, &fp))) return rc;
+    if (fp != hd.fingerprint) return fail(DBSIM_EINVAL, "the checkpoint belongs to another network");
+    const unsigned char* in = static_cast<const unsigned char*>(buf);
+    const size_t N = p.N;
+    DevNet& n = h->net;
+    size_t at_ = up8(sizeof hd);
+    const unsigned char* V = in + at_;
+    at_ += up8(4 * N);
+    const unsigned char* Iou = in + at_;
+    at_ += up8(4 * N);
+    const unsigned char* J = in + at_;
+    at_ += up8(4 * N) * p.U;
+    const unsigned char* ref = in + at_;
+    at_ += up8(N);
+    const unsigned char* pops = in + at_;
+    at_ += up8(sizeof(PopParams) * p.n_pops);
+    const uint32_t* bc = reinterpret_cast<const uint32_t*>(in + at_);
+    at_ += up8(4 * (hd.bin - hd.b0));
+    const unsigned char* spk = in + at_;
+    at_ += up8(4 * hd.n_spk);
+    uint64_t tot = 0;
+    for (uint64_t b = hd.b0; b < hd.bin; b++) tot += bc[b - hd.b0];
+    if (tot != hd.n_spk) return fail(DBSIM_EINVAL, "corrupt checkpoint: spike counts do not add up");
+    HIPCHK(h, hipMemcpy(n.V, V, 4 * N, hipMemcpyHostToDevice), "hipMemcpy");
+    HIPCHK(h, hipMemcpy(n.Iou, Iou, 4 * N, hipMemcpyHostToDevice), "hipMemcpy");
+    HIPCHK(h, hipMemcpy(n.J, J, 4 * N * p.U, hipMemcpyHostToDevice), "hipMemcpy");
+    HIPCHK(h, hipMemcpy(n.ref, ref, N, hipMemcpyHostToDevice), "hipMemcpy");
+    HIPCHK(h, hipMemcpy((void*)n.pops, pops, sizeof(PopParams) * p.n_pops, hipMemcpyHostToDevice), "hipMemcpy");
+    // spike history: the saved bins at their original stream offsets
+    const uint64_t m = p.MB - 1;
+    std::vector<unsigned long long> st(p.MB, 0);
+    std::vector<uint32_t> cnt(p.MB, 0);
+    uint64_t off = hd.off0;
+    for (uint64_t b = hd.b0; b < hd.bin; b++) {
+        st[b & m] = off;
+        cnt[b & m] = bc[b - hd.b0];
+        off += bc[b - hd.b0];
+    }
+    st[hd.bin & m] = off;
+    HIPCHK(h, hipMemcpy(n.bin_start, st.data(), 8 * (size_t)p.MB, hipMemcpyHostToDevice), "hipMemcpy");
+    HIPCHK(h, hipMemcpy(n.bin_cnt, cnt.data(), 4 * (size_t)p.MB, hipMemcpyHostToDevice), "hipMemcpy");
+    {
+        uint64_t a = hd.off0 & (p.RC - 1), left = hd.n_spk, w = 0;
+        while (left) {
+            const uint64_t k = std::min<uint64_t>(left, p.RC - a);
+            HIPCHK(h, hipMemcpy(n.rec + a, spk + 4 * w, 4 * k, hipMemcpyHostToDevice), "hipMemcpy");
+            w += k;
+            left -= k;
+            a = 0;
+        }
+    }
+    if (p.host_record) h->hbend[hd.bin & (p.HMB - 1)] = off; // the host record starts at this bin
+    if (bold) {
+        const size_t R = p.n_regions;
+        HIPCHK(h, hipMemcpy((void*)n.bold_zs, in + at_, 8 * R, hipMemcpyHostToDevice), "hipMemcpy");
+        at_ += 8 * R;
+        HIPCHK(h, hipMemcpy(n.bold, in + at_, 8 * 4 * R, hipMemcpyHostToDevice), "hipMemcpy");
+        at_ += 8 * 4 * R;
+        HIPCHK(h, hipMemcpy(n.bold_y, in + at_, 8 * (size_t)kBoldRing * R, hipMemcpyHostToDevice), "hipMemcpy");
+        at_ += 8 * (size_t)kBoldRing * R;
+        HIPCHK(h, hipMemcpy(n.bold_ctl, hd.bold_ctl, 16, hipMemcpyHostToDevice), "hipMemcpy");
+        n.bw_h = hd.bw[0];
+        n.bw_htau = hd.bw[1];
+        n.bw_kappa = hd.bw[2];
+        n.bw_gamma = hd.bw[3];
+        n.bw_inv_alpha = hd.bw[4];
+        n.bw_rho = hd.bw[5];
+        n.bw_V0 = hd.bw[6];
+        n.bw_k1 = hd.bw[7];
+        n.bw_k2 = hd.bw[8];
+        n.bw_k3 = hd.bw[9];
+        n.tr_bins = (uint32_t)hd.tr_bins;
+    }
+    n.bold_on = bold ? 1 : 0;
+    // counters; the next bin's delay >= 2 events, which the saved handle had assembled ahead
+    // while its last bin ran, are assembled again here from the restored spike history
+    Ctl c{};
+    c.edge_events = hd.edge_events;
+    c.spikes = hd.spikes;
+    c.inject_until = hd.inject_until;
+    const bool ahead = hd.bin >= 1 && p.D >= 2;
+    c.bin = ahead ? hd.bin - 1 : hd.bin;
+    HIPCHK(h, hipMemcpy(n.ctl, &c, sizeof c, hipMemcpyHostToDevice), "hipMemcpy(ctl)");
+    if (ahead) {
+        HIPCHK(h, enqueue_ahead(h, h->stream), "partition launch");
+        HIPCHK(h, launch_pass_reset(n, h->stream), "reset launch");
+        HIPCHK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        const unsigned long long b = hd.bin;
+        HIPCHK(h, hipMemcpy(&n.ctl->bin, &b, sizeof b, hipMemcpyHostToDevice), "hipMemcpy(ctl)");
+    }
+    // the kernels take the network descriptor by value: re-capture the graphs
+    if (h->g_multi) (void)hipGraphExecDestroy(h->g_multi);
+    if (h->g_one) (void)hipGraphExecDestroy(h->g_one);
+    h->g_multi = h->g_one = nullptr;
+    h->step = hd.bin * p.S;
+    h->first_bin = hd.bin;
+    return sync_and_check(h);
+}
+
 
 int dbsim_export_csr(dbsim* h, uint64_t* row_ptr, uint32_t* seg, uint32_t* tgt, float* w0, float* w1) {
     int rc = check_usable(h);

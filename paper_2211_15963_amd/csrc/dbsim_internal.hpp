@@ -20,7 +20,7 @@
 //     that one 64-byte read gives everything a (spike, delay) segment needs;
 //   the event arena of the fan-in, sized by each tile's total in-degree (the most
 //     events a tile can receive in one bin: an edge delivers at most once per bin).
-//     Single-pass form (the tiles' carry buffers fit a workgroup's LDS): blocks of
+//     Single-pass form (on request, where the tiles' carry buffers fit a workgroup's LDS): blocks of
 //     kFanBlock records, a 16-bit key array (target within the tile | inhibitory
 //     source << 15) beside the weights; tile t owns blocks tile_base[t] ..
 //     tile_base[t+1]: its in-degree in whole blocks plus two part-filled blocks per
@@ -183,6 +183,10 @@ struct DevNet {
 hipError_t prepare_kernels(); // one-time function attributes (LDS opt-in); call outside graph capture
 // fan-in of the delays d_lo..d_hi of the current bin (ahead = 0) or of the next one (ahead = 1)
 hipError_t launch_scatter(const DevNet& n, int grid, hipStream_t st, uint32_t d_lo, uint32_t d_hi, uint32_t ahead);
+// the two halves of launch_scatter in the two-pass form: the partition into the super-tile
+// streams (k_part), and their bucketing into the tile arena (k_bucket)
+hipError_t launch_part(const DevNet& n, int grid, hipStream_t st, uint32_t d_lo, uint32_t d_hi, uint32_t ahead);
+hipError_t launch_bucket(const DevNet& n, int grid, hipStream_t st);
 hipError_t launch_gather(const DevNet& n, hipStream_t st);
 hipError_t launch_pass_reset(const DevNet& n, hipStream_t st);
 hipError_t launch_neuron(const DevNet& n, int s0, int s1, hipStream_t st);

@@ -6,20 +6,22 @@
 //              pushes a spike list through destination lists; here the delay ring
 //              is read backwards, so all events of a bin land in one accumulator).
 //              Whole delay segments are read (contiguous 12-byte edge records) and
-//              their events are radix-partitioned through LDS, with one global
-//              reservation per non-empty bucket per round instead of one atomic per
-//              event: straight into the target tiles in whole chunks (carry buffers
-//              per tile) when the tiles are few, else into at most 64 super-tile
-//              streams. Launched twice per bin: delays 2..D of bin k+1 while bin k's
-//              neurons are stepped (side stream), delay 1 at the start of bin k+1.
+//              their events are radix-partitioned through LDS into at most 64
+//              super-tile streams, with one global reservation per non-empty bucket
+//              per round instead of one atomic per event. Launched twice per bin:
+//              delays 2..D of bin k+1 while bin k's neurons are stepped (side
+//              stream), delay 1 at the start of bin k+1.
 //              After each workgroup's first chunk the chunks come from a counter.
-//   k_bucket   second pass of the two-pass form: each super-tile stream is
-//              partitioned into its tiles the same way, in rounds handed out by a
-//              counter; the next round's records are copied global -> LDS directly
-//              (no registers) while the current round is reserved and written.
+//   k_bucket   second pass: each super-tile stream is partitioned into its tiles
+//              the same way, in rounds handed out by a counter; the next round's
+//              records are copied global -> LDS directly (no registers) while the
+//              current round is reserved and written.
 //   k_gather   one workgroup per tile: sums its events in LDS as int64 fixed
 //              point (exact, so any order gives the same bits), converts once
 //              to float, writes A.
+//   k_fan, k_gather_blk  the single-pass form (on request): the partition goes
+//              straight into per-workgroup blocks of every tile through carry
+//              buffers in LDS, and the gather reads the tile's blocks.
 //   k_neuron   one lane per neuron, S substeps fused in registers: Philox
 //              Poisson background, Euler update of V (CV equation), threshold,
 //              reset and refractory clamp, receptor decay (eq. 3); at the bin
@@ -596,27 +598,26 @@ template <> struct RecOf<2> {
 constexpr uint32_t kNoBlock = 0xFFFFFFFFu; // the workgroup holds no block of the tile
 constexpr uint32_t kNoSpace = 0xFFFFFFFEu; // the tile's blocks ran out (kErrArena raised)
 
-// LDS of k_fan: the delay lists and one chunk's segments (as k_part), and per tile a carry
-// buffer of C records (16-bit key: target within the tile | inhibitory source << 15, and the
-// weights), its claimed slots, the workgroup's current block of the tile and the records
-// already in that block, and the list of tiles to move out.
+// LDS of k_fan: the delay lists, one chunk's segments (start, length) and its segment counter,
+// and per tile a carry buffer of C records (16-bit key: target within the tile | inhibitory
+// source << 15, and the weights), its claimed slots, the workgroup's current block of the tile
+// and the records already in that block, and the list of tiles to move out.
 struct FanLayout {
-    size_t dpre, dstart, sstart, bufw, cnt, blk, spre, dcnt, wave, bufk, fill, flist, smap, total;
+    size_t dpre, dstart, sstart, bufw, cnt, blk, slen, dcnt, wave, bufk, fill, flist, total;
     __host__ __device__ FanLayout(uint32_t T, uint32_t C, uint32_t KW, uint32_t D) {
         LdsLayout L;
         dpre = L.take(8 * ((size_t)D + 1), 8);
         dstart = L.take(8 * (size_t)D, 8);
         sstart = L.take(8 * (size_t)kFanThreads, 8);
-        bufw = L.take(4 * (size_t)KW * C * T, 8);
+        bufw = L.take(4 * (size_t)KW * C * T, 16);
         cnt = L.take(4 * (size_t)T, 4);
         blk = L.take(4 * (size_t)T, 4);
-        spre = L.take(4 * ((size_t)kFanThreads + 4), 4);
+        slen = L.take(4 * (size_t)kFanThreads, 4);
         dcnt = L.take(4 * ((size_t)D + 1), 4);
         wave = L.take(4 * 32, 4);
-        bufk = L.take(2 * (size_t)C * T, 2);
+        bufk = L.take(2 * (size_t)C * T, 16);
         fill = L.take(2 * (size_t)T, 2);
         flist = L.take(2 * (size_t)T, 2);
-        smap = L.take(2 * ((size_t)kFanThreads + 2), 2);
         total = L.take(0, 16);
     }
 };
@@ -630,7 +631,8 @@ struct Fan {
     uint32_t* blk;   // current block (kNoBlock / kNoSpace)
     uint16_t* fill;  // records in the current block
     uint16_t* flist; // tiles to move out
-    uint32_t* nfl;   // their number
+    uint32_t* nfl;   // their number: three counters used in turn by the iterations, and a fourth
+                     // for the final list
     __device__ void at(unsigned char* base, const FanLayout& l) {
         bufw = reinterpret_cast<W*>(base + l.bufw);
         bufk = reinterpret_cast<uint16_t*>(base + l.bufk);
@@ -643,14 +645,13 @@ struct Fan {
 };
 
 // Moves the carry buffers of the listed tiles into the workgroup's blocks: C records each
-// (full buffers), or cnt[t] (the rest, at the end of a pass). One thread per tile takes a
-// new block of the tile when the current one cannot hold them (the block left behind is
-// full: its count is K), then C consecutive threads per tile copy the records, so a tile's
-// records land contiguously. Ends with the moved buffers empty and the list cleared. The
-// first barrier also orders the reset of the list counter after every thread has read it.
+// (full buffers), or cnt[t] (the rest, at the end of a pass). One lane per tile: it takes a
+// new block of the tile when the current one cannot hold them (the block left behind is full:
+// its count is K), copies the records in 16-byte pieces (a full buffer starts at a multiple of
+// C records in its block, so the pieces are aligned) and empties the buffer. Ends with a
+// barrier.
 template <int KW>
 __device__ void fan_move(const DevNet& net, Fan<KW>& F, uint32_t nfl, bool full) {
-    using W = typename WeightOf<KW>::type;
     const uint32_t tid = threadIdx.x, C = net.fan_C, K = net.fan_K;
     for (uint32_t x = tid; x < nfl; x += kFanThreads) {
         const uint32_t t = F.flist[x];
@@ -671,60 +672,59 @@ __device__ void fan_move(const DevNet& net, Fan<KW>& F, uint32_t nfl, bool full)
         }
         F.blk[t] = b;
         F.fill[t] = (uint16_t)(f + n);
-    }
-    __syncthreads();
-    if (tid == 0) *F.nfl = 0;
-    const uint32_t cs = 31u - __clz(C); // C is a power of two
-    for (uint32_t x = tid; x < (nfl << cs); x += kFanThreads) {
-        const uint32_t t = F.flist[x >> cs], s = x & (C - 1u);
-        const uint32_t b = F.blk[t];
-        const uint32_t n = full ? C : F.cnt[t];
-        if (s < n && b < kNoSpace) {
-            const size_t pos = (size_t)b * K + (F.fill[t] - n) + s;
-            net.evk[pos] = F.bufk[t * C + s];
-            reinterpret_cast<W*>(net.ev)[pos] = F.bufw[t * C + s];
+        if (b < kNoSpace) {
+            const size_t pos = (size_t)b * K + f;
+            if (full) { // C records: keys 2C bytes (C / 4 pieces of 8), weights 4 KW C bytes
+                const uint2* sk = reinterpret_cast<const uint2*>(F.bufk + (size_t)t * C);
+                uint2* dk = reinterpret_cast<uint2*>(net.evk + pos);
+                for (uint32_t q = 0; q < C / 4u; q++) dk[q] = sk[q];
+                const uint4* sw = reinterpret_cast<const uint4*>(F.bufw + (size_t)t * C);
+                uint4* dw = reinterpret_cast<uint4*>(reinterpret_cast<typename WeightOf<KW>::type*>(net.ev) + pos);
+                for (uint32_t q = 0; q < C * KW / 4u; q++) dw[q] = sw[q];
+            } else {
+                for (uint32_t q = 0; q < n; q++) {
+                    net.evk[pos + q] = F.bufk[t * C + q];
+                    reinterpret_cast<typename WeightOf<KW>::type*>(net.ev)[pos + q] = F.bufw[t * C + q];
+                }
+            }
         }
-        // a full buffer's claim count restarts (claims past C belong to events still held
-        // in registers, which claim again); read only by the next insertion, after the barrier
-        if (full && s == 0) F.cnt[t] = 0u;
+        // claims past C belong to events still held in registers, which claim again
+        F.cnt[t] = 0u;
     }
     __syncthreads();
-    if (!full) {
-        for (uint32_t x = tid; x < nfl; x += kFanThreads) F.cnt[F.flist[x]] = 0u;
-        __syncthreads();
-    }
 }
 
 } // namespace
 
-// Single-pass fan-in (the tiles fit the LDS carry buffers): the same chunks of (spike, delay)
-// segments and the same loads as k_part, but every event goes straight into the carry buffer of
-// its target tile (one LDS counter claim). A full buffer is moved out as C contiguous records
-// into a block of K records that the workgroup took from the tile's block range (one global
-// claim per block, not per event). Each thread holds up to kMaxBatch events in register slots
-// and walks its own stride of the current chunk's events: an event that finds its buffer full
-// stays in its slot and claims again in the next iteration, and freed slots are refilled right
-// after the claims, so their loads are in flight while the full buffers are moved. At the end
-// every part-filled buffer is moved and every block the workgroup holds gets its record count,
-// so k_gather_blk reads each tile's blocks in full.
+// Single-pass fan-in (the tiles fit the LDS carry buffers). A chunk is up to kFanThreads
+// (spike, delay) segments (one row-header read each); every wavefront takes whole segments
+// from the chunk's counter and fills each of its kMaxBatch register slots with up to 64
+// consecutive records of its current segment (one per lane: coalesced loads, no search). Every
+// held event claims a slot in the carry buffer of its target tile (one LDS counter); a full
+// buffer is moved out as C contiguous records into a block of K records that the workgroup
+// took from the tile's block range (one global claim per block, not per event). An event that
+// finds its buffer full stays in its slot and claims again in the next iteration; a slot is
+// refilled when it is free in every lane of the wavefront, and the loads are issued right after
+// the claims, so they are in flight while the full buffers are moved. At the end every
+// part-filled buffer is moved and every block the workgroup holds gets its record count, so
+// k_gather_blk reads each tile's blocks in full.
 template <int KW>
 __global__ void __launch_bounds__(kFanThreads) k_fan(DevNet net, uint32_t d_lo, uint32_t d_hi, uint32_t ahead) {
-    using W = typename WeightOf<KW>::type;
     extern __shared__ __align__(16) unsigned char dyn[];
     const uint32_t D = net.D, T = net.T, C = net.fan_C;
     const FanLayout L(T, C, KW, D);
     unsigned long long* s_dpre = reinterpret_cast<unsigned long long*>(dyn + L.dpre);
     unsigned long long* s_dstart = reinterpret_cast<unsigned long long*>(dyn + L.dstart);
     unsigned long long* s_sstart = reinterpret_cast<unsigned long long*>(dyn + L.sstart);
-    uint32_t* s_spre = reinterpret_cast<uint32_t*>(dyn + L.spre);
+    uint32_t* s_slen = reinterpret_cast<uint32_t*>(dyn + L.slen);
     uint32_t* s_dcnt = reinterpret_cast<uint32_t*>(dyn + L.dcnt);
     uint32_t* s_wave = reinterpret_cast<uint32_t*>(dyn + L.wave);
     uint32_t* s_flag = s_wave + 24; // three vote words, used in turn
-    uint16_t* s_map = reinterpret_cast<uint16_t*>(dyn + L.smap);
+    uint32_t* s_segnext = s_wave + 28; // next segment of the chunk to hand to a wavefront
     Fan<KW> F;
     F.at(dyn, L);
     const unsigned long long k = net.ctl->bin + ahead;
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
     for (uint32_t x = tid; x < D; x += kFanThreads) {
         const uint32_t d = x + 1;
         uint32_t cnt = 0;
@@ -751,10 +751,8 @@ __global__ void __launch_bounds__(kFanThreads) k_fan(DevNet net, uint32_t d_lo, 
         F.blk[t] = kNoBlock;
         F.fill[t] = 0;
     }
-    if (tid == 0) {
-        *F.nfl = 0u;
-        s_flag[0] = s_flag[1] = s_flag[2] = 0u;
-    }
+    if (tid == 0)
+        for (int x = 0; x < 4; x++) F.nfl[x] = s_flag[x] = 0u;
     const uint32_t G = gridDim.x;
     const unsigned long long cw = (unsigned long long)(ahead ? net.chunks_per_wg : 1u) * G;
     const uint32_t spc = (uint32_t)min((unsigned long long)kFanThreads, max(32ull, (total + cw - 1) / cw));
@@ -763,12 +761,14 @@ __global__ void __launch_bounds__(kFanThreads) k_fan(DevNet net, uint32_t d_lo, 
     const uint32_t nslots = max(1u, min((uint32_t)kMaxBatch, net.round_events / kFanThreads));
     unsigned long long my_events = 0;
     __shared__ unsigned long long s_pc;
-    // the current chunk (uniform) and this thread's next event in it (events tid + j NT)
+    // the current chunk (uniform); this wavefront's current segment (wave-uniform)
     unsigned long long c = blockIdx.x;
-    uint32_t ec = 0, nseg = 0, mb_bits = 0, nmap = 0, jn = 0;
+    uint32_t nseg = 0;
     bool have = false;
-    // Reads the headers of chunk c, lays out its events (prefix and coarse map) and claims the
-    // next chunk; every thread's loads of the previous chunk have been issued before this.
+    unsigned long long seg_base = 0;
+    uint32_t seg_left = 0;
+    // Reads the row headers of chunk c's segments and claims the next chunk; every thread's
+    // loads of the previous chunk have been issued before this.
     auto setup_chunk = [&]() {
         __syncthreads();
         have = c < nchunks;
@@ -791,25 +791,20 @@ __global__ void __launch_bounds__(kFanThreads) k_fan(DevNet net, uint32_t d_lo, 
             const uint32_t so = hp[1 + d], eo = hp[2 + d];
             s_sstart[tid] = (((unsigned long long)(rs.y & 0x7FFFFFFFu) << 32) | rs.x) + so;
             len = eo - so;
+            s_slen[tid] = len;
         }
-        const uint32_t ex = block_exclusive_scan<kFanThreads>(len, s_wave, &ec);
-        s_spre[tid] = ex;
-        if (tid == 0) s_spre[kFanThreads] = ec;
-        mb_bits = 0;
-        while (((ec + (1u << mb_bits) - 1) >> mb_bits) > (uint32_t)kFanThreads) mb_bits++;
-        if (len) {
-            const uint32_t m0 = (ex + (1u << mb_bits) - 1) >> mb_bits;
-            const uint32_t m1 = (ex + len + (1u << mb_bits) - 1) >> mb_bits;
-            for (uint32_t m = m0; m < m1; m++) s_map[m] = (uint16_t)tid;
+        uint32_t ec;
+        (void)block_exclusive_scan<kFanThreads>(len, s_wave, &ec);
+        if (tid == 0) {
+            *s_segnext = 0u;
+            s_pc = G + atomicAdd(&net.ctl->pnext, 1ull);
         }
-        nmap = (ec + (1u << mb_bits) - 1) >> mb_bits;
-        if (tid == 0) s_pc = G + atomicAdd(&net.ctl->pnext, 1ull);
         __syncthreads();
         c = s_pc;
-        jn = 0;
+        seg_left = 0;
         my_events += ec;
     };
-    // the held events: their edge index and the record as loaded (weights, then target |
+    // The held events: their edge index and the record as loaded (weights, then target |
     // class << 31). Every slot is reloaded in every iteration, unconditionally (a held event
     // reads its own record again, an empty slot any valid one), so the loads land straight in
     // the slots' registers and are first waited for by the next iteration's claims.
@@ -824,6 +819,7 @@ __global__ void __launch_bounds__(kFanThreads) k_fan(DevNet net, uint32_t d_lo, 
     }
     setup_chunk();
     for (uint32_t it = 0;; it++) {
+        uint32_t* nfl_it = &F.nfl[it % 3u]; // list counter of this iteration
         // claims of the events held (loaded in the previous iteration, or waiting for a buffer)
 #pragma unroll
         for (int u = 0; u < kMaxBatch; u++) {
@@ -839,48 +835,62 @@ __global__ void __launch_bounds__(kFanThreads) k_fan(DevNet net, uint32_t d_lo, 
                 if (slot < C) {
                     F.bufk[t * C + slot] = (uint16_t)((tgt & lmask) | ((key >> 31) << 15));
                     F.bufw[t * C + slot] = RecOf<KW>::weights(rec[u]);
-                    if (slot == C - 1u) F.flist[atomicAdd(F.nfl, 1u)] = (uint16_t)t;
+                    if (slot == C - 1u) F.flist[atomicAdd(nfl_it, 1u)] = (uint16_t)t;
                     pend &= ~(1u << u);
                 }
             }
         }
-        // refill the free slots from this thread's stride of the chunk, then load every slot:
-        // the loads stay in flight through the vote and the buffer moves
+        // refill the slots that are free in the whole wavefront with up to 64 consecutive
+        // records of the wavefront's current segment (taking whole segments from the chunk)
         if (have) {
 #pragma unroll
             for (int u = 0; u < kMaxBatch; u++) {
-                const uint32_t e = jn * kFanThreads + tid;
-                if (u < (int)nslots && !(pend & (1u << u)) && e < ec) {
-                    const uint32_t m = e >> mb_bits;
-                    const uint32_t lo = s_map[m], hi = m + 1 < nmap ? s_map[m + 1] : nseg - 1;
-                    const uint32_t sg = lo + seg_search(s_spre + lo, hi - lo + 1, e);
-                    eidx[u] = s_sstart[sg] + (e - s_spre[sg]);
-                    pend |= 1u << u;
-                    jn++;
+                if (u < (int)nslots && __ballot((pend >> u) & 1u) == 0ull) {
+                    while (seg_left == 0u) { // the next nonempty segment of the chunk, if any
+                        uint32_t sg = 0;
+                        if (lane == 0) sg = atomicAdd(s_segnext, 1u);
+                        sg = __shfl(sg, 0, 64);
+                        if (sg >= nseg) break;
+                        seg_base = s_sstart[sg];
+                        seg_left = s_slen[sg];
+                    }
+                    if (seg_left) {
+                        const uint32_t n = min(64u, seg_left);
+                        if (lane < n) {
+                            eidx[u] = seg_base + lane;
+                            pend |= 1u << u;
+                        }
+                        seg_base += n;
+                        seg_left -= n;
+                    }
                 }
             }
         }
 #pragma unroll
         for (int u = 0; u < kMaxBatch; u++) rec[u] = reinterpret_cast<const Rec*>(net.edge)[eidx[u]];
-        // vote: 1 = events of the chunk still to load, 2 = events held; three words in turn,
-        // the one for two iterations ahead cleared after this barrier
-        const uint32_t vote = (have && jn * kFanThreads + tid < ec ? 1u : 0u) | (pend ? 2u : 0u);
+        // vote: 1 = this chunk may still hold events to load, 2 = events held. The vote words
+        // and list counters are used in turn by three iterations: read after this barrier, the
+        // ones for two iterations ahead are cleared here (their last readers passed the
+        // previous barrier, their next writers start after the next one)
+        const bool more = have && (seg_left != 0u || *s_segnext < nseg);
+        const uint32_t vote = (more ? 1u : 0u) | (pend ? 2u : 0u);
         if (vote) atomicOr(&s_flag[it % 3u], vote);
         __syncthreads();
-        const uint32_t fl = s_flag[it % 3u], nfl = *F.nfl;
-        if (tid == 0) s_flag[(it + 2u) % 3u] = 0u;
+        const uint32_t fl = s_flag[it % 3u], nfl = *nfl_it;
+        if (tid == 0) s_flag[(it + 2u) % 3u] = F.nfl[(it + 2u) % 3u] = 0u;
         if (nfl) fan_move<KW>(net, F, nfl, true);
         if (!(fl & 1u)) {
             if (have) setup_chunk(); // every event of this chunk is loaded: the next chunk
             if (!have && !(fl & 2u)) break;
         }
     }
-    // the part-filled buffers, then the record count of every block held
+    // the part-filled buffers (listed with the fourth counter), then the record count of every
+    // block held
     __syncthreads();
     for (uint32_t t = tid; t < T; t += kFanThreads)
-        if (F.cnt[t]) F.flist[atomicAdd(F.nfl, 1u)] = (uint16_t)t;
+        if (F.cnt[t]) F.flist[atomicAdd(&F.nfl[3], 1u)] = (uint16_t)t;
     __syncthreads();
-    const uint32_t nfl = *F.nfl;
+    const uint32_t nfl = F.nfl[3];
     if (nfl) fan_move<KW>(net, F, nfl, false);
     for (uint32_t t = tid; t < T; t += kFanThreads) {
         const uint32_t b = F.blk[t];
@@ -1501,6 +1511,24 @@ hipError_t prepare_kernels() {
     return e;
 }
 
+hipError_t launch_part(const DevNet& n, int grid, hipStream_t st, uint32_t d_lo, uint32_t d_hi, uint32_t ahead) {
+    const size_t la = part_lds_bytes(n.NS, n.round_events, n.D);
+    if (n.KW == 2)
+        hipLaunchKernelGGL(k_part<2>, dim3(grid), dim3(kScatterThreads), la, st, n, d_lo, d_hi, ahead);
+    else
+        hipLaunchKernelGGL(k_part<1>, dim3(grid), dim3(kScatterThreads), la, st, n, d_lo, d_hi, ahead);
+    return hipGetLastError();
+}
+
+hipError_t launch_bucket(const DevNet& n, int grid, hipStream_t st) {
+    const size_t lb = bucket_lds_bytes(1u << n.ts_bits, n.bucket_events);
+    if (n.KW == 2)
+        hipLaunchKernelGGL(k_bucket<2>, dim3(grid), dim3(kScatterThreads), lb, st, n);
+    else
+        hipLaunchKernelGGL(k_bucket<1>, dim3(grid), dim3(kScatterThreads), lb, st, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_scatter(const DevNet& n, int grid, hipStream_t st, uint32_t d_lo, uint32_t d_hi, uint32_t ahead) {
     if (n.blocked) {
         const size_t lf = fan_lds_bytes(n.T, n.fan_C, n.KW, n.D);
@@ -1510,19 +1538,9 @@ hipError_t launch_scatter(const DevNet& n, int grid, hipStream_t st, uint32_t d_
             hipLaunchKernelGGL(k_fan<1>, dim3(grid), dim3(kFanThreads), lf, st, n, d_lo, d_hi, ahead);
         return hipGetLastError();
     }
-    const size_t la = part_lds_bytes(n.NS, n.round_events, n.D);
-    const size_t lb = bucket_lds_bytes(1u << n.ts_bits, n.bucket_events);
-    if (n.KW == 2)
-        hipLaunchKernelGGL(k_part<2>, dim3(grid), dim3(kScatterThreads), la, st, n, d_lo, d_hi, ahead);
-    else
-        hipLaunchKernelGGL(k_part<1>, dim3(grid), dim3(kScatterThreads), la, st, n, d_lo, d_hi, ahead);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_part(n, grid, st, d_lo, d_hi, ahead);
     if (e != hipSuccess) return e;
-    if (n.KW == 2)
-        hipLaunchKernelGGL(k_bucket<2>, dim3(grid), dim3(kScatterThreads), lb, st, n);
-    else
-        hipLaunchKernelGGL(k_bucket<1>, dim3(grid), dim3(kScatterThreads), lb, st, n);
-    return hipGetLastError();
+    return launch_bucket(n, grid, st);
 }
 
 hipError_t launch_pass_reset(const DevNet& n, hipStream_t st) {

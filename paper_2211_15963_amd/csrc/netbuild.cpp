@@ -176,18 +176,19 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     while ((1u << (p.tile_bits + 1)) <= tile_neurons) p.tile_bits++;
     p.T = (p.N + (1u << p.tile_bits) - 1) >> p.tile_bits;
     if (p.T > (uint32_t)kMaxTilesLds) return "network too large for the tile histogram (too many neurons)";
-    // fan-in form: one pass straight into the tiles when a carry buffer of at least
-    // kFanMinChunk records per tile fits one workgroup's LDS (T up to about 2,900 tiles with
-    // two weights per edge), else two passes through at most kMaxSuperTiles super-tile
-    // streams of a power-of-two number of tiles each
-    p.blocked = !(opts.flags & DBSIM_F_TWO_PASS) && p.T <= 65535u && fan_chunk_records(p, 1) != 0;
+    // fan-in form: two passes through at most kMaxSuperTiles super-tile streams of a
+    // power-of-two number of tiles each (the faster form on every measured network); on
+    // request, one pass straight into per-workgroup tile blocks when a carry buffer of at
+    // least kFanMinChunk records per tile fits one workgroup's LDS (T up to about 2,900
+    // tiles with two weights per edge), which needs no streams
+    p.blocked = (opts.flags & DBSIM_F_SINGLE_PASS) != 0 && p.T <= 65535u && fan_chunk_records(p, 1) != 0;
     p.ts_bits = 0;
     if (!p.blocked)
         while (((p.T + (1u << p.ts_bits) - 1) >> p.ts_bits) > kMaxSuperTiles) p.ts_bits++;
     p.NS = p.blocked ? 0u : (p.T + (1u << p.ts_bits) - 1) >> p.ts_bits;
     p.HW = (p.D + 3 + 3) & ~3u;
-    // default schedule: single pass, one workgroup per CU with the largest carry buffers;
-    // two passes, two partition workgroups per CU and the largest LDS round that fits
+    // default schedule: two passes, two partition workgroups per CU and the largest LDS
+    // round that fits; single pass, one workgroup per CU with the largest carry buffers
     p.scatter_wgs_per_cu = p.blocked ? 1 : 2;
     p.round_events = max_round_events(p, p.scatter_wgs_per_cu);
     p.bucket_events = max_bucket_events(p, p.scatter_wgs_per_cu);

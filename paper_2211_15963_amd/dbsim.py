@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libdbsim.so")
 ABI_VERSION = 2
 REC_REGIONS = 1
 F_NO_GRAPH = 1
-F_TWO_PASS = 2
+F_SINGLE_PASS = 2
 F_NO_HOST_RECORD = 4
 STATIC_BYTES = 64 << 20  # DBSIM_STATIC_BYTES: the static region of dbsim_create_static
 
@@ -124,7 +124,8 @@ EXPORTED = ["dbsim_abi_version", "dbsim_last_error", "dbsim_create", "dbsim_foot
             "dbsim_step", "dbsim_sync", "dbsim_read_spikes", "dbsim_read_region_signal", "dbsim_read_state",
             "dbsim_write_state", "dbsim_export_csr", "dbsim_set_timing", "dbsim_get_stats", "dbsim_destroy",
             "dbsim_derive_constants", "dbsim_export_network", "dbsim_create_static", "dbsim_receptor_currents",
-            "dbsim_build", "dbsim_create_built", "dbsim_built_free"]
+            "dbsim_build", "dbsim_create_built", "dbsim_built_free", "dbsim_checkpoint_size",
+            "dbsim_checkpoint_save", "dbsim_checkpoint_restore"]
 
 
 def lib():
@@ -164,6 +165,9 @@ def lib():
                                            POINTER(c_uint64)]
     L.dbsim_read_state.argtypes = [H, POINTER(c_float), POINTER(c_float), POINTER(c_int32)]
     L.dbsim_write_state.argtypes = [H, POINTER(c_float), POINTER(c_float), POINTER(c_int32)]
+    L.dbsim_checkpoint_size.argtypes = [H, POINTER(c_uint64)]
+    L.dbsim_checkpoint_save.argtypes = [H, c_void_p, c_uint64, POINTER(c_uint64)]
+    L.dbsim_checkpoint_restore.argtypes = [H, c_void_p, c_uint64]
     L.dbsim_export_csr.argtypes = [H, POINTER(c_uint64), POINTER(c_uint32), POINTER(c_uint32), POINTER(c_float),
                                    POINTER(c_float)]
     L.dbsim_derive_constants.argtypes = [POINTER(SimDesc), POINTER(Desc), c_uint32, POINTER(PopConstants), c_uint32,
@@ -225,7 +229,7 @@ class _TorchAllocator:
 
 def make_desc(spec: NetSpec, record_regions: bool = True, spike_record_capacity: int = 0, record_bins: int = 0,
               device: int = -1, stream_handle: Optional[int] = None, allocator: Optional[_TorchAllocator] = None,
-              host_threads: int = 0, no_graph: bool = False, two_pass: bool = False, host_record: bool = True,
+              host_threads: int = 0, no_graph: bool = False, single_pass: bool = False, host_record: bool = True,
               host_spike_capacity: int = 0):
     holder = spec.to_c()
     d = SimDesc()
@@ -240,7 +244,7 @@ def make_desc(spec: NetSpec, record_regions: bool = True, spike_record_capacity:
         d.dev_alloc = allocator.alloc
         d.dev_free = allocator.free
     d.host_threads = int(host_threads)
-    d.flags = (F_NO_GRAPH if no_graph else 0) | (F_TWO_PASS if two_pass else 0) | (0 if host_record else F_NO_HOST_RECORD)
+    d.flags = (F_NO_GRAPH if no_graph else 0) | (F_SINGLE_PASS if single_pass else 0) | (0 if host_record else F_NO_HOST_RECORD)
     d.host_spike_capacity = int(host_spike_capacity)
     return d, holder
 
@@ -290,12 +294,12 @@ class Built:
 
     def __init__(self, spec: NetSpec, record_regions: bool = True, spike_record_capacity: int = 0,
                  record_bins: int = 0, host_threads: Optional[int] = None, no_graph: bool = False,
-                 two_pass: bool = False, host_record: bool = True, host_spike_capacity: int = 0):
+                 single_pass: bool = False, host_record: bool = True, host_spike_capacity: int = 0):
         if host_threads is None:
             host_threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
         self.spec = spec
         self._desc, self._holder = make_desc(spec, record_regions, spike_record_capacity, record_bins, -1, None, None,
-                                             host_threads, no_graph, two_pass, host_record, host_spike_capacity)
+                                             host_threads, no_graph, single_pass, host_record, host_spike_capacity)
         h = c_void_p()
         _check(lib().dbsim_build(byref(self._desc), byref(h)))
         self._b = h
@@ -337,7 +341,7 @@ class Simulator:
 
     def __init__(self, spec: NetSpec, record_regions: bool = True, use_torch: bool = True, device: int = 0,
                  spike_record_capacity: int = 0, record_bins: int = 0, host_threads: Optional[int] = None,
-                 no_graph: bool = False, stream=None, two_pass: bool = False, static_region: bool = False,
+                 no_graph: bool = False, stream=None, single_pass: bool = False, static_region: bool = False,
                  host_record: bool = True, host_spike_capacity: int = 0, built: Optional["Built"] = None):
         L = lib()
         if host_threads is None:
@@ -358,7 +362,7 @@ class Simulator:
         self.specs = list(spec) if isinstance(spec, (list, tuple)) else [spec]
         first = self.specs[0]
         self._desc, self._holder = make_desc(first, record_regions, spike_record_capacity, record_bins, device,
-                                             stream_handle, self._alloc, host_threads, no_graph, two_pass,
+                                             stream_handle, self._alloc, host_threads, no_graph, single_pass,
                                              host_record, host_spike_capacity)
         h = c_void_p()
         if isinstance(spec, (list, tuple)):
@@ -526,6 +530,20 @@ class Simulator:
         J = np.ascontiguousarray(J, np.float32).reshape(-1)
         ref = np.ascontiguousarray(ref, np.int32)
         _check(lib().dbsim_write_state(self._h, _p(V, c_float), _p(J, c_float), _p(ref, c_int32)))
+
+    def checkpoint(self) -> bytes:
+        """Byte image of the run's state at the current bin boundary (dbsim_checkpoint_save)."""
+        n = c_uint64(0)
+        _check(lib().dbsim_checkpoint_size(self._h, byref(n)))
+        buf = np.zeros(int(n.value), np.uint8)
+        _check(lib().dbsim_checkpoint_save(self._h, buf.ctypes.data_as(c_void_p), buf.size, byref(n)))
+        return buf[: int(n.value)].tobytes()
+
+    def restore(self, image: bytes) -> None:
+        """Loads a checkpoint into this not yet stepped handle (dbsim_checkpoint_restore)."""
+        buf = np.frombuffer(image, np.uint8)
+        _check(lib().dbsim_checkpoint_restore(self._h, buf.ctypes.data_as(c_void_p), buf.size))
+        self.steps_done = int(self.stats()["steps"])
 
     def export_csr(self, edges: bool = True):
         """(row_ptr, seg [N, D+1], tgt, w0, w1); with edges=False only row_ptr and seg."""

@@ -131,28 +131,30 @@ def test_null_arguments(L):
 def test_footprint_matches_layout(L):
     from paper_2211_15963_amd import dbsim as D
     s = configs.share(n=100000, indegree=556)
-    fp = D.footprint(s)
     E = s.num_edges()
     assert E == 100000 * 556
-    # single pass: 12 B per edge (target and two weights), and the event arena of 256-record
-    # blocks (2 B key + 8 B weights + a 4 B count per block): every one of the 25 tiles of 4096
-    # neurons gets its in-degree in whole blocks plus two part-filled blocks per workgroup (at
-    # most 512) and bin
+    # default, two passes: 12 B edge records (target and two weights), 12 B super-tile stream
+    # and 12 B tile arena records per edge
+    fp = D.footprint(s)
+    assert 36 * E < fp < 36 * E + 60 * 100000 + (64 << 20)
+    # single pass: the 12 B edge records and the event arena of 256-record blocks (2 B key +
+    # 8 B weights + a 4 B count per block): every one of the 25 tiles of 4096 neurons gets its
+    # in-degree in whole blocks plus two part-filled blocks per workgroup (at most 512) and bin
     def arena(n, k, T, K=256, G=512):
         tin = [k * (min(n, (t + 1) * 4096) - t * 4096) for t in range(T)]
         blocks = sum(x // K + 2 * G for x in tin)
         return blocks * K * 10 + blocks * 4
+    fp1 = D.footprint(s, single_pass=True)
     lo = 12 * E + arena(100000, 556, 25)
-    assert lo < fp < lo + 60 * 100000 + (64 << 20)
+    assert lo < fp1 < lo + 60 * 100000 + (64 << 20)
     # 1490 tiles still fit the carry buffers (8 records each)
     s = configs.share(n=6100000, indegree=20)
-    fp, E = D.footprint(s), s.num_edges()
+    fp1, E = D.footprint(s, single_pass=True), s.num_edges()
     lo = 12 * E + arena(6100000, 20, 1490)
     # per neuron: a 64 B row header, the state, and the spike-history ring of at least
     # (D + 1) N entries rounded up to a power of two
-    assert lo < fp < lo + 220 * 6100000 + (64 << 20)
-    # forced through two passes: 12 B super-tile stream and 12 B arena records per edge
-    fp2 = D.footprint(s, two_pass=True)
+    assert lo < fp1 < lo + 220 * 6100000 + (64 << 20)
+    fp2 = D.footprint(s)
     assert 36 * E < fp2 < 36 * E + 220 * 6100000 + (64 << 20)
 
 

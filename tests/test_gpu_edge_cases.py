@@ -57,9 +57,9 @@ def test_degenerate_network_bit_exact(Sim, name, bins):
         assert n_spk == bins * spec.num_neurons
     else:
         assert n_spk > 0 and orc.edge_events == 0
-    for two_pass in (False, True):
-        _say(f"{name}: N={spec.num_neurons}, {bins} bins, two_pass={two_pass}")
-        sim = Sim(spec, two_pass=two_pass)
+    for single_pass in (False, True):
+        _say(f"{name}: N={spec.num_neurons}, {bins} bins, single_pass={single_pass}")
+        sim = Sim(spec, single_pass=single_pass)
         sim.step(bins * S)
         assert _same(sim, orc, spec) == n_spk
         sim.close()

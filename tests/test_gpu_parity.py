@@ -124,9 +124,9 @@ def test_mixed_launch_sequence_bit_exact(Sim):
     reset by whichever kernel follows them), in both fan-in forms, against the oracle."""
     spec = configs.share(n=20000, indegree=300, seed=16)
     S = spec.steps_per_bin
-    for two_pass in (False, True):
-        _say(f"share 20000 / k300 seed 16: mixed launch sequence, two_pass={two_pass}")
-        sim = Sim(spec, two_pass=two_pass)
+    for single_pass in (False, True):
+        _say(f"share 20000 / k300 seed 16: mixed launch sequence, single_pass={single_pass}")
+        sim = Sim(spec, single_pass=single_pass)
         orc = Oracle(spec, 32)
         plan = [("graph", 20 * S), ("step", 3), ("step", S - 3), ("timed", 7 * S + 4), ("graph", 9 * S - 4),
                 ("tune", 0), ("graph", 12 * S), ("timed", 5), ("step", 2 * S - 5)]
@@ -205,21 +205,21 @@ def test_one_hip_runtime_in_process(Sim):
     assert len(maps) == 1, maps
 
 
-def test_two_pass_fanin_bit_exact(Sim):
+def test_single_pass_fanin_bit_exact(Sim):
     spec = configs.share(n=20000, indegree=556, seed=5)
-    _say("share 20000 / k556 seed 5, fan-in forced through super-tile streams, 400 steps")
-    sim = Sim(spec, two_pass=True)
-    assert sim.info.fanin_passes == 2
+    _say("share 20000 / k556 seed 5, single-pass fan-in, 400 steps")
+    sim = Sim(spec, single_pass=True)
+    assert sim.info.fanin_passes == 1
     sim.step(400)
     orc = Oracle(spec, 32)
     orc.step(400)
     _compare(sim, orc, spec)
     sim.close()
-    # one weight per edge (8-byte records, copied into LDS with 12-byte reads) over 3 tiles
+    # one weight per edge (8-byte records) over 5 tiles
     spec = configs.tiny(seed=8, n_exc=16000, n_inh=4000, indegree=100)
-    _say("tiny-recipe 20000 / k100 seed 8 (one weight per edge), two-pass fan-in, 300 steps")
-    sim = Sim(spec, two_pass=True)
-    assert sim.info.fanin_passes == 2
+    _say("tiny-recipe 20000 / k100 seed 8 (one weight per edge), single-pass fan-in, 300 steps")
+    sim = Sim(spec, single_pass=True)
+    assert sim.info.fanin_passes == 1
     sim.step(300)
     orc = Oracle(spec, 32)
     orc.step(300)
@@ -227,8 +227,8 @@ def test_two_pass_fanin_bit_exact(Sim):
     _compare(sim, orc, spec)
     sim.close()
     spec = configs.multi_region(n_regions=20, per_region=1000, seed=6)
-    _say("multi-region 20 x 1000 seed 6, two-pass fan-in, 300 steps")
-    sim = Sim(spec, two_pass=True)
+    _say("multi-region 20 x 1000 seed 6, single-pass fan-in, 300 steps")
+    sim = Sim(spec, single_pass=True)
     sim.step(300)
     orc = Oracle(spec, 32)
     orc.step(300)
@@ -236,20 +236,20 @@ def test_two_pass_fanin_bit_exact(Sim):
     sim.close()
 
 
-@pytest.mark.parametrize("two_pass", [False, True])
-def test_fanin_schedules_agree(Sim, two_pass):
+@pytest.mark.parametrize("single_pass", [False, True])
+def test_fanin_schedules_agree(Sim, single_pass):
     """Every partition schedule gives the same bits (exact integer arrival sums)."""
     spec = configs.share(n=60000, indegree=300, seed=7)
-    _say(f"share 60000 / k300, schedules compared, two_pass={two_pass}")
-    ref = Sim(spec, two_pass=two_pass)
-    assert ref.info.fanin_passes == (2 if two_pass else 1)
+    _say(f"share 60000 / k300, schedules compared, single_pass={single_pass}")
+    ref = Sim(spec, single_pass=single_pass)
+    assert ref.info.fanin_passes == (1 if single_pass else 2)
     ref.step(200)
     r_sp, r_st = ref.spikes(), ref.state()
     r_ev = ref.stats()["edge_events"]
     assert len(r_sp[0]) > 0
     ref.close()
     for wgs, re, cpw, ap in ((1, 0, 1, 1), (2, 256, 64, 9), (3, 512, 2, 2), (8, 0, 8, 0), (4, 1536, 4, 5)):
-        sim = Sim(spec, two_pass=two_pass)
+        sim = Sim(spec, single_pass=single_pass)
         try:
             sim.set_tuning(scatter_wgs_per_cu=wgs, round_events=re, chunks_per_wg=cpw, ahead_passes=ap)
         except Exception as ex:  # a schedule that does not fit the LDS is refused up front
@@ -305,9 +305,9 @@ def test_ou_background_bit_exact(Sim):
     _compare(sim, orc, spec)
     sim.close()
     spec = configs.share(n=20000, indegree=300, seed=15)
-    for two_pass in (False, True):
-        _say(f"share 20000 / k300 seed 15: OU on the inhibitory population from bin 5, two_pass={two_pass}")
-        sim = Sim(spec, two_pass=two_pass)
+    for single_pass in (False, True):
+        _say(f"share 20000 / k300 seed 15: OU on the inhibitory population from bin 5, single_pass={single_pass}")
+        sim = Sim(spec, single_pass=single_pass)
         sim.step(5 * S + 3)  # switched on mid-bin
         sim.set_ou_background([0.0, 20.0], [0.0, 40.0], [0.0, 4.0])
         sim.step(25 * S - 3)
@@ -334,9 +334,9 @@ def test_spike_injection_bit_exact(Sim):
     _compare(sim, orc, spec)
     sim.close()
     spec = configs.share(n=20000, indegree=300, seed=13)
-    for two_pass in (False, True):
-        _say(f"share 20000 / k300 seed 13: injection 0.02 for 20 bins from bin 10, two_pass={two_pass}")
-        sim = Sim(spec, two_pass=two_pass)
+    for single_pass in (False, True):
+        _say(f"share 20000 / k300 seed 13: injection 0.02 for 20 bins from bin 10, single_pass={single_pass}")
+        sim = Sim(spec, single_pass=single_pass)
         sim.step(10 * S)
         sim.set_spike_injection(0.02, 20)
         sim.step(30 * S)

@@ -75,17 +75,17 @@ def test_share_600k_element_wise_both_forms(Sim):
     orc.set_threads(_threads())
     orc.step(K * S)
     assert orc.spikes()[0].size > 100_000
-    for two_pass in (False, True):
-        _say(f"share 600000 / k125 seed 31: GPU, {K} bins, two_pass={two_pass}")
-        sim = Sim(spec, two_pass=two_pass)
+    for single_pass in (False, True):
+        _say(f"share 600000 / k125 seed 31: GPU, {K} bins, single_pass={single_pass}")
+        sim = Sim(spec, single_pass=single_pass)
         info = sim.info
         assert info.n_tiles == 147
-        assert info.fanin_passes == (2 if two_pass else 1)
+        assert info.fanin_passes == (1 if single_pass else 2)
         n_blocks = (spec.num_neurons + 255) // 256
         assert n_blocks > 2000  # several compaction groups and level-1 readout groups of 256 blocks
         sim.step(K * S)
-        _compare(sim, orc, spec, f"600k two_pass={two_pass}")
-        _compare_regions(sim, orc, spec, f"600k two_pass={two_pass}")
+        _compare(sim, orc, spec, f"600k single_pass={single_pass}")
+        _compare_regions(sim, orc, spec, f"600k single_pass={single_pass}")
         sim.close()
 
 
@@ -148,9 +148,9 @@ def test_conversion_ties_bit_exact(Sim):
     orc.step(20 * S)
     st, _ = orc.spikes()
     assert len(st) == 20 * spec.num_neurons, "the drive does not fire every neuron in every bin"
-    for two_pass in (False, True):
-        _say(f"conversion ties, saturated 4 x 500 neurons, 20 bins, two_pass={two_pass}")
-        sim = Sim(spec, two_pass=two_pass)
+    for single_pass in (False, True):
+        _say(f"conversion ties, saturated 4 x 500 neurons, 20 bins, single_pass={single_pass}")
+        sim = Sim(spec, single_pass=single_pass)
         sim.step(20 * S)
-        _compare(sim, orc, spec, f"ties two_pass={two_pass}")
+        _compare(sim, orc, spec, f"ties single_pass={single_pass}")
         sim.close()

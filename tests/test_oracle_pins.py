@@ -544,24 +544,27 @@ def test_point_evaluations_agree_with_full_run():
 
 def test_euler_step_convergence():
     """Euler-Maruyama step size (Extended Data Fig. 1 compares 1 ms with 0.001 ms on a
-    1000-neuron LIF network). With a deterministic drive (constant I_ext, no Poisson
-    noise, so the runs differ only by the step size) the relative V error against the
-    finest step shrinks as the step shrinks. Informational numbers are printed."""
-    errs = {}
-    ref = None
-    for dt in (0.0625, 0.125, 0.25, 0.5, 1.0):
-        spec = configs.tiny(bg_rate_hz=0.0, dt_ms=dt)
-        for p in spec.pops:
-            p.I_ext = 560.0
-        o = Oracle(spec, 64)
-        o.step(int(round(50.0 / dt)))
-        V = o.state()[0]
-        if ref is None:
-            ref = V
-        else:
-            errs[dt] = float(np.linalg.norm(V - ref) / np.linalg.norm(ref))
-    print("relative V error at 50 ms vs dt = 0.0625 ms:", {k: round(v, 4) for k, v in errs.items()})
-    assert errs[0.125] < errs[1.0]
+    1000-neuron LIF network). With a deterministic drive (constant I_ext, no Poisson noise,
+    so the runs differ only by the step size), the population rate of the recurrent tiny
+    network over 100-300 ms converges as the step shrinks: its relative distance to the
+    rate at dt = 1/16 ms grows strictly from 1/8 to 1 ms and is below 2 % at 1/8 ms. (Single
+    spike times and V are chaotic in this network, so they are not compared.)"""
+    for I_ext in (560.0, 600.0):
+        rate = {}
+        for dt in (0.0625, 0.125, 0.25, 0.5, 1.0):
+            spec = configs.tiny(bg_rate_hz=0.0, dt_ms=dt)
+            for p in spec.pops:
+                p.I_ext = I_ext
+            o = Oracle(spec, 64)
+            o.step(int(round(300.0 / dt)))
+            steps, _ = o.spikes()
+            rate[dt] = float(np.sum(steps * dt >= 100.0)) / (spec.num_neurons * 0.2)
+        err = [abs(rate[dt] - rate[0.0625]) / rate[0.0625] for dt in (0.125, 0.25, 0.5, 1.0)]
+        print(f"I_ext {I_ext} pA: rate {rate[0.0625]:.3f} Hz at dt = 1/16 ms; relative rate error at "
+              f"1/8, 1/4, 1/2, 1 ms: {np.round(err, 4)}")
+        assert rate[0.0625] > 5.0
+        assert all(a < b for a, b in zip(err, err[1:])), err
+        assert err[0] < 0.02, err
 
 
 def test_threaded_oracle_equals_one_thread():
