@@ -487,8 +487,8 @@ def _rocpd(db):
 
 
 def _short(name):
-    for k in ("k_part", "k_bucket", "k_gather", "k_neuron", "k_compact", "k_region_partials", "k_readout_close",
-              "copyBuffer"):
+    for k in ("k_part", "k_bucket", "k_gather_blk", "k_gather", "k_fan", "k_neuron", "k_compact", "k_drain",
+              "k_region_partials", "k_readout_close", "k_pass_reset", "copyBuffer"):
         if k in name:
             return k
     return name
