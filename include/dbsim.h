@@ -88,6 +88,8 @@ typedef struct dbsim_desc {
 #define DBSIM_F_NO_GRAPH 1u /* launch kernels directly instead of replaying HIP graphs */
 #define DBSIM_F_NO_HOST_RECORD 4u /* keep the raster only in the device ring (no pinned host
                                      memory; reads copy from the device) */
+#define DBSIM_F_HOST_BUILD 8u /* build the connection table on the host threads even where the
+                                 device construction applies (same table; for comparisons) */
 #define DBSIM_F_SINGLE_PASS 2u /* fan-in in one pass into per-workgroup blocks of each tile
                                   (no super-tile streams: about a third less device memory,
                                   slower on every measured network); taken where the tiles'
@@ -122,6 +124,8 @@ typedef struct dbsim_info {
     uint32_t frac_bits;        /* F of the fixed-point arrival sums */
     uint32_t n_members;        /* networks in the handle (1 unless an ensemble) */
     uint32_t fanin_passes;     /* 1: single-pass fan-in into tile blocks, 2: through super-tile streams */
+    uint32_t device_built;     /* 1: the connection table was generated on the device */
+    uint32_t reserved;
 } dbsim_info;
 
 typedef struct dbsim_member {
@@ -361,6 +365,20 @@ int dbsim_write_state(struct dbsim* h, const float* V, const float* J, const int
  *   one. Its spike and region-signal history starts at the checkpoint's bin (earlier bins:
  *   ERANGE); its tuning, timing and launch mode stay its own.
  */
+/*
+ * The in-edges of one target as the device construction of the connection table draws
+ * them, evaluated on the host threads (no device needed): for checking the device
+ * generator against the input generator (dbnet_in_edges) edge by edge. members as for
+ * dbsim_create_ensemble; target is a global neuron id (members one after another).
+ * Writes up to cap edges in the generator's order: global source ids, weights, delays
+ * (bins) and the projection index within the member; *n_out = the in-degree (ETRUNC if
+ * cap is smaller). EINVAL where the device construction does not apply (lognormal
+ * weights) or for an invalid description or target.
+ */
+int dbsim_check_device_generator(const dbnet_desc* members, uint32_t n_members, uint64_t target, uint32_t* src,
+                                 float* w0, float* w1, uint8_t* delay, uint32_t* proj, uint64_t cap,
+                                 uint64_t* n_out);
+
 int dbsim_checkpoint_size(struct dbsim* h, uint64_t* bytes);
 int dbsim_checkpoint_save(struct dbsim* h, void* buf, uint64_t cap, uint64_t* n_out);
 int dbsim_checkpoint_restore(struct dbsim* h, const void* buf, uint64_t len);

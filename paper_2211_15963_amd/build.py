@@ -20,7 +20,7 @@ HIPFLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contra
             "-fno-gpu-flush-denormals-to-zero", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
             "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
-SOURCES = ["kernels.hip", "netbuild.cpp", "abi.cpp"]
+SOURCES = ["kernels.hip", "devbuild.hip", "netbuild.cpp", "abi.cpp"]
 
 
 def hipcc():

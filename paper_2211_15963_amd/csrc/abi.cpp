@@ -123,6 +123,7 @@ struct dbsim {
     double ms[kPhases] = {0, 0, 0, 0};
     uint64_t timed_bins = 0;
     double build_seconds = 0.0;
+    bool device_built = false; // the connection table was generated on the device
 };
 
 // A network built on the host and not yet deployed (dbsim_build -> dbsim_create_built).
@@ -476,7 +477,7 @@ static int build_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32_
                                       "dbsim_create_static holds " + std::to_string((size_t)DBSIM_STATIC_BYTES));
         }
         auto t0 = std::chrono::steady_clock::now();
-        m = build_tables(b->mem, b->plan, desc->host_threads, b->ht);
+        m = build_tables(b->mem, b->plan, desc->host_threads, b->ht, !b->plan.dev_build);
         if (!m.empty()) {
             delete b;
             return fail(DBSIM_EINVAL, m);
@@ -491,6 +492,79 @@ static int build_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32_
         delete b;
         return fail(DBSIM_EINVAL, "unexpected exception while building the network");
     }
+}
+
+// Connection table generated on the device (plan.dev_build), into the handle's edge and
+// header arrays, with the temporaries in its tile arena and super-tile streams. A delay
+// segment too long for the device sort sends the construction back to the host threads.
+static int device_build(dbsim* h, HostTables& ht, unsigned host_threads) {
+    const Plan& p = h->plan;
+    const auto t0 = std::chrono::steady_clock::now();
+    unsigned char* ev = h->dev + p.ev.off;
+    // the generator's tables, in the order gen_tables_bytes lays them out
+    size_t o = p.gl.tables;
+    hipError_t pe = hipSuccess;
+    auto put = [&](const void* src, size_t bytes) -> unsigned char* {
+        unsigned char* d = ev + o;
+        if (bytes && pe == hipSuccess) pe = hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, h->stream);
+        o += (bytes + 255) & ~(size_t)255;
+        return d;
+    };
+    DevBuild b{};
+    b.g.pops = reinterpret_cast<const GenPop*>(put(ht.gpops.data(), sizeof(GenPop) * ht.gpops.size()));
+    b.g.members = reinterpret_cast<const GenMember*>(put(ht.gmembers.data(), sizeof(GenMember) * ht.gmembers.size()));
+    b.g.projs = reinterpret_cast<const GenProj*>(put(ht.gprojs.data(), sizeof(GenProj) * ht.gprojs.size()));
+    b.g.cands = reinterpret_cast<const GenCand*>(put(ht.gcands.data(), sizeof(GenCand) * ht.gcands.size()));
+    b.g.cpops = reinterpret_cast<const GenCandPop*>(put(ht.gcpops.data(), sizeof(GenCandPop) * ht.gcpops.size()));
+    const uint8_t zero = 0;
+    b.g.dtab = put(ht.gdtab.empty() ? &zero : ht.gdtab.data(), ht.gdtab.empty() ? 1 : ht.gdtab.size());
+    b.g.n_pops = (uint32_t)ht.gpops.size();
+    b.g.kmax = ht.gkmax;
+    b.g.hcap = ht.ghcap;
+    b.g.scratch_words = gen_scratch_words(ht.gkmax, ht.ghcap);
+    b.scratch = reinterpret_cast<uint32_t*>(h->dev + p.sev.off);
+    b.batch = p.gen_batch;
+    b.cnt = reinterpret_cast<uint32_t*>(ev + p.gl.cnt);
+    b.cur = reinterpret_cast<unsigned long long*>(ev + p.gl.cur);
+    b.rowlen = reinterpret_cast<unsigned long long*>(ev + p.gl.rowlen);
+    b.rowptr = reinterpret_cast<unsigned long long*>(ev + p.gl.rowptr);
+    b.sums = reinterpret_cast<unsigned long long*>(ev + p.gl.sums);
+    b.tb = ev + p.gl.tb;
+    b.flags = reinterpret_cast<uint32_t*>(ev + p.gl.flags);
+    b.edge = reinterpret_cast<uint32_t*>(h->dev + p.edge.off);
+    b.hdr = reinterpret_cast<uint32_t*>(h->dev + p.hdr.off);
+    b.N = p.N;
+    b.E = p.E;
+    b.D = p.D;
+    b.HW = p.HW;
+    b.KW = p.KW;
+    b.wlim = std::ldexp(1.0, 52 - (int)p.F);
+    HIPCHK(h, pe, "hipMemcpy(generator tables)");
+    if (o > p.gl.cnt) return fail(DBSIM_EINVAL, "internal error: generator tables overrun their slot");
+    HIPCHK(h, launch_device_build(b, h->stream), "device construction launch");
+    uint32_t flags = 0;
+    unsigned long long total = 0;
+    const uint64_t nb = ((uint64_t)p.N + 1023) / 1024;
+    HIPCHK(h, hipMemcpyAsync(&flags, b.flags, 4, hipMemcpyDeviceToHost, h->stream), "hipMemcpy");
+    HIPCHK(h, hipMemcpyAsync(&total, b.sums + nb, 8, hipMemcpyDeviceToHost, h->stream), "hipMemcpy");
+    HIPCHK(h, hipStreamSynchronize(h->stream), "device construction");
+    if (flags & kGenWeight)
+        return fail(DBSIM_EINVAL, "a weight is too large for the fixed-point format (|w| * 2^frac_bits must stay below 2^52)");
+    if (flags & (kGenBadDelay | kGenShort)) return fail(DBSIM_EINVAL, "network generator failed on the device");
+    if (total != p.E) return fail(DBSIM_EINVAL, "internal error: device construction edge count mismatch");
+    if (flags & kGenLongSegment) { // a delay segment longer than the device sort takes
+        const std::string m = build_tables(h->mem, p, host_threads, ht, true);
+        if (!m.empty()) return fail(DBSIM_EINVAL, m);
+        HIPCHK(h, hipMemcpyAsync(h->dev + p.hdr.off, ht.hdr.data(), 4 * ht.hdr.size(), hipMemcpyHostToDevice, h->stream),
+               "hipMemcpy");
+        HIPCHK(h, hipMemcpyAsync(h->dev + p.edge.off, ht.edge.get(), 4 * ht.edge_words, hipMemcpyHostToDevice,
+                                 h->stream), "hipMemcpy");
+        HIPCHK(h, hipStreamSynchronize(h->stream), "upload");
+    } else {
+        h->device_built = true;
+    }
+    h->build_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return DBSIM_OK;
 }
 
 // Device phase: allocation, streams, upload and initial state from a built network, which
@@ -627,10 +701,10 @@ static int deploy_impl(dbsim_built* bt, const dbsim_desc* dev_opts, dbsim** out)
         if (e == hipSuccess) e = up(p.pops, ht.pops.data(), sizeof(PopParams) * ht.pops.size());
         if (e == hipSuccess) e = up(p.ptab, ht.ptab.data(), 4 * ht.ptab.size());
         if (e == hipSuccess) e = up(p.blk, ht.blk.data(), sizeof(uint2) * ht.blk.size());
-        if (e == hipSuccess) e = up(p.hdr, ht.hdr.data(), 4 * ht.hdr.size());
+        if (e == hipSuccess && !p.dev_build) e = up(p.hdr, ht.hdr.data(), 4 * ht.hdr.size());
         if (e == hipSuccess) e = up(p.st_base, ht.st_base.data(), 8 * ht.st_base.size());
         if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.st_fill.off, 0, p.st_fill.bytes, h->stream);
-        if (e == hipSuccess) e = up(p.edge, ht.edge.get(), 4 * ht.edge_words);
+        if (e == hipSuccess && !p.dev_build) e = up(p.edge, ht.edge.get(), 4 * ht.edge_words);
         if (e == hipSuccess) e = up(p.tile_base, ht.tile_base.data(), 8 * ht.tile_base.size());
         if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.tile_fill.off, 0, p.tile_fill.bytes, h->stream);
         if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.grp_cnt.off, 0, p.grp_cnt.bytes, h->stream);
@@ -655,6 +729,14 @@ static int deploy_impl(dbsim_built* bt, const dbsim_desc* dev_opts, dbsim** out)
             release_device(h);
             delete h;
             return fail(DBSIM_EDEVICE, msg);
+        }
+        if (p.dev_build) {
+            const int rc = device_build(h, ht, desc->host_threads);
+            if (rc) {
+                release_device(h);
+                delete h;
+                return rc;
+            }
         }
         // grid of the partition kernels: scatter_wgs_per_cu blocks per CU
         hipDeviceProp_t prop;
@@ -791,6 +873,7 @@ int dbsim_get_info(dbsim* h, dbsim_info* info) {
     info->frac_bits = p.F;
     info->n_members = p.n_members;
     info->fanin_passes = p.blocked ? 1u : 2u;
+    info->device_built = h->device_built ? 1u : 0u;
     return DBSIM_OK;
 }
 
@@ -1016,6 +1099,53 @@ int dbsim_write_state(dbsim* h, const float* V, const float* J, const int32_t* r
         HIPCHK(h, hipMemcpy(h->net.ref, r.data(), N, hipMemcpyHostToDevice), "hipMemcpy");
     }
     return DBSIM_OK;
+}
+
+int dbsim_check_device_generator(const dbnet_desc* members, uint32_t n_members, uint64_t target, uint32_t* src,
+                                 float* w0, float* w1, uint8_t* delay, uint32_t* proj, uint64_t cap,
+                                 uint64_t* n_out) {
+    if (!members || !n_members || !n_out) return fail(DBSIM_EINVAL, "null argument or no network");
+    try {
+        Members mem;
+        mem.assign(members, n_members);
+        char err[512];
+        for (uint32_t k = 0; k < n_members; k++)
+            if (dbnet_validate(&mem.m[k], err, sizeof err) != 0) return fail(DBSIM_EINVAL, err);
+        if (target >= mem.nbase.back()) return fail(DBSIM_EINVAL, "target out of range");
+        HostTables ht;
+        const std::string m = make_gen_tables(mem, ht);
+        if (!m.empty()) return fail(DBSIM_EINVAL, m);
+        GenTables g{};
+        g.pops = ht.gpops.data();
+        g.members = ht.gmembers.data();
+        g.projs = ht.gprojs.data();
+        g.cands = ht.gcands.data();
+        g.cpops = ht.gcpops.data();
+        g.dtab = ht.gdtab.data();
+        g.n_pops = (uint32_t)ht.gpops.size();
+        g.kmax = ht.gkmax;
+        g.hcap = ht.ghcap;
+        g.scratch_words = gen_scratch_words(ht.gkmax, ht.ghcap);
+        std::vector<uint32_t> scratch(g.scratch_words);
+        uint64_t n = 0;
+        const bool ok = gen_target(g, target, scratch.data(),
+                                   [&](uint64_t s, uint32_t, float a, float b, uint32_t dl, uint32_t j) {
+                                       if (n < cap) {
+                                           if (src) src[n] = (uint32_t)s;
+                                           if (w0) w0[n] = a;
+                                           if (w1) w1[n] = b;
+                                           if (delay) delay[n] = (uint8_t)dl;
+                                           if (proj) proj[n] = j;
+                                       }
+                                       n++;
+                                   });
+        *n_out = n;
+        if (!ok) return fail(DBSIM_EINVAL, "a candidate set is smaller than its in-degree");
+        if (n > cap) return fail(DBSIM_ETRUNC, "buffers too small; *n_out holds the in-degree");
+        return DBSIM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(DBSIM_ENOMEM, "host allocation failed");
+    }
 }
 
 // ------------------------------------------------------------------ checkpoint and resume

@@ -1,0 +1,234 @@
+// devbuild.hip - construction of the connection table on the device.
+//
+// The same table the host construction builds (netbuild.cpp): rows by presynaptic neuron,
+// delay segments in ascending delay, each segment sorted by target (equal targets, which
+// only distinct projections can give, in projection order), records of (weights, target |
+// inhibitory source << 31), and 64-byte row headers. Steps, all on the handle's stream:
+//   k_gen_count   one thread per target draws its in-edges (gen_target) and counts them
+//                 per (source, delay), in batches of targets (per-thread scratch);
+//   k_gen_rows    per source: delay-segment offsets within the row, row length;
+//   k_scan_*      row starts (exclusive scan of the row lengths, 64-bit);
+//   k_gen_cursors per source: row header (start | class bit), one cursor per segment;
+//   k_gen_fill    the in-edges drawn again, each placed at its segment's cursor;
+//   k_gen_sort    one wavefront per row orders every segment by (target, projection).
+// The draws are counter-based, so the second generation repeats the first exactly.
+#include <algorithm>
+
+#include "dbsim_internal.hpp"
+#include "devgen.hpp"
+
+namespace dbs {
+
+__global__ void __launch_bounds__(256) k_gen_clear(uint32_t* p, uint64_t n) {
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (uint64_t)gridDim.x * blockDim.x)
+        p[x] = 0u;
+}
+
+__global__ void __launch_bounds__(256) k_gen_count(DevBuild b, uint64_t i0, uint64_t i1) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t i = i0 + t;
+    if (i >= i1) return;
+    uint32_t* sc = b.scratch + t * b.g.scratch_words;
+    const uint32_t D = b.D;
+    const uint64_t N = b.N;
+    bool bad = false;
+    const bool ok = gen_target(b.g, i, sc, [&](uint64_t s, uint32_t, float, float, uint32_t dl, uint32_t) {
+        if (dl >= 1u && dl <= D && s < N) atomicAdd(&b.cnt[s * D + dl - 1], 1u);
+        else bad = true;
+    });
+    if (bad) atomicOr(&b.flags[0], kGenBadDelay);
+    if (!ok) atomicOr(&b.flags[0], kGenShort);
+}
+
+__global__ void __launch_bounds__(256) k_gen_rows(DevBuild b) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= b.N) return;
+    uint32_t* hp = b.hdr + j * b.HW;
+    unsigned long long acc = 0;
+    hp[2] = 0u;
+    for (uint32_t x = 0; x < b.D; x++) {
+        acc += b.cnt[j * b.D + x];
+        hp[3 + x] = (uint32_t)acc;
+    }
+    b.rowlen[j] = acc;
+}
+
+// exclusive scan of n 64-bit values, 1024 per block (256 threads x 4)
+__device__ unsigned long long block_scan_u64(unsigned long long v, unsigned long long* sh, unsigned long long* total) {
+    const uint32_t tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (uint32_t o = 1; o < blockDim.x; o <<= 1) {
+        const unsigned long long y = tid >= o ? sh[tid - o] : 0ull;
+        __syncthreads();
+        sh[tid] += y;
+        __syncthreads();
+    }
+    *total = sh[blockDim.x - 1];
+    const unsigned long long r = sh[tid] - v;
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(256) k_scan_a(const unsigned long long* in, unsigned long long* out, uint64_t n,
+                                                unsigned long long* sums) {
+    __shared__ unsigned long long sh[256];
+    const uint64_t base = (uint64_t)blockIdx.x * 1024 + 4ull * threadIdx.x;
+    unsigned long long v[4], loc = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        v[q] = base + q < n ? in[base + q] : 0ull;
+        loc += v[q];
+    }
+    unsigned long long tot;
+    unsigned long long ex = block_scan_u64(loc, sh, &tot);
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        if (base + q < n) out[base + q] = ex;
+        ex += v[q];
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// one block: exclusive scan of the nb block sums in place, the total at sums[nb]
+__global__ void __launch_bounds__(256) k_scan_b(unsigned long long* sums, uint64_t nb) {
+    __shared__ unsigned long long sh[256];
+    unsigned long long carry = 0;
+    for (uint64_t c0 = 0; c0 < nb; c0 += 256) {
+        const uint64_t x = c0 + threadIdx.x;
+        const unsigned long long v = x < nb ? sums[x] : 0ull;
+        unsigned long long tot;
+        const unsigned long long ex = block_scan_u64(v, sh, &tot);
+        if (x < nb) sums[x] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) sums[nb] = carry;
+}
+
+__global__ void __launch_bounds__(256) k_scan_c(unsigned long long* out, uint64_t n, const unsigned long long* sums) {
+    const uint64_t base = (uint64_t)blockIdx.x * 1024 + 4ull * threadIdx.x;
+    const unsigned long long add = sums[blockIdx.x];
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+        if (base + q < n) out[base + q] += add;
+}
+
+__global__ void __launch_bounds__(256) k_gen_cursors(DevBuild b) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= b.N) return;
+    uint32_t* hp = b.hdr + j * b.HW;
+    const unsigned long long r0 = b.rowptr[j];
+    const unsigned long long inh = b.g.pops[gen_pop_of(b.g, j)].exc ? 0ull : 1ull;
+    const unsigned long long rs = r0 | (inh << 63);
+    hp[0] = (uint32_t)rs;
+    hp[1] = (uint32_t)(rs >> 32);
+    for (uint32_t x = 0; x < b.D; x++) b.cur[j * b.D + x] = r0 + hp[2 + x];
+}
+
+template <int KW>
+__global__ void __launch_bounds__(256) k_gen_fill(DevBuild b, uint64_t i0, uint64_t i1) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t i = i0 + t;
+    if (i >= i1) return;
+    uint32_t* sc = b.scratch + t * b.g.scratch_words;
+    const uint32_t D = b.D;
+    const uint64_t N = b.N, E = b.E;
+    const double wlim = b.wlim;
+    bool bad = false, wbad = false;
+    gen_target(b.g, i, sc, [&](uint64_t s, uint32_t exc, float w0, float w1, uint32_t dl, uint32_t j) {
+        if (!(dl >= 1u && dl <= D && s < N)) {
+            bad = true;
+            return;
+        }
+        const unsigned long long pos = atomicAdd(&b.cur[s * D + dl - 1], 1ull);
+        if (pos >= E) {
+            bad = true;
+            return;
+        }
+        const uint32_t key = (uint32_t)i | ((exc ? 0u : 1u) << 31);
+        if (KW == 2)
+            reinterpret_cast<uint3*>(b.edge)[pos] = make_uint3(__float_as_uint(w0), __float_as_uint(w1), key);
+        else
+            reinterpret_cast<uint2*>(b.edge)[pos] = make_uint2(__float_as_uint(w0), key);
+        b.tb[pos] = (uint8_t)j;
+        if (!(fabs((double)w0) < wlim) || !(fabs((double)w1) < wlim)) wbad = true;
+    });
+    if (bad) atomicOr(&b.flags[0], kGenBadDelay);
+    if (wbad) atomicOr(&b.flags[0], kGenWeight);
+}
+
+// one wavefront per row: every delay segment ordered by (target, projection) through LDS
+template <int KW>
+__global__ void __launch_bounds__(64) k_gen_sort(DevBuild b) {
+    constexpr uint32_t RW = 1 + KW;
+    __shared__ uint32_t s_rec[kGenSortMax * RW];
+    __shared__ uint8_t s_tb[kGenSortMax];
+    const uint64_t j = blockIdx.x;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t* hp = b.hdr + j * b.HW;
+    const unsigned long long r0 = (unsigned long long)hp[0] | ((unsigned long long)(hp[1] & 0x7FFFFFFFu) << 32);
+    for (uint32_t x = 0; x < b.D; x++) {
+        const unsigned long long s0 = r0 + hp[2 + x];
+        const uint32_t L = hp[3 + x] - hp[2 + x];
+        if (L < 2u) continue;
+        if (L > kGenSortMax || s0 + L > b.E) {
+            if (lane == 0) atomicOr(&b.flags[0], kGenLongSegment);
+            continue;
+        }
+        for (uint32_t e = lane; e < L; e += 64) {
+#pragma unroll
+            for (uint32_t w = 0; w < RW; w++) s_rec[e * RW + w] = b.edge[(s0 + e) * RW + w];
+            s_tb[e] = b.tb[s0 + e];
+        }
+        __syncthreads();
+        for (uint32_t e = lane; e < L; e += 64) {
+            const unsigned long long ke = ((unsigned long long)(s_rec[e * RW + KW] & 0x7FFFFFFFu) << 8) | s_tb[e];
+            uint32_t rank = 0;
+            for (uint32_t f = 0; f < L; f++) {
+                const unsigned long long kf = ((unsigned long long)(s_rec[f * RW + KW] & 0x7FFFFFFFu) << 8) | s_tb[f];
+                rank += kf < ke ? 1u : 0u;
+            }
+#pragma unroll
+            for (uint32_t w = 0; w < RW; w++) b.edge[(s0 + rank) * RW + w] = s_rec[e * RW + w];
+        }
+        __syncthreads();
+    }
+}
+
+static unsigned grid_of(uint64_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t launch_device_build(const DevBuild& b, hipStream_t st) {
+    const uint64_t N = b.N;
+    hipLaunchKernelGGL(k_gen_clear, dim3(grid_of(N * b.D, 256 * 16) + 1), dim3(256), 0, st, b.cnt, N * b.D);
+    hipLaunchKernelGGL(k_gen_clear, dim3(1), dim3(256), 0, st, b.flags, (uint64_t)4);
+    hipError_t e = hipGetLastError();
+    for (uint64_t i0 = 0; i0 < N && e == hipSuccess; i0 += b.batch) {
+        const uint64_t i1 = std::min<uint64_t>(N, i0 + b.batch);
+        hipLaunchKernelGGL(k_gen_count, dim3(grid_of(i1 - i0, 256)), dim3(256), 0, st, b, i0, i1);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gen_rows, dim3(grid_of(N, 256)), dim3(256), 0, st, b);
+    const uint64_t nb = (N + 1023) / 1024;
+    hipLaunchKernelGGL(k_scan_a, dim3((unsigned)nb), dim3(256), 0, st, b.rowlen, b.rowptr, N, b.sums);
+    hipLaunchKernelGGL(k_scan_b, dim3(1), dim3(256), 0, st, b.sums, nb);
+    hipLaunchKernelGGL(k_scan_c, dim3((unsigned)nb), dim3(256), 0, st, b.rowptr, N, b.sums);
+    hipLaunchKernelGGL(k_gen_cursors, dim3(grid_of(N, 256)), dim3(256), 0, st, b);
+    e = hipGetLastError();
+    for (uint64_t i0 = 0; i0 < N && e == hipSuccess; i0 += b.batch) {
+        const uint64_t i1 = std::min<uint64_t>(N, i0 + b.batch);
+        if (b.KW == 2)
+            hipLaunchKernelGGL(k_gen_fill<2>, dim3(grid_of(i1 - i0, 256)), dim3(256), 0, st, b, i0, i1);
+        else
+            hipLaunchKernelGGL(k_gen_fill<1>, dim3(grid_of(i1 - i0, 256)), dim3(256), 0, st, b, i0, i1);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
+    if (b.KW == 2)
+        hipLaunchKernelGGL(k_gen_sort<2>, dim3((unsigned)N), dim3(64), 0, st, b);
+    else
+        hipLaunchKernelGGL(k_gen_sort<1>, dim3((unsigned)N), dim3(64), 0, st, b);
+    return hipGetLastError();
+}
+
+} // namespace dbs

@@ -143,6 +143,124 @@ uint32_t Members::member_of(uint64_t i) const {
     return (uint32_t)(std::upper_bound(nbase.begin(), nbase.end(), i) - nbase.begin()) - 1;
 }
 
+// Candidate rule of the input generator: is population q a source of projection pr for
+// targets in population tp (class filter, then the source mode)?
+static bool gen_candidate(const dbnet_desc& d, const dbnet_proj& pr, uint32_t tp, uint32_t q) {
+    const dbnet_pop& P = d.pops[q];
+    if (pr.src_class == DBNET_CLASS_EXC && !P.exc) return false;
+    if (pr.src_class == DBNET_CLASS_INH && P.exc) return false;
+    switch (pr.src_mode) {
+    case DBNET_SRC_ALL: return true;
+    case DBNET_SRC_SAME_REGION: return P.region == d.pops[tp].region;
+    case DBNET_SRC_OTHER_REGIONS: return P.region != d.pops[tp].region;
+    case DBNET_SRC_POP: return (int32_t)q == pr.src_pop;
+    default: return false;
+    }
+}
+
+std::string make_gen_tables(const Members& mem, HostTables& h) {
+    h.gpops.clear();
+    h.gmembers.clear();
+    h.gprojs.clear();
+    h.gcands.clear();
+    h.gcpops.clear();
+    h.gdtab.clear();
+    h.gkmax = 1;
+    for (size_t m = 0; m < mem.m.size(); m++) {
+        const dbnet_desc& d = mem.m[m];
+        GenMember gm{};
+        gm.seed = d.seed;
+        gm.nbase = mem.nbase[m];
+        gm.net_id = d.net_id;
+        gm.kw = dbnet_weights_per_edge(&d);
+        gm.n_pops = d.n_pops;
+        gm.n_regions = d.n_regions;
+        gm.proj0 = (uint32_t)h.gprojs.size();
+        gm.n_projs = d.n_projs;
+        std::vector<uint64_t> off(d.n_pops + 1, 0);
+        for (uint32_t q = 0; q < d.n_pops; q++) off[q + 1] = off[q] + d.pops[q].size;
+        for (uint32_t q = 0; q < d.n_pops; q++) {
+            GenPop gp{};
+            gp.first = mem.nbase[m] + off[q];
+            gp.off = off[q];
+            gp.size = d.pops[q].size;
+            gp.exc = d.pops[q].exc ? 1u : 0u;
+            gp.member = (uint32_t)m;
+            gp.local = q;
+            gp.region = d.pops[q].region;
+            h.gpops.push_back(gp);
+        }
+        for (uint32_t j = 0; j < d.n_projs; j++) {
+            const dbnet_proj& pr = d.projs[j];
+            if (pr.indegree > 0 && pr.w_dist == DBNET_W_LOGNORMAL)
+                return "lognormal weights are drawn through libm and generated on the host";
+            GenProj gj{};
+            gj.dst_pop = pr.dst_pop;
+            gj.indegree = pr.indegree;
+            gj.w_dist = pr.w_dist == DBNET_W_UNIFORM ? 0u : 1u;
+            gj.d_mode = pr.d_mode;
+            gj.d_min = pr.d_min;
+            gj.d_max = pr.d_max;
+            gj.w_a = pr.w_a;
+            gj.w_b = pr.w_b;
+            gj.w_scale_exc = pr.w_scale_exc;
+            gj.w_scale_inh = pr.w_scale_inh;
+            gj.cand0 = (uint32_t)h.gcands.size();
+            h.gkmax = std::max(h.gkmax, pr.indegree);
+            if (pr.d_mode == DBNET_D_DISTANCE && pr.indegree > 0) {
+                // the generator's delay of a source in region a for a target in region b
+                gj.dtab = (uint32_t)h.gdtab.size();
+                const uint32_t R = d.n_regions;
+                h.gdtab.resize(h.gdtab.size() + (size_t)R * R);
+                for (uint32_t a = 0; a < R; a++)
+                    for (uint32_t b = 0; b < R; b++) {
+                        const float* xs = d.region_xyz_mm + 3 * a;
+                        const float* xt = d.region_xyz_mm + 3 * b;
+                        const double dx = (double)xs[0] - xt[0], dy = (double)xs[1] - xt[1], dz = (double)xs[2] - xt[2];
+                        const double dist = std::sqrt(dx * dx + dy * dy + dz * dz);
+                        const double bins = std::ceil(dist / ((double)d.velocity_mm_per_ms * (double)d.bin_ms));
+                        const uint32_t dl = bins < (double)pr.d_min ? pr.d_min
+                                            : bins > (double)pr.d_max ? pr.d_max : (uint32_t)bins;
+                        h.gdtab[gj.dtab + (size_t)a * R + b] = (uint8_t)dl;
+                    }
+            }
+            // candidates for every target population (ascending population order, the target
+            // itself removed from the index space)
+            for (uint32_t tp = 0; tp < d.n_pops; tp++) {
+                GenCand c{};
+                c.c0 = (uint32_t)h.gcpops.size();
+                c.self_base = ~0ull;
+                uint64_t mm = 0;
+                for (uint32_t q = 0; q < d.n_pops; q++) {
+                    if (!gen_candidate(d, pr, tp, q)) continue;
+                    if (q == tp) c.self_base = mm;
+                    mm += d.pops[q].size;
+                    GenCandPop cp{};
+                    cp.end = mm;
+                    cp.first = mem.nbase[m] + off[q];
+                    cp.size = d.pops[q].size;
+                    cp.exc = d.pops[q].exc ? 1u : 0u;
+                    h.gcpops.push_back(cp);
+                }
+                c.nc = (uint32_t)h.gcpops.size() - c.c0;
+                c.M = mm - (c.self_base != ~0ull ? 1 : 0);
+                h.gcands.push_back(c);
+            }
+            h.gprojs.push_back(gj);
+        }
+        h.gmembers.push_back(gm);
+    }
+    h.ghcap = pow2_at_least32(2ull * h.gkmax + 2);
+    return "";
+}
+
+size_t gen_tables_bytes(const HostTables& h) {
+    auto a = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    return a(sizeof(GenPop) * h.gpops.size()) + a(sizeof(GenMember) * h.gmembers.size()) +
+           a(sizeof(GenProj) * h.gprojs.size()) + a(sizeof(GenCand) * h.gcands.size()) +
+           a(sizeof(GenCandPop) * h.gcpops.size()) + a(h.gdtab.size() + 1);
+}
+
 std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     if (opts.abi_version != DBSIM_ABI_VERSION) return "dbsim_desc.abi_version does not match the library";
     if (mem.m.empty()) return "no network given";
@@ -313,6 +431,38 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     slot(p.rpop, 8 * 4 * (size_t)p.n_pops);
     slot(p.ctl, sizeof(Ctl));
     p.total = off;
+    // connection table on the device: two-pass form (its streams and arena are free before
+    // the first bin), weights of exact double arithmetic, and room for the temporaries
+    p.dev_build = false;
+    p.gen_batch = 0;
+    p.gl = Plan::GenLayout{};
+    if (!p.blocked && !(opts.flags & DBSIM_F_HOST_BUILD) && p.E > 0) {
+        HostTables gt;
+        if (make_gen_tables(mem, gt).empty()) {
+            size_t o = 0;
+            auto take = [&](size_t bytes) {
+                const size_t at = o;
+                o += (bytes + 255) & ~(size_t)255;
+                return at;
+            };
+            Plan::GenLayout& g = p.gl;
+            g.tables = take(gen_tables_bytes(gt));
+            g.cnt = take(4 * (size_t)N * p.D);
+            g.cur = take(8 * (size_t)N * p.D);
+            g.rowlen = take(8 * (N + 1));
+            g.rowptr = take(8 * (N + 1));
+            g.sums = take(8 * (N / 1024 + 2));
+            g.tb = take(E);
+            g.flags = take(16);
+            g.end = o;
+            const size_t sw = 4 * (size_t)gen_scratch_words(gt.gkmax, gt.ghcap);
+            const uint64_t batch = std::min<uint64_t>({(uint64_t)N, p.sev.bytes / sw, 1ull << 20});
+            if (g.end <= p.ev.bytes && batch >= std::min<uint64_t>(N, 4096)) {
+                p.dev_build = true;
+                p.gen_batch = (uint32_t)batch;
+            }
+        }
+    }
     return "";
 }
 
@@ -364,7 +514,7 @@ void fill_populations(const Members& mem, const Plan& p, std::vector<PopParams>&
     if (first) (*first)[p.n_pops] = off;
 }
 
-std::string build_tables(const Members& mem, const Plan& p, unsigned threads, HostTables& h) {
+std::string build_tables(const Members& mem, const Plan& p, unsigned threads, HostTables& h, bool with_edges) {
     const unsigned nt = threads ? threads : std::max(1u, std::thread::hardware_concurrency());
     const uint32_t N = p.N, D = p.D, KW = p.KW;
     const uint32_t M = (uint32_t)mem.m.size();
@@ -428,6 +578,11 @@ std::string build_tables(const Members& mem, const Plan& p, unsigned threads, Ho
             h.V0[i] = dbnet_v0(&mem.m[m], (uint32_t)(i - mem.nbase[m]));
         }
     });
+
+    // super-tile stream slices: the sum of their tiles' slices
+    h.st_base.assign((size_t)p.NS + 1, 0ull);
+    for (uint32_t x = 0; x <= p.NS; x++) h.st_base[x] = h.tile_base[std::min<uint64_t>((uint64_t)x << p.ts_bits, p.T)];
+    if (!with_edges) return make_gen_tables(mem, h);
 
     size_t scratch_bytes = 0;
     uint32_t kmax = 1;
@@ -642,9 +797,6 @@ std::string build_tables(const Members& mem, const Plan& p, unsigned threads, Ho
         hp[1] = (uint32_t)(rs >> 32);
         for (uint32_t x = 0; x <= D; x++) hp[2 + x] = h.seg[(size_t)j * (D + 1) + x];
     }
-    // super-tile stream slices: the sum of their tiles' slices
-    h.st_base.assign((size_t)p.NS + 1, 0ull);
-    for (uint32_t x = 0; x <= p.NS; x++) h.st_base[x] = h.tile_base[std::min<uint64_t>((uint64_t)x << p.ts_bits, p.T)];
     return "";
 }
 

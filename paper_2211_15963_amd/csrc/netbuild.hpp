@@ -15,6 +15,7 @@
 #include "dbnet.h"
 #include "dbsim.h"
 #include "dbsim_internal.hpp"
+#include "devgen.hpp"
 
 namespace dbs {
 
@@ -49,6 +50,14 @@ struct Plan {
     uint32_t HMB = 0;         // bins of offsets kept beside it (power of two)
     uint64_t E = 0;  // edges
     bool regions_on = false;
+    // connection table built on the device (else on the host): the temporaries live in the
+    // tile arena (counts, cursors, row lengths, tie-breaks, the generator's tables) and the
+    // super-tile streams (per-thread generator scratch, gen_batch targets at a time)
+    bool dev_build = false;
+    uint32_t gen_batch = 0;
+    struct GenLayout {
+        size_t tables = 0, cnt = 0, cur = 0, rowlen = 0, rowptr = 0, sums = 0, tb = 0, flags = 0, end = 0;
+    } gl;
     // byte offsets of every device array inside one allocation
     struct Slot {
         size_t off = 0, bytes = 0;
@@ -89,7 +98,23 @@ struct HostTables {
     std::vector<uint32_t> hdr; // [N][HW] device row headers
     std::vector<uint64_t> tile_base, st_base;
     std::vector<uint32_t> reg_blk_ptr, reg_blk, reg_size, l1_ptr, l1_region;
+    // the generator's tables for the device construction (plan.dev_build)
+    std::vector<GenPop> gpops;
+    std::vector<GenMember> gmembers;
+    std::vector<GenProj> gprojs;
+    std::vector<GenCand> gcands;
+    std::vector<GenCandPop> gcpops;
+    std::vector<uint8_t> gdtab;
+    uint32_t gkmax = 0, ghcap = 0;
 };
+
+// The generator's tables of the members for the device construction. Returns an empty
+// string, or why the device construction does not apply (lognormal weights).
+std::string make_gen_tables(const Members& mem, HostTables& h);
+// Bytes of the tables as laid out in device memory (each array 256-byte aligned).
+size_t gen_tables_bytes(const HostTables& h);
+// u32 words of generator scratch per target thread.
+inline uint32_t gen_scratch_words(uint32_t kmax, uint32_t hcap) { return hcap + 3u * kmax + 1u; }
 
 // Per-population parameters and derived constants of the plan's populations (members one
 // after another): PopParams and the Poisson thresholds [n_pops][kMaxPoisson]; optionally the
@@ -97,8 +122,9 @@ struct HostTables {
 void fill_populations(const Members& mem, const Plan& p, std::vector<PopParams>& pops, std::vector<uint32_t>& ptab,
                       std::vector<uint64_t>* first, std::vector<uint32_t>* indeg);
 
-// Generates the networks (threads: 0 = all cores) and builds every host table.
+// Builds every host table (threads: 0 = all cores); the connection table (edge records and
+// row headers) too when with_edges, else the generator's tables for the device construction.
 // Returns an empty string on success, else the reason.
-std::string build_tables(const Members& mem, const Plan& p, unsigned threads, HostTables& h);
+std::string build_tables(const Members& mem, const Plan& p, unsigned threads, HostTables& h, bool with_edges);
 
 } // namespace dbs

@@ -11,7 +11,7 @@ from __future__ import annotations
 import ctypes
 import os
 from ctypes import (CFUNCTYPE, POINTER, Structure, byref, c_char_p, c_double, c_float, c_int, c_int32, c_size_t,
-                    c_uint32, c_uint64, c_void_p)
+                    c_uint8, c_uint32, c_uint64, c_void_p)
 from typing import Optional
 
 import numpy as np
@@ -25,6 +25,7 @@ ABI_VERSION = 2
 REC_REGIONS = 1
 F_NO_GRAPH = 1
 F_SINGLE_PASS = 2
+F_HOST_BUILD = 8
 F_NO_HOST_RECORD = 4
 STATIC_BYTES = 64 << 20  # DBSIM_STATIC_BYTES: the static region of dbsim_create_static
 
@@ -54,7 +55,8 @@ class SimInfo(Structure):
     _fields_ = [("num_neurons", c_uint64), ("num_edges", c_uint64), ("receptors", c_uint32),
                 ("weights_per_edge", c_uint32), ("steps_per_bin", c_uint32), ("max_delay", c_uint32),
                 ("n_regions", c_uint32), ("tile_neurons", c_uint32), ("n_tiles", c_uint32), ("frac_bits", c_uint32),
-                ("n_members", c_uint32), ("fanin_passes", c_uint32)]
+                ("n_members", c_uint32), ("fanin_passes", c_uint32), ("device_built", c_uint32),
+                ("reserved", c_uint32)]
 
 
 class SimMember(Structure):
@@ -125,7 +127,7 @@ EXPORTED = ["dbsim_abi_version", "dbsim_last_error", "dbsim_create", "dbsim_foot
             "dbsim_write_state", "dbsim_export_csr", "dbsim_set_timing", "dbsim_get_stats", "dbsim_destroy",
             "dbsim_derive_constants", "dbsim_export_network", "dbsim_create_static", "dbsim_receptor_currents",
             "dbsim_build", "dbsim_create_built", "dbsim_built_free", "dbsim_checkpoint_size",
-            "dbsim_checkpoint_save", "dbsim_checkpoint_restore"]
+            "dbsim_checkpoint_save", "dbsim_checkpoint_restore", "dbsim_check_device_generator"]
 
 
 def lib():
@@ -165,6 +167,9 @@ def lib():
                                            POINTER(c_uint64)]
     L.dbsim_read_state.argtypes = [H, POINTER(c_float), POINTER(c_float), POINTER(c_int32)]
     L.dbsim_write_state.argtypes = [H, POINTER(c_float), POINTER(c_float), POINTER(c_int32)]
+    L.dbsim_check_device_generator.argtypes = [POINTER(Desc), c_uint32, c_uint64, POINTER(c_uint32), POINTER(c_float),
+                                               POINTER(c_float), POINTER(c_uint8), POINTER(c_uint32), c_uint64,
+                                               POINTER(c_uint64)]
     L.dbsim_checkpoint_size.argtypes = [H, POINTER(c_uint64)]
     L.dbsim_checkpoint_save.argtypes = [H, c_void_p, c_uint64, POINTER(c_uint64)]
     L.dbsim_checkpoint_restore.argtypes = [H, c_void_p, c_uint64]
@@ -230,7 +235,7 @@ class _TorchAllocator:
 def make_desc(spec: NetSpec, record_regions: bool = True, spike_record_capacity: int = 0, record_bins: int = 0,
               device: int = -1, stream_handle: Optional[int] = None, allocator: Optional[_TorchAllocator] = None,
               host_threads: int = 0, no_graph: bool = False, single_pass: bool = False, host_record: bool = True,
-              host_spike_capacity: int = 0):
+              host_spike_capacity: int = 0, host_build: bool = False):
     holder = spec.to_c()
     d = SimDesc()
     d.abi_version = ABI_VERSION
@@ -244,7 +249,8 @@ def make_desc(spec: NetSpec, record_regions: bool = True, spike_record_capacity:
         d.dev_alloc = allocator.alloc
         d.dev_free = allocator.free
     d.host_threads = int(host_threads)
-    d.flags = (F_NO_GRAPH if no_graph else 0) | (F_SINGLE_PASS if single_pass else 0) | (0 if host_record else F_NO_HOST_RECORD)
+    d.flags = ((F_NO_GRAPH if no_graph else 0) | (F_SINGLE_PASS if single_pass else 0) |
+               (0 if host_record else F_NO_HOST_RECORD) | (F_HOST_BUILD if host_build else 0))
     d.host_spike_capacity = int(host_spike_capacity)
     return d, holder
 
@@ -268,6 +274,26 @@ def footprint(spec, record_regions: bool = True, **kw) -> int:
         d, holder = make_desc(spec, record_regions=record_regions, **kw)
         _check(lib().dbsim_footprint(byref(d), byref(out)))
     return int(out.value)
+
+
+def device_generator_in_edges(spec, target: int):
+    """In-edges of one target (global id) as the device construction draws them, evaluated
+    on the host: (src global ids, w0, w1, delays, projection indices)."""
+    specs = list(spec) if isinstance(spec, (list, tuple)) else [spec]
+    arr, holders = _member_array(specs)
+    n = c_uint64(0)
+    rc = lib().dbsim_check_device_generator(arr, len(specs), int(target), None, None, None, None, None, 0, byref(n))
+    if rc not in (OK, ETRUNC):
+        _check(rc)
+    k = int(n.value)
+    src = np.zeros(max(k, 1), np.uint32)
+    w0 = np.zeros(max(k, 1), np.float32)
+    w1 = np.zeros(max(k, 1), np.float32)
+    dl = np.zeros(max(k, 1), np.uint8)
+    pj = np.zeros(max(k, 1), np.uint32)
+    _check(lib().dbsim_check_device_generator(arr, len(specs), int(target), _p(src, c_uint32), _p(w0, c_float),
+                                              _p(w1, c_float), _p(dl, c_uint8), _p(pj, c_uint32), k, byref(n)))
+    return src[:k], w0[:k], w1[:k], dl[:k], pj[:k]
 
 
 def derive_constants(spec, **kw) -> list:
@@ -294,12 +320,14 @@ class Built:
 
     def __init__(self, spec: NetSpec, record_regions: bool = True, spike_record_capacity: int = 0,
                  record_bins: int = 0, host_threads: Optional[int] = None, no_graph: bool = False,
-                 single_pass: bool = False, host_record: bool = True, host_spike_capacity: int = 0):
+                 single_pass: bool = False, host_record: bool = True, host_spike_capacity: int = 0,
+                 host_build: bool = False):
         if host_threads is None:
             host_threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
         self.spec = spec
         self._desc, self._holder = make_desc(spec, record_regions, spike_record_capacity, record_bins, -1, None, None,
-                                             host_threads, no_graph, single_pass, host_record, host_spike_capacity)
+                                             host_threads, no_graph, single_pass, host_record, host_spike_capacity,
+                                             host_build)
         h = c_void_p()
         _check(lib().dbsim_build(byref(self._desc), byref(h)))
         self._b = h
@@ -342,7 +370,8 @@ class Simulator:
     def __init__(self, spec: NetSpec, record_regions: bool = True, use_torch: bool = True, device: int = 0,
                  spike_record_capacity: int = 0, record_bins: int = 0, host_threads: Optional[int] = None,
                  no_graph: bool = False, stream=None, single_pass: bool = False, static_region: bool = False,
-                 host_record: bool = True, host_spike_capacity: int = 0, built: Optional["Built"] = None):
+                 host_record: bool = True, host_spike_capacity: int = 0, built: Optional["Built"] = None,
+                 host_build: bool = False):
         L = lib()
         if host_threads is None:
             # the process's CPU share (OMP_NUM_THREADS) rather than every core of the machine
@@ -363,7 +392,7 @@ class Simulator:
         first = self.specs[0]
         self._desc, self._holder = make_desc(first, record_regions, spike_record_capacity, record_bins, device,
                                              stream_handle, self._alloc, host_threads, no_graph, single_pass,
-                                             host_record, host_spike_capacity)
+                                             host_record, host_spike_capacity, host_build)
         h = c_void_p()
         if isinstance(spec, (list, tuple)):
             self._members, self._member_holders = _member_array(self.specs)
