@@ -77,7 +77,7 @@ def run_gpu(args):
     log(f"building {spec.name}: {spec.num_neurons} neurons, {spec.num_edges()} synapses")
     t0 = time.time()
     sim = Simulator(spec, record_regions=True, device=0, no_graph=args.mode == "direct")
-    log(f"built in {time.time() - t0:.1f} s (host construction {sim.stats()['build_seconds']:.1f} s), "
+    log(f"built in {time.time() - t0:.1f} s (construction {sim.stats()['build_seconds']:.1f} s), "
         f"device bytes {sim.stats()['hbm_bytes'] / 1e9:.2f} GB")
     S = sim.S
     # the network starts from a synchronous transient (every V drawn in [V_reset, V_th), no

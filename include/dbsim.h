@@ -109,7 +109,9 @@ typedef struct dbsim_stats {
     double ms_gather;
     double ms_neuron;
     double ms_readout;
-    double build_seconds;  /* host time spent constructing the network in dbsim_create */
+    double build_seconds;  /* time spent constructing the network: the host phase, plus the
+                              device construction of the connection table where it ran (its
+                              duration is added at the first synchronisation after create) */
 } dbsim_stats;
 
 typedef struct dbsim_info {

@@ -124,6 +124,7 @@ struct dbsim {
     uint64_t timed_bins = 0;
     double build_seconds = 0.0;
     bool device_built = false; // the connection table was generated on the device
+    hipEvent_t ev_build[2] = {nullptr, nullptr}; // around the device construction, until timed
 };
 
 // A network built on the host and not yet deployed (dbsim_build -> dbsim_create_built).
@@ -367,6 +368,17 @@ int sync_and_check(dbsim* h) {
     HIPCHK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
     Ctl c;
     HIPCHK(h, hipMemcpy(&c, h->net.ctl, sizeof c, hipMemcpyDeviceToHost), "hipMemcpy(ctl)");
+    if (h->ev_build[0]) { // the device construction's duration joins the construction time
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, h->ev_build[0], h->ev_build[1]) == hipSuccess) h->build_seconds += 1e-3 * ms;
+        (void)hipEventDestroy(h->ev_build[0]);
+        (void)hipEventDestroy(h->ev_build[1]);
+        h->ev_build[0] = h->ev_build[1] = nullptr;
+    }
+    if (c.err & kErrBuild) {
+        h->dead = DBSIM_EDEVICE;
+        return fail(DBSIM_EDEVICE, "device construction of the connection table failed a consistency check");
+    }
     if (c.err) {
         h->dead = DBSIM_EOVERFLOW;
         return fail(DBSIM_EOVERFLOW, "device-side capacity exceeded (error bits " + std::to_string(c.err) + ")");
@@ -375,6 +387,11 @@ int sync_and_check(dbsim* h) {
 }
 
 void release_device(dbsim* h) {
+    for (auto& x : h->ev_build)
+        if (x) {
+            (void)hipEventDestroy(x);
+            x = nullptr;
+        }
     if (h->g_multi) (void)hipGraphExecDestroy(h->g_multi);
     if (h->g_one) (void)hipGraphExecDestroy(h->g_one);
     h->g_multi = h->g_one = nullptr;
@@ -495,11 +512,12 @@ static int build_impl(const dbsim_desc* desc, const dbnet_desc* members, uint32_
 }
 
 // Connection table generated on the device (plan.dev_build), into the handle's edge and
-// header arrays, with the temporaries in its tile arena and super-tile streams. A delay
-// segment too long for the device sort sends the construction back to the host threads.
-static int device_build(dbsim* h, HostTables& ht, unsigned host_threads) {
+// header arrays, with the temporaries in its tile arena and super-tile streams. Only the
+// copies of the generator's tables are awaited (their host memory dies with the built
+// network); the construction itself runs on the handle's stream ahead of the first bin,
+// and its duration joins build_seconds at the next synchronisation.
+static int device_build(dbsim* h, HostTables& ht) {
     const Plan& p = h->plan;
-    const auto t0 = std::chrono::steady_clock::now();
     unsigned char* ev = h->dev + p.ev.off;
     // the generator's tables, in the order gen_tables_bytes lays them out
     size_t o = p.gl.tables;
@@ -518,6 +536,9 @@ static int device_build(dbsim* h, HostTables& ht, unsigned host_threads) {
     b.g.cpops = reinterpret_cast<const GenCandPop*>(put(ht.gcpops.data(), sizeof(GenCandPop) * ht.gcpops.size()));
     const uint8_t zero = 0;
     b.g.dtab = put(ht.gdtab.empty() ? &zero : ht.gdtab.data(), ht.gdtab.empty() ? 1 : ht.gdtab.size());
+    if (o > p.gl.cnt) return fail(DBSIM_EINVAL, "internal error: generator tables overrun their slot");
+    HIPCHK(h, pe, "hipMemcpy(generator tables)");
+    HIPCHK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
     b.g.n_pops = (uint32_t)ht.gpops.size();
     b.g.kmax = ht.gkmax;
     b.g.hcap = ht.ghcap;
@@ -530,7 +551,8 @@ static int device_build(dbsim* h, HostTables& ht, unsigned host_threads) {
     b.rowptr = reinterpret_cast<unsigned long long*>(ev + p.gl.rowptr);
     b.sums = reinterpret_cast<unsigned long long*>(ev + p.gl.sums);
     b.tb = ev + p.gl.tb;
-    b.flags = reinterpret_cast<uint32_t*>(ev + p.gl.flags);
+    b.err = &h->net.ctl->err;
+    b.stage = reinterpret_cast<uint32_t*>(h->dev + p.sev.off);
     b.edge = reinterpret_cast<uint32_t*>(h->dev + p.edge.off);
     b.hdr = reinterpret_cast<uint32_t*>(h->dev + p.hdr.off);
     b.N = p.N;
@@ -539,31 +561,15 @@ static int device_build(dbsim* h, HostTables& ht, unsigned host_threads) {
     b.HW = p.HW;
     b.KW = p.KW;
     b.wlim = std::ldexp(1.0, 52 - (int)p.F);
-    HIPCHK(h, pe, "hipMemcpy(generator tables)");
-    if (o > p.gl.cnt) return fail(DBSIM_EINVAL, "internal error: generator tables overrun their slot");
-    HIPCHK(h, launch_device_build(b, h->stream), "device construction launch");
-    uint32_t flags = 0;
-    unsigned long long total = 0;
-    const uint64_t nb = ((uint64_t)p.N + 1023) / 1024;
-    HIPCHK(h, hipMemcpyAsync(&flags, b.flags, 4, hipMemcpyDeviceToHost, h->stream), "hipMemcpy");
-    HIPCHK(h, hipMemcpyAsync(&total, b.sums + nb, 8, hipMemcpyDeviceToHost, h->stream), "hipMemcpy");
-    HIPCHK(h, hipStreamSynchronize(h->stream), "device construction");
-    if (flags & kGenWeight)
-        return fail(DBSIM_EINVAL, "a weight is too large for the fixed-point format (|w| * 2^frac_bits must stay below 2^52)");
-    if (flags & (kGenBadDelay | kGenShort)) return fail(DBSIM_EINVAL, "network generator failed on the device");
-    if (total != p.E) return fail(DBSIM_EINVAL, "internal error: device construction edge count mismatch");
-    if (flags & kGenLongSegment) { // a delay segment longer than the device sort takes
-        const std::string m = build_tables(h->mem, p, host_threads, ht, true);
-        if (!m.empty()) return fail(DBSIM_EINVAL, m);
-        HIPCHK(h, hipMemcpyAsync(h->dev + p.hdr.off, ht.hdr.data(), 4 * ht.hdr.size(), hipMemcpyHostToDevice, h->stream),
-               "hipMemcpy");
-        HIPCHK(h, hipMemcpyAsync(h->dev + p.edge.off, ht.edge.get(), 4 * ht.edge_words, hipMemcpyHostToDevice,
-                                 h->stream), "hipMemcpy");
-        HIPCHK(h, hipStreamSynchronize(h->stream), "upload");
-    } else {
-        h->device_built = true;
+    const bool timed = !h->static_mem; // a handle in the static region creates no events
+    if (timed) {
+        HIPCHK(h, hipEventCreate(&h->ev_build[0]), "hipEventCreate");
+        HIPCHK(h, hipEventCreate(&h->ev_build[1]), "hipEventCreate");
+        HIPCHK(h, hipEventRecord(h->ev_build[0], h->stream), "hipEventRecord");
     }
-    h->build_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    HIPCHK(h, launch_device_build(b, h->stream), "device construction launch");
+    if (timed) HIPCHK(h, hipEventRecord(h->ev_build[1], h->stream), "hipEventRecord");
+    h->device_built = true;
     return DBSIM_OK;
 }
 
@@ -731,7 +737,7 @@ static int deploy_impl(dbsim_built* bt, const dbsim_desc* dev_opts, dbsim** out)
             return fail(DBSIM_EDEVICE, msg);
         }
         if (p.dev_build) {
-            const int rc = device_build(h, ht, desc->host_threads);
+            const int rc = device_build(h, ht);
             if (rc) {
                 release_device(h);
                 delete h;

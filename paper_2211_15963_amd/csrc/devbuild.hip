@@ -36,8 +36,7 @@ __global__ void __launch_bounds__(256) k_gen_count(DevBuild b, uint64_t i0, uint
         if (dl >= 1u && dl <= D && s < N) atomicAdd(&b.cnt[s * D + dl - 1], 1u);
         else bad = true;
     });
-    if (bad) atomicOr(&b.flags[0], kGenBadDelay);
-    if (!ok) atomicOr(&b.flags[0], kGenShort);
+    if (bad || !ok) atomicOr(b.err, kErrBuild);
 }
 
 __global__ void __launch_bounds__(256) k_gen_rows(DevBuild b) {
@@ -90,8 +89,9 @@ __global__ void __launch_bounds__(256) k_scan_a(const unsigned long long* in, un
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-// one block: exclusive scan of the nb block sums in place, the total at sums[nb]
-__global__ void __launch_bounds__(256) k_scan_b(unsigned long long* sums, uint64_t nb) {
+// one block: exclusive scan of the nb block sums in place, the total at sums[nb] (which
+// must be the edge count E)
+__global__ void __launch_bounds__(256) k_scan_b(unsigned long long* sums, uint64_t nb, uint64_t E, uint32_t* err) {
     __shared__ unsigned long long sh[256];
     unsigned long long carry = 0;
     for (uint64_t c0 = 0; c0 < nb; c0 += 256) {
@@ -102,7 +102,10 @@ __global__ void __launch_bounds__(256) k_scan_b(unsigned long long* sums, uint64
         if (x < nb) sums[x] = carry + ex;
         carry += tot;
     }
-    if (threadIdx.x == 0) sums[nb] = carry;
+    if (threadIdx.x == 0) {
+        sums[nb] = carry;
+        if (carry != E) atomicOr(err, kErrBuild);
+    }
 }
 
 __global__ void __launch_bounds__(256) k_scan_c(unsigned long long* out, uint64_t n, const unsigned long long* sums) {
@@ -153,11 +156,12 @@ __global__ void __launch_bounds__(256) k_gen_fill(DevBuild b, uint64_t i0, uint6
         b.tb[pos] = (uint8_t)j;
         if (!(fabs((double)w0) < wlim) || !(fabs((double)w1) < wlim)) wbad = true;
     });
-    if (bad) atomicOr(&b.flags[0], kGenBadDelay);
-    if (wbad) atomicOr(&b.flags[0], kGenWeight);
+    if (bad || wbad) atomicOr(b.err, kErrBuild);
 }
 
-// one wavefront per row: every delay segment ordered by (target, projection) through LDS
+// one wavefront per row: every delay segment ordered by (target, projection), through LDS
+// up to kGenSortMax records, else through a copy in the stage array (keys distinct: a
+// projection draws a source at most once per target)
 template <int KW>
 __global__ void __launch_bounds__(64) k_gen_sort(DevBuild b) {
     constexpr uint32_t RW = 1 + KW;
@@ -171,27 +175,47 @@ __global__ void __launch_bounds__(64) k_gen_sort(DevBuild b) {
         const unsigned long long s0 = r0 + hp[2 + x];
         const uint32_t L = hp[3 + x] - hp[2 + x];
         if (L < 2u) continue;
-        if (L > kGenSortMax || s0 + L > b.E) {
-            if (lane == 0) atomicOr(&b.flags[0], kGenLongSegment);
+        if (s0 + L > b.E) {
+            if (lane == 0) atomicOr(b.err, kErrBuild);
             continue;
         }
-        for (uint32_t e = lane; e < L; e += 64) {
+        if (L <= kGenSortMax) {
+            for (uint32_t e = lane; e < L; e += 64) {
 #pragma unroll
-            for (uint32_t w = 0; w < RW; w++) s_rec[e * RW + w] = b.edge[(s0 + e) * RW + w];
-            s_tb[e] = b.tb[s0 + e];
-        }
-        __syncthreads();
-        for (uint32_t e = lane; e < L; e += 64) {
-            const unsigned long long ke = ((unsigned long long)(s_rec[e * RW + KW] & 0x7FFFFFFFu) << 8) | s_tb[e];
-            uint32_t rank = 0;
-            for (uint32_t f = 0; f < L; f++) {
-                const unsigned long long kf = ((unsigned long long)(s_rec[f * RW + KW] & 0x7FFFFFFFu) << 8) | s_tb[f];
-                rank += kf < ke ? 1u : 0u;
+                for (uint32_t w = 0; w < RW; w++) s_rec[e * RW + w] = b.edge[(s0 + e) * RW + w];
+                s_tb[e] = b.tb[s0 + e];
             }
+            __syncthreads();
+            for (uint32_t e = lane; e < L; e += 64) {
+                const unsigned long long ke = ((unsigned long long)(s_rec[e * RW + KW] & 0x7FFFFFFFu) << 8) | s_tb[e];
+                uint32_t rank = 0;
+                for (uint32_t f = 0; f < L; f++) {
+                    const unsigned long long kf = ((unsigned long long)(s_rec[f * RW + KW] & 0x7FFFFFFFu) << 8) | s_tb[f];
+                    rank += kf < ke ? 1u : 0u;
+                }
 #pragma unroll
-            for (uint32_t w = 0; w < RW; w++) b.edge[(s0 + rank) * RW + w] = s_rec[e * RW + w];
+                for (uint32_t w = 0; w < RW; w++) b.edge[(s0 + rank) * RW + w] = s_rec[e * RW + w];
+            }
+            __syncthreads();
+        } else {
+            for (uint32_t e = lane; e < L; e += 64)
+#pragma unroll
+                for (uint32_t w = 0; w < RW; w++) b.stage[(s0 + e) * RW + w] = b.edge[(s0 + e) * RW + w];
+            __syncthreads();
+            for (uint32_t e = lane; e < L; e += 64) {
+                const unsigned long long ke =
+                    ((unsigned long long)(b.stage[(s0 + e) * RW + KW] & 0x7FFFFFFFu) << 8) | b.tb[s0 + e];
+                uint32_t rank = 0;
+                for (uint32_t f = 0; f < L; f++) {
+                    const unsigned long long kf =
+                        ((unsigned long long)(b.stage[(s0 + f) * RW + KW] & 0x7FFFFFFFu) << 8) | b.tb[s0 + f];
+                    rank += kf < ke ? 1u : 0u;
+                }
+#pragma unroll
+                for (uint32_t w = 0; w < RW; w++) b.edge[(s0 + rank) * RW + w] = b.stage[(s0 + e) * RW + w];
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -200,7 +224,6 @@ static unsigned grid_of(uint64_t n, unsigned bs) { return (unsigned)((n + bs - 1
 hipError_t launch_device_build(const DevBuild& b, hipStream_t st) {
     const uint64_t N = b.N;
     hipLaunchKernelGGL(k_gen_clear, dim3(grid_of(N * b.D, 256 * 16) + 1), dim3(256), 0, st, b.cnt, N * b.D);
-    hipLaunchKernelGGL(k_gen_clear, dim3(1), dim3(256), 0, st, b.flags, (uint64_t)4);
     hipError_t e = hipGetLastError();
     for (uint64_t i0 = 0; i0 < N && e == hipSuccess; i0 += b.batch) {
         const uint64_t i1 = std::min<uint64_t>(N, i0 + b.batch);
@@ -211,7 +234,7 @@ hipError_t launch_device_build(const DevBuild& b, hipStream_t st) {
     hipLaunchKernelGGL(k_gen_rows, dim3(grid_of(N, 256)), dim3(256), 0, st, b);
     const uint64_t nb = (N + 1023) / 1024;
     hipLaunchKernelGGL(k_scan_a, dim3((unsigned)nb), dim3(256), 0, st, b.rowlen, b.rowptr, N, b.sums);
-    hipLaunchKernelGGL(k_scan_b, dim3(1), dim3(256), 0, st, b.sums, nb);
+    hipLaunchKernelGGL(k_scan_b, dim3(1), dim3(256), 0, st, b.sums, nb, b.E, b.err);
     hipLaunchKernelGGL(k_scan_c, dim3((unsigned)nb), dim3(256), 0, st, b.rowptr, N, b.sums);
     hipLaunchKernelGGL(k_gen_cursors, dim3(grid_of(N, 256)), dim3(256), 0, st, b);
     e = hipGetLastError();

@@ -233,19 +233,20 @@ struct DevBuild {
     unsigned long long* rowptr;   // [N + 1]
     unsigned long long* sums;     // [N / 1024 + 2] block sums of the row scan
     uint8_t* tb;                  // [E] projection of every placed edge (order of equal targets)
-    uint32_t* flags;              // [4] kGen* error bits
+    uint32_t* err;                // the handle's sticky error word (a failed check sets kErrBuild)
+    uint32_t* stage;              // [E][1 + KW] copy of long segments while they are ordered
     uint32_t* edge;               // the edge records [E][1 + KW]
     uint32_t* hdr;                // the row headers [N][HW]
     uint64_t N, E;
     uint32_t D, HW, KW;
     double wlim;                  // |w| must stay below 2^(52 - F)
 };
-constexpr uint32_t kGenBadDelay = 1u, kGenShort = 2u, kGenWeight = 4u, kGenLongSegment = 8u;
-constexpr uint32_t kGenSortMax = 2048; // longest delay segment the device sort takes
+constexpr uint32_t kGenSortMax = 2048; // delay segments up to this length are ordered in LDS
+constexpr uint32_t kErrBuild = 4u;      // error-word bit: a consistency check of the construction failed
 
-// Enqueues the whole construction on st (its temporaries must be zero where stated: the
-// launcher clears them itself with kernels). The caller checks flags and the edge total
-// (rowptr[N]) after synchronising.
+// Enqueues the whole construction on st; nothing is awaited. Checks that cannot fail for
+// a validated description (delays in range, the edge total, no placement past a segment)
+// set kErrBuild in the handle's error word, which the next synchronisation reports.
 hipError_t launch_device_build(const DevBuild& b, hipStream_t st);
 
 } // namespace dbs

@@ -436,7 +436,18 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     p.dev_build = false;
     p.gen_batch = 0;
     p.gl = Plan::GenLayout{};
-    if (!p.blocked && !(opts.flags & DBSIM_F_HOST_BUILD) && p.E > 0) {
+    // the device checks nothing it could report before the first bin, so the fixed-point
+    // range of the weights (|w| 2^F < 2^52) is bounded here from the distributions' limits;
+    // a description that may exceed it is built and checked exactly on the host
+    bool wfit = true;
+    for (const auto& d : mem.m)
+        for (uint32_t j = 0; j < d.n_projs; j++) {
+            const dbnet_proj& pr = d.projs[j];
+            const double a = std::max(std::fabs((double)pr.w_a), pr.w_dist == DBNET_W_CONST ? 0.0 : std::fabs((double)pr.w_b));
+            const double sc = std::max(std::fabs((double)pr.w_scale_exc), std::fabs((double)pr.w_scale_inh));
+            if (!(a * sc * (1.0 + 0x1p-20) < std::ldexp(1.0, 52 - (int)p.F))) wfit = false;
+        }
+    if (!p.blocked && !(opts.flags & DBSIM_F_HOST_BUILD) && p.E > 0 && wfit) {
         HostTables gt;
         if (make_gen_tables(mem, gt).empty()) {
             size_t o = 0;

@@ -73,6 +73,16 @@ def test_ensemble_constant_weights_one_weight_per_edge(Sim):
     _same_tables(Sim, tw, "one weight per edge, uniform, 20000 / k100")
 
 
+def test_long_segments_and_duplicate_pairs(Sim):
+    """16 hub neurons feed every one of 20,000 targets 8 times at delay 1 (segments of about
+    10,000 records, beyond the LDS sort), and an all-to-all projection can pick a hub for
+    the same target again (equal targets in one segment, ordered by projection)."""
+    from netgen.desc import NetSpec, PopSpec, ProjSpec, SRC_POP, D_UNIFORM
+    pops = [PopSpec(16, True), PopSpec(20000, True)]
+    projs = [ProjSpec(8, dst_pop=1, src_mode=SRC_POP, src_pop=0), ProjSpec(50, d_mode=D_UNIFORM, d_min=1, d_max=3)]
+    _same_tables(Sim, NetSpec(pops, projs, seed=17, name="hubs"), "hubs 16 -> 20000")
+
+
 def test_lognormal_weights_stay_on_the_host(Sim):
     sim = Sim(configs.tiny(seed=0))
     assert sim.info.device_built == 0
