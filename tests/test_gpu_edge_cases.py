@@ -63,3 +63,24 @@ def test_degenerate_network_bit_exact(Sim, name, bins):
         sim.step(bins * S)
         assert _same(sim, orc, spec) == n_spk
         sim.close()
+
+
+def test_longest_delays_and_finest_step(Sim):
+    """The largest delay a description may hold (255 bins) and the most substeps per bin
+    (dt = 1/16 ms, S = 16): 300 bins, so spikes of the first bins arrive 255 bins later."""
+    from netgen import configs
+    spec = configs.share(n=3000, indegree=100, seed=51, d_max=255)
+    spec.dt_ms = 0.0625
+    assert spec.steps_per_bin == 16 and spec.max_delay == 255
+    S, bins = spec.steps_per_bin, 300
+    _say(f"share 3000 / k100, delays 1..255 bins, dt 1/16 ms: oracle, {bins} bins")
+    orc = Oracle(spec, 32)
+    orc.step(bins * S)
+    assert len(orc.spikes()[0]) > 1000
+    for single_pass in (False, True):
+        _say(f"  GPU, single_pass={single_pass}")
+        sim = Sim(spec, single_pass=single_pass)
+        assert sim.info.max_delay == 255 and sim.info.steps_per_bin == 16
+        sim.step(bins * S)
+        _same(sim, orc, spec)
+        sim.close()
