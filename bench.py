@@ -488,10 +488,16 @@ def _rocpd(db):
 
 def _short(name):
     for k in ("k_part", "k_bucket", "k_gather_blk", "k_gather", "k_fan", "k_neuron", "k_compact", "k_drain",
-              "k_region_partials", "k_readout_close", "k_pass_reset", "copyBuffer"):
+              "k_region_partials", "k_readout_close", "k_pass_reset", "k_gen_count", "k_gen_fill", "k_gen_sort",
+              "k_gen_rows", "k_gen_cursors", "k_gen_clear", "k_scan_a", "k_scan_b", "k_scan_c", "copyBuffer"):
         if k in name:
             return k
     return name
+
+
+def _construction(name):
+    """Kernels of the device construction of the connection table (once per network)."""
+    return "k_gen_" in name or "k_scan_" in name
 
 
 def summarize_profiles(args):
@@ -517,7 +523,9 @@ def summarize_profiles(args):
     ev_per_bin = tot["edge_events"] / tot["bins"]
     per_bin = {}
     for name in set(fetch) | set(write):
-        if "dbs" not in name:  # the library's kernels only (not the runtime's copy/fill kernels)
+        # the library's per-bin kernels only (not the runtime's copy/fill kernels, not the
+        # one-time construction)
+        if "dbs" not in name or _construction(name):
             continue
         if "FETCH_SIZE" in fetch.get(name, {}) and "WRITE_SIZE" in write.get(name, {}):
             # mean per dispatch x dispatches per bin (the partition kernels run twice a bin)
@@ -540,8 +548,16 @@ def summarize_profiles(args):
              "partition overlaps the neuron step on a second stream, so per-bin sums exceed the bin time):",
              f"  {'kernel':46s} {'calls':>6s} {'avg us':>10s}"]
     for name, v in sorted(trace.items(), key=lambda kv: -kv[1]["calls"] * kv[1]["avg_us"]):
+        if _construction(name):
+            continue
         lines.append(f"  {name[:46]:46s} {v['calls']:6d} {v['avg_us']:10.2f}  "
                      f"({v['calls'] * v['avg_us'] / tot['bins']:8.2f} us per bin)")
+    cons = {k: v for k, v in trace.items() if _construction(k)}
+    if cons:
+        lines += ["", "Network construction on the device (once, before the first bin):"]
+        for name, v in sorted(cons.items(), key=lambda kv: -kv[1]["calls"] * kv[1]["avg_us"]):
+            lines.append(f"  {_short(name):16s} {v['calls']:4d} launches  {v['calls'] * v['avg_us'] / 1e3:9.1f} ms")
+        lines.append(f"  total {sum(v['calls'] * v['avg_us'] for v in cons.values()) / 1e6:.2f} s")
     # the one-stream timed window: what bench.py's phase timers measure (roofline.avg_launch_ms)
     alone_bins = max((v["alone_calls"] for k, v in trace.items() if "k_neuron" in k), default=0)
     if alone_bins:

@@ -25,9 +25,9 @@
 //     source << 15) beside the weights; tile t owns blocks tile_base[t] ..
 //     tile_base[t+1]: its in-degree in whole blocks plus two part-filled blocks per
 //     workgroup and bin (each workgroup and pass leaves at most one). Two-pass
-//     form: records of 1 + KW words (target | source class << 31, then the
-//     weights) in slice tile_base[t] .. tile_base[t+1]; the super-tile streams
-//     use the same record format;
+//     form: the same 16-bit keys beside the weights, tile t's slice tile_base[t] ..
+//     tile_base[t+1]; the super-tile streams hold records of 1 + KW words (target |
+//     source class << 31, then the weights);
 //   spike history: rec u32[RC] ring of (id << 4 | substep), per-bin start u64[MB]
 //     and count u32[MB] (rings indexed by bin & (MB-1));
 //   region readout: per-block partial sums f64/u32, per-region block lists,
@@ -129,11 +129,11 @@ struct DevNet {
     // connection table
     const uint32_t* hdr;  // [N][HW] row headers
     const uint32_t* edge; // [E][1 + KW] records: the weights, then target | inhibitory source << 31
-    // event arena. Two-pass form: records of (1 + KW) words (target | source class << 31,
-    // weights), tile t's slice tile_base[t] .. tile_base[t+1], tile_fill[t] records this bin.
-    // Single-pass form: blocks of fan_K records, keys evk (target within tile | inhibitory
-    // source << 15) beside the weights ev (KW floats per record); tile t owns blocks
-    // tile_base[t] .. tile_base[t+1], tile_fill[t] of them taken this bin, bcnt[b] records in b.
+    // event arena: keys evk (target within tile | inhibitory source << 15) beside the weights
+    // ev (KW floats per record). Two-pass form: tile t's slice tile_base[t] .. tile_base[t+1],
+    // tile_fill[t] records this bin. Single-pass form: blocks of fan_K records; tile t owns
+    // blocks tile_base[t] .. tile_base[t+1], tile_fill[t] of them taken this bin, bcnt[b]
+    // records in b.
     uint32_t* ev;
     uint16_t* evk;
     uint32_t* bcnt;

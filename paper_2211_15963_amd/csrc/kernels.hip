@@ -305,6 +305,25 @@ __device__ void write_runs(const DevNet& net, Round& R, uint32_t ne, uint32_t nb
     __syncthreads();
 }
 
+// The tile arena's records: a 16-bit key (target within the tile | inhibitory source << 15)
+// in evk beside the weights in ev, consecutive threads writing consecutive records of a run.
+template <int KW>
+__device__ void write_runs_arena(const DevNet& net, Round& R, uint32_t ne, uint32_t nb, uint32_t b0) {
+    const uint32_t lmask = (1u << net.tile_bits) - 1u;
+    for (uint32_t q = threadIdx.x; q < ne; q += kScatterThreads) {
+        const uint32_t key = R.s_key[q];
+        const uint32_t b = bucket_of(net, key, nb, b0, net.tile_bits);
+        const unsigned long long gb = R.gbase[b];
+        if (gb != ~0ull) {
+            const unsigned long long pos = gb + (q - R.lstart[b]);
+            net.evk[pos] = (uint16_t)((key & lmask) | ((key >> 31) << 15));
+            if (KW == 2) reinterpret_cast<float2*>(net.ev)[pos] = R.s_w[q];
+            else reinterpret_cast<float*>(net.ev)[pos] = R.s_w[q].x;
+        }
+    }
+    __syncthreads();
+}
+
 } // namespace
 
 // The fan-in of the arrivals due at the start of bin k: the delay-d segments of the rows of
@@ -557,7 +576,7 @@ __global__ void __launch_bounds__(kScatterThreads) k_bucket(DevNet net) {
         place_batch(R, B, ne, nbt);
         if (tid == 0) s_claim = cn < nchunks ? 2ull * G + claim : ~0ull;
         __syncthreads();
-        write_runs<KW>(net, R, ne, nt, t0, net.tile_bits, net.ev);
+        write_runs_arena<KW>(net, R, ne, nt, t0);
         c = cn;
         cn = s_claim;
     }
@@ -915,34 +934,32 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(DevNet net) {
     const uint32_t t = blockIdx.x;
     const uint32_t i0 = t << net.tile_bits;
     const uint32_t nt = min(1u << net.tile_bits, net.N - i0);
-    const uint32_t lmask = (1u << net.tile_bits) - 1u;
     for (uint32_t x = threadIdx.x; x < nt * U; x += blockDim.x) acc[x] = 0ull;
     __syncthreads();
     const unsigned long long b0 = net.tile_base[t];
     const uint32_t cnt = (uint32_t)min((unsigned long long)net.tile_fill[t], net.tile_base[t + 1] - b0);
     const double qs = net.qscale;
+    const uint16_t* kk = net.evk + b0;
     for (uint32_t eb = 0; eb < cnt; eb += kLoadBatch * blockDim.x) {
         // load a batch of records first (latency cover), then accumulate them
-        uint3 r[kLoadBatch];
+        uint32_t key[kLoadBatch];
+        float2 w[kLoadBatch];
 #pragma unroll
         for (int u = 0; u < kLoadBatch; u++) {
             // clamped, so the loads are unconditional (no branch between them)
             const uint32_t e = min(eb + u * blockDim.x + threadIdx.x, cnt - 1);
-            if (KW == 2) {
-                r[u] = reinterpret_cast<const uint3*>(net.ev)[b0 + e];
-            } else {
-                const uint2 q = reinterpret_cast<const uint2*>(net.ev)[b0 + e];
-                r[u] = make_uint3(q.x, q.y, 0u);
-            }
+            key[u] = kk[e];
+            if (KW == 2) w[u] = reinterpret_cast<const float2*>(net.ev)[b0 + e];
+            else w[u] = make_float2(reinterpret_cast<const float*>(net.ev)[b0 + e], 0.0f);
         }
 #pragma unroll
         for (int u = 0; u < kLoadBatch; u++) {
             const uint32_t e = eb + u * blockDim.x + threadIdx.x;
             if (e < cnt) {
-                const uint32_t lt = r[u].x & lmask;
-                const uint32_t u0 = (r[u].x >> 31) ? (uint32_t)KW : 0u;
-                atomicAdd(&acc[lt * U + u0], quant(__uint_as_float(r[u].y), qs));
-                if (KW == 2) atomicAdd(&acc[lt * U + u0 + 1], quant(__uint_as_float(r[u].z), qs));
+                const uint32_t lt = key[u] & 0x7FFFu;
+                const uint32_t u0 = (key[u] >> 15) ? (uint32_t)KW : 0u;
+                atomicAdd(&acc[lt * U + u0], quant(w[u].x, qs));
+                if (KW == 2) atomicAdd(&acc[lt * U + u0 + 1], quant(w[u].y, qs));
             }
         }
     }

@@ -394,9 +394,9 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
         slot(p.ev, 4 * (size_t)p.KW * recs);
         slot(p.evk, 2 * recs);
         slot(p.bcnt, 4 * (size_t)p.tile_blk[p.T]);
-    } else {
-        slot(p.ev, 4 * (size_t)(1 + p.KW) * E);
-        slot(p.evk, 16);
+    } else { // records of a 16-bit key array beside the weights
+        slot(p.ev, 4 * (size_t)p.KW * E + 64);
+        slot(p.evk, 2 * E + 64);
         slot(p.bcnt, 16);
     }
     slot(p.tile_base, 8 * ((size_t)p.T + 1));
