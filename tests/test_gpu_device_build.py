@@ -1,7 +1,8 @@
 """Connection table generated on the device (the default where it applies) against the
 host construction (DBSIM_F_HOST_BUILD): the same rows, delay segments, targets and weight
-bit patterns on the share and region recipes, an ensemble, constant weights and one weight
-per edge; descriptions with lognormal weights stay on the host. The oracle parity tests
+bit patterns on the share and region recipes, an ensemble, constant weights, one weight
+per edge, long segments, and an in-degree that takes the thread-per-target generator;
+descriptions with lognormal weights stay on the host. The oracle parity tests
 run on device-built tables too, since that is the default."""
 import sys
 
@@ -81,6 +82,12 @@ def test_long_segments_and_duplicate_pairs(Sim):
     pops = [PopSpec(16, True), PopSpec(20000, True)]
     projs = [ProjSpec(8, dst_pop=1, src_mode=SRC_POP, src_pop=0), ProjSpec(50, d_mode=D_UNIFORM, d_min=1, d_max=3)]
     _same_tables(Sim, NetSpec(pops, projs, seed=17, name="hubs"), "hubs 16 -> 20000")
+
+
+def test_thread_per_target_generator(Sim):
+    """In-degree 5,000: the wavefront generator's LDS sets would not fit, so one thread per
+    target draws the in-edges with scratch in the streams (batches of targets)."""
+    _same_tables(Sim, configs.share(n=12000, indegree=5000, seed=19), "share 12000 / k5000")
 
 
 def test_lognormal_weights_stay_on_the_host(Sim):
