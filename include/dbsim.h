@@ -127,7 +127,9 @@ typedef struct dbsim_info {
     uint32_t n_members;        /* networks in the handle (1 unless an ensemble) */
     uint32_t fanin_passes;     /* 1: single-pass fan-in into tile blocks, 2: through super-tile streams */
     uint32_t device_built;     /* 1: the connection table was generated on the device */
-    uint32_t reserved;
+    uint32_t stream_record_bytes; /* super-tile stream record: 12, or 10 (a 2-byte key beside
+                                     the weight pair, when every weight is non-negative and
+                                     there are two per edge); 0 in the single-pass form */
 } dbsim_info;
 
 typedef struct dbsim_member {
@@ -162,7 +164,9 @@ int dbsim_create(const dbsim_desc* desc, struct dbsim** out);
  * the default stream) as direct launches, one kernel after another, with the same results
  * as dbsim_create (no phase timers: dbsim_set_timing(h, 1) gives ESTATE; spikes are read
  * from the device ring, as with DBSIM_F_NO_HOST_RECORD). Everything the
- * kernels read is initialised here, whatever the region held before. The region is shared:
+ * kernels read is initialised here, whatever the region held before (creation copies the
+ * tables and synchronises the stream, so it runs outside a capture; the bins it then runs
+ * allocate nothing and may be captured by the caller). The region is shared:
  * one such handle per device at a time (ESTATE while another is alive; dbsim_destroy frees
  * the region for the next). Errors: EINVAL when the footprint (dbsim_footprint) exceeds
  * DBSIM_STATIC_BYTES (checked before any device work) or dev_alloc is set; otherwise as

@@ -207,6 +207,9 @@ void fill_devnet(dbsim* h) {
     n.st_base = at<const uint64_t>(b, p.st_base);
     n.st_fill = at<uint32_t>(b, p.st_fill);
     n.sev = at<uint32_t>(b, p.sev);
+    n.narrow = p.narrow ? 1u : 0u;
+    n.sevk = reinterpret_cast<uint16_t*>(b + p.sev.off);
+    n.sevw = reinterpret_cast<uint2*>(b + p.sev.off + ((2 * (size_t)p.st_cap + 255) & ~(size_t)255));
     n.stage = at<uint32_t>(b, p.stage);
     n.grp_cnt = at<uint32_t>(b, p.grp_cnt);
     n.n_grp = p.n_grp;
@@ -696,14 +699,15 @@ static int deploy_impl(dbsim_built* bt, const dbsim_desc* dev_opts, dbsim** out)
         };
         hipError_t e = prepare_kernels_once(h->device);
         const size_t N = p.N;
-        std::vector<float> zeros((size_t)p.U * N, 0.0f);
-        std::vector<uint8_t> z8(N, 0), pend(N, 0xFF);
+        auto fill = [&](const Plan::Slot& sl, int v) -> hipError_t {
+            return hipMemsetAsync(h->dev + sl.off, v, sl.bytes, h->stream);
+        };
         if (e == hipSuccess) e = up(p.V, ht.V0.data(), 4 * N);
-        if (e == hipSuccess) e = up(p.J, zeros.data(), 4 * (size_t)p.U * N);
-        if (e == hipSuccess) e = up(p.A, zeros.data(), 4 * (size_t)p.U * N);
-        if (e == hipSuccess) e = up(p.Iou, zeros.data(), 4 * N);
-        if (e == hipSuccess) e = up(p.ref, z8.data(), N);
-        if (e == hipSuccess) e = up(p.pend, pend.data(), N);
+        if (e == hipSuccess) e = fill(p.J, 0);   // +0.0f
+        if (e == hipSuccess) e = fill(p.A, 0);
+        if (e == hipSuccess) e = fill(p.Iou, 0);
+        if (e == hipSuccess) e = fill(p.ref, 0);
+        if (e == hipSuccess) e = fill(p.pend, 0xFF); // no partial bin pending
         if (e == hipSuccess) e = up(p.pops, ht.pops.data(), sizeof(PopParams) * ht.pops.size());
         if (e == hipSuccess) e = up(p.ptab, ht.ptab.data(), 4 * ht.ptab.size());
         if (e == hipSuccess) e = up(p.blk, ht.blk.data(), sizeof(uint2) * ht.blk.size());
@@ -880,6 +884,7 @@ int dbsim_get_info(dbsim* h, dbsim_info* info) {
     info->n_members = p.n_members;
     info->fanin_passes = p.blocked ? 1u : 2u;
     info->device_built = h->device_built ? 1u : 0u;
+    info->stream_record_bytes = p.blocked ? 0u : p.narrow ? 10u : 4u * (1u + p.KW);
     return DBSIM_OK;
 }
 

@@ -110,6 +110,7 @@ struct DevNet {
     uint32_t ahead_passes;  // partition passes of the next bin's delay >= 2 fan-in (two-pass form)
     uint32_t fan_C;         // single-pass form: records per carry buffer
     uint32_t fan_K;         // single-pass form: records per block
+    uint32_t narrow;        // two-pass form: 10-byte stream records (sevk beside sevw)
     uint64_t RCmask;
     uint32_t MBmask;
     double qscale;   // 2^F
@@ -141,7 +142,12 @@ struct DevNet {
     uint32_t* tile_fill;
     const uint64_t* st_base; // super-tile stream slices [NS + 1]
     uint32_t* st_fill;       // records written per super-tile this bin (reset by the gather)
-    uint32_t* sev;           // super-tile stream records (same format as ev)
+    uint32_t* sev;           // super-tile stream records: (target | source class << 31, weights)
+    // or, narrow (every weight non-negative, two weights per edge): a 16-bit key array sevk
+    // (target within the super-tile, low 16 bits) beside the weight pairs sevw, whose sign
+    // bits carry the source class (w0) and the key's bit 16 (w1); slices start at even records
+    uint16_t* sevk;
+    uint2* sevw;
     // spikes: per-block staging (256 slots per neuron block), per-group counts (two bin
     // parities x groups of 256 blocks), then the dense history ring
     uint32_t* stage;

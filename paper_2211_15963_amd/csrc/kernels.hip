@@ -234,6 +234,26 @@ __device__ __forceinline__ void dma_round(const uint32_t* src, unsigned long lon
     }
 }
 
+// The same for narrow stream records: per instruction pair, 128 records' weights (16 bytes
+// per lane, lane l at byte 16 l) and keys (4 bytes per lane, lane l at byte 4 l). The round
+// starts at an even record, so every copy is aligned; lanes past ne repeat the last pair,
+// which lies inside the slice (slices start even, so the record after an odd count does).
+__device__ __forceinline__ void dma_round_narrow(const DevNet& net, unsigned long long first, uint32_t ne,
+                                                 uint2* stage_w, uint16_t* stage_k, uint32_t w0) {
+    const uint32_t w = threadIdx.x >> 6, nw = kScatterThreads >> 6, l = threadIdx.x & 63u;
+    const uint32_t nch = (ne + 127u) >> 7;
+    const uint32_t last = (ne - 1u) & ~1u;
+    for (uint32_t c = w - w0; c < nch; c += nw - w0) {
+        const uint32_t e = min(c * 128u + 2u * l, last);
+        __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)(net.sevw + first + e),
+                                         (__attribute__((address_space(3))) void*)(stage_w + (size_t)c * 128u), 16, 0,
+                                         0);
+        __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)(net.sevk + first + e),
+                                         (__attribute__((address_space(3))) void*)(stage_k + (size_t)c * 128u), 4, 0,
+                                         0);
+    }
+}
+
 __device__ __forceinline__ uint32_t bucket_of(const DevNet& net, uint32_t key, uint32_t nb, uint32_t b0, uint32_t bshift) {
     const uint32_t b = ((key & 0x7FFFFFFFu) >> bshift) - b0;
     return b < nb ? b : 0u;
@@ -301,6 +321,26 @@ __device__ void write_runs(const DevNet& net, Round& R, uint32_t ne, uint32_t nb
         const uint32_t b = bucket_of(net, key, nb, b0, bshift);
         const unsigned long long gb = R.gbase[b];
         if (gb != ~0ull) store_record<KW>(out, gb + (q - R.lstart[b]), key, R.s_w[q]);
+    }
+    __syncthreads();
+}
+
+// Narrow stream records: the key within the super-tile (17 bits at most) as a 16-bit key
+// beside the weight pair, whose sign bits (free: every weight is non-negative) carry the
+// source class (w0) and the key's bit 16 (w1).
+__device__ void write_runs_narrow(const DevNet& net, Round& R, uint32_t ne, uint32_t nb, uint32_t bshift) {
+    const uint32_t smask = (1u << (net.tile_bits + net.ts_bits)) - 1u;
+    for (uint32_t q = threadIdx.x; q < ne; q += kScatterThreads) {
+        const uint32_t key = R.s_key[q];
+        const uint32_t b = bucket_of(net, key, nb, 0, bshift);
+        const unsigned long long gb = R.gbase[b];
+        if (gb != ~0ull) {
+            const unsigned long long pos = gb + (q - R.lstart[b]);
+            const uint32_t loc = key & smask;
+            const float2 w = R.s_w[q];
+            net.sevk[pos] = (uint16_t)loc;
+            net.sevw[pos] = make_uint2(__float_as_uint(w.x) | (key & 0x80000000u), __float_as_uint(w.y) | ((loc >> 16) << 31));
+        }
     }
     __syncthreads();
 }
@@ -463,7 +503,8 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
             place_batch(R, B, ne, nbt);
             if (tid == 0 && r0 == 0) s_pc = G + claim; // read by every thread at the end of the chunk
             __syncthreads();
-            write_runs<KW>(net, R, ne, nb, 0, bshift, net.sev);
+            if (KW == 2 && net.narrow) write_runs_narrow(net, R, ne, nb, bshift);
+            else write_runs<KW>(net, R, ne, nb, 0, bshift, net.sev);
         }
         if (ec == 0) { // no round: claim here
             if (tid == 0) s_pc = G + atomicAdd(&net.ctl->pnext, 1ull);
@@ -494,6 +535,10 @@ __global__ void __launch_bounds__(kScatterThreads) k_bucket(DevNet net) {
     const uint32_t RE = net.bucket_events, NS = net.NS, TS = 1u << net.ts_bits, G = gridDim.x;
     const BucketLayout L(TS, RE);
     uint4* stage = reinterpret_cast<uint4*>(dyn + L.stage);
+    // narrow records: the weights, then the keys, in the same staging bytes
+    const bool narrow = KW == 2 && net.narrow;
+    uint2* stage_w = reinterpret_cast<uint2*>(dyn + L.stage);
+    uint16_t* stage_k = reinterpret_cast<uint16_t*>(dyn + L.stage + 8 * (size_t)RE);
     unsigned long long* s_cpre = reinterpret_cast<unsigned long long*>(dyn + L.cpre);
     unsigned long long* s_sbase = reinterpret_cast<unsigned long long*>(dyn + L.sbase);
     Round R;
@@ -539,7 +584,8 @@ __global__ void __launch_bounds__(kScatterThreads) k_bucket(DevNet net) {
         uint32_t st, ne;
         unsigned long long r0;
         locate(c, st, r0, ne);
-        dma_round<KW>(net.sev, s_sbase[st] + r0, ne, stage, 0);
+        if (narrow) dma_round_narrow(net, s_sbase[st] + r0, ne, stage_w, stage_k, 0);
+        else dma_round<KW>(net.sev, s_sbase[st] + r0, ne, stage, 0);
     }
     while (c < nchunks) {
         uint32_t st, ne;
@@ -556,10 +602,17 @@ __global__ void __launch_bounds__(kScatterThreads) k_bucket(DevNet net) {
         for (int u = 0; u < kMaxBatch; u++) {
             const uint32_t e = u * kScatterThreads + tid;
             if (u < (int)nbt && e < ne) {
-                const uint4 q = stage[e];
-                B.key[u] = q.x;
-                B.w[u] = make_float2(__uint_as_float(q.y), KW == 2 ? __uint_as_float(q.z) : 0.0f);
-                B.br[u] = rank_event(net, R, B.key[u], nt, t0, net.tile_bits);
+                if (narrow) { // key within the super-tile, so the tiles count from 0
+                    const uint2 wv = stage_w[e];
+                    B.key[u] = (uint32_t)stage_k[e] | ((wv.y >> 31) << 16) | (wv.x & 0x80000000u);
+                    B.w[u] = make_float2(__uint_as_float(wv.x & 0x7FFFFFFFu), __uint_as_float(wv.y & 0x7FFFFFFFu));
+                    B.br[u] = rank_event(net, R, B.key[u], nt, 0, net.tile_bits);
+                } else {
+                    const uint4 q = stage[e];
+                    B.key[u] = q.x;
+                    B.w[u] = make_float2(__uint_as_float(q.y), KW == 2 ? __uint_as_float(q.z) : 0.0f);
+                    B.br[u] = rank_event(net, R, B.key[u], nt, t0, net.tile_bits);
+                }
             }
         }
         __syncthreads();
@@ -567,7 +620,8 @@ __global__ void __launch_bounds__(kScatterThreads) k_bucket(DevNet net) {
             uint32_t st2, ne2;
             unsigned long long r2;
             locate(cn, st2, r2, ne2);
-            dma_round<KW>(net.sev, s_sbase[st2] + r2, ne2, stage, 1);
+            if (narrow) dma_round_narrow(net, s_sbase[st2] + r2, ne2, stage_w, stage_k, 1);
+            else dma_round<KW>(net.sev, s_sbase[st2] + r2, ne2, stage, 1);
         }
         // the claim travels with wavefront 0's reservations (one wait for both)
         unsigned long long claim = 0;
@@ -576,7 +630,7 @@ __global__ void __launch_bounds__(kScatterThreads) k_bucket(DevNet net) {
         place_batch(R, B, ne, nbt);
         if (tid == 0) s_claim = cn < nchunks ? 2ull * G + claim : ~0ull;
         __syncthreads();
-        write_runs_arena<KW>(net, R, ne, nt, t0);
+        write_runs_arena<KW>(net, R, ne, nt, narrow ? 0u : t0);
         c = cn;
         cn = s_claim;
     }

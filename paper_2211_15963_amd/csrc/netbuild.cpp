@@ -405,6 +405,26 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     slot(p.st_fill, 4 * (size_t)p.NS + 4);
     // 64 spare bytes: the partition kernels copy 8-byte records with 12-byte reads
     slot(p.sev, p.blocked ? 16 : 4 * (size_t)(1 + p.KW) * E + 64);
+    // narrow stream records: two weights per edge, every weight non-negative (its sign bit
+    // free: the parameters that shape it are not negative and not -0), and a key within the
+    // super-tile of at most 17 bits; the 12-byte region holds both arrays
+    p.narrow = false;
+    p.st_cap = 0;
+    if (!p.blocked && p.KW == 2 && p.tile_bits + p.ts_bits <= 17) {
+        bool nonneg = true;
+        for (const auto& d : mem.m)
+            for (uint32_t j = 0; j < d.n_projs; j++) {
+                const dbnet_proj& pr = d.projs[j];
+                if (std::signbit(pr.w_scale_exc) || std::signbit(pr.w_scale_inh)) nonneg = false;
+                if (pr.w_dist != DBNET_W_LOGNORMAL && std::signbit(pr.w_a)) nonneg = false;
+            }
+        const uint64_t cap = E + p.NS + 128;
+        const size_t need = ((2 * (size_t)cap + 255) & ~(size_t)255) + 8 * (size_t)cap;
+        if (nonneg && need <= p.sev.bytes) {
+            p.narrow = true;
+            p.st_cap = cap;
+        }
+    }
     p.n_grp = (p.n_blocks + 255) / 256;
     slot(p.stage, 4 * (size_t)p.n_blocks * kNeuronBlock);
     slot(p.grp_cnt, 4 * 2 * (size_t)p.n_grp);
@@ -593,6 +613,12 @@ std::string build_tables(const Members& mem, const Plan& p, unsigned threads, Ho
     // super-tile stream slices: the sum of their tiles' slices
     h.st_base.assign((size_t)p.NS + 1, 0ull);
     for (uint32_t x = 0; x <= p.NS; x++) h.st_base[x] = h.tile_base[std::min<uint64_t>((uint64_t)x << p.ts_bits, p.T)];
+    if (p.narrow) // slices start at even records (the bucketing copies record pairs)
+        for (uint32_t x = 0, add = 0; x < p.NS; x++) {
+            const uint64_t len = h.st_base[x + 1] + add - h.st_base[x];
+            if (len & 1) add++;
+            h.st_base[x + 1] += add;
+        }
     if (!with_edges) return make_gen_tables(mem, h);
 
     size_t scratch_bytes = 0;

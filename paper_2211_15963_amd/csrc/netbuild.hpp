@@ -40,6 +40,8 @@ struct Plan {
     uint32_t n_l1 = 0;  // level-1 readout groups (256 neuron blocks each, per region)
     uint32_t n_grp = 0; // compaction groups (256 consecutive neuron blocks each)
     bool blocked = false;         // single-pass fan-in into tile blocks (else two passes)
+    bool narrow = false;          // two-pass form with 10-byte stream records
+    uint64_t st_cap = 0;          // narrow: stream record capacity (padded slices and a margin)
     uint32_t NS = 0, ts_bits = 0; // super-tiles, log2(tiles per super-tile) of the two-pass form
     std::vector<uint64_t> tile_blk; // single-pass form: first block of every tile [T + 1]
     uint32_t HW = 0;              // words per row header

@@ -56,7 +56,7 @@ class SimInfo(Structure):
                 ("weights_per_edge", c_uint32), ("steps_per_bin", c_uint32), ("max_delay", c_uint32),
                 ("n_regions", c_uint32), ("tile_neurons", c_uint32), ("n_tiles", c_uint32), ("frac_bits", c_uint32),
                 ("n_members", c_uint32), ("fanin_passes", c_uint32), ("device_built", c_uint32),
-                ("reserved", c_uint32)]
+                ("stream_record_bytes", c_uint32)]
 
 
 class SimMember(Structure):

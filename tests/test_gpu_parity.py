@@ -236,6 +236,27 @@ def test_single_pass_fanin_bit_exact(Sim):
     sim.close()
 
 
+def test_stream_record_formats(Sim):
+    """Non-negative weights with two per edge use 10-byte super-tile stream records (a 2-byte
+    key beside the weight pair, two key bits in the weights' sign bits); a description with
+    negative weights keeps the 12-byte records. Both equal the oracle bit for bit."""
+    spec = configs.share(n=20000, indegree=300, seed=61)
+    sim = Sim(spec)
+    assert sim.info.stream_record_bytes == 10
+    sim.close()
+    neg = configs.share(n=20000, indegree=300, seed=62)
+    for p in neg.projs:
+        p.w_a = -0.25   # weights uniform in [-0.25, 1)
+    _say("share 20000 / k300 seed 62 with negative weights: 12-byte stream records, 300 steps")
+    sim = Sim(neg)
+    assert sim.info.stream_record_bytes == 12
+    sim.step(300)
+    orc = Oracle(neg, 32)
+    orc.step(300)
+    _compare(sim, orc, neg)
+    sim.close()
+
+
 @pytest.mark.parametrize("single_pass", [False, True])
 def test_fanin_schedules_agree(Sim, single_pass):
     """Every partition schedule gives the same bits (exact integer arrival sums)."""

@@ -81,6 +81,7 @@ def test_share_600k_element_wise_both_forms(Sim):
         info = sim.info
         assert info.n_tiles == 147
         assert info.fanin_passes == (1 if single_pass else 2)
+        assert info.stream_record_bytes == (0 if single_pass else 10)
         n_blocks = (spec.num_neurons + 255) // 256
         assert n_blocks > 2000  # several compaction groups and level-1 readout groups of 256 blocks
         sim.step(K * S)
