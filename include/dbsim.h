@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define DBSIM_ABI_VERSION 2u
+#define DBSIM_ABI_VERSION 3u
 
 typedef enum dbsim_status {
     DBSIM_OK = 0,
@@ -82,6 +82,14 @@ typedef struct dbsim_desc {
                                        up to a power of two); 0 = 2^24; unused with
                                        DBSIM_F_NO_HOST_RECORD. The last 2^20 bins' offsets are
                                        kept beside them. */
+    uint32_t stream_permille;       /* two-pass form: records each super-tile stream holds per
+                                       partition pass, in thousandths of the super-tile's
+                                       in-edges (1..1000; 1000 = every edge, the most one pass
+                                       can carry). 0 = 125, and at least 2^20 records (or all
+                                       in-edges, if fewer). Runs that find their stream full
+                                       go straight to the tile arena, one atomic per event:
+                                       slower, same results (dbsim_stats.spilled_events). */
+    uint32_t reserved;              /* 0 */
 } dbsim_desc;
 
 /* flags */
@@ -91,10 +99,10 @@ typedef struct dbsim_desc {
 #define DBSIM_F_HOST_BUILD 8u /* build the connection table on the host threads even where the
                                  device construction applies (same table; for comparisons) */
 #define DBSIM_F_SINGLE_PASS 2u /* fan-in in one pass into per-workgroup blocks of each tile
-                                  (no super-tile streams: about a third less device memory,
-                                  slower on every measured network); taken where the tiles'
-                                  carry buffers fit one workgroup's LDS (up to about 2,900
-                                  tiles), else the default two passes. Same results. */
+                                  (no super-tile streams; slower on every measured network);
+                                  taken where the tiles' carry buffers fit one workgroup's
+                                  LDS (up to about 2,900 tiles), else the default two
+                                  passes. Same results. */
 
 typedef struct dbsim_stats {
     uint64_t steps;        /* Euler steps completed (queued) */
@@ -112,6 +120,8 @@ typedef struct dbsim_stats {
     double build_seconds;  /* time spent constructing the network: the host phase, plus the
                               device construction of the connection table where it ran (its
                               duration is added at the first synchronisation after create) */
+    uint64_t spilled_events; /* events of completed bins that found their super-tile stream
+                                full and were placed in the tile arena directly */
 } dbsim_stats;
 
 typedef struct dbsim_info {
@@ -130,6 +140,9 @@ typedef struct dbsim_info {
     uint32_t stream_record_bytes; /* super-tile stream record: 12, or 10 (a 2-byte key beside
                                      the weight pair, when every weight is non-negative and
                                      there are two per edge); 0 in the single-pass form */
+    uint32_t reserved;
+    uint64_t stream_records;   /* records the super-tile streams hold in all (0 in the
+                                  single-pass form) */
 } dbsim_info;
 
 typedef struct dbsim_member {

@@ -555,7 +555,6 @@ static int device_build(dbsim* h, HostTables& ht) {
     b.sums = reinterpret_cast<unsigned long long*>(ev + p.gl.sums);
     b.tb = ev + p.gl.tb;
     b.err = &h->net.ctl->err;
-    b.stage = reinterpret_cast<uint32_t*>(h->dev + p.sev.off);
     b.edge = reinterpret_cast<uint32_t*>(h->dev + p.edge.off);
     b.hdr = reinterpret_cast<uint32_t*>(h->dev + p.hdr.off);
     b.N = p.N;
@@ -885,6 +884,7 @@ int dbsim_get_info(dbsim* h, dbsim_info* info) {
     info->fanin_passes = p.blocked ? 1u : 2u;
     info->device_built = h->device_built ? 1u : 0u;
     info->stream_record_bytes = p.blocked ? 0u : p.narrow ? 10u : 4u * (1u + p.KW);
+    info->stream_records = p.blocked ? 0u : p.st_total;
     return DBSIM_OK;
 }
 
@@ -1789,6 +1789,7 @@ int dbsim_get_stats(dbsim* h, dbsim_stats* s) {
     s->ms_neuron = h->ms[2];
     s->ms_readout = h->ms[3];
     s->build_seconds = h->build_seconds;
+    s->spilled_events = c.spilled;
     return DBSIM_OK;
 }
 

@@ -55,6 +55,8 @@ constexpr uint32_t kTileLdsBytes = 128u * 1024u; // LDS accumulator per tile
 constexpr uint32_t kErrArena = 1u;    // arena slice overflow (cannot happen by construction)
 constexpr uint32_t kErrLayout = 2u;   // a table entry outside its tile group (cannot happen by construction)
 constexpr uint32_t kMaxSuperTiles = 64; // buckets of the first partition pass
+constexpr uint32_t kStreamPermille = 125; // default stream slice: 1/8 of the super-tile's in-edges,
+constexpr uint64_t kStreamFloor = 1ull << 20; // and at least this many records (or all of them)
 constexpr uint32_t kBoldRing = 1024;     // BOLD samples kept per region (power of two)
 constexpr int kLoadBatch = 8;          // gather: records loaded per thread before they are consumed
 constexpr int kMaxBatch = 8;           // partition: events per thread per round
@@ -95,6 +97,7 @@ struct Ctl {
     unsigned long long bnext;        // next k_bucket round to hand out (work queue)
     unsigned long long pnext;        // next k_part chunk to hand out (work queue)
     unsigned long long inject_until; // output spikes are injected in bins below this one
+    unsigned long long spilled;      // partitioned events whose super-tile stream was full
 };
 
 struct DevNet {
@@ -141,7 +144,8 @@ struct DevNet {
     const uint64_t* tile_base;
     uint32_t* tile_fill;
     const uint64_t* st_base; // super-tile stream slices [NS + 1]
-    uint32_t* st_fill;       // records written per super-tile this bin (reset by the gather)
+    uint32_t* st_fill;       // [2 NS] records reserved per super-tile this pass, then the
+                             // complement of the first reservation that did not fit (0: none)
     uint32_t* sev;           // super-tile stream records: (target | source class << 31, weights)
     // or, narrow (every weight non-negative, two weights per edge): a 16-bit key array sevk
     // (target within the super-tile, low 16 bits) beside the weight pairs sevw, whose sign

@@ -310,8 +310,8 @@ __global__ void __launch_bounds__(256) k_gen_fill(DevBuild b, uint64_t i0, uint6
 }
 
 // one wavefront per row: every delay segment ordered by (target, projection), through LDS
-// up to kGenSortMax records, else through a copy in the stage array (keys distinct: a
-// projection draws a source at most once per target)
+// up to kGenSortMax records, else in place (keys distinct: a projection draws a source at
+// most once per target)
 template <int KW>
 __global__ void __launch_bounds__(64) k_gen_sort(DevBuild b) {
     constexpr uint32_t RW = 1 + KW;
@@ -348,23 +348,36 @@ __global__ void __launch_bounds__(64) k_gen_sort(DevBuild b) {
             }
             __syncthreads();
         } else {
-            for (uint32_t e = lane; e < L; e += 64)
+            // longer segments in place, by a bitonic network whose comparators all put the
+            // smaller key first (a flip over each block of k, then half-cleaners): the
+            // positions from L up to the next power of two stand for keys above every key
+            // and are never touched
+            uint32_t P = 2;
+            while (P < L) P <<= 1;
+            for (uint32_t k = 2; k <= P; k <<= 1) {
+                for (uint32_t jd = k >> 1; jd > 0; jd >>= 1) {
+                    for (uint32_t q = lane; q < P / 2; q += 64) {
+                        const uint32_t i = ((q & ~(jd - 1)) << 1) | (q & (jd - 1)); // bit jd clear
+                        const uint32_t pi = jd == (k >> 1) ? (i ^ (k - 1)) : (i | jd);
+                        if (pi >= L) continue;
+                        const unsigned long long ei = s0 + i, ep = s0 + pi;
+                        const unsigned long long ki = ((unsigned long long)(b.edge[ei * RW + KW] & 0x7FFFFFFFu) << 8) | b.tb[ei];
+                        const unsigned long long kp = ((unsigned long long)(b.edge[ep * RW + KW] & 0x7FFFFFFFu) << 8) | b.tb[ep];
+                        if (ki > kp) {
 #pragma unroll
-                for (uint32_t w = 0; w < RW; w++) b.stage[(s0 + e) * RW + w] = b.edge[(s0 + e) * RW + w];
-            __syncthreads();
-            for (uint32_t e = lane; e < L; e += 64) {
-                const unsigned long long ke =
-                    ((unsigned long long)(b.stage[(s0 + e) * RW + KW] & 0x7FFFFFFFu) << 8) | b.tb[s0 + e];
-                uint32_t rank = 0;
-                for (uint32_t f = 0; f < L; f++) {
-                    const unsigned long long kf =
-                        ((unsigned long long)(b.stage[(s0 + f) * RW + KW] & 0x7FFFFFFFu) << 8) | b.tb[s0 + f];
-                    rank += kf < ke ? 1u : 0u;
+                            for (uint32_t w = 0; w < RW; w++) {
+                                const uint32_t a = b.edge[ei * RW + w];
+                                b.edge[ei * RW + w] = b.edge[ep * RW + w];
+                                b.edge[ep * RW + w] = a;
+                            }
+                            const uint8_t ta = b.tb[ei];
+                            b.tb[ei] = b.tb[ep];
+                            b.tb[ep] = ta;
+                        }
+                    }
+                    __syncthreads();
                 }
-#pragma unroll
-                for (uint32_t w = 0; w < RW; w++) b.edge[(s0 + rank) * RW + w] = b.stage[(s0 + e) * RW + w];
             }
-            __syncthreads();
         }
     }
 }
@@ -375,8 +388,8 @@ hipError_t launch_device_build(const DevBuild& b, hipStream_t st) {
     const uint64_t N = b.N;
     // wavefront generator when its LDS (hash set and two index buffers per wavefront) fits
     // 64 KiB per block of up to four wavefronts; else one thread per target with scratch
-    const size_t per = 4ull * (b.g.hcap + 2ull * b.g.kmax);
-    const uint32_t wpb = per <= 65536 ? (uint32_t)std::min<size_t>(4, 65536 / per) : 0u;
+    const size_t per = gen_wave_lds(b.g.kmax, b.g.hcap);
+    const uint32_t wpb = per <= kGenWaveLds ? (uint32_t)std::min<size_t>(4, kGenWaveLds / per) : 0u;
     const unsigned wgrid = wpb ? (unsigned)std::min<uint64_t>((N + wpb - 1) / wpb, 256ull * 64) : 0u;
     hipLaunchKernelGGL(k_gen_clear, dim3(grid_of(N * b.D, 256 * 16) + 1), dim3(256), 0, st, b.cnt, N * b.D);
     hipError_t e = hipGetLastError();

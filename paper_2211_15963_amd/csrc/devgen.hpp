@@ -234,7 +234,6 @@ struct DevBuild {
     unsigned long long* sums;     // [N / 1024 + 2] block sums of the row scan
     uint8_t* tb;                  // [E] projection of every placed edge (order of equal targets)
     uint32_t* err;                // the handle's sticky error word (a failed check sets kErrBuild)
-    uint32_t* stage;              // [E][1 + KW] copy of long segments while they are ordered
     uint32_t* edge;               // the edge records [E][1 + KW]
     uint32_t* hdr;                // the row headers [N][HW]
     uint64_t N, E;
@@ -242,6 +241,10 @@ struct DevBuild {
     double wlim;                  // |w| must stay below 2^(52 - F)
 };
 constexpr uint32_t kGenSortMax = 2048; // delay segments up to this length are ordered in LDS
+// LDS bytes of the wavefront generator per wavefront (hash set and two index buffers); it
+// runs where one wavefront's fit 64 KiB, else one thread per target with scratch
+inline size_t gen_wave_lds(uint32_t kmax, uint32_t hcap) { return 4ull * (hcap + 2ull * kmax); }
+constexpr size_t kGenWaveLds = 65536;
 constexpr uint32_t kErrBuild = 4u;      // error-word bit: a consistency check of the construction failed
 
 // Enqueues the whole construction on st; nothing is awaited. Checks that cannot fail for

@@ -291,36 +291,75 @@ __device__ __forceinline__ void store_record(uint32_t* out, unsigned long long p
         reinterpret_cast<uint2*>(out)[pos] = make_uint2(key, __float_as_uint(w.x));
 }
 
+constexpr unsigned long long kSpillRun = ~1ull; // gbase of a run whose stream is full
+
 // Runs (unbuffered): one reservation per non-empty bucket in out_fill (slice of bucket b:
-// out_base[b0+b] .. out_base[b0+b+1]); sets gbase and the sorted starts.
-__device__ void reserve_runs(const DevNet& net, Round& R, uint32_t nb, uint32_t b0, const uint64_t* out_base,
+// out_base[b0+b] .. out_base[b0+b+1]); sets gbase and the sorted starts. A tile arena slice
+// holds every event its tile can receive (overflow is an error that cannot happen); a
+// super-tile stream (SPILL) holds a share of them: a run that does not fit is marked
+// kSpillRun, and the stream's valid records end at the first such reservation, kept as
+// the largest ~base in out_fill[NS + b] (the reservations that fit are exactly those
+// before it, since the fill only grows).
+// Returns whether a run of the round was marked (the same on every thread).
+template <bool SPILL>
+__device__ bool reserve_runs(const DevNet& net, Round& R, uint32_t nb, uint32_t b0, const uint64_t* out_base,
                              uint32_t* out_fill) {
+    int spilled = 0;
     for (uint32_t t = threadIdx.x; t < nb; t += kScatterThreads) {
         const uint32_t h = R.hist[t];
         unsigned long long gb = ~0ull;
         if (h) {
             const uint32_t base = atomicAdd(&out_fill[b0 + t], h);
             const unsigned long long s0 = out_base[b0 + t];
-            if ((unsigned long long)base + h <= out_base[b0 + t + 1] - s0) gb = s0 + base;
-            else atomicOr(&net.ctl->err, kErrArena);
+            if ((unsigned long long)base + h <= out_base[b0 + t + 1] - s0) {
+                gb = s0 + base;
+            } else if (SPILL) {
+                atomicMax(&out_fill[net.NS + b0 + t], ~base);
+                atomicAdd(&net.ctl->spilled, (unsigned long long)h);
+                gb = kSpillRun;
+                spilled = 1;
+            } else {
+                atomicOr(&net.ctl->err, kErrArena);
+            }
         }
         R.gbase[t] = gb;
         R.lstart[t] = h;
     }
-    __syncthreads();
+    const bool any = SPILL ? __syncthreads_or(spilled) != 0 : false;
+    if (!SPILL) __syncthreads();
     block_scan_inplace(R.lstart, nb, R.s_wave);
     __syncthreads();
+    return any;
 }
 
-// consecutive threads write consecutive records of a bucket's run
+// An event whose super-tile stream was full goes straight to its tile's arena slice, with
+// one atomic for its place (the bucketing of the stream's records reserves after it).
 template <int KW>
+__device__ void spill_event(const DevNet& net, uint32_t key, float2 w) {
+    const uint32_t tgt = key & 0x7FFFFFFFu, t = tgt >> net.tile_bits;
+    const uint32_t slot = atomicAdd(&net.tile_fill[t], 1u);
+    const unsigned long long s0 = net.tile_base[t];
+    if (slot < net.tile_base[t + 1] - s0) {
+        const unsigned long long pos = s0 + slot;
+        net.evk[pos] = (uint16_t)((tgt & ((1u << net.tile_bits) - 1u)) | ((key >> 31) << 15));
+        if (KW == 2) reinterpret_cast<float2*>(net.ev)[pos] = w;
+        else reinterpret_cast<float*>(net.ev)[pos] = w.x;
+    } else {
+        atomicOr(&net.ctl->err, kErrArena);
+    }
+}
+
+// consecutive threads write consecutive records of a bucket's run (SPILL: some runs of the
+// round are marked and go to the tile arena instead)
+template <int KW, bool SPILL>
 __device__ void write_runs(const DevNet& net, Round& R, uint32_t ne, uint32_t nb, uint32_t b0, uint32_t bshift,
                            uint32_t* out) {
     for (uint32_t q = threadIdx.x; q < ne; q += kScatterThreads) {
         const uint32_t key = R.s_key[q];
         const uint32_t b = bucket_of(net, key, nb, b0, bshift);
         const unsigned long long gb = R.gbase[b];
-        if (gb != ~0ull) store_record<KW>(out, gb + (q - R.lstart[b]), key, R.s_w[q]);
+        if (SPILL && gb == kSpillRun) spill_event<KW>(net, key, R.s_w[q]);
+        else if (gb != ~0ull) store_record<KW>(out, gb + (q - R.lstart[b]), key, R.s_w[q]);
     }
     __syncthreads();
 }
@@ -328,13 +367,16 @@ __device__ void write_runs(const DevNet& net, Round& R, uint32_t ne, uint32_t nb
 // Narrow stream records: the key within the super-tile (17 bits at most) as a 16-bit key
 // beside the weight pair, whose sign bits (free: every weight is non-negative) carry the
 // source class (w0) and the key's bit 16 (w1).
+template <bool SPILL>
 __device__ void write_runs_narrow(const DevNet& net, Round& R, uint32_t ne, uint32_t nb, uint32_t bshift) {
     const uint32_t smask = (1u << (net.tile_bits + net.ts_bits)) - 1u;
     for (uint32_t q = threadIdx.x; q < ne; q += kScatterThreads) {
         const uint32_t key = R.s_key[q];
         const uint32_t b = bucket_of(net, key, nb, 0, bshift);
         const unsigned long long gb = R.gbase[b];
-        if (gb != ~0ull) {
+        if (SPILL && gb == kSpillRun) {
+            spill_event<2>(net, key, R.s_w[q]);
+        } else if (gb != ~0ull) {
             const unsigned long long pos = gb + (q - R.lstart[b]);
             const uint32_t loc = key & smask;
             const float2 w = R.s_w[q];
@@ -499,12 +541,17 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
             // reservations (one wait for both)
             unsigned long long claim = 0;
             if (tid == 0 && r0 == 0) claim = atomicAdd(&net.ctl->pnext, 1ull);
-            reserve_runs(net, R, nb, 0, net.st_base, net.st_fill);
+            const bool spill = reserve_runs<true>(net, R, nb, 0, net.st_base, net.st_fill);
             place_batch(R, B, ne, nbt);
             if (tid == 0 && r0 == 0) s_pc = G + claim; // read by every thread at the end of the chunk
             __syncthreads();
-            if (KW == 2 && net.narrow) write_runs_narrow(net, R, ne, nb, bshift);
-            else write_runs<KW>(net, R, ne, nb, 0, bshift, net.sev);
+            if (KW == 2 && net.narrow) {
+                if (spill) write_runs_narrow<true>(net, R, ne, nb, bshift);
+                else write_runs_narrow<false>(net, R, ne, nb, bshift);
+            } else {
+                if (spill) write_runs<KW, true>(net, R, ne, nb, 0, bshift, net.sev);
+                else write_runs<KW, false>(net, R, ne, nb, 0, bshift, net.sev);
+            }
         }
         if (ec == 0) { // no round: claim here
             if (tid == 0) s_pc = G + atomicAdd(&net.ctl->pnext, 1ull);
@@ -520,11 +567,12 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
     // bin close): no grid-wide completion count, whose same-address atomics cost tens of us
 }
 
-// Records in super-tile stream st. A stream never holds more than its slice (each edge
-// fires at most once per bin); the clamp keeps the reads inside it even if that
-// invariant were broken (k_part has then raised kErrArena).
+// Records in super-tile stream st: the reservations that fit its slice (the others went
+// to the tile arena directly), which end at the first one that did not.
 __device__ __forceinline__ uint32_t stream_fill(const DevNet& net, uint32_t st) {
-    return (uint32_t)min((unsigned long long)net.st_fill[st], net.st_base[st + 1] - net.st_base[st]);
+    const uint32_t lim = net.st_fill[net.NS + st];
+    const uint32_t f = lim ? min(net.st_fill[st], ~lim) : net.st_fill[st];
+    return (uint32_t)min((unsigned long long)f, net.st_base[st + 1] - net.st_base[st]);
 }
 
 // Second pass when the tiles are too many for the carry buffers: each super-tile stream is
@@ -626,7 +674,7 @@ __global__ void __launch_bounds__(kScatterThreads) k_bucket(DevNet net) {
         // the claim travels with wavefront 0's reservations (one wait for both)
         unsigned long long claim = 0;
         if (tid == 0 && cn < nchunks) claim = atomicAdd(&net.ctl->bnext, 1ull);
-        reserve_runs(net, R, nt, t0, net.tile_base, net.tile_fill);
+        reserve_runs<false>(net, R, nt, t0, net.tile_base, net.tile_fill);
         place_batch(R, B, ne, nbt);
         if (tid == 0) s_claim = cn < nchunks ? 2ull * G + claim : ~0ull;
         __syncthreads();
@@ -640,7 +688,7 @@ __global__ void __launch_bounds__(kScatterThreads) k_bucket(DevNet net) {
 
 // between two partition passes of one bin: empty streams and work-queue counters
 __global__ void __launch_bounds__(256) k_pass_reset(DevNet net) {
-    for (uint32_t x = threadIdx.x; x < net.NS; x += blockDim.x) net.st_fill[x] = 0;
+    for (uint32_t x = threadIdx.x; x < 2 * net.NS; x += blockDim.x) net.st_fill[x] = 0;
     if (threadIdx.x == 0) {
         net.ctl->pnext = 0;
         net.ctl->bnext = 0;
@@ -1023,7 +1071,7 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(DevNet net) {
     // arena, and the next bin's delay >= 2 records start from the front (the bin close
     // clears them again after those have been bucketed)
     if (t == 0)
-        for (uint32_t x = threadIdx.x; x < net.NS; x += blockDim.x) net.st_fill[x] = 0;
+        for (uint32_t x = threadIdx.x; x < 2 * net.NS; x += blockDim.x) net.st_fill[x] = 0;
     // this bin's events assembled ahead are delivered now (no partition of the next bin
     // runs before the gather has finished)
     if (t == 0 && threadIdx.x == 0) {
@@ -1547,7 +1595,7 @@ __global__ void __launch_bounds__(256) k_readout_close(DevNet net) {
     }
     // the super-tile streams are empty again: the next bin's delay >= 2 records have been
     // bucketed before this kernel starts, its delay-1 records come next
-    for (uint32_t x = threadIdx.x; x < net.NS; x += blockDim.x) net.st_fill[x] = 0;
+    for (uint32_t x = threadIdx.x; x < 2 * net.NS; x += blockDim.x) net.st_fill[x] = 0;
     if (threadIdx.x == 0) {
         const uint32_t m = net.MBmask;
         const uint32_t c = net.bin_cnt[k & m];

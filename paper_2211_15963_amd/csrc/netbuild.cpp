@@ -355,11 +355,9 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
         s.bytes = bytes;
         off += (bytes + 255) & ~(size_t)255;
     };
-    // single-pass form: tile t's blocks hold its total in-degree in whole blocks plus two
-    // part-filled blocks per workgroup and bin (one per workgroup and pass)
-    p.tile_blk.clear();
-    if (p.blocked) {
-        std::vector<uint64_t> tin(p.T, 0);
+    // in-edges of every tile (the most events it can receive in one bin)
+    std::vector<uint64_t> tin(p.T, 0);
+    {
         uint64_t i0 = 0;
         for (size_t k = 0; k < mem.m.size(); k++)
             for (uint32_t q = 0; q < mem.m[k].n_pops; q++) {
@@ -371,12 +369,35 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
                 }
                 i0 = i1;
             }
+    }
+    // single-pass form: tile t's blocks hold its total in-degree in whole blocks plus two
+    // part-filled blocks per workgroup and bin (one per workgroup and pass)
+    p.tile_blk.clear();
+    if (p.blocked) {
         p.tile_blk.assign((size_t)p.T + 1, 0);
         for (uint32_t t = 0; t < p.T; t++)
             p.tile_blk[t + 1] = p.tile_blk[t] + tin[t] / kFanBlock + 2ull * kFanMaxGrid;
         if (p.tile_blk[p.T] >= 0xFFFFFFF0ull) return "network too large for the single-pass event arena";
     }
     const size_t N = p.N, U = p.U, E = p.E;
+    // the device checks nothing it could report before the first bin, so the fixed-point
+    // range of the weights (|w| 2^F < 2^52) is bounded here from the distributions' limits;
+    // a description that may exceed it is built and checked exactly on the host
+    bool wfit = true;
+    for (const auto& d : mem.m)
+        for (uint32_t j = 0; j < d.n_projs; j++) {
+            const dbnet_proj& pr = d.projs[j];
+            const double a = std::max(std::fabs((double)pr.w_a), pr.w_dist == DBNET_W_CONST ? 0.0 : std::fabs((double)pr.w_b));
+            const double sc = std::max(std::fabs((double)pr.w_scale_exc), std::fabs((double)pr.w_scale_inh));
+            if (!(a * sc * (1.0 + 0x1p-20) < std::ldexp(1.0, 52 - (int)p.F))) wfit = false;
+        }
+    HostTables gt;
+    const bool gen_ok = !p.blocked && !(opts.flags & DBSIM_F_HOST_BUILD) && p.E > 0 && wfit &&
+                        make_gen_tables(mem, gt).empty();
+    // per-target scratch of the thread-per-target generator (in the streams, which are free
+    // before the first bin); the wavefront generator needs none
+    const size_t gen_sw = gen_ok ? 4 * (size_t)gen_scratch_words(gt.gkmax, gt.ghcap) : 1;
+    const bool gen_threads = gen_ok && gen_wave_lds(gt.gkmax, gt.ghcap) > kGenWaveLds;
     slot(p.V, 4 * N);
     slot(p.J, 4 * U * N);
     slot(p.ref, N);
@@ -401,15 +422,13 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     }
     slot(p.tile_base, 8 * ((size_t)p.T + 1));
     slot(p.tile_fill, 4 * (size_t)p.T);
+    // fill counters of the super-tile streams, then the first failed reservation of each
     slot(p.st_base, 8 * ((size_t)p.NS + 1));
-    slot(p.st_fill, 4 * (size_t)p.NS + 4);
-    // 64 spare bytes: the partition kernels copy 8-byte records with 12-byte reads
-    slot(p.sev, p.blocked ? 16 : 4 * (size_t)(1 + p.KW) * E + 64);
+    slot(p.st_fill, 8 * (size_t)p.NS + 4);
     // narrow stream records: two weights per edge, every weight non-negative (its sign bit
     // free: the parameters that shape it are not negative and not -0), and a key within the
-    // super-tile of at most 17 bits; the 12-byte region holds both arrays
+    // super-tile of at most 17 bits
     p.narrow = false;
-    p.st_cap = 0;
     if (!p.blocked && p.KW == 2 && p.tile_bits + p.ts_bits <= 17) {
         bool nonneg = true;
         for (const auto& d : mem.m)
@@ -418,12 +437,37 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
                 if (std::signbit(pr.w_scale_exc) || std::signbit(pr.w_scale_inh)) nonneg = false;
                 if (pr.w_dist != DBNET_W_LOGNORMAL && std::signbit(pr.w_a)) nonneg = false;
             }
-        const uint64_t cap = E + p.NS + 128;
-        const size_t need = ((2 * (size_t)cap + 255) & ~(size_t)255) + 8 * (size_t)cap;
-        if (nonneg && need <= p.sev.bytes) {
-            p.narrow = true;
-            p.st_cap = cap;
-        }
+        p.narrow = nonneg;
+    }
+    // stream slices: a share of each super-tile's in-edges (all of them would cover the
+    // worst case, every edge firing in one pass; a bin at 15 Hz fills about 1.5 %), even
+    // sized for the narrow records (the bucketing copies record pairs)
+    if (opts.stream_permille > 1000) return "stream_permille must lie in 0..1000";
+    p.st_permille = opts.stream_permille ? opts.stream_permille : kStreamPermille;
+    p.st_len.assign(p.NS, 0);
+    p.st_total = 0;
+    for (uint32_t x = 0; x < p.NS; x++) {
+        uint64_t in = 0;
+        for (uint32_t t = x << p.ts_bits; t < std::min<uint32_t>(p.T, (x + 1) << p.ts_bits); t++) in += tin[t];
+        uint64_t len = (in * p.st_permille + 999) / 1000;
+        if (!opts.stream_permille) len = std::max(len, std::min<uint64_t>(in, kStreamFloor));
+        len = std::max<uint64_t>(len, 2);
+        if (p.narrow) len = (len + 1) & ~1ull;
+        p.st_len[x] = len;
+        p.st_total += len;
+    }
+    // 64 spare bytes: the partition kernels copy 8-byte records with 12-byte reads
+    p.st_cap = p.narrow ? p.st_total + 128 : 0;
+    if (p.blocked) {
+        slot(p.sev, 16);
+    } else {
+        size_t sb = p.narrow ? ((2 * (size_t)p.st_cap + 255) & ~(size_t)255) + 8 * (size_t)p.st_cap
+                             : 4 * (size_t)(1 + p.KW) * p.st_total + 64;
+        // the thread-per-target generator's batches of up to 2^20 targets, within the
+        // worst-case stream size
+        if (gen_threads)
+            sb = std::max(sb, std::min(4 * (size_t)(1 + p.KW) * E + 64, gen_sw * std::min<size_t>(N, 1u << 20)));
+        slot(p.sev, sb);
     }
     p.n_grp = (p.n_blocks + 255) / 256;
     slot(p.stage, 4 * (size_t)p.n_blocks * kNeuronBlock);
@@ -456,42 +500,27 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     p.dev_build = false;
     p.gen_batch = 0;
     p.gl = Plan::GenLayout{};
-    // the device checks nothing it could report before the first bin, so the fixed-point
-    // range of the weights (|w| 2^F < 2^52) is bounded here from the distributions' limits;
-    // a description that may exceed it is built and checked exactly on the host
-    bool wfit = true;
-    for (const auto& d : mem.m)
-        for (uint32_t j = 0; j < d.n_projs; j++) {
-            const dbnet_proj& pr = d.projs[j];
-            const double a = std::max(std::fabs((double)pr.w_a), pr.w_dist == DBNET_W_CONST ? 0.0 : std::fabs((double)pr.w_b));
-            const double sc = std::max(std::fabs((double)pr.w_scale_exc), std::fabs((double)pr.w_scale_inh));
-            if (!(a * sc * (1.0 + 0x1p-20) < std::ldexp(1.0, 52 - (int)p.F))) wfit = false;
-        }
-    if (!p.blocked && !(opts.flags & DBSIM_F_HOST_BUILD) && p.E > 0 && wfit) {
-        HostTables gt;
-        if (make_gen_tables(mem, gt).empty()) {
-            size_t o = 0;
-            auto take = [&](size_t bytes) {
-                const size_t at = o;
-                o += (bytes + 255) & ~(size_t)255;
-                return at;
-            };
-            Plan::GenLayout& g = p.gl;
-            g.tables = take(gen_tables_bytes(gt));
-            g.cnt = take(4 * (size_t)N * p.D);
-            g.cur = take(8 * (size_t)N * p.D);
-            g.rowlen = take(8 * (N + 1));
-            g.rowptr = take(8 * (N + 1));
-            g.sums = take(8 * (N / 1024 + 2));
-            g.tb = take(E);
-            g.flags = take(16);
-            g.end = o;
-            const size_t sw = 4 * (size_t)gen_scratch_words(gt.gkmax, gt.ghcap);
-            const uint64_t batch = std::min<uint64_t>({(uint64_t)N, p.sev.bytes / sw, 1ull << 20});
-            if (g.end <= p.ev.bytes && batch >= std::min<uint64_t>(N, 4096)) {
-                p.dev_build = true;
-                p.gen_batch = (uint32_t)batch;
-            }
+    if (gen_ok) {
+        size_t o = 0;
+        auto take = [&](size_t bytes) {
+            const size_t at = o;
+            o += (bytes + 255) & ~(size_t)255;
+            return at;
+        };
+        Plan::GenLayout& g = p.gl;
+        g.tables = take(gen_tables_bytes(gt));
+        g.cnt = take(4 * (size_t)N * p.D);
+        g.cur = take(8 * (size_t)N * p.D);
+        g.rowlen = take(8 * (N + 1));
+        g.rowptr = take(8 * (N + 1));
+        g.sums = take(8 * (N / 1024 + 2));
+        g.tb = take(E);
+        g.flags = take(16);
+        g.end = o;
+        const uint64_t batch = std::min<uint64_t>({(uint64_t)N, p.sev.bytes / gen_sw, 1ull << 20});
+        if (g.end <= p.ev.bytes && batch >= std::min<uint64_t>(N, 4096)) {
+            p.dev_build = true;
+            p.gen_batch = (uint32_t)batch;
         }
     }
     return "";
@@ -610,15 +639,9 @@ std::string build_tables(const Members& mem, const Plan& p, unsigned threads, Ho
         }
     });
 
-    // super-tile stream slices: the sum of their tiles' slices
+    // super-tile stream slices (the plan's sizes, one after another)
     h.st_base.assign((size_t)p.NS + 1, 0ull);
-    for (uint32_t x = 0; x <= p.NS; x++) h.st_base[x] = h.tile_base[std::min<uint64_t>((uint64_t)x << p.ts_bits, p.T)];
-    if (p.narrow) // slices start at even records (the bucketing copies record pairs)
-        for (uint32_t x = 0, add = 0; x < p.NS; x++) {
-            const uint64_t len = h.st_base[x + 1] + add - h.st_base[x];
-            if (len & 1) add++;
-            h.st_base[x + 1] += add;
-        }
+    for (uint32_t x = 0; x < p.NS; x++) h.st_base[x + 1] = h.st_base[x] + p.st_len[x];
     if (!with_edges) return make_gen_tables(mem, h);
 
     size_t scratch_bytes = 0;

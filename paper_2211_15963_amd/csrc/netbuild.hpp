@@ -41,7 +41,10 @@ struct Plan {
     uint32_t n_grp = 0; // compaction groups (256 consecutive neuron blocks each)
     bool blocked = false;         // single-pass fan-in into tile blocks (else two passes)
     bool narrow = false;          // two-pass form with 10-byte stream records
-    uint64_t st_cap = 0;          // narrow: stream record capacity (padded slices and a margin)
+    uint32_t st_permille = 0;     // stream slice per super-tile, in thousandths of its in-edges
+    std::vector<uint64_t> st_len; // records of every super-tile's stream slice [NS]
+    uint64_t st_total = 0;        // their sum
+    uint64_t st_cap = 0;          // narrow: stream record capacity (the slices and a margin)
     uint32_t NS = 0, ts_bits = 0; // super-tiles, log2(tiles per super-tile) of the two-pass form
     std::vector<uint64_t> tile_blk; // single-pass form: first block of every tile [T + 1]
     uint32_t HW = 0;              // words per row header

@@ -53,9 +53,9 @@ int main(void) {
   P(dbnet_pop); P(dbnet_proj); P(dbnet_desc); P(dbsim_desc); P(dbsim_stats); P(dbsim_info);
   O(dbnet_desc, seed); O(dbnet_desc, pops); O(dbnet_desc, region_xyz_mm);
   O(dbsim_desc, net); O(dbsim_desc, spike_record_capacity); O(dbsim_desc, hip_stream); O(dbsim_desc, flags);
-  O(dbsim_desc, host_spike_capacity);
-  O(dbsim_stats, ms_scatter); O(dbsim_stats, build_seconds); O(dbsim_info, frac_bits); O(dbsim_info, n_members);
-  O(dbsim_info, fanin_passes);
+  O(dbsim_desc, host_spike_capacity); O(dbsim_desc, stream_permille);
+  O(dbsim_stats, ms_scatter); O(dbsim_stats, build_seconds); O(dbsim_stats, spilled_events);
+  O(dbsim_info, frac_bits); O(dbsim_info, n_members); O(dbsim_info, fanin_passes); O(dbsim_info, stream_records);
   P(dbsim_member); O(dbsim_member, first_region);
   P(dbsim_bold_params); O(dbsim_bold_params, activity_scale); O(dbsim_bold_params, tr_bins);
   return 0;
@@ -82,7 +82,10 @@ def test_struct_layouts_match_ctypes(L):
     assert int(out["dbsim_desc.hip_stream"]) == D.SimDesc.hip_stream.offset
     assert int(out["dbsim_desc.flags"]) == D.SimDesc.flags.offset
     assert int(out["dbsim_desc.host_spike_capacity"]) == D.SimDesc.host_spike_capacity.offset
+    assert int(out["dbsim_desc.stream_permille"]) == D.SimDesc.stream_permille.offset
     assert int(out["dbsim_stats.ms_scatter"]) == D.SimStats.ms_scatter.offset
+    assert int(out["dbsim_stats.spilled_events"]) == D.SimStats.spilled_events.offset
+    assert int(out["dbsim_info.stream_records"]) == D.SimInfo.stream_records.offset
     assert int(out["dbsim_info.frac_bits"]) == D.SimInfo.frac_bits.offset
     assert int(out["dbsim_info.n_members"]) == D.SimInfo.n_members.offset
     assert int(out["dbsim_info.fanin_passes"]) == D.SimInfo.fanin_passes.offset
@@ -128,15 +131,50 @@ def test_null_arguments(L):
     assert L.dbsim_sync(None) == D.EINVAL
 
 
+def _stream_records(n, k, permille=0, tile=4096, even=True):
+    """Records of the super-tile streams of a one-population network of n neurons with
+    in-degree k (at most 64 super-tiles, so one tile each up to 64 tiles): a share of each
+    super-tile's in-edges, by default 1/8 and at least 2^20 records (or all of them)."""
+    T = (n + tile - 1) // tile
+    per = 1
+    while (T + per - 1) // per > 64:
+        per *= 2
+    total = 0
+    for x in range((T + per - 1) // per):
+        lo, hi = x * per * tile, min(n, (x + 1) * per * tile)
+        inn = k * (hi - lo)
+        ln = -(-inn * (permille or 125) // 1000)
+        if not permille:
+            ln = max(ln, min(inn, 1 << 20))
+        ln = max(ln, 2)
+        total += ln + (ln & 1 if even else 0)
+    return total
+
+
 def test_footprint_matches_layout(L):
     from paper_2211_15963_amd import dbsim as D
     s = configs.share(n=100000, indegree=556)
     E = s.num_edges()
     assert E == 100000 * 556
-    # default, two passes: 12 B edge records (target and two weights), 12 B super-tile stream
-    # records and 10 B tile arena records (2 B key beside the weights) per edge
+    # default, two passes: 12 B edge records (target and two weights), 10 B tile arena
+    # records (2 B key beside the weights) per edge, and 10 B narrow super-tile stream
+    # records for a share of each super-tile's in-edges
     fp = D.footprint(s)
-    assert 34 * E < fp < 34 * E + 60 * 100000 + (64 << 20)
+    st = 10 * _stream_records(100000, 556)
+    assert st < 10 * E // 2
+    assert 22 * E + st < fp < 22 * E + st + 60 * 100000 + (64 << 20)
+    # streams for every edge (the worst case: all of them firing in one pass)
+    fpw = D.footprint(s, stream_permille=1000)
+    assert 32 * E < fpw < 32 * E + 60 * 100000 + (64 << 20)
+    assert abs((fpw - fp) - 10 * (E - _stream_records(100000, 556))) < 4096
+    # 12 B stream records where a weight may be negative
+    neg = configs.share(n=100000, indegree=556)
+    neg.projs[0].w_scale_inh = -4.0
+    fpn = D.footprint(neg, stream_permille=250)
+    st = 12 * _stream_records(100000, 556, 250, even=False)
+    assert 22 * E + st < fpn < 22 * E + st + 60 * 100000 + (64 << 20)
+    with pytest.raises(D.DbsimError, match="stream_permille"):
+        D.footprint(s, stream_permille=1001)
     # single pass: the 12 B edge records and the event arena of 256-record blocks (2 B key +
     # 8 B weights + a 4 B count per block): every one of the 25 tiles of 4096 neurons gets its
     # in-degree in whole blocks plus two part-filled blocks per workgroup (at most 512) and bin
@@ -155,7 +193,8 @@ def test_footprint_matches_layout(L):
     # (D + 1) N entries rounded up to a power of two
     assert lo < fp1 < lo + 220 * 6100000 + (64 << 20)
     fp2 = D.footprint(s)
-    assert 34 * E < fp2 < 34 * E + 220 * 6100000 + (64 << 20)
+    st = 10 * _stream_records(6100000, 20)
+    assert 22 * E + st < fp2 < 22 * E + st + 220 * 6100000 + (64 << 20)
 
 
 def test_ensemble_footprint_and_validation(L):

@@ -257,6 +257,33 @@ def test_stream_record_formats(Sim):
     sim.close()
 
 
+@pytest.mark.parametrize("negative", [False, True])
+def test_full_streams_spill_to_arena(Sim, negative):
+    """Super-tile streams smaller than a pass's events: with one in a thousand of each
+    super-tile's in-edges nearly every run finds its stream full and goes to the tile arena
+    event by event; with one in a hundred only some do. Both equal the oracle bit for bit, in
+    both stream record formats."""
+    spec = configs.share(n=20000, indegree=300, seed=63)
+    if negative:
+        for p in spec.projs:
+            p.w_a = -0.25
+    orc = Oracle(spec, 32)
+    orc.step(300)
+    for permille in (1, 10):
+        _say(f"share 20000 / k300 seed 63, negative weights {negative}, stream_permille {permille}, 300 steps")
+        sim = Sim(spec, stream_permille=permille)
+        assert sim.info.stream_record_bytes == (12 if negative else 10)
+        E = spec.num_edges()
+        assert sim.info.stream_records <= E * permille // 1000 + 64
+        sim.step(300)
+        st = sim.stats()
+        assert st["spilled_events"] > 0
+        if permille == 10:
+            assert st["spilled_events"] < st["edge_events"]
+        _compare(sim, orc, spec)
+        sim.close()
+
+
 @pytest.mark.parametrize("single_pass", [False, True])
 def test_fanin_schedules_agree(Sim, single_pass):
     """Every partition schedule gives the same bits (exact integer arrival sums)."""
