@@ -89,7 +89,14 @@ typedef struct dbsim_desc {
                                        in-edges, if fewer). Runs that find their stream full
                                        go straight to the tile arena, one atomic per event:
                                        slower, same results (dbsim_stats.spilled_events). */
-    uint32_t reserved;              /* 0 */
+    uint32_t arena_permille;        /* two-pass form: records each tile's arena slice holds per
+                                       bin, in thousandths of the tile's in-edges (1..1000;
+                                       1000 = every edge, the most one bin can deliver). 0 =
+                                       125, and at least 2^16 records (or all in-edges, if
+                                       fewer). Events that find their slice full are summed
+                                       into an exact int64 accumulator per target with one
+                                       atomic each: slower, same results
+                                       (dbsim_stats.overflow_events). */
 } dbsim_desc;
 
 /* flags */
@@ -120,8 +127,11 @@ typedef struct dbsim_stats {
     double build_seconds;  /* time spent constructing the network: the host phase, plus the
                               device construction of the connection table where it ran (its
                               duration is added at the first synchronisation after create) */
-    uint64_t spilled_events; /* events of completed bins that found their super-tile stream
-                                full and were placed in the tile arena directly */
+    uint64_t spilled_events;  /* partitioned events (this handle's bins, and the next bin's
+                                 part assembled ahead) that found their super-tile stream
+                                 full and were placed in the tile arena directly */
+    uint64_t overflow_events; /* likewise, events that found their tile's arena slice full
+                                 and were summed into the per-target accumulator */
 } dbsim_stats;
 
 typedef struct dbsim_info {
@@ -143,6 +153,8 @@ typedef struct dbsim_info {
     uint32_t reserved;
     uint64_t stream_records;   /* records the super-tile streams hold in all (0 in the
                                   single-pass form) */
+    uint64_t arena_records;    /* records the tile arena holds in all (two-pass form; the
+                                  single-pass form's blocks otherwise) */
 } dbsim_info;
 
 typedef struct dbsim_member {

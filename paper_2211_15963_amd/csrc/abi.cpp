@@ -203,6 +203,7 @@ void fill_devnet(dbsim* h) {
     n.evk = at<uint16_t>(b, p.evk);
     n.bcnt = at<uint32_t>(b, p.bcnt);
     n.tile_base = at<const uint64_t>(b, p.tile_base);
+    n.ovf = at<unsigned long long>(b, p.ovf);
     n.tile_fill = at<uint32_t>(b, p.tile_fill);
     n.st_base = at<const uint64_t>(b, p.st_base);
     n.st_fill = at<uint32_t>(b, p.st_fill);
@@ -716,6 +717,7 @@ static int deploy_impl(dbsim_built* bt, const dbsim_desc* dev_opts, dbsim** out)
         if (e == hipSuccess && !p.dev_build) e = up(p.edge, ht.edge.get(), 4 * ht.edge_words);
         if (e == hipSuccess) e = up(p.tile_base, ht.tile_base.data(), 8 * ht.tile_base.size());
         if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.tile_fill.off, 0, p.tile_fill.bytes, h->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.ovf.off, 0, p.ovf.bytes, h->stream);
         if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.grp_cnt.off, 0, p.grp_cnt.bytes, h->stream);
         if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.bin_start.off, 0, p.bin_start.bytes, h->stream);
         if (e == hipSuccess) e = hipMemsetAsync(h->dev + p.bin_cnt.off, 0, p.bin_cnt.bytes, h->stream);
@@ -885,6 +887,7 @@ int dbsim_get_info(dbsim* h, dbsim_info* info) {
     info->device_built = h->device_built ? 1u : 0u;
     info->stream_record_bytes = p.blocked ? 0u : p.narrow ? 10u : 4u * (1u + p.KW);
     info->stream_records = p.blocked ? 0u : p.st_total;
+    info->arena_records = p.blocked ? (uint64_t)p.tile_blk[p.T] * kFanBlock : p.ta_total;
     return DBSIM_OK;
 }
 
@@ -1790,6 +1793,7 @@ int dbsim_get_stats(dbsim* h, dbsim_stats* s) {
     s->ms_readout = h->ms[3];
     s->build_seconds = h->build_seconds;
     s->spilled_events = c.spilled;
+    s->overflow_events = c.overflow;
     return DBSIM_OK;
 }
 

@@ -52,11 +52,13 @@ constexpr int kScatterSegs = 512;     // (spike, delay) segments per partition c
 constexpr int kGatherThreads = 1024;
 constexpr int kMaxTilesLds = 16384;   // most tiles (at most 256 buckets in the second partition pass)
 constexpr uint32_t kTileLdsBytes = 128u * 1024u; // LDS accumulator per tile
-constexpr uint32_t kErrArena = 1u;    // arena slice overflow (cannot happen by construction)
+constexpr uint32_t kErrArena = 1u;    // single-pass block arena overflow (cannot happen by construction)
 constexpr uint32_t kErrLayout = 2u;   // a table entry outside its tile group (cannot happen by construction)
 constexpr uint32_t kMaxSuperTiles = 64; // buckets of the first partition pass
 constexpr uint32_t kStreamPermille = 125; // default stream slice: 1/8 of the super-tile's in-edges,
 constexpr uint64_t kStreamFloor = 1ull << 20; // and at least this many records (or all of them)
+constexpr uint32_t kArenaPermille = 125;  // default tile arena slice: 1/8 of the tile's in-edges,
+constexpr uint64_t kArenaFloor = 1ull << 16; // and at least this many records (or all of them)
 constexpr uint32_t kBoldRing = 1024;     // BOLD samples kept per region (power of two)
 constexpr int kLoadBatch = 8;          // gather: records loaded per thread before they are consumed
 constexpr int kMaxBatch = 8;           // partition: events per thread per round
@@ -98,6 +100,7 @@ struct Ctl {
     unsigned long long pnext;        // next k_part chunk to hand out (work queue)
     unsigned long long inject_until; // output spikes are injected in bins below this one
     unsigned long long spilled;      // partitioned events whose super-tile stream was full
+    unsigned long long overflow;     // events whose tile arena slice was full (summed in ovf)
 };
 
 struct DevNet {
@@ -135,12 +138,15 @@ struct DevNet {
     const uint32_t* edge; // [E][1 + KW] records: the weights, then target | inhibitory source << 31
     // event arena: keys evk (target within tile | inhibitory source << 15) beside the weights
     // ev (KW floats per record). Two-pass form: tile t's slice tile_base[t] .. tile_base[t+1],
-    // tile_fill[t] records this bin. Single-pass form: blocks of fan_K records; tile t owns
-    // blocks tile_base[t] .. tile_base[t+1], tile_fill[t] of them taken this bin, bcnt[b]
-    // records in b.
+    // tile_fill[t] records reserved this bin, tile_fill[T + t] the complement of the first
+    // reservation that did not fit (0: none), whose events were summed into ovf (int64 fixed
+    // point, [N][U], zero again after the tile's gather). Single-pass form: blocks of fan_K
+    // records; tile t owns blocks tile_base[t] .. tile_base[t+1], tile_fill[t] of them taken
+    // this bin, bcnt[b] records in b.
     uint32_t* ev;
     uint16_t* evk;
     uint32_t* bcnt;
+    unsigned long long* ovf;
     const uint64_t* tile_base;
     uint32_t* tile_fill;
     const uint64_t* st_base; // super-tile stream slices [NS + 1]

@@ -291,19 +291,17 @@ __device__ __forceinline__ void store_record(uint32_t* out, unsigned long long p
         reinterpret_cast<uint2*>(out)[pos] = make_uint2(key, __float_as_uint(w.x));
 }
 
-constexpr unsigned long long kSpillRun = ~1ull; // gbase of a run whose stream is full
+constexpr unsigned long long kSpillRun = ~1ull; // gbase of a run whose slice is full
 
 // Runs (unbuffered): one reservation per non-empty bucket in out_fill (slice of bucket b:
-// out_base[b0+b] .. out_base[b0+b+1]); sets gbase and the sorted starts. A tile arena slice
-// holds every event its tile can receive (overflow is an error that cannot happen); a
-// super-tile stream (SPILL) holds a share of them: a run that does not fit is marked
-// kSpillRun, and the stream's valid records end at the first such reservation, kept as
-// the largest ~base in out_fill[NS + b] (the reservations that fit are exactly those
-// before it, since the fill only grows).
-// Returns whether a run of the round was marked (the same on every thread).
-template <bool SPILL>
+// out_base[b0+b] .. out_base[b0+b+1]); sets gbase and the sorted starts. A slice holds a
+// share of the events its bucket can receive in a pass (super-tile streams) or a bin (tile
+// arena): a run that does not fit is marked kSpillRun and counted in *marked, and the
+// slice's valid records end at the first such reservation, kept as the largest ~base in
+// out_fill[nlim + b0 + b] (the reservations that fit are exactly those before it, since
+// the fill only grows). Returns whether a run of the round was marked (on every thread).
 __device__ bool reserve_runs(const DevNet& net, Round& R, uint32_t nb, uint32_t b0, const uint64_t* out_base,
-                             uint32_t* out_fill) {
+                             uint32_t* out_fill, uint32_t nlim, unsigned long long* marked) {
     int spilled = 0;
     for (uint32_t t = threadIdx.x; t < nb; t += kScatterThreads) {
         const uint32_t h = R.hist[t];
@@ -313,29 +311,37 @@ __device__ bool reserve_runs(const DevNet& net, Round& R, uint32_t nb, uint32_t 
             const unsigned long long s0 = out_base[b0 + t];
             if ((unsigned long long)base + h <= out_base[b0 + t + 1] - s0) {
                 gb = s0 + base;
-            } else if (SPILL) {
-                atomicMax(&out_fill[net.NS + b0 + t], ~base);
-                atomicAdd(&net.ctl->spilled, (unsigned long long)h);
+            } else {
+                atomicMax(&out_fill[nlim + b0 + t], ~base);
+                atomicAdd(marked, (unsigned long long)h);
                 gb = kSpillRun;
                 spilled = 1;
-            } else {
-                atomicOr(&net.ctl->err, kErrArena);
             }
         }
         R.gbase[t] = gb;
         R.lstart[t] = h;
     }
-    const bool any = SPILL ? __syncthreads_or(spilled) != 0 : false;
-    if (!SPILL) __syncthreads();
+    const bool any = __syncthreads_or(spilled) != 0;
     block_scan_inplace(R.lstart, nb, R.s_wave);
     __syncthreads();
     return any;
 }
 
-// An event whose super-tile stream was full goes straight to its tile's arena slice, with
-// one atomic for its place (the bucketing of the stream's records reserves after it).
+// An event past its tile's arena slice: its fixed-point weights are added to the target's
+// per-receptor sums in ovf (one atomic each; exact in any order), which the tile's gather
+// adds to the slice's sums.
 template <int KW>
-__device__ void spill_event(const DevNet& net, uint32_t key, float2 w) {
+__device__ void overflow_event(const DevNet& net, uint32_t tgt, uint32_t inh, float2 w) {
+    unsigned long long* o = net.ovf + (size_t)tgt * (2 * KW) + (inh ? KW : 0);
+    atomicAdd(o, quant(w.x, net.qscale));
+    if (KW == 2) atomicAdd(o + 1, quant(w.y, net.qscale));
+}
+
+// An event whose super-tile stream was full goes straight to its tile's arena slice, with
+// one atomic for its place (the bucketing of the stream's records reserves after it), or,
+// if that is full too, to the overflow sums. Returns whether it overflowed.
+template <int KW>
+__device__ bool spill_event(const DevNet& net, uint32_t key, float2 w) {
     const uint32_t tgt = key & 0x7FFFFFFFu, t = tgt >> net.tile_bits;
     const uint32_t slot = atomicAdd(&net.tile_fill[t], 1u);
     const unsigned long long s0 = net.tile_base[t];
@@ -344,9 +350,11 @@ __device__ void spill_event(const DevNet& net, uint32_t key, float2 w) {
         net.evk[pos] = (uint16_t)((tgt & ((1u << net.tile_bits) - 1u)) | ((key >> 31) << 15));
         if (KW == 2) reinterpret_cast<float2*>(net.ev)[pos] = w;
         else reinterpret_cast<float*>(net.ev)[pos] = w.x;
-    } else {
-        atomicOr(&net.ctl->err, kErrArena);
+        return false;
     }
+    atomicMax(&net.tile_fill[net.T + t], ~slot);
+    overflow_event<KW>(net, tgt, key >> 31, w);
+    return true;
 }
 
 // consecutive threads write consecutive records of a bucket's run (SPILL: some runs of the
@@ -354,13 +362,15 @@ __device__ void spill_event(const DevNet& net, uint32_t key, float2 w) {
 template <int KW, bool SPILL>
 __device__ void write_runs(const DevNet& net, Round& R, uint32_t ne, uint32_t nb, uint32_t b0, uint32_t bshift,
                            uint32_t* out) {
+    uint32_t nov = 0;
     for (uint32_t q = threadIdx.x; q < ne; q += kScatterThreads) {
         const uint32_t key = R.s_key[q];
         const uint32_t b = bucket_of(net, key, nb, b0, bshift);
         const unsigned long long gb = R.gbase[b];
-        if (SPILL && gb == kSpillRun) spill_event<KW>(net, key, R.s_w[q]);
+        if (SPILL && gb == kSpillRun) nov += spill_event<KW>(net, key, R.s_w[q]) ? 1u : 0u;
         else if (gb != ~0ull) store_record<KW>(out, gb + (q - R.lstart[b]), key, R.s_w[q]);
     }
+    if (SPILL && nov) atomicAdd(&net.ctl->overflow, (unsigned long long)nov);
     __syncthreads();
 }
 
@@ -370,12 +380,13 @@ __device__ void write_runs(const DevNet& net, Round& R, uint32_t ne, uint32_t nb
 template <bool SPILL>
 __device__ void write_runs_narrow(const DevNet& net, Round& R, uint32_t ne, uint32_t nb, uint32_t bshift) {
     const uint32_t smask = (1u << (net.tile_bits + net.ts_bits)) - 1u;
+    uint32_t nov = 0;
     for (uint32_t q = threadIdx.x; q < ne; q += kScatterThreads) {
         const uint32_t key = R.s_key[q];
         const uint32_t b = bucket_of(net, key, nb, 0, bshift);
         const unsigned long long gb = R.gbase[b];
         if (SPILL && gb == kSpillRun) {
-            spill_event<2>(net, key, R.s_w[q]);
+            nov += spill_event<2>(net, key, R.s_w[q]) ? 1u : 0u;
         } else if (gb != ~0ull) {
             const unsigned long long pos = gb + (q - R.lstart[b]);
             const uint32_t loc = key & smask;
@@ -384,19 +395,24 @@ __device__ void write_runs_narrow(const DevNet& net, Round& R, uint32_t ne, uint
             net.sevw[pos] = make_uint2(__float_as_uint(w.x) | (key & 0x80000000u), __float_as_uint(w.y) | ((loc >> 16) << 31));
         }
     }
+    if (SPILL && nov) atomicAdd(&net.ctl->overflow, (unsigned long long)nov);
     __syncthreads();
 }
 
 // The tile arena's records: a 16-bit key (target within the tile | inhibitory source << 15)
 // in evk beside the weights in ev, consecutive threads writing consecutive records of a run.
-template <int KW>
-__device__ void write_runs_arena(const DevNet& net, Round& R, uint32_t ne, uint32_t nb, uint32_t b0) {
+// SPILL: some runs of the round are marked; their events go to the overflow sums (target =
+// tbase + the key's target field: the super-tile's first neuron for the narrow stream keys).
+template <int KW, bool SPILL>
+__device__ void write_runs_arena(const DevNet& net, Round& R, uint32_t ne, uint32_t nb, uint32_t b0, uint32_t tbase) {
     const uint32_t lmask = (1u << net.tile_bits) - 1u;
     for (uint32_t q = threadIdx.x; q < ne; q += kScatterThreads) {
         const uint32_t key = R.s_key[q];
         const uint32_t b = bucket_of(net, key, nb, b0, net.tile_bits);
         const unsigned long long gb = R.gbase[b];
-        if (gb != ~0ull) {
+        if (SPILL && gb == kSpillRun) {
+            overflow_event<KW>(net, tbase + (key & 0x7FFFFFFFu), key >> 31, R.s_w[q]);
+        } else if (gb != ~0ull) {
             const unsigned long long pos = gb + (q - R.lstart[b]);
             net.evk[pos] = (uint16_t)((key & lmask) | ((key >> 31) << 15));
             if (KW == 2) reinterpret_cast<float2*>(net.ev)[pos] = R.s_w[q];
@@ -541,7 +557,7 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
             // reservations (one wait for both)
             unsigned long long claim = 0;
             if (tid == 0 && r0 == 0) claim = atomicAdd(&net.ctl->pnext, 1ull);
-            const bool spill = reserve_runs<true>(net, R, nb, 0, net.st_base, net.st_fill);
+            const bool spill = reserve_runs(net, R, nb, 0, net.st_base, net.st_fill, net.NS, &net.ctl->spilled);
             place_batch(R, B, ne, nbt);
             if (tid == 0 && r0 == 0) s_pc = G + claim; // read by every thread at the end of the chunk
             __syncthreads();
@@ -674,11 +690,13 @@ __global__ void __launch_bounds__(kScatterThreads) k_bucket(DevNet net) {
         // the claim travels with wavefront 0's reservations (one wait for both)
         unsigned long long claim = 0;
         if (tid == 0 && cn < nchunks) claim = atomicAdd(&net.ctl->bnext, 1ull);
-        reserve_runs<false>(net, R, nt, t0, net.tile_base, net.tile_fill);
+        const bool spill = reserve_runs(net, R, nt, t0, net.tile_base, net.tile_fill, net.T, &net.ctl->overflow);
         place_batch(R, B, ne, nbt);
         if (tid == 0) s_claim = cn < nchunks ? 2ull * G + claim : ~0ull;
         __syncthreads();
-        write_runs_arena<KW>(net, R, ne, nt, narrow ? 0u : t0);
+        const uint32_t tbase = narrow ? st << (net.tile_bits + net.ts_bits) : 0u;
+        if (spill) write_runs_arena<KW, true>(net, R, ne, nt, narrow ? 0u : t0, tbase);
+        else write_runs_arena<KW, false>(net, R, ne, nt, narrow ? 0u : t0, tbase);
         c = cn;
         cn = s_claim;
     }
@@ -1039,7 +1057,11 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(DevNet net) {
     for (uint32_t x = threadIdx.x; x < nt * U; x += blockDim.x) acc[x] = 0ull;
     __syncthreads();
     const unsigned long long b0 = net.tile_base[t];
-    const uint32_t cnt = (uint32_t)min((unsigned long long)net.tile_fill[t], net.tile_base[t + 1] - b0);
+    // the slice's records: the reservations before the first that did not fit (lim != 0),
+    // whose events and all after it were summed in ovf
+    const uint32_t lim = net.tile_fill[net.T + t];
+    const uint32_t f = lim ? min(net.tile_fill[t], ~lim) : net.tile_fill[t];
+    const uint32_t cnt = (uint32_t)min((unsigned long long)f, net.tile_base[t + 1] - b0);
     const double qs = net.qscale;
     const uint16_t* kk = net.evk + b0;
     for (uint32_t eb = 0; eb < cnt; eb += kLoadBatch * blockDim.x) {
@@ -1066,7 +1088,18 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(DevNet net) {
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) net.tile_fill[t] = 0;
+    if (lim) { // the overflow sums of the tile's targets, cleared for the next bin
+        unsigned long long* o = net.ovf + (size_t)i0 * U;
+        for (uint32_t x = threadIdx.x; x < nt * U; x += blockDim.x) {
+            acc[x] += o[x];
+            o[x] = 0ull;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        net.tile_fill[t] = 0;
+        net.tile_fill[net.T + t] = 0;
+    }
     // the super-tile streams are empty again: this bin's delay-1 records are in the tile
     // arena, and the next bin's delay >= 2 records start from the front (the bin close
     // clears them again after those have been bucketed)

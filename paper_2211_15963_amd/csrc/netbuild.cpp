@@ -398,6 +398,40 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     // before the first bin); the wavefront generator needs none
     const size_t gen_sw = gen_ok ? 4 * (size_t)gen_scratch_words(gt.gkmax, gt.ghcap) : 1;
     const bool gen_threads = gen_ok && gen_wave_lds(gt.gkmax, gt.ghcap) > kGenWaveLds;
+    // the construction's temporaries in the arena's weight slot (free before the first bin)
+    p.gl = Plan::GenLayout{};
+    if (gen_ok) {
+        size_t o = 0;
+        auto take = [&](size_t bytes) {
+            const size_t at = o;
+            o += (bytes + 255) & ~(size_t)255;
+            return at;
+        };
+        Plan::GenLayout& g = p.gl;
+        g.tables = take(gen_tables_bytes(gt));
+        g.cnt = take(4 * (size_t)N * p.D);
+        g.cur = take(8 * (size_t)N * p.D);
+        g.rowlen = take(8 * (N + 1));
+        g.rowptr = take(8 * (N + 1));
+        g.sums = take(8 * (N / 1024 + 2));
+        g.tb = take(E);
+        g.flags = take(16);
+        g.end = o;
+    }
+    // tile arena slices of the two-pass form: a share of each tile's in-edges (all of them
+    // would cover the worst case, every edge firing in one bin; a bin at 15 Hz fills about
+    // 1.5 %); the events past a full slice go to the per-target overflow sums
+    if (opts.arena_permille > 1000) return "arena_permille must lie in 0..1000";
+    p.ta_permille = opts.arena_permille ? opts.arena_permille : kArenaPermille;
+    p.ta_len.assign(p.blocked ? 0 : p.T, 0);
+    p.ta_total = 0;
+    for (uint32_t t = 0; !p.blocked && t < p.T; t++) {
+        uint64_t len = (tin[t] * p.ta_permille + 999) / 1000;
+        if (!opts.arena_permille) len = std::max(len, std::min<uint64_t>(tin[t], kArenaFloor));
+        len = std::max<uint64_t>(len, 1);
+        p.ta_len[t] = len;
+        p.ta_total += len;
+    }
     slot(p.V, 4 * N);
     slot(p.J, 4 * U * N);
     slot(p.ref, N);
@@ -416,12 +450,15 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
         slot(p.evk, 2 * recs);
         slot(p.bcnt, 4 * (size_t)p.tile_blk[p.T]);
     } else { // records of a 16-bit key array beside the weights
-        slot(p.ev, 4 * (size_t)p.KW * E + 64);
-        slot(p.evk, 2 * E + 64);
+        slot(p.ev, std::max(4 * (size_t)p.KW * p.ta_total + 64, p.gl.end));
+        slot(p.evk, 2 * (size_t)p.ta_total + 64);
         slot(p.bcnt, 16);
     }
+    // per-target int64 sums of the events past their tile's arena slice ([N][U])
+    slot(p.ovf, p.blocked ? 16 : 8 * U * N);
     slot(p.tile_base, 8 * ((size_t)p.T + 1));
-    slot(p.tile_fill, 4 * (size_t)p.T);
+    // fill counters of the tiles, then the first failed reservation of each
+    slot(p.tile_fill, 8 * (size_t)p.T);
     // fill counters of the super-tile streams, then the first failed reservation of each
     slot(p.st_base, 8 * ((size_t)p.NS + 1));
     slot(p.st_fill, 8 * (size_t)p.NS + 4);
@@ -499,24 +536,8 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
     // the first bin), weights of exact double arithmetic, and room for the temporaries
     p.dev_build = false;
     p.gen_batch = 0;
-    p.gl = Plan::GenLayout{};
     if (gen_ok) {
-        size_t o = 0;
-        auto take = [&](size_t bytes) {
-            const size_t at = o;
-            o += (bytes + 255) & ~(size_t)255;
-            return at;
-        };
-        Plan::GenLayout& g = p.gl;
-        g.tables = take(gen_tables_bytes(gt));
-        g.cnt = take(4 * (size_t)N * p.D);
-        g.cur = take(8 * (size_t)N * p.D);
-        g.rowlen = take(8 * (N + 1));
-        g.rowptr = take(8 * (N + 1));
-        g.sums = take(8 * (N / 1024 + 2));
-        g.tb = take(E);
-        g.flags = take(16);
-        g.end = o;
+        const Plan::GenLayout& g = p.gl;
         const uint64_t batch = std::min<uint64_t>({(uint64_t)N, p.sev.bytes / gen_sw, 1ull << 20});
         if (g.end <= p.ev.bytes && batch >= std::min<uint64_t>(N, 4096)) {
             p.dev_build = true;
@@ -627,7 +648,7 @@ std::string build_tables(const Members& mem, const Plan& p, unsigned threads, Ho
     if (p.blocked) {
         h.tile_base = p.tile_blk;
     } else {
-        for (uint32_t t = 0; t < p.T; t++) h.tile_base[t + 1] += h.tile_base[t];
+        for (uint32_t t = 0; t < p.T; t++) h.tile_base[t + 1] = h.tile_base[t] + p.ta_len[t];
     }
 
     // initial membrane potentials

@@ -45,6 +45,9 @@ struct Plan {
     std::vector<uint64_t> st_len; // records of every super-tile's stream slice [NS]
     uint64_t st_total = 0;        // their sum
     uint64_t st_cap = 0;          // narrow: stream record capacity (the slices and a margin)
+    uint32_t ta_permille = 0;     // tile arena slice, in thousandths of the tile's in-edges
+    std::vector<uint64_t> ta_len; // records of every tile's arena slice [T] (two-pass form)
+    uint64_t ta_total = 0;        // their sum
     uint32_t NS = 0, ts_bits = 0; // super-tiles, log2(tiles per super-tile) of the two-pass form
     std::vector<uint64_t> tile_blk; // single-pass form: first block of every tile [T + 1]
     uint32_t HW = 0;              // words per row header
@@ -67,7 +70,7 @@ struct Plan {
     struct Slot {
         size_t off = 0, bytes = 0;
     };
-    Slot V, J, ref, pend, A, Iou, pops, ptab, blk, hdr, edge, ev, evk, bcnt, tile_base, tile_fill, st_base, st_fill,
+    Slot V, J, ref, pend, A, Iou, pops, ptab, blk, hdr, edge, ev, evk, bcnt, ovf, tile_base, tile_fill, st_base, st_fill,
         sev, stage,
         grp_cnt, rec, bin_start, bin_cnt, blk_sig, blk_cnt, reg_blk_ptr, reg_blk, reg_size, l1_ptr, l1_region, l1_sig,
         l1_cnt, sig, sig_cnt, bold_zs, bold, bold_y, bold_ctl, rblk, rpop, ctl;

@@ -42,7 +42,7 @@ class SimDesc(Structure):
                 ("spike_record_capacity", c_uint64), ("record_bins", c_uint32), ("device", c_int32),
                 ("hip_stream", c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_ctx", c_void_p),
                 ("host_threads", c_uint32), ("flags", c_uint32), ("host_spike_capacity", c_uint64),
-                ("stream_permille", c_uint32), ("reserved", c_uint32)]
+                ("stream_permille", c_uint32), ("arena_permille", c_uint32)]
 
 
 class SimStats(Structure):
@@ -50,7 +50,7 @@ class SimStats(Structure):
                 ("num_neurons", c_uint64), ("num_edges", c_uint64), ("hbm_bytes", c_uint64),
                 ("timed_bins", c_uint64), ("ms_scatter", c_double), ("ms_gather", c_double),
                 ("ms_neuron", c_double), ("ms_readout", c_double), ("build_seconds", c_double),
-                ("spilled_events", c_uint64)]
+                ("spilled_events", c_uint64), ("overflow_events", c_uint64)]
 
 
 class SimInfo(Structure):
@@ -58,7 +58,8 @@ class SimInfo(Structure):
                 ("weights_per_edge", c_uint32), ("steps_per_bin", c_uint32), ("max_delay", c_uint32),
                 ("n_regions", c_uint32), ("tile_neurons", c_uint32), ("n_tiles", c_uint32), ("frac_bits", c_uint32),
                 ("n_members", c_uint32), ("fanin_passes", c_uint32), ("device_built", c_uint32),
-                ("stream_record_bytes", c_uint32), ("reserved", c_uint32), ("stream_records", c_uint64)]
+                ("stream_record_bytes", c_uint32), ("reserved", c_uint32), ("stream_records", c_uint64),
+                ("arena_records", c_uint64)]
 
 
 class SimMember(Structure):
@@ -237,7 +238,8 @@ class _TorchAllocator:
 def make_desc(spec: NetSpec, record_regions: bool = True, spike_record_capacity: int = 0, record_bins: int = 0,
               device: int = -1, stream_handle: Optional[int] = None, allocator: Optional[_TorchAllocator] = None,
               host_threads: int = 0, no_graph: bool = False, single_pass: bool = False, host_record: bool = True,
-              host_spike_capacity: int = 0, host_build: bool = False, stream_permille: int = 0):
+              host_spike_capacity: int = 0, host_build: bool = False, stream_permille: int = 0,
+              arena_permille: int = 0):
     holder = spec.to_c()
     d = SimDesc()
     d.abi_version = ABI_VERSION
@@ -255,6 +257,7 @@ def make_desc(spec: NetSpec, record_regions: bool = True, spike_record_capacity:
                (0 if host_record else F_NO_HOST_RECORD) | (F_HOST_BUILD if host_build else 0))
     d.host_spike_capacity = int(host_spike_capacity)
     d.stream_permille = int(stream_permille)
+    d.arena_permille = int(arena_permille)
     return d, holder
 
 
@@ -324,13 +327,13 @@ class Built:
     def __init__(self, spec: NetSpec, record_regions: bool = True, spike_record_capacity: int = 0,
                  record_bins: int = 0, host_threads: Optional[int] = None, no_graph: bool = False,
                  single_pass: bool = False, host_record: bool = True, host_spike_capacity: int = 0,
-                 host_build: bool = False, stream_permille: int = 0):
+                 host_build: bool = False, stream_permille: int = 0, arena_permille: int = 0):
         if host_threads is None:
             host_threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
         self.spec = spec
         self._desc, self._holder = make_desc(spec, record_regions, spike_record_capacity, record_bins, -1, None, None,
                                              host_threads, no_graph, single_pass, host_record, host_spike_capacity,
-                                             host_build, stream_permille)
+                                             host_build, stream_permille, arena_permille)
         h = c_void_p()
         _check(lib().dbsim_build(byref(self._desc), byref(h)))
         self._b = h
@@ -369,6 +372,8 @@ class Simulator:
     stream_permille: records each super-tile stream holds per partition pass, in thousandths
     of its in-edges (0: the library default; 1000: every edge). Events that find their
     stream full are placed in the tile arena directly (stats()["spilled_events"]).
+    arena_permille: likewise for each tile's arena slice per bin; events that find it full
+    are summed into a per-target accumulator (stats()["overflow_events"]).
     built: deploy a network built on the host (Built, made from this same spec); the build's
     recording and form options apply, this call's device, stream and allocator.
     """
@@ -377,7 +382,7 @@ class Simulator:
                  spike_record_capacity: int = 0, record_bins: int = 0, host_threads: Optional[int] = None,
                  no_graph: bool = False, stream=None, single_pass: bool = False, static_region: bool = False,
                  host_record: bool = True, host_spike_capacity: int = 0, built: Optional["Built"] = None,
-                 host_build: bool = False, stream_permille: int = 0):
+                 host_build: bool = False, stream_permille: int = 0, arena_permille: int = 0):
         L = lib()
         if host_threads is None:
             # the process's CPU share (OMP_NUM_THREADS) rather than every core of the machine
@@ -398,7 +403,8 @@ class Simulator:
         first = self.specs[0]
         self._desc, self._holder = make_desc(first, record_regions, spike_record_capacity, record_bins, device,
                                              stream_handle, self._alloc, host_threads, no_graph, single_pass,
-                                             host_record, host_spike_capacity, host_build, stream_permille)
+                                             host_record, host_spike_capacity, host_build, stream_permille,
+                                             arena_permille)
         h = c_void_p()
         if isinstance(spec, (list, tuple)):
             self._members, self._member_holders = _member_array(self.specs)

@@ -53,9 +53,9 @@ int main(void) {
   P(dbnet_pop); P(dbnet_proj); P(dbnet_desc); P(dbsim_desc); P(dbsim_stats); P(dbsim_info);
   O(dbnet_desc, seed); O(dbnet_desc, pops); O(dbnet_desc, region_xyz_mm);
   O(dbsim_desc, net); O(dbsim_desc, spike_record_capacity); O(dbsim_desc, hip_stream); O(dbsim_desc, flags);
-  O(dbsim_desc, host_spike_capacity); O(dbsim_desc, stream_permille);
-  O(dbsim_stats, ms_scatter); O(dbsim_stats, build_seconds); O(dbsim_stats, spilled_events);
-  O(dbsim_info, frac_bits); O(dbsim_info, n_members); O(dbsim_info, fanin_passes); O(dbsim_info, stream_records);
+  O(dbsim_desc, host_spike_capacity); O(dbsim_desc, stream_permille); O(dbsim_desc, arena_permille);
+  O(dbsim_stats, ms_scatter); O(dbsim_stats, build_seconds); O(dbsim_stats, spilled_events); O(dbsim_stats, overflow_events);
+  O(dbsim_info, frac_bits); O(dbsim_info, n_members); O(dbsim_info, fanin_passes); O(dbsim_info, stream_records); O(dbsim_info, arena_records);
   P(dbsim_member); O(dbsim_member, first_region);
   P(dbsim_bold_params); O(dbsim_bold_params, activity_scale); O(dbsim_bold_params, tr_bins);
   return 0;
@@ -86,6 +86,9 @@ def test_struct_layouts_match_ctypes(L):
     assert int(out["dbsim_stats.ms_scatter"]) == D.SimStats.ms_scatter.offset
     assert int(out["dbsim_stats.spilled_events"]) == D.SimStats.spilled_events.offset
     assert int(out["dbsim_info.stream_records"]) == D.SimInfo.stream_records.offset
+    assert int(out["dbsim_desc.arena_permille"]) == D.SimDesc.arena_permille.offset
+    assert int(out["dbsim_stats.overflow_events"]) == D.SimStats.overflow_events.offset
+    assert int(out["dbsim_info.arena_records"]) == D.SimInfo.arena_records.offset
     assert int(out["dbsim_info.frac_bits"]) == D.SimInfo.frac_bits.offset
     assert int(out["dbsim_info.n_members"]) == D.SimInfo.n_members.offset
     assert int(out["dbsim_info.fanin_passes"]) == D.SimInfo.fanin_passes.offset
@@ -151,30 +154,53 @@ def _stream_records(n, k, permille=0, tile=4096, even=True):
     return total
 
 
+def _arena_records(n, k, permille=0, tile=4096):
+    """Records of the tile arena of a one-population network: a share of each tile's
+    in-edges, by default 1/8 and at least 2^16 records (or all of them)."""
+    total = 0
+    for lo in range(0, n, tile):
+        inn = k * (min(n, lo + tile) - lo)
+        ln = -(-inn * (permille or 125) // 1000)
+        if not permille:
+            ln = max(ln, min(inn, 1 << 16))
+        total += max(ln, 1)
+    return total
+
+
 def test_footprint_matches_layout(L):
     from paper_2211_15963_amd import dbsim as D
-    s = configs.share(n=100000, indegree=556)
+    n, k = 100000, 556
+    s = configs.share(n=n, indegree=k)
     E = s.num_edges()
-    assert E == 100000 * 556
-    # default, two passes: 12 B edge records (target and two weights), 10 B tile arena
-    # records (2 B key beside the weights) per edge, and 10 B narrow super-tile stream
-    # records for a share of each super-tile's in-edges
+    assert E == n * k
+    # every edge in the intermediate buffers: 12 B edge records (target and two weights), 10 B
+    # narrow super-tile stream records and 10 B tile arena records (2 B key beside the
+    # weights) per edge, and the per-target overflow sums (4 receptors x 8 B)
+    fpw = D.footprint(s, stream_permille=1000, arena_permille=1000)
+    assert 32 * E + 32 * n < fpw < 32 * E + 32 * n + 60 * n + (64 << 20)
+    # default: a share of each super-tile's and tile's in-edges; the arena's weight slot holds
+    # the device construction's temporaries at least (E bytes of projections, 12 B of counts
+    # and cursors per (neuron, delay), 16 B of row lengths and starts per neuron)
     fp = D.footprint(s)
-    st = 10 * _stream_records(100000, 556)
-    assert st < 10 * E // 2
-    assert 22 * E + st < fp < 22 * E + st + 60 * 100000 + (64 << 20)
-    # streams for every edge (the worst case: all of them firing in one pass)
-    fpw = D.footprint(s, stream_permille=1000)
-    assert 32 * E < fpw < 32 * E + 60 * 100000 + (64 << 20)
-    assert abs((fpw - fp) - 10 * (E - _stream_records(100000, 556))) < 4096
+    st, ta = _stream_records(n, k), _arena_records(n, k)
+    assert st < E // 2 and ta < E // 2
+    gen = E + 12 * n * 10 + 16 * n
+    lo = 12 * E + 10 * st + 2 * ta + max(8 * ta, gen) + 32 * n
+    assert lo < fp < lo + 60 * n + (64 << 20)
+    # with the construction on the host the arena is its own size
+    fph = D.footprint(s, host_build=True)
+    lo = 12 * E + 10 * st + 10 * ta + 32 * n
+    assert lo < fph < lo + 60 * n + (64 << 20)
     # 12 B stream records where a weight may be negative
-    neg = configs.share(n=100000, indegree=556)
+    neg = configs.share(n=n, indegree=k)
     neg.projs[0].w_scale_inh = -4.0
-    fpn = D.footprint(neg, stream_permille=250)
-    st = 12 * _stream_records(100000, 556, 250, even=False)
-    assert 22 * E + st < fpn < 22 * E + st + 60 * 100000 + (64 << 20)
+    fpn = D.footprint(neg, stream_permille=250, arena_permille=1000, host_build=True)
+    st = 12 * _stream_records(n, k, 250, even=False)
+    assert 22 * E + st < fpn < 22 * E + st + 32 * n + 60 * n + (64 << 20)
     with pytest.raises(D.DbsimError, match="stream_permille"):
         D.footprint(s, stream_permille=1001)
+    with pytest.raises(D.DbsimError, match="arena_permille"):
+        D.footprint(s, arena_permille=1001)
     # single pass: the 12 B edge records and the event arena of 256-record blocks (2 B key +
     # 8 B weights + a 4 B count per block): every one of the 25 tiles of 4096 neurons gets its
     # in-degree in whole blocks plus two part-filled blocks per workgroup (at most 512) and bin
@@ -192,9 +218,10 @@ def test_footprint_matches_layout(L):
     # per neuron: a 64 B row header, the state, and the spike-history ring of at least
     # (D + 1) N entries rounded up to a power of two
     assert lo < fp1 < lo + 220 * 6100000 + (64 << 20)
-    fp2 = D.footprint(s)
-    st = 10 * _stream_records(6100000, 20)
-    assert 22 * E + st < fp2 < 22 * E + st + 220 * 6100000 + (64 << 20)
+    fp2 = D.footprint(s, host_build=True)
+    st, ta = 10 * _stream_records(6100000, 20), 10 * _arena_records(6100000, 20)
+    lo = 12 * E + st + ta + 32 * 6100000
+    assert lo < fp2 < lo + 220 * 6100000 + (64 << 20)
 
 
 def test_ensemble_footprint_and_validation(L):
