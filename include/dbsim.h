@@ -147,9 +147,10 @@ typedef struct dbsim_info {
     uint32_t n_members;        /* networks in the handle (1 unless an ensemble) */
     uint32_t fanin_passes;     /* 1: single-pass fan-in into tile blocks, 2: through super-tile streams */
     uint32_t device_built;     /* 1: the connection table was generated on the device */
-    uint32_t stream_record_bytes; /* super-tile stream record: 12, or 10 (a 2-byte key beside
-                                     the weight pair, when every weight is non-negative and
-                                     there are two per edge); 0 in the single-pass form */
+    uint32_t stream_record_bytes; /* super-tile stream record: 4 bytes per weight and 4 for
+                                     the key (12 or 8), or 10 (a 2-byte key beside the weight
+                                     pair, when every weight is non-negative and there are two
+                                     per edge); 0 in the single-pass form */
     uint32_t reserved;
     uint64_t stream_records;   /* records the super-tile streams hold in all (0 in the
                                   single-pass form) */

@@ -313,6 +313,23 @@ def test_full_arena_slices_sum_exactly(Sim, negative):
         sim.close()
 
 
+def test_small_buffers_one_weight_per_edge(Sim):
+    """The one-weight form (two receptors, 12-byte stream records) with streams and arena
+    slices of one in a thousand of their in-edges: spills and overflow sums, against the
+    oracle over a second of biological time."""
+    spec = configs.tiny(seed=13)
+    _say("tiny seed 13, stream_permille 1, arena_permille 1, 10000 steps")
+    sim = Sim(spec, stream_permille=1, arena_permille=1)
+    assert sim.info.weights_per_edge == 1 and sim.info.stream_record_bytes == 8
+    sim.step(10000)
+    st = sim.stats()
+    assert st["spilled_events"] > 0 and st["overflow_events"] > 0
+    orc = Oracle(spec, 32)
+    orc.step(10000)
+    _compare(sim, orc, spec)
+    sim.close()
+
+
 def test_small_buffers_on_a_region_network(Sim):
     """A region network (neurons project mostly into their own region, so a few tiles take
     a bin's events in bursts) with streams and arena slices of one in a hundred of their
