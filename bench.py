@@ -206,9 +206,10 @@ def run_small_configs(args):
 
 def run_served(args):
     """Served stream: seeded Poisson arrivals of requests of log-uniform size, admitted by
-    footprint, built on host threads and advanced together on the device. First at the
-    offered rate (an overload: network construction on the host bounds the service rate),
-    then at 70% of the sustained completion rate measured there, where queues are stable."""
+    footprint, built on host threads (connection tables on the device) and advanced
+    together on the device. First at the offered rate (an overload: the device's throughput
+    on many small networks bounds the service rate), then at 70% of the sustained
+    completion rate measured there, where queues are stable."""
     from netgen import configs
     from paper_2211_15963_amd.serve import Request, Server
 
