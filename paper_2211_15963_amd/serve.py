@@ -18,7 +18,10 @@ a seeded network description plus a biological duration. The server:
   different requests overlap on the device;
 * retires a request when its last slice has completed: reads its results, frees its
   memory and admits the next waiting requests. A request whose build, step or read
-  fails retires with the error and frees its memory; the others go on.
+  fails retires with the error and frees its memory; the others go on;
+* cancels a request at its cancel_at_s (relative to the start) or when cancel(rid) is
+  called from another thread: waiting, building or resident, it retires with the error
+  "cancelled" and frees what it holds.
 
 Each request's result depends only on its own description (every handle is
 independent and bit-deterministic), so a request gives the same bits alone and in
@@ -28,6 +31,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import hashlib
+import threading
 import time
 from dataclasses import dataclass, field
 from typing import Dict, List, Optional
@@ -43,6 +47,7 @@ class Request:
     spec: object          # netgen NetSpec
     n_steps: int          # Euler steps to run (whole bins for full results)
     arrival_s: float = 0.0
+    cancel_at_s: Optional[float] = None  # the client withdraws the request at this time
     # filled by the server
     footprint: int = 0
     t_admit: float = float("nan")
@@ -109,6 +114,19 @@ class Server:
         self.build_threads = int(build_threads)
         self.state_digest = state_digest
         self.full_results = full_results
+        self._lock = threading.Lock()
+        self._cancelled: set = set()
+
+    def cancel(self, rid: int) -> None:
+        """Withdraws request rid (callable from any thread while run() serves)."""
+        with self._lock:
+            self._cancelled.add(rid)
+
+    def _is_cancelled(self, r: Request, now: float) -> bool:
+        if r.cancel_at_s is not None and now >= r.cancel_at_s:
+            return True
+        with self._lock:
+            return r.rid in self._cancelled
 
     def _build(self, req: Request) -> Built:
         """Host phase, on a pool thread: validation, plan and tables; no HIP or torch call."""
@@ -152,6 +170,12 @@ class Server:
                         done.append(r)
                     else:
                         waiting.append(r)
+                # withdrawn requests that hold nothing yet
+                for r in [r for r in waiting if self._is_cancelled(r, now)]:
+                    waiting.remove(r)
+                    r.error, r.t_done = "cancelled", now
+                    done.append(r)
+                    progressed = True
                 # admission: arrival order, by footprint and slot
                 while (waiting and len(active) + len(building) < self.max_active
                        and in_use + waiting[0].footprint <= self.hbm_budget):
@@ -163,6 +187,14 @@ class Server:
                 # finished builds are deployed (here, on the serving thread) and join the active set
                 for fut in [f for f in building if f.done()]:
                     r = building.pop(fut)
+                    if self._is_cancelled(r, time.perf_counter() - t0):
+                        if fut.exception() is None:
+                            fut.result().free()
+                        r.error, r.t_done = "cancelled", time.perf_counter() - t0
+                        in_use -= r.footprint
+                        done.append(r)
+                        progressed = True
+                        continue
                     try:
                         sim, stream = self._deploy(r, fut.result())
                     except Exception as ex:  # a failed build or deploy retires the request with its error
@@ -192,9 +224,12 @@ class Server:
                         a.inflight.append(ev)
                         a.enqueued += n
                         progressed = True
-                # retire finished and failed requests (destroy waits for the handle's stream)
+                # retire finished, failed and withdrawn requests (destroy waits for the handle's stream)
                 still = []
+                now = time.perf_counter() - t0
                 for a in active:
+                    if a.req.error is None and self._is_cancelled(a.req, now):
+                        a.req.error = "cancelled"
                     if a.req.error is not None or (a.enqueued >= a.req.n_steps and not a.inflight):
                         if a.req.error is None:
                             try:

@@ -141,3 +141,41 @@ def test_a_failing_request_retires_alone(monkeypatch):
         if r.error is None:
             _say(f"  request {r.rid}: alone run")
             _same(r.result, _alone(r))
+
+
+def test_cancelled_requests_retire_and_free_their_memory():
+    """Requests withdrawn while waiting (at arrival), while resident (by their cancel time)
+    and from another thread (Server.cancel) retire with the error "cancelled" whatever state
+    they were in, and free their memory; the other requests complete with the same bits as
+    alone."""
+    import threading
+    import torch
+    from paper_2211_15963_amd.serve import Request, Server
+    reqs = _requests(5, seed=15, n_hi=5e4, d_hi_s=0.1, gap_s=0.0)
+    reqs[1].cancel_at_s = 0.0                                   # withdrawn on arrival
+    for k in (2, 3):                                            # long: 20 s of biological time
+        reqs[k] = Request(k, reqs[k].spec, 200_000, arrival_s=0.0)
+    reqs[2].cancel_at_s = 0.5
+    _say(f"serve 5 requests, 1 withdrawn on arrival, 2 at 0.5 s, 3 from another thread at 0.7 s; "
+         f"sizes {[r.spec.num_neurons for r in reqs]}")
+    torch.cuda.synchronize()
+    m0 = torch.cuda.memory_allocated()
+    srv = Server(max_active=4, slice_bins=5, build_workers=2)
+    timer = threading.Timer(0.7, srv.cancel, args=(3,))
+    timer.start()
+    try:
+        out = srv.run(reqs)
+    finally:
+        timer.cancel()
+    by = {r.rid: r for r in out["requests"]}
+    assert sorted(by) == [0, 1, 2, 3, 4]
+    for k in (1, 2, 3):
+        assert by[k].error == "cancelled" and by[k].result is None, (k, by[k].error)
+    # 2 and 3 were resident (deployed) when withdrawn, and 3 was withdrawn by the thread
+    assert by[2].t_built < 0.5 <= by[2].t_done and by[3].t_built < 0.7 <= by[3].t_done
+    assert out["completed"] == 2 and out["failed"] == 3
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == m0
+    for k in (0, 4):
+        _say(f"  request {k}: alone run")
+        _same(by[k].result, _alone(by[k]))
