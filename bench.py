@@ -132,7 +132,8 @@ def run_gpu(args):
         "ms_neuron": p1["ms_neuron"] - p0["ms_neuron"], "ms_readout": p1["ms_readout"] - p0["ms_readout"],
         "timed_bins": p1["timed_bins"] - p0["timed_bins"], "spec": spec, "build_s": s1["build_seconds"],
         "hbm_bytes": s1["hbm_bytes"], "tuning": sim.tuning(),
-        "run_totals": {"bins": s2["bins"], "edge_events": s2["edge_events"], "spilled_events": s2["spilled_events"]},
+        "run_totals": {"bins": s2["bins"], "edge_events": s2["edge_events"], "spilled_events": s2["spilled_events"],
+                       "overflow_events": s2["overflow_events"]},
     }
     sim.close()
     return out
