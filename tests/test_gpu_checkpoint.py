@@ -142,3 +142,23 @@ def test_checkpoint_errors(Sim):
     _same_after(a, c, spec, 6, 10)
     a.close()
     c.close()
+
+
+def test_resume_with_small_buffers(Sim):
+    """Streams and arena slices of one in a hundred of their in-edges on both sides: the
+    restore re-assembles the next bin's delay >= 2 events through the slow paths (spills and
+    overflow sums) and the continued run equals the uninterrupted one."""
+    spec = configs.share(n=20000, indegree=300, seed=43)
+    S, K, M = spec.steps_per_bin, 25, 25
+    _say(f"share 20000 / k300 seed 43, stream and arena shares 10 per mille, checkpoint at bin {K}, {M} more")
+    a = Sim(spec, stream_permille=10, arena_permille=10)
+    a.step(K * S)
+    image = a.checkpoint()
+    a.step(M * S)
+    assert a.stats()["overflow_events"] > 0
+    b = Sim(spec, stream_permille=10, arena_permille=10)
+    b.restore(image)
+    b.step(M * S)
+    _same_after(a, b, spec, K, M)
+    a.close()
+    b.close()

@@ -40,3 +40,26 @@ def test_ensemble_members_equal_alone_and_oracle():
             Ve, Je, re = ens.member_state(m)
             assert np.array_equal(Ve.astype(np.float64), Vo) and np.array_equal(Je.astype(np.float64), Jo)
     ens.close()
+
+
+def test_ensemble_with_small_buffers_equals_default():
+    """The whole ensemble's streams and arena slices at one in a hundred of their in-edges
+    (spills and overflow sums across members): every member bit-identical to the default
+    buffers' run."""
+    from paper_2211_15963_amd import Simulator
+    members = [configs.ensemble_member(m, seed=4, n_lo=1500, n_hi=12000) for m in range(5)]
+    steps = 300
+    _say(f"ensemble of {len(members)} members with 10 per mille buffers vs default, {steps} steps")
+    ref = Simulator(members)
+    ref.step(steps)
+    small = Simulator(members, stream_permille=10, arena_permille=10)
+    small.step(steps)
+    st = small.stats()
+    assert st["overflow_events"] > 0 and st["edge_events"] == ref.stats()["edge_events"]
+    for m in range(len(members)):
+        a, b = ref.member_spikes(m), small.member_spikes(m)
+        assert len(a[0]) > 0 and np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), m
+        for x, y in zip(ref.member_state(m), small.member_state(m)):
+            assert np.array_equal(x, y), m
+    ref.close()
+    small.close()
