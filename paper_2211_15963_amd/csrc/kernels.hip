@@ -522,18 +522,16 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
         }
         const uint32_t nmap = (ec + (1u << mb_bits) - 1) >> mb_bits;
         __syncthreads();
-        for (uint32_t r0 = 0; r0 < ec; r0 += RE) {
-            const uint32_t ne = min(RE, ec - r0);
-            const uint32_t nbt = (ne + kScatterThreads - 1) / kScatterThreads;
-            for (uint32_t t = tid; t < nb; t += kScatterThreads) R.hist[t] = 0;
-            __syncthreads();
-            Batch B;
-            // all loads of the batch are issued before any is used (latency cover); the
-            // segment of each event is found from the coarse map, independently per event
+        // a round's loads: all of them issued before any is used (latency cover); the segment
+        // of each event is found from the coarse map, independently per event
+        Batch B;
+        auto load_round = [&](uint32_t ra) {
+            const uint32_t na = min(RE, ec - ra);
+            const uint32_t nba = (na + kScatterThreads - 1) / kScatterThreads;
 #pragma unroll
             for (int u = 0; u < kMaxBatch; u++) {
-                if (u < (int)nbt) {
-                    const uint32_t ge = r0 + min(u * kScatterThreads + tid, ne - 1);
+                if (u < (int)nba) {
+                    const uint32_t ge = ra + min(u * kScatterThreads + tid, na - 1);
                     const uint32_t m = ge >> mb_bits;
                     const uint32_t lo = s_map[m], hi = m + 1 < nmap ? s_map[m + 1] : nseg - 1;
                     const uint32_t sg = lo + seg_search(s_spre + lo, hi - lo + 1, ge);
@@ -549,6 +547,13 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
                     }
                 }
             }
+        };
+        if (ec) load_round(0);
+        for (uint32_t r0 = 0; r0 < ec; r0 += RE) {
+            const uint32_t ne = min(RE, ec - r0);
+            const uint32_t nbt = (ne + kScatterThreads - 1) / kScatterThreads;
+            for (uint32_t t = tid; t < nb; t += kScatterThreads) R.hist[t] = 0;
+            __syncthreads();
 #pragma unroll
             for (int u = 0; u < kMaxBatch; u++)
                 if (u < (int)nbt && u * kScatterThreads + tid < ne) B.br[u] = rank_event(net, R, B.key[u], nb, 0, bshift);
@@ -561,6 +566,9 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
             place_batch(R, B, ne, nbt);
             if (tid == 0 && r0 == 0) s_pc = G + claim; // read by every thread at the end of the chunk
             __syncthreads();
+            // this round's events are in LDS: the next round's loads go out now and land
+            // while the runs are written
+            if (r0 + RE < ec) load_round(r0 + RE);
             if (KW == 2 && net.narrow) {
                 if (spill) write_runs_narrow<true>(net, R, ne, nb, bshift);
                 else write_runs_narrow<false>(net, R, ne, nb, bshift);
