@@ -484,29 +484,50 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
     // counter (a workgroup that starts late, behind another kernel's workgroups, takes
     // fewer); the next one is claimed while this one is read
     __shared__ unsigned long long s_pc;
-    unsigned long long c = blockIdx.x;
-    while (c < nchunks) {
-        const unsigned long long i0 = c * spc;
-        const uint32_t nseg = (uint32_t)min((unsigned long long)spc, total - i0);
-        uint32_t len = 0;
-        if (tid < nseg) {
-            const unsigned long long it = i0 + tid;
+    // this thread's segment of a chunk: the spiking neuron j, then its row header (row start,
+    // bit 63: inhibitory source; the delay segment offsets). For the next chunk both are
+    // fetched during the current chunk's first two rounds (pf: 1 neuron, 2 header too)
+    uint32_t pf = 0, pf_d = 0, pf_j = 0, pf_so = 0, pf_eo = 0;
+    uint2 pf_rs = make_uint2(0u, 0u);
+    unsigned long long pf_c = ~0ull;
+    auto fetch_id = [&](unsigned long long cn) {
+        pf = 0;
+        pf_c = cn;
+        const unsigned long long in0 = cn * spc;
+        if (cn < nchunks && tid < min((unsigned long long)spc, total - in0)) {
+            const unsigned long long it = in0 + tid;
             uint32_t lo = 0, hi = D;
             while (hi - lo > 1u) {
                 const uint32_t mid = (lo + hi) >> 1;
                 if (s_dpre[mid] <= it) lo = mid;
                 else hi = mid;
             }
-            const uint32_t d = lo + 1;
-            const uint32_t j = net.rec[(s_dstart[lo] + (it - s_dpre[lo])) & net.RCmask] >> 4;
-            // row header of j: row start (bit 63: inhibitory source), then the delay segment
-            // offsets (the records carry the source class themselves)
-            const uint32_t* hp = net.hdr + (size_t)j * net.HW;
-            const uint2 rs = *reinterpret_cast<const uint2*>(hp);
-            const uint32_t so = hp[1 + d], eo = hp[2 + d];
-            s_sstart[tid] = (((unsigned long long)(rs.y & 0x7FFFFFFFu) << 32) | rs.x) + so;
-            len = eo - so;
+            pf_d = lo + 1;
+            pf_j = net.rec[(s_dstart[lo] + (it - s_dpre[lo])) & net.RCmask] >> 4;
+            pf = 1;
         }
+    };
+    auto fetch_hdr = [&]() {
+        if (pf == 1) {
+            const uint32_t* hp = net.hdr + (size_t)pf_j * net.HW;
+            pf_rs = *reinterpret_cast<const uint2*>(hp);
+            pf_so = hp[1 + pf_d];
+            pf_eo = hp[2 + pf_d];
+            pf = 2;
+        }
+    };
+    unsigned long long c = blockIdx.x;
+    while (c < nchunks) {
+        const unsigned long long i0 = c * spc;
+        const uint32_t nseg = (uint32_t)min((unsigned long long)spc, total - i0);
+        uint32_t len = 0;
+        if (pf_c != c) fetch_id(c);
+        fetch_hdr();
+        if (tid < nseg) {
+            s_sstart[tid] = (((unsigned long long)(pf_rs.y & 0x7FFFFFFFu) << 32) | pf_rs.x) + pf_so;
+            len = pf_eo - pf_so;
+        }
+        pf_c = ~0ull;
         uint32_t ec;
         const uint32_t ex = block_exclusive_scan(len, R.s_wave, &ec);
         s_spre[tid] = ex;
@@ -567,8 +588,10 @@ __global__ void __launch_bounds__(kScatterThreads) k_part(DevNet net, uint32_t d
             if (tid == 0 && r0 == 0) s_pc = G + claim; // read by every thread at the end of the chunk
             __syncthreads();
             // this round's events are in LDS: the next round's loads go out now and land
-            // while the runs are written
+            // while the runs are written, and with them the next chunk's segment lookups
             if (r0 + RE < ec) load_round(r0 + RE);
+            if (r0 == 0) fetch_id(s_pc);
+            else if (r0 == RE) fetch_hdr();
             if (KW == 2 && net.narrow) {
                 if (spill) write_runs_narrow<true>(net, R, ne, nb, bshift);
                 else write_runs_narrow<false>(net, R, ne, nb, bshift);
