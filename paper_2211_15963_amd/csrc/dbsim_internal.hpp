@@ -18,16 +18,17 @@
 //     (HW = D + 3 rounded up to 4 words: the row start as u64 with the source
 //     class in bit 63, then the D + 1 delay segment offsets inside the row), so
 //     that one 64-byte read gives everything a (spike, delay) segment needs;
-//   the event arena of the fan-in, sized by each tile's total in-degree (the most
-//     events a tile can receive in one bin: an edge delivers at most once per bin).
-//     Single-pass form (on request, where the tiles' carry buffers fit a workgroup's LDS): blocks of
-//     kFanBlock records, a 16-bit key array (target within the tile | inhibitory
-//     source << 15) beside the weights; tile t owns blocks tile_base[t] ..
-//     tile_base[t+1]: its in-degree in whole blocks plus two part-filled blocks per
-//     workgroup and bin (each workgroup and pass leaves at most one). Two-pass
-//     form: the same 16-bit keys beside the weights, tile t's slice tile_base[t] ..
-//     tile_base[t+1]; the super-tile streams hold records of 1 + KW words (target |
-//     source class << 31, then the weights);
+//   the event arena of the fan-in. Single-pass form (on request, where the tiles'
+//     carry buffers fit a workgroup's LDS): blocks of kFanBlock records, a 16-bit key
+//     array (target within the tile | inhibitory source << 15) beside the weights; tile
+//     t owns blocks tile_base[t] .. tile_base[t+1]: its in-degree in whole blocks (the
+//     most events a tile can receive in one bin: an edge delivers at most once per bin)
+//     plus two part-filled blocks per workgroup and bin (each workgroup and pass leaves
+//     at most one). Two-pass form: the same 16-bit keys beside the weights, tile t's
+//     slice tile_base[t] .. tile_base[t+1] a share of its in-edges, the events past a
+//     full slice summed in the per-target overflow sums ovf; the super-tile streams
+//     (slices of a share of each super-tile's in-edges) hold records of 1 + KW words
+//     (target | source class << 31, then the weights) or the narrow form below;
 //   spike history: rec u32[RC] ring of (id << 4 | substep), per-bin start u64[MB]
 //     and count u32[MB] (rings indexed by bin & (MB-1));
 //   region readout: per-block partial sums f64/u32, per-region block lists,

@@ -477,8 +477,9 @@ std::string make_plan(const dbsim_desc& opts, const Members& mem, Plan& p) {
         p.narrow = nonneg;
     }
     // stream slices: a share of each super-tile's in-edges (all of them would cover the
-    // worst case, every edge firing in one pass; a bin at 15 Hz fills about 1.5 %), even
-    // sized for the narrow records (the bucketing copies record pairs)
+    // worst case, every edge firing in one pass; a pass at 15 Hz fills about 1.4 %), even
+    // sized for the narrow records (the bucketing copies record pairs); the runs past a
+    // full slice go to the tile arena event by event
     if (opts.stream_permille > 1000) return "stream_permille must lie in 0..1000";
     p.st_permille = opts.stream_permille ? opts.stream_permille : kStreamPermille;
     p.st_len.assign(p.NS, 0);
