@@ -11,6 +11,8 @@ larger sizes or in rare numerical regimes.
 * Fixed-point conversion ties: constant weights and a saturating drive make every target's
   bin sum exactly n q(w), chosen half-way between two floats both below and above 2^24,
   with both rounding directions of round-half-even.
+* A synchronous burst: nearly every neuron fires in one bin and every delay is one bin, so
+  the next bin delivers nearly every edge of the table at once.
 """
 import os
 import sys
@@ -155,3 +157,38 @@ def test_conversion_ties_bit_exact(Sim):
         sim.step(20 * S)
         _compare(sim, orc, spec, f"ties single_pass={single_pass}")
         sim.close()
+
+
+def test_synchronous_burst_through_the_buffers(Sim):
+    """99 % of a 600,000-neuron network fires in bin 0 (spike injection) and every delay is
+    one bin, so bin 1 delivers ~99 % of the 6e7 edges at once. Streams and arena sized for
+    every edge (1000 per mille) take it without a slow-path event (the worst case of one
+    bin); the default shares send most of it past their slices (spills into the arena,
+    overflow sums) and give the same bits. Bins 0-1 are checked against the oracle too."""
+    spec = configs.share(n=600_000, indegree=100, seed=71, d_max=1)
+    S, E = spec.steps_per_bin, spec.num_edges()
+    _say("share 600000 / k100, all delays 1, 99 % injected in bin 0: every-edge vs default buffers, 5 bins")
+    full = Sim(spec, stream_permille=1000, arena_permille=1000)
+    full.set_spike_injection(0.99, 1)
+    full.step(2 * S)
+    st2 = full.stats()
+    assert st2["edge_events"] >= 0.98 * E and st2["spilled_events"] == 0 and st2["overflow_events"] == 0
+    orc = Oracle(spec, 32)
+    orc.set_threads(_threads())
+    orc.set_injection(0.99, 1)
+    orc.step(2 * S)
+    _compare(full, orc, spec, "burst, bins 0-1")
+    full.step(3 * S)
+    assert full.stats()["spilled_events"] == 0 and full.stats()["overflow_events"] == 0
+    small = Sim(spec)
+    small.set_spike_injection(0.99, 1)
+    small.step(5 * S)
+    st = small.stats()
+    assert st["spilled_events"] > 0.1 * E and st["overflow_events"] > 0.5 * E
+    a, b = full.spikes(), small.spikes()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    for x, y in zip(full.state(), small.state()):
+        assert np.array_equal(x, y)
+    assert st["edge_events"] == full.stats()["edge_events"]
+    full.close()
+    small.close()
