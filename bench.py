@@ -132,6 +132,8 @@ def run_gpu(args):
         "ms_neuron": p1["ms_neuron"] - p0["ms_neuron"], "ms_readout": p1["ms_readout"] - p0["ms_readout"],
         "timed_bins": p1["timed_bins"] - p0["timed_bins"], "spec": spec, "build_s": s1["build_seconds"],
         "hbm_bytes": s1["hbm_bytes"], "tuning": sim.tuning(),
+        "buffers": {"stream_records": int(sim.info.stream_records), "arena_records": int(sim.info.arena_records),
+                    "stream_record_bytes": int(sim.info.stream_record_bytes)},
         "run_totals": {"bins": s2["bins"], "edge_events": s2["edge_events"], "spilled_events": s2["spilled_events"],
                        "overflow_events": s2["overflow_events"]},
     }
@@ -721,7 +723,8 @@ def main():
                    "neurons": spec.num_neurons, "synapses": spec.num_edges(), "dt_ms": spec.dt_ms,
                    "bin_ms": spec.bin_ms, "regime_hz": args.regime, "mean_rate_hz": round(g["rate_hz"], 3),
                    "rtf": g["wall"] / g["bio_s"], "launch": args.mode, "build_s": round(g["build_s"], 1),
-                   "device_gb": round(g["hbm_bytes"] / 1e9, 2), "fanin_schedule": g["tuning"],
+                   "device_gb": round(g["hbm_bytes"] / 1e9, 2), "fanin_buffers": g["buffers"],
+                   "fanin_schedule": g["tuning"],
                    "run_totals": g["run_totals"]},
         "rtf_15hz": g["wall"] / g["bio_s"] if args.regime == 15 else None,
         "regimes": regimes,
